@@ -1,0 +1,239 @@
+"""Seeded synthetic inputs: the double relativistic Harris sheet.
+
+This module only prepares inputs.  It holds none of the particle or field
+arithmetic of the semi-implicit step, and it imports nothing else from this
+package besides the parameter calculator, so both the GPU path and the CPU
+checker can take their inputs from here.
+
+Setup (Schoeffler et al. 2025, Sec. 2):
+  * two current sheets at y = +-L_y/2 in a periodic box y in [-L_y, L_y),
+    i.e. the sheets sit at +-Y/4 for a box of height Y = 2 L_y;
+  * each sheet: counter-drifting Maxwell-Juettner (MJ) populations boosted
+    along +-z with drift speed v_d, density n0 sech^2((y -+ L_y/2)/a);
+  * a uniform background of density n_b at rest;
+  * B0 from pressure balance and a from Ampere's law (params.harris).
+
+The paper prints the double-sheet B_x profile with a sign garble (its form is
+3 B0 at y = 0 and does not reverse).  The profile used here reverses at both
+sheets: B_x = B0 [tanh((y + L_y/2)/a) - tanh((y - L_y/2)/a) - 1].
+
+The paper's tearing runs grow from noise; the workloads add a seed
+delta B_y = eps B0 cos(2 pi x / X) at cell centres, uniform in y (and z), which
+is divergence-free on the grid.  The particles do not depend on eps.
+
+Loading: per cell and species, half the macro-particles belong to the sheet
+population and half to the background; positions are uniform in the cell and
+shared by the species (pair loading, exact charge neutrality); the
+weight carries the density, w = n(y_p) V / (particles of that population per
+cell).  A sheet particle drifts with the sign of the nearer sheet; positrons
+(species 0, q = +1) drift along +z on the upper sheet and electrons (species 1,
+q = -1) along -z.  MJ momenta come from an inverse-CDF table of
+u^2 exp(-(gamma - 1)/theta); the drift boost uses the flipping method of
+Zenitani (2015).
+
+Layout of the generated particles: sorted by bin = cell * nspecies + species,
+cells in natural order (i + nx (j + ny k)), so ``bin_start`` is known up front.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import Dict, Optional
+
+import numpy as np
+
+from . import params as _params
+
+N0 = 1.0 / (4.0 * math.pi)   # omega_pe0 = 1 with c = m_e = e = 1
+
+
+@dataclass(frozen=True)
+class Workload:
+    """One synthetic double-Harris workload (sizes and physics knobs)."""
+
+    name: str
+    dim: int
+    nx: int
+    ny: int
+    nz: int
+    dx_over_a: float          # cell size in units of the sheet half thickness a
+    ppc: int                  # macro-particles per cell per species
+    cfl: float = 0.5          # dt = cfl * dx / c
+    theta_s: float = 1.0      # sheet temperature T / (m c^2)
+    beta_d: float = 0.3       # sheet drift speed
+    nb_over_n0: float = 0.1   # background density ratio
+    theta_b: float = 0.1      # background temperature
+    eps: float = 0.01         # delta B_y seed amplitude / B0
+    seed: int = 0
+    steps: int = 10
+    q: tuple = (1.0, -1.0)
+    m: tuple = (1.0, 1.0)
+
+    @property
+    def nspecies(self) -> int:
+        return len(self.q)
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * self.ny * (self.nz if self.dim == 3 else 1)
+
+    @property
+    def nparticles(self) -> int:
+        return self.ncells * self.nspecies * self.ppc
+
+    @property
+    def harris(self) -> _params.HarrisParams:
+        return _params.harris(N0, self.theta_s, self.beta_d)
+
+    @property
+    def dx(self) -> float:
+        return self.dx_over_a * self.harris.a
+
+    @property
+    def dt(self) -> float:
+        return self.cfl * self.dx
+
+    @property
+    def sigma_c(self) -> float:
+        """Cold magnetisation of the background (derived, not imposed)."""
+        return _params.sigma_cold(self.harris.B0, self.nb_over_n0 * N0, self.m[0])
+
+
+# The workloads: 2D 64x32 (small, all parities), 2D 1024x512 (throughput),
+# 2D 256x128 (adjoint), 3D 128x64x64 and 3D 256x128x128.
+WORKLOADS: Dict[str, Workload] = {
+    "harris2d_64x32": Workload("harris2d_64x32", 2, 64, 32, 1, 0.5, 16, seed=1, steps=10),
+    "harris2d_1024x512": Workload("harris2d_1024x512", 2, 1024, 512, 1, 1.0, 64, seed=2, steps=100),
+    "harris2d_256x128": Workload("harris2d_256x128", 2, 256, 128, 1, 0.5, 32, seed=3, steps=20),
+    "harris3d_128x64x64": Workload("harris3d_128x64x64", 3, 128, 64, 64, 0.5, 16, seed=4, steps=50),
+    "harris3d_256x128x128": Workload("harris3d_256x128x128", 3, 256, 128, 128, 0.5, 8, seed=5, steps=20),
+}
+
+
+def workload(name: str, **overrides) -> Workload:
+    wl = WORKLOADS[name]
+    return replace(wl, **overrides) if overrides else wl
+
+
+# ----------------------------------------------------------------------------
+# Maxwell-Juettner sampling
+# ----------------------------------------------------------------------------
+def _mj_table(theta: float, npts: int = 1 << 15):
+    gmax = 1.0 + 60.0 * theta
+    umax = math.sqrt(gmax * gmax - 1.0)
+    u = np.linspace(0.0, umax, npts)
+    g = np.sqrt(1.0 + u * u)
+    f = u * u * np.exp(-(g - 1.0) / theta)
+    cdf = np.concatenate([[0.0], np.cumsum(0.5 * (f[1:] + f[:-1]) * np.diff(u))])
+    cdf /= cdf[-1]
+    return cdf, u
+
+
+def sample_mj(rng: np.random.Generator, theta: float, n: int) -> np.ndarray:
+    """Isotropic MJ momenta (u = gamma v / c), shape (3, n)."""
+    cdf, ut = _mj_table(theta)
+    umag = np.interp(rng.random(n), cdf, ut)
+    cz = 2.0 * rng.random(n) - 1.0
+    ph = 2.0 * math.pi * rng.random(n)
+    sz = np.sqrt(np.maximum(0.0, 1.0 - cz * cz))
+    return np.stack([umag * sz * np.cos(ph), umag * sz * np.sin(ph), umag * cz])
+
+
+def boost_z(rng: np.random.Generator, u: np.ndarray, beta: np.ndarray) -> np.ndarray:
+    """Boost rest-frame momenta along z by beta (array), flipping method."""
+    g = np.sqrt(1.0 + (u * u).sum(axis=0))
+    Gd = 1.0 / np.sqrt(1.0 - beta * beta)
+    uz = u[2].copy()
+    flip = -beta * uz / g > rng.random(u.shape[1])
+    uz[flip] = -uz[flip]
+    out = u.copy()
+    out[2] = Gd * (uz + beta * g)
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Particles and fields
+# ----------------------------------------------------------------------------
+def make_particles(wl: Workload, seed: Optional[int] = None) -> Dict[str, np.ndarray]:
+    """Generate the bin-sorted particle state in FP64.
+
+    Returns a dict with ``cell`` (int32, natural cell index), ``species``
+    (uint8), ``off`` (dim, n) offsets in [0,1), ``u`` (3, n), ``w`` (n), and
+    ``bin_start`` (int32, ncells * nspecies + 1).
+    """
+    seed = wl.seed if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64(seed))
+    hp = wl.harris
+    S, ppc, nc = wl.nspecies, wl.ppc, wl.ncells
+    n = nc * S * ppc
+    n_sheet = ppc // 2
+    n_bg = ppc - n_sheet
+    dx = wl.dx
+    Y = wl.ny * dx
+    Ly = 0.5 * Y
+    V = dx * dx * (dx if wl.dim == 3 else 1.0)
+
+    p = np.arange(n, dtype=np.int64)
+    cell = (p // (S * ppc)).astype(np.int32)
+    species = ((p // ppc) % S).astype(np.uint8)
+    k_in = p % ppc
+    is_sheet = k_in < n_sheet
+
+    # pair loading: every species gets the same positions (and hence the
+    # same weights), so the initial state is exactly charge neutral
+    off1 = rng.random((wl.dim, nc, 1, ppc))
+    off = np.broadcast_to(off1, (wl.dim, nc, S, ppc)).reshape(wl.dim, n).copy()
+    j = (cell.astype(np.int64) // wl.nx) % wl.ny
+    y = (j + off[1]) * dx - 0.5 * Y           # physical y in [-Y/2, Y/2)
+
+    dens_sheet = N0 * (1.0 / np.cosh((y - 0.5 * Ly) / hp.a) ** 2 + 1.0 / np.cosh((y + 0.5 * Ly) / hp.a) ** 2)
+    w = np.where(is_sheet, dens_sheet * V / n_sheet, wl.nb_over_n0 * N0 * V / n_bg)
+
+    u = np.empty((3, n))
+    ns = int(is_sheet.sum())
+    us = sample_mj(rng, wl.theta_s, ns)
+    qv = np.asarray(wl.q)[species[is_sheet]]
+    beta = wl.beta_d * np.sign(y[is_sheet]) * np.sign(qv)
+    beta[beta == 0] = wl.beta_d
+    u[:, is_sheet] = boost_z(rng, us, beta)
+    u[:, ~is_sheet] = sample_mj(rng, wl.theta_b, n - ns)
+
+    counts = np.full(nc * S, ppc, dtype=np.int64)
+    bin_start = np.zeros(nc * S + 1, dtype=np.int64)
+    np.cumsum(counts, out=bin_start[1:])
+    return {
+        "cell": cell,
+        "species": species,
+        "off": off,
+        "u": u,
+        "w": w,
+        "bin_start": bin_start.astype(np.int32),
+    }
+
+
+def make_fields(wl: Workload, eps: Optional[float] = None):
+    """Initial E (zero, at nodes) and B (at cell centres), both (3, ncells) FP64."""
+    eps = wl.eps if eps is None else eps
+    hp = wl.harris
+    dx = wl.dx
+    nx, ny = wl.nx, wl.ny
+    nz = wl.nz if wl.dim == 3 else 1
+    Y = ny * dx
+    X = nx * dx
+    Ly = 0.5 * Y
+    yc = (np.arange(ny) + 0.5) * dx - 0.5 * Y
+    xc = (np.arange(nx) + 0.5) * dx
+    bx = hp.B0 * (np.tanh((yc + 0.5 * Ly) / hp.a) - np.tanh((yc - 0.5 * Ly) / hp.a) - 1.0)
+    by = eps * hp.B0 * np.cos(2.0 * math.pi * xc / X)
+    B = np.zeros((3, nz, ny, nx))
+    B[0] = bx[None, :, None]
+    B[1] = by[None, None, :]
+    E = np.zeros((3, nz * ny * nx))
+    return E, B.reshape(3, -1).copy()
+
+
+def seed_direction(wl: Workload) -> np.ndarray:
+    """d B / d eps: the seed pattern B0 cos(2 pi x / X) in B_y, shape (3, ncells)."""
+    _, B1 = make_fields(wl, eps=1.0)
+    _, B0 = make_fields(wl, eps=0.0)
+    return B1 - B0
