@@ -1,0 +1,171 @@
+/*
+ * relsim.h - C ABI of the MI355X (gfx950) library for the per-particle hot
+ * path of the relativistic semi-implicit PIC step (RelSIM, an energy-
+ * conserving ECsim-type scheme; Schoeffler et al. 2025, Sec. 2: explicit
+ * pusher, implicit field solve, mass-matrix linearised current).
+ *
+ * The step n -> n+1, with x at half-integer and u = gamma v at integer times:
+ *   S1 gather B^n at x^{n+1/2}                  (CIC from cell centres)
+ *   S2 gbar = gamma(u^n), b = beta_s B_p/(gbar c), beta_s = q_s dt/(2 m_s),
+ *      alpha = (I - [b]x + b b^T)/(1 + b^2)
+ *   S3 Jhat_g = V^-1 sum_p w q W_g alpha u/gbar,
+ *      M_{g,g'} = V^-1 sum_p (w q beta/gbar) W_g W_g' alpha
+ *   S4 [I + (c th dt)^2 C_CN C_NC + 4 pi th dt M] E_th = E^n + c th dt C_CN B^n - 4 pi th dt Jhat
+ *   S5 B^{n+1} = B^n - c dt C_NC E_th,  E^{n+1} = (E_th - (1 - th) E^n)/th
+ *   S6 E_p = sum_g W_g E_th_g, ubar = alpha (u + beta E_p), u^{n+1} = 2 ubar - u,
+ *      x^{n+3/2} = x^{n+1/2} + dt u^{n+1}/gamma(u^{n+1})
+ *   S7 W = sum_p w m c^2 (gamma - 1) + V/(8 pi) (sum |E|^2 + sum |B|^2)
+ *
+ * Conventions
+ *   - Gaussian units.  Periodic grid nx x ny (x nz), every extent >= 3.
+ *     E, Jhat and M live at nodes (i,j,k)*dx, B at cell centres
+ *     (i+1/2, j+1/2, k+1/2)*dx.  Node and cell (i,j,k) share the linear index
+ *     i + nx*(j + ny*k); N = nx*ny*nz (nz = 1 in 2D, where d/dz = 0).
+ *   - Grid arrays are FP64, component-major: E, B, Jhat [3][N].
+ *     M is [noff][9][N]: noff = 9 (2D) or 27 (3D); offset index
+ *     sum_d (delta_d + 1) 3^d over delta in {-1,0,1}^dim (x fastest); the
+ *     3x3 block row-major.  Entry [o][3r+c][g] couples E_c at node g+delta(o)
+ *     into row r of node g.
+ *   - Every array argument is a DEVICE pointer owned by the caller.  The
+ *     library allocates no device memory after relsim_init: it carves the
+ *     caller's workspace.  Host scalars returned (iters, residuals, energies)
+ *     make the call synchronous; all other calls are asynchronous on the
+ *     stream given to relsim_init.
+ *   - Return value: RELSIM_OK (0) or a negative error code; relsim_strerror
+ *     and relsim_last_error give text.  No exception crosses the ABI.  A
+ *     context is not thread safe; several contexts may coexist.
+ */
+#ifndef RELSIM_H
+#define RELSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RELSIM_OK 0
+#define RELSIM_EINVAL (-1)        /* bad parameter, size or pointer            */
+#define RELSIM_ENOTCONVERGED (-2) /* linear solve hit its iteration limit       */
+#define RELSIM_EHIP (-3)          /* a HIP runtime call failed (text captured)  */
+#define RELSIM_ENONFINITE (-4)    /* NaN/Inf met in a reduction or the solve    */
+#define RELSIM_ERANGE (-5)        /* a particle moved more than one cell, or a
+                                     bin exceeded 65535 particles              */
+
+#define RELSIM_FP64 0  /* particle state and particle arithmetic in double    */
+#define RELSIM_MIXED 1 /* particle state/arithmetic in float, per-cell moments
+                          reduced in float, grid accumulation in double      */
+
+typedef struct relsim_ctx relsim_ctx;
+
+typedef struct {
+  int32_t dim;                 /* 2 or 3                                          */
+  int32_t nx, ny, nz;          /* cells per dimension (nz ignored in 2D), >= 3    */
+  double dx, dy, dz;           /* cell sizes                                      */
+  double dt, c, theta;         /* time step, speed of light, time centring of E   */
+  int32_t precision;           /* RELSIM_FP64 or RELSIM_MIXED                     */
+  int32_t nspecies;            /* 1..8                                            */
+  double q[8], m[8];           /* charge and mass per species                    */
+  int64_t max_particles;       /* capacity of every particle array (< 2^31)       */
+  double gmres_rtol;           /* stop when ||r - A E_th|| <= rtol ||r||          */
+  int32_t gmres_restart;       /* Krylov dimension (1..64)                        */
+  int32_t gmres_maxit;         /* total Arnoldi steps allowed                     */
+  int32_t nonrelativistic;     /* 1: gamma == 1, kinetic energy m|u|^2/2          */
+  int32_t group;               /* lanes per cell in the particle kernels:
+                                  0 = choose from the mean occupancy, else
+                                  8, 16, 32 or 64                                 */
+} relsim_params;
+
+/* Particle state: structure of arrays, sorted by bin = cell * nspecies + s,
+ * so that the particles of (cell, species) occupy
+ * [bin_start[bin], bin_start[bin+1]).  Each array exists twice ("front" and
+ * "back"); the re-sort writes into the back set and then swaps the two sets
+ * (and the two bin_start arrays) inside this struct.  off[d] in [0,1) is the
+ * position inside the cell in units of the cell size; u[k] = gamma v_k;
+ * w = number of physical particles represented.  Element type is double for
+ * RELSIM_FP64 and float for RELSIM_MIXED; off[2] is unused in 2D. */
+typedef struct {
+  int64_t n;                   /* particles in use                                */
+  int32_t *bin_start;          /* [ncells*nspecies + 1]                           */
+  int32_t *cell;               /* [capacity] linear cell index (kept by sorts)    */
+  void *off[3];
+  void *u[3];
+  void *w;
+  int32_t *bin_start_back;
+  int32_t *cell_back;
+  void *off_back[3];
+  void *u_back[3];
+  void *w_back;
+  const uint8_t *species;      /* [n] species id, read only by relsim_sort        */
+} relsim_particles;
+
+/* Bytes of device workspace relsim_init needs for these parameters. */
+size_t relsim_workspace_bytes(const relsim_params *p);
+
+/* Validate parameters and create a context bound to the current HIP device
+ * and to `hip_stream` (a hipStream_t; NULL = default stream).  `workspace`
+ * must be a device buffer of at least relsim_workspace_bytes(p) bytes that
+ * stays valid, and unused by the caller, until relsim_finalize.  Allocates a
+ * small pinned host buffer and timing events; no device memory. */
+int relsim_init(const relsim_params *p, void *hip_stream, void *workspace, size_t workspace_bytes,
+                relsim_ctx **out);
+void relsim_finalize(relsim_ctx *ctx);
+
+/* a1 (general form): stable sort of arbitrary particles by bin.  Reads
+ * part->cell and part->species for the front set, writes the sorted state to
+ * the back set and swaps.  bin_start is rebuilt. */
+int relsim_sort(relsim_ctx *ctx, relsim_particles *part);
+
+/* a2-a4 (S1-S3): gather B^n, form alpha per particle and deposit Jhat [3][N]
+ * and M [noff][9][N] (both overwritten, FP64).  Particles must be bin-sorted. */
+int relsim_deposit_moments(relsim_ctx *ctx, const relsim_particles *part, const double *B_n, double *Jhat,
+                           double *M);
+
+/* a5 (S4-S5): restarted GMRES for E_th from the initial guess E^n, then the
+ * field update.  E_theta, E_np1, B_np1 are written.  iters / rel_resid (host
+ * pointers, may be NULL) receive the Arnoldi steps taken and the final true
+ * relative residual.  Synchronous (one small device-to-host copy per Arnoldi
+ * step).  Returns RELSIM_ENOTCONVERGED with the last iterate written when
+ * gmres_maxit is reached. */
+int relsim_field_solve(relsim_ctx *ctx, const double *M, const double *Jhat, const double *E_n, const double *B_n,
+                       double *E_theta, double *E_np1, double *B_np1, int32_t *iters, double *rel_resid);
+
+/* a6 (S6, +a1 when resort != 0): push every particle in place with E_th and
+ * B^n, move it across at most one cell face per dimension (periodic), and,
+ * if resort, re-sort it into the back set by a stable counting sort over the
+ * neighbour moves and swap.  With resort == 0 the particles stay in their
+ * old bins (their offsets may then lie in [-1, 2)), which is only valid as
+ * the last call on that state.  Returns RELSIM_ERANGE if a particle moved
+ * more than one cell (the state is then undefined). */
+int relsim_push(relsim_ctx *ctx, relsim_particles *part, const double *E_theta, const double *B_n, int32_t resort);
+
+/* a7 (S7): out[0..3] = kinetic, electric, magnetic, total energy (host
+ * array), accumulated in FP64 in both precisions.  Synchronous. */
+int relsim_energy(relsim_ctx *ctx, const relsim_particles *part, const double *E, const double *B, double out[4]);
+
+/* Field operators, exposed for tests and for the adjoint (all FP64 [3][N]).
+ * out = C_NC in (nodes -> centres), C_CN in (centres -> nodes), or the S4
+ * operator A applied to x. */
+int relsim_curl_nc(relsim_ctx *ctx, const double *in, double *out);
+int relsim_curl_cn(relsim_ctx *ctx, const double *in, double *out);
+int relsim_apply_A(relsim_ctx *ctx, const double *M, const double *x, double *out);
+
+/* Per-kernel timing with HIP events on the context's stream.  When enabled,
+ * every kernel launch is bracketed by events; relsim_timing_read
+ * synchronises and returns, per kernel name, the summed milliseconds and the
+ * launch count (up to `cap` entries, names copied into `names` as
+ * NUL-terminated strings of at most 47 characters).  Returns the number of
+ * entries or a negative error. */
+int relsim_timing_enable(relsim_ctx *ctx, int32_t on);
+int relsim_timing_reset(relsim_ctx *ctx);
+int relsim_timing_read(relsim_ctx *ctx, int32_t cap, char (*names)[48], double *ms, int64_t *count);
+
+const char *relsim_strerror(int code);
+const char *relsim_last_error(const relsim_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RELSIM_H */

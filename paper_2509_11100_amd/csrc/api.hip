@@ -1,0 +1,633 @@
+// C ABI of librelsim: parameter validation, workspace carving, per-kernel
+// timing, the host side of restarted GMRES, and the entry points declared in
+// include/relsim.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "relsim_internal.h"
+
+using namespace relsim;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct TimedLaunch {
+  int name;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct relsim_ctx {
+  relsim_params p;
+  KParams kp;
+  Layout L;
+  hipStream_t st;
+  char *ws;
+  int device;
+  std::string err;
+  double *host;  // pinned scratch for small device-to-host copies
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<TimedLaunch> pending;
+  std::vector<std::string> names;
+  std::map<std::string, int> name_id;
+  std::vector<double> ms;
+  std::vector<int64_t> count;
+
+  template <typename X>
+  X *at(size_t off) const {
+    return reinterpret_cast<X *>(ws + off);
+  }
+};
+
+namespace {
+
+int fail(relsim_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(relsim_ctx *c, hipError_t e, const char *where) {
+  return fail(c, RELSIM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_CHECK(c, expr)                        \
+  do {                                            \
+    hipError_t e_ = (expr);                       \
+    if (e_ != hipSuccess) return hip_fail(c, e_, #expr); \
+  } while (0)
+
+int name_index(relsim_ctx *c, const char *name) {
+  auto it = c->name_id.find(name);
+  if (it != c->name_id.end()) return it->second;
+  const int id = (int)c->names.size();
+  c->names.push_back(name);
+  c->name_id[name] = id;
+  c->ms.push_back(0.0);
+  c->count.push_back(0);
+  return id;
+}
+
+void harvest(relsim_ctx *c) {
+  if (c->pending.empty()) return;
+  hipStreamSynchronize(c->st);
+  for (auto &t : c->pending) {
+    float v = 0.f;
+    if (hipEventElapsedTime(&v, t.a, t.b) == hipSuccess) {
+      c->ms[t.name] += v;
+      c->count[t.name] += 1;
+    }
+    c->pool.push_back(t.a);
+    c->pool.push_back(t.b);
+  }
+  c->pending.clear();
+}
+
+// Run `f` (which enqueues one kernel or a short fixed sequence) bracketed by
+// events when timing is on.
+template <typename F>
+void timed(relsim_ctx *c, const char *name, F &&f) {
+  if (!c->timing) {
+    f();
+    return;
+  }
+  if (c->pool.size() < 2) harvest(c);
+  TimedLaunch t;
+  t.name = name_index(c, name);
+  t.b = c->pool.back();
+  c->pool.pop_back();
+  t.a = c->pool.back();
+  c->pool.pop_back();
+  hipEventRecord(t.a, c->st);
+  f();
+  hipEventRecord(t.b, c->st);
+  c->pending.push_back(t);
+}
+
+int validate(const relsim_params *p, std::string &msg) {
+  if (!p) return msg = "null params", RELSIM_EINVAL;
+  if (p->dim != 2 && p->dim != 3) return msg = "dim must be 2 or 3", RELSIM_EINVAL;
+  if (p->nx < 3 || p->ny < 3 || (p->dim == 3 && p->nz < 3)) return msg = "every grid extent must be >= 3", RELSIM_EINVAL;
+  const double nc = (double)p->nx * p->ny * (p->dim == 3 ? p->nz : 1);
+  if (nc * std::max(1, p->nspecies) >= 2147483647.0) return msg = "too many cells", RELSIM_EINVAL;
+  if (!(p->dx > 0) || !(p->dy > 0) || (p->dim == 3 && !(p->dz > 0))) return msg = "cell sizes must be > 0", RELSIM_EINVAL;
+  if (!(p->dt > 0) || !std::isfinite(p->dt)) return msg = "dt must be finite and > 0", RELSIM_EINVAL;
+  if (!(p->c > 0) || !std::isfinite(p->c)) return msg = "c must be finite and > 0", RELSIM_EINVAL;
+  if (!(p->theta >= 0.5 && p->theta <= 1.0)) return msg = "theta must lie in [1/2, 1]", RELSIM_EINVAL;
+  if (p->precision != RELSIM_FP64 && p->precision != RELSIM_MIXED) return msg = "unknown precision", RELSIM_EINVAL;
+  if (p->nspecies < 1 || p->nspecies > 8) return msg = "nspecies must be 1..8", RELSIM_EINVAL;
+  for (int s = 0; s < p->nspecies; ++s)
+    if (!(p->m[s] > 0) || !std::isfinite(p->q[s])) return msg = "species mass must be > 0, charge finite", RELSIM_EINVAL;
+  if (p->max_particles < 0 || p->max_particles >= 2147483647LL) return msg = "max_particles must be < 2^31", RELSIM_EINVAL;
+  if (p->gmres_restart < 1 || p->gmres_restart > kMaxRestart) return msg = "gmres_restart must be 1..64", RELSIM_EINVAL;
+  if (p->gmres_maxit < 1) return msg = "gmres_maxit must be >= 1", RELSIM_EINVAL;
+  if (!(p->gmres_rtol > 0)) return msg = "gmres_rtol must be > 0", RELSIM_EINVAL;
+  if (p->group != 0 && p->group != 8 && p->group != 16 && p->group != 32 && p->group != 64)
+    return msg = "group must be 0, 8, 16, 32 or 64", RELSIM_EINVAL;
+  return RELSIM_OK;
+}
+
+Layout make_layout(const relsim_params *p) {
+  Layout L{};
+  const size_t nc = (size_t)p->nx * p->ny * (p->dim == 3 ? p->nz : 1);
+  const size_t nb = nc * p->nspecies;
+  const size_t es = p->precision == RELSIM_MIXED ? 4 : 8;
+  const size_t np = (size_t)std::max<int64_t>(p->max_particles, 1);
+  const size_t nd = (size_t)n_dirs(p->dim);
+  const size_t n3 = 3 * nc;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.S = take((size_t)n_cell_moments(p->dim) * nc * es);
+  L.cnt = take(nd * nb * 2);
+  L.pre = take(nd * nb * 2);
+  L.total = take(nb * 4);
+  L.scan_tmp = take(std::max(scan_tmp_elems((int)nb + 1), scan_tmp_elems((int)gsort_tmp_elems(np))) * 4 + 64);
+  L.dirc = take(np);
+  L.err = take(64);
+  L.gm_V = take((size_t)(p->gmres_restart + 1) * n3 * 8);
+  L.gm_t = take(n3 * 8);
+  L.gm_b = take(n3 * 8);
+  L.gm_r = take(n3 * 8);
+  L.gm_part = take((size_t)kDotBlocks * (kMaxRestart + 2) * 8);
+  L.gm_small = take(4 * (kMaxRestart + 2) * 8);
+  L.red_part = take((size_t)kRedBlocks * 8 * 4);
+  L.gs_k0 = take(np * 4);
+  L.gs_k1 = take(np * 4);
+  L.gs_v0 = take(np * 4);
+  L.gs_v1 = take(np * 4);
+  L.gs_hist = take(gsort_tmp_elems(np) * 4);
+  L.end = o;
+  return L;
+}
+
+KParams make_kparams(const relsim_params *p) {
+  KParams k{};
+  k.dim = p->dim;
+  k.nx = p->nx;
+  k.ny = p->ny;
+  k.nz = p->dim == 3 ? p->nz : 1;
+  k.ncells = k.nx * k.ny * k.nz;
+  k.nspecies = p->nspecies;
+  k.nbins = k.ncells * k.nspecies;
+  k.nonrel = p->nonrelativistic ? 1 : 0;
+  k.dx = p->dx;
+  k.dy = p->dy;
+  k.dz = p->dim == 3 ? p->dz : 1.0;
+  k.dt = p->dt;
+  k.c = p->c;
+  k.theta = p->theta;
+  k.V = k.dx * k.dy * (p->dim == 3 ? k.dz : 1.0);
+  k.inv_dx = 1.0 / k.dx;
+  k.inv_dy = 1.0 / k.dy;
+  k.inv_dz = 1.0 / k.dz;
+  for (int s = 0; s < 8; ++s) {
+    k.q[s] = s < p->nspecies ? p->q[s] : 0.0;
+    k.m[s] = s < p->nspecies ? p->m[s] : 1.0;
+    k.beta[s] = s < p->nspecies ? p->q[s] * p->dt / (2.0 * p->m[s]) : 0.0;
+  }
+  return k;
+}
+
+int choose_group(const relsim_ctx *c, int64_t n) {
+  if (c->p.group) return c->p.group;
+  const double mean = (double)n / (double)c->kp.ncells;
+  int g = 8;
+  while (g < 64 && 2.0 * g <= 0.5 * mean) g *= 2;
+  return g;
+}
+
+PartPtrs front(const relsim_particles *pt) {
+  PartPtrs pp;
+  pp.bin_start = pt->bin_start;
+  for (int d = 0; d < 3; ++d) {
+    pp.off[d] = pt->off[d];
+    pp.u[d] = pt->u[d];
+  }
+  pp.w = pt->w;
+  return pp;
+}
+
+void swap_sets(relsim_particles *pt) {
+  std::swap(pt->bin_start, pt->bin_start_back);
+  std::swap(pt->cell, pt->cell_back);
+  for (int d = 0; d < 3; ++d) {
+    std::swap(pt->off[d], pt->off_back[d]);
+    std::swap(pt->u[d], pt->u_back[d]);
+  }
+  std::swap(pt->w, pt->w_back);
+}
+
+int check_particles(relsim_ctx *c, const relsim_particles *pt, bool need_back) {
+  if (!pt) return fail(c, RELSIM_EINVAL, "null particles");
+  if (pt->n < 0 || pt->n > c->p.max_particles) return fail(c, RELSIM_EINVAL, "particle count outside [0, max_particles]");
+  if (!pt->bin_start || !pt->off[0] || !pt->off[1] || (c->p.dim == 3 && !pt->off[2]) || !pt->u[0] || !pt->u[1] ||
+      !pt->u[2] || !pt->w)
+    return fail(c, RELSIM_EINVAL, "null particle array");
+  if (need_back && (!pt->bin_start_back || !pt->cell_back || !pt->off_back[0] || !pt->off_back[1] ||
+                    (c->p.dim == 3 && !pt->off_back[2]) || !pt->u_back[0] || !pt->u_back[1] || !pt->u_back[2] ||
+                    !pt->w_back))
+    return fail(c, RELSIM_EINVAL, "null back-buffer particle array");
+  return RELSIM_OK;
+}
+
+// Deferred error flags raised by kernels (bit 0: move > 1 cell or non-finite
+// position; bit 1: bin over 65535 particles; bit 2: bad cell/species id).
+int check_flags(relsim_ctx *c) {
+  HIP_CHECK(c, hipMemcpyAsync(c->host, c->at<int32_t>(c->L.err), sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+  HIP_CHECK(c, hipStreamSynchronize(c->st));
+  int32_t f;
+  std::memcpy(&f, c->host, sizeof(f));
+  if (f == 0) return RELSIM_OK;
+  HIP_CHECK(c, hipMemsetAsync(c->at<int32_t>(c->L.err), 0, sizeof(int32_t), c->st));
+  if (f & 1) return fail(c, RELSIM_ERANGE, "a particle moved more than one cell in a step, or its position is not finite");
+  if (f & 2) return fail(c, RELSIM_ERANGE, "a (cell, species) bin holds more than 65535 particles");
+  return fail(c, RELSIM_EINVAL, "cell index or species id out of range in relsim_sort input");
+}
+
+int launch_status(relsim_ctx *c, const char *where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, where);
+  return RELSIM_OK;
+}
+
+// device -> host copy of k doubles into c->host, synchronising
+int fetch(relsim_ctx *c, const double *dev, int k) {
+  HIP_CHECK(c, hipMemcpyAsync(c->host, dev, sizeof(double) * k, hipMemcpyDeviceToHost, c->st));
+  HIP_CHECK(c, hipStreamSynchronize(c->st));
+  return RELSIM_OK;
+}
+
+// out = A x   (uses gm_t as the curl scratch)
+void apply_A(relsim_ctx *c, const double *M, const double *x, double *out) {
+  double *t = c->at<double>(c->L.gm_t);
+  timed(c, "curl_nc", [&] { launch_curl(c->kp, x, t, 1, c->st); });
+  timed(c, "apply_A", [&] { launch_apply_A_tail(c->kp, M, x, t, out, c->st); });
+}
+
+int norm2(relsim_ctx *c, const double *x, size_t n, double *out) {
+  double *part = c->at<double>(c->L.red_part);
+  double *res = c->at<double>(c->L.gm_small) + 3 * (kMaxRestart + 2);
+  timed(c, "sumsq", [&] {
+    launch_sumsq_partials(x, n, part, c->st);
+    launch_reduce_partials(part, kRedBlocks, 1, res, c->st);
+  });
+  int rc = fetch(c, res, 1);
+  if (rc) return rc;
+  *out = std::sqrt(c->host[0]);
+  return RELSIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t relsim_workspace_bytes(const relsim_params *p) {
+  std::string msg;
+  if (validate(p, msg) != RELSIM_OK) return 0;
+  return make_layout(p).end;
+}
+
+int relsim_init(const relsim_params *p, void *hip_stream, void *workspace, size_t workspace_bytes, relsim_ctx **out) {
+  if (!out) return RELSIM_EINVAL;
+  *out = nullptr;
+  std::string msg;
+  const int v = validate(p, msg);
+  if (v != RELSIM_OK) return v;
+  const Layout L = make_layout(p);
+  if (!workspace || workspace_bytes < L.end) return RELSIM_EINVAL;
+  relsim_ctx *c = new (std::nothrow) relsim_ctx();
+  if (!c) return RELSIM_EINVAL;
+  c->p = *p;
+  if (c->p.dim == 2) c->p.nz = 1;
+  c->kp = make_kparams(&c->p);
+  c->L = L;
+  c->st = (hipStream_t)hip_stream;
+  c->ws = (char *)workspace;
+  hipGetDevice(&c->device);
+  if (hipHostMalloc((void **)&c->host, 4096, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return RELSIM_EHIP;
+  }
+  for (int i = 0; i < 4096; ++i) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) break;
+    c->pool.push_back(e);
+  }
+  if (hipMemsetAsync(c->at<int32_t>(L.err), 0, 64, c->st) != hipSuccess) {
+    relsim_finalize(c);
+    return RELSIM_EHIP;
+  }
+  *out = c;
+  return RELSIM_OK;
+}
+
+void relsim_finalize(relsim_ctx *c) {
+  if (!c) return;
+  hipStreamSynchronize(c->st);
+  for (auto &t : c->pending) {
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  for (auto e : c->pool) hipEventDestroy(e);
+  if (c->host) hipHostFree(c->host);
+  delete c;
+}
+
+int relsim_sort(relsim_ctx *c, relsim_particles *pt) {
+  if (!c) return RELSIM_EINVAL;
+  int rc = check_particles(c, pt, true);
+  if (rc) return rc;
+  if (!pt->cell) return fail(c, RELSIM_EINVAL, "relsim_sort needs the cell array");
+  if (c->p.nspecies > 1 && !pt->species) return fail(c, RELSIM_EINVAL, "relsim_sort needs species ids");
+  void *offb[3] = {pt->off_back[0], pt->off_back[1], pt->off_back[2]};
+  void *ub[3] = {pt->u_back[0], pt->u_back[1], pt->u_back[2]};
+  timed(c, "general_sort", [&] {
+    launch_gsort(c->kp, c->p.precision, pt->n, pt->cell, pt->species, front(pt), c->at<int32_t>(c->L.gs_k0),
+                 c->at<int32_t>(c->L.gs_k1), c->at<int32_t>(c->L.gs_v0), c->at<int32_t>(c->L.gs_v1),
+                 c->at<int32_t>(c->L.gs_hist), c->at<int32_t>(c->L.scan_tmp), c->at<int32_t>(c->L.err),
+                 pt->bin_start_back, pt->cell_back, offb, ub, pt->w_back, c->st);
+  });
+  rc = launch_status(c, "relsim_sort");
+  if (rc) return rc;
+  rc = check_flags(c);
+  if (rc) return rc;
+  swap_sets(pt);
+  return RELSIM_OK;
+}
+
+int relsim_deposit_moments(relsim_ctx *c, const relsim_particles *pt, const double *B_n, double *Jhat, double *M) {
+  if (!c) return RELSIM_EINVAL;
+  int rc = check_particles(c, pt, false);
+  if (rc) return rc;
+  if (!B_n || !Jhat || !M) return fail(c, RELSIM_EINVAL, "null grid array");
+  const int G = choose_group(c, pt->n);
+  void *S = c->at<char>(c->L.S);
+  timed(c, "deposit_cells", [&] { launch_deposit_cells(c->kp, c->p.precision, G, front(pt), B_n, S, c->st); });
+  timed(c, "assemble_nodes", [&] { launch_assemble(c->kp, c->p.precision, S, Jhat, M, c->st); });
+  return launch_status(c, "relsim_deposit_moments");
+}
+
+int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, const double *B_n, int32_t resort) {
+  if (!c) return RELSIM_EINVAL;
+  int rc = check_particles(c, pt, resort != 0);
+  if (rc) return rc;
+  if (!E_theta || !B_n) return fail(c, RELSIM_EINVAL, "null grid array");
+  const int G = choose_group(c, pt->n);
+  uint8_t *dirc = c->at<uint8_t>(c->L.dirc);
+  uint16_t *cnt = c->at<uint16_t>(c->L.cnt);
+  uint16_t *pre = c->at<uint16_t>(c->L.pre);
+  int32_t *total = c->at<int32_t>(c->L.total);
+  int32_t *err = c->at<int32_t>(c->L.err);
+  timed(c, "push", [&] {
+    launch_push(c->kp, c->p.precision, G, front(pt), E_theta, B_n, dirc, cnt, err, resort ? 1 : 0, c->st);
+  });
+  if (resort) {
+    timed(c, "sort_offsets", [&] { launch_sort_offsets(c->kp, cnt, pre, total, err, c->st); });
+    timed(c, "sort_scan", [&] {
+      launch_scan(total, pt->bin_start_back, c->kp.nbins, c->at<int32_t>(c->L.scan_tmp), c->st);
+    });
+    void *offb[3] = {pt->off_back[0], pt->off_back[1], pt->off_back[2]};
+    void *ub[3] = {pt->u_back[0], pt->u_back[1], pt->u_back[2]};
+    timed(c, "sort_scatter", [&] {
+      launch_sort_scatter(c->kp, c->p.precision, G, front(pt), dirc, pre, pt->bin_start_back, pt->cell_back, offb, ub,
+                          pt->w_back, (int)pt->n, err, c->st);
+    });
+    rc = launch_status(c, "relsim_push");
+    if (rc) return rc;
+    swap_sets(pt);
+    return RELSIM_OK;
+  }
+  return launch_status(c, "relsim_push");
+}
+
+int relsim_energy(relsim_ctx *c, const relsim_particles *pt, const double *E, const double *B, double out[4]) {
+  if (!c) return RELSIM_EINVAL;
+  int rc = check_particles(c, pt, false);
+  if (rc) return rc;
+  if (!E || !B || !out) return fail(c, RELSIM_EINVAL, "null argument");
+  rc = check_flags(c);
+  if (rc) return rc;
+  const int G = choose_group(c, pt->n);
+  double *part = c->at<double>(c->L.red_part);
+  double *res = c->at<double>(c->L.gm_small);
+  const size_t n3 = 3 * (size_t)c->kp.ncells;
+  timed(c, "kinetic", [&] {
+    launch_kinetic(c->kp, c->p.precision, G, front(pt), part, c->st);
+    launch_reduce_partials(part, kRedBlocks, 1, res, c->st);
+  });
+  timed(c, "field_energy", [&] {
+    launch_sumsq_partials(E, n3, part + kRedBlocks, c->st);
+    launch_reduce_partials(part + kRedBlocks, kRedBlocks, 1, res + 1, c->st);
+    launch_sumsq_partials(B, n3, part + 2 * kRedBlocks, c->st);
+    launch_reduce_partials(part + 2 * kRedBlocks, kRedBlocks, 1, res + 2, c->st);
+  });
+  rc = launch_status(c, "relsim_energy");
+  if (rc) return rc;
+  rc = fetch(c, res, 3);
+  if (rc) return rc;
+  const double f = c->kp.V / (8.0 * M_PI);
+  out[0] = c->host[0];
+  out[1] = f * c->host[1];
+  out[2] = f * c->host[2];
+  out[3] = out[0] + out[1] + out[2];
+  for (int i = 0; i < 4; ++i)
+    if (!std::isfinite(out[i])) return fail(c, RELSIM_ENONFINITE, "energy is not finite");
+  return RELSIM_OK;
+}
+
+int relsim_curl_nc(relsim_ctx *c, const double *in, double *out) {
+  if (!c || !in || !out) return RELSIM_EINVAL;
+  timed(c, "curl_nc", [&] { launch_curl(c->kp, in, out, 1, c->st); });
+  return launch_status(c, "relsim_curl_nc");
+}
+
+int relsim_curl_cn(relsim_ctx *c, const double *in, double *out) {
+  if (!c || !in || !out) return RELSIM_EINVAL;
+  timed(c, "curl_cn", [&] { launch_curl(c->kp, in, out, 0, c->st); });
+  return launch_status(c, "relsim_curl_cn");
+}
+
+int relsim_apply_A(relsim_ctx *c, const double *M, const double *x, double *out) {
+  if (!c || !M || !x || !out) return RELSIM_EINVAL;
+  if (x == out) return fail(c, RELSIM_EINVAL, "relsim_apply_A cannot work in place");
+  apply_A(c, M, x, out);
+  return launch_status(c, "relsim_apply_A");
+}
+
+int relsim_field_solve(relsim_ctx *c, const double *M, const double *Jhat, const double *E_n, const double *B_n,
+                       double *E_theta, double *E_np1, double *B_np1, int32_t *iters, double *rel_resid) {
+  if (!c) return RELSIM_EINVAL;
+  if (!M || !Jhat || !E_n || !B_n || !E_theta || !E_np1 || !B_np1) return fail(c, RELSIM_EINVAL, "null grid array");
+  if (E_theta == E_n || E_theta == E_np1 || B_np1 == B_n) return fail(c, RELSIM_EINVAL, "aliased solve arguments");
+  int rc = check_flags(c);
+  if (rc) return rc;
+  const size_t n3 = 3 * (size_t)c->kp.ncells;
+  const int m = c->p.gmres_restart;
+  double *V = c->at<double>(c->L.gm_V);
+  double *b = c->at<double>(c->L.gm_b);
+  double *r = c->at<double>(c->L.gm_r);
+  double *part = c->at<double>(c->L.gm_part);
+  double *hdev = c->at<double>(c->L.gm_small);
+  double *ydev = hdev + (kMaxRestart + 2);
+  double *x = E_theta;
+  timed(c, "rhs", [&] { launch_rhs(c->kp, E_n, B_n, Jhat, b, c->st); });
+  HIP_CHECK(c, hipMemcpyAsync(x, E_n, n3 * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  double bnorm;
+  rc = norm2(c, b, n3, &bnorm);
+  if (rc) return rc;
+  if (!std::isfinite(bnorm)) return fail(c, RELSIM_ENONFINITE, "right-hand side is not finite");
+  const double tol = c->p.gmres_rtol * bnorm;
+  int total_it = 0;
+  double rel = 0.0;
+  bool converged = false;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  for (;;) {
+    // true residual r = b - A x
+    apply_A(c, M, x, r);
+    timed(c, "axpby", [&] { launch_axpby(1.0, b, -1.0, r, n3, c->st); });
+    double beta;
+    rc = norm2(c, r, n3, &beta);
+    if (rc) return rc;
+    if (!std::isfinite(beta)) return fail(c, RELSIM_ENONFINITE, "GMRES residual is not finite");
+    rel = bnorm > 0 ? beta / bnorm : 0.0;
+    if (beta <= tol) {
+      converged = true;
+      break;
+    }
+    if (total_it >= c->p.gmres_maxit) break;
+    timed(c, "axpby", [&] { launch_axpby(1.0 / beta, r, 0.0, V, n3, c->st); });
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jdone = 0;
+    for (int j = 0; j < m; ++j) {
+      double *vj = V + (size_t)j * n3;
+      double *w = V + (size_t)(j + 1) * n3;
+      apply_A(c, M, vj, w);
+      // classical Gram-Schmidt, twice; the second pass also returns |w|^2
+      timed(c, "mdot", [&] { launch_mdot(V, n3, j + 1, w, n3, part, hdev, c->st); });
+      rc = fetch(c, hdev, j + 1);
+      if (rc) return rc;
+      std::vector<double> h(c->host, c->host + j + 1);
+      timed(c, "maxpy", [&] { launch_maxpy(V, n3, j + 1, hdev, w, n3, c->st); });
+      timed(c, "mdot", [&] { launch_mdot(V, n3, j + 2, w, n3, part, hdev, c->st); });
+      rc = fetch(c, hdev, j + 2);
+      if (rc) return rc;
+      double s2 = 0.0;
+      for (int k = 0; k <= j; ++k) {
+        s2 += c->host[k] * c->host[k];
+        h[k] += c->host[k];
+      }
+      double ww = c->host[j + 1];
+      timed(c, "maxpy", [&] { launch_maxpy(V, n3, j + 1, hdev, w, n3, c->st); });
+      double hn2 = ww - s2;
+      double hn;
+      if (hn2 > 1e-4 * ww) {
+        hn = std::sqrt(hn2);
+      } else {
+        rc = norm2(c, w, n3, &hn);
+        if (rc) return rc;
+      }
+      if (!std::isfinite(hn)) return fail(c, RELSIM_ENONFINITE, "GMRES Arnoldi vector is not finite");
+      for (int k = 0; k <= j; ++k) H[(size_t)k * m + j] = h[k];
+      H[(size_t)(j + 1) * m + j] = hn;
+      for (int k = 0; k < j; ++k) {
+        const double a = H[(size_t)k * m + j], bb = H[(size_t)(k + 1) * m + j];
+        H[(size_t)k * m + j] = cs[k] * a + sn[k] * bb;
+        H[(size_t)(k + 1) * m + j] = -sn[k] * a + cs[k] * bb;
+      }
+      const double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
+      const double den = std::hypot(a, bb);
+      cs[j] = den > 0 ? a / den : 1.0;
+      sn[j] = den > 0 ? bb / den : 0.0;
+      H[(size_t)j * m + j] = den;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++total_it;
+      jdone = j + 1;
+      const bool last = std::fabs(g[j + 1]) <= tol || hn == 0.0 || j == m - 1 || total_it >= c->p.gmres_maxit;
+      if (last) break;
+      timed(c, "axpby", [&] { launch_axpby(1.0 / hn, w, 0.0, w, n3, c->st); });
+    }
+    // y = H^-1 g (upper triangular), x += V y
+    for (int k = jdone - 1; k >= 0; --k) {
+      double s = g[k];
+      for (int l = k + 1; l < jdone; ++l) s -= H[(size_t)k * m + l] * y[l];
+      y[k] = H[(size_t)k * m + k] != 0.0 ? s / H[(size_t)k * m + k] : 0.0;
+    }
+    for (int k = 0; k < jdone; ++k) c->host[k] = -y[k];
+    HIP_CHECK(c, hipMemcpyAsync(ydev, c->host, sizeof(double) * jdone, hipMemcpyHostToDevice, c->st));
+    timed(c, "maxpy", [&] { launch_maxpy(V, n3, jdone, ydev, x, n3, c->st); });
+    // the copy reads c->host; make sure it finished before the host buffer is reused
+    HIP_CHECK(c, hipStreamSynchronize(c->st));
+  }
+  timed(c, "field_update", [&] { launch_field_update(c->kp, E_n, B_n, x, E_np1, B_np1, c->st); });
+  rc = launch_status(c, "relsim_field_solve");
+  if (rc) return rc;
+  if (iters) *iters = total_it;
+  if (rel_resid) *rel_resid = rel;
+  if (!converged) return fail(c, RELSIM_ENOTCONVERGED, "GMRES reached gmres_maxit before gmres_rtol");
+  return RELSIM_OK;
+}
+
+int relsim_timing_enable(relsim_ctx *c, int32_t on) {
+  if (!c) return RELSIM_EINVAL;
+  c->timing = on != 0;
+  return RELSIM_OK;
+}
+
+int relsim_timing_reset(relsim_ctx *c) {
+  if (!c) return RELSIM_EINVAL;
+  harvest(c);
+  std::fill(c->ms.begin(), c->ms.end(), 0.0);
+  std::fill(c->count.begin(), c->count.end(), 0);
+  return RELSIM_OK;
+}
+
+int relsim_timing_read(relsim_ctx *c, int32_t cap, char (*names)[48], double *ms, int64_t *count) {
+  if (!c) return RELSIM_EINVAL;
+  harvest(c);
+  const int n = std::min<int>(cap, (int)c->names.size());
+  for (int i = 0; i < n; ++i) {
+    if (names) {
+      std::strncpy(names[i], c->names[i].c_str(), 47);
+      names[i][47] = 0;
+    }
+    if (ms) ms[i] = c->ms[i];
+    if (count) count[i] = c->count[i];
+  }
+  return n;
+}
+
+const char *relsim_strerror(int code) {
+  switch (code) {
+    case RELSIM_OK: return "ok";
+    case RELSIM_EINVAL: return "invalid argument";
+    case RELSIM_ENOTCONVERGED: return "linear solve did not converge";
+    case RELSIM_EHIP: return "HIP runtime error";
+    case RELSIM_ENONFINITE: return "non-finite value";
+    case RELSIM_ERANGE: return "value out of range";
+    default: return "unknown error";
+  }
+}
+
+const char *relsim_last_error(const relsim_ctx *c) { return c ? c->err.c_str() : "no context"; }
+
+}  // extern "C"

@@ -1,0 +1,269 @@
+// Grid kernels of the implicit field solve (S4-S5), all FP64: discrete curls,
+// the S4 operator, right-hand side, field update, and the BLAS-1 pieces of
+// restarted GMRES (multi-dot, multi-axpy, norms) with fixed-order reductions.
+//
+// Both curls use one stencil shape: the difference along d averaged over the
+// transverse corners of a 2x2(x2) cube.  Nodes -> centre of cell (i,j,k)
+// reads the cube of nodes starting at (i,j,k); centres -> node (i,j,k) reads
+// the cube of cells starting at (i-1,j-1,k-1).  That makes C_CN the exact
+// transpose of C_NC on the periodic grid.
+#include "relsim_internal.h"
+
+namespace relsim {
+namespace {
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int q = nb >> 3;
+  if (b >= (q << 3)) return b;
+  return (b & 7) * q + (b >> 3);
+}
+
+// Cube of 2^DIM values of the three components starting at (i0, j0, k0).
+template <int DIM>
+__device__ __forceinline__ void load_cube(const KParams &kp, const double *__restrict__ F, int i0, int j0, int k0,
+                                          double c[3][8]) {
+  const size_t N = (size_t)kp.ncells;
+  const int x0 = wrapi(i0, kp.nx), x1 = wrapi(i0 + 1, kp.nx);
+  const int y0 = wrapi(j0, kp.ny), y1 = wrapi(j0 + 1, kp.ny);
+  const int z0 = DIM == 3 ? wrapi(k0, kp.nz) : 0, z1 = DIM == 3 ? wrapi(k0 + 1, kp.nz) : 0;
+#pragma unroll
+  for (int a = 0; a < (DIM == 3 ? 8 : 4); ++a) {
+    const size_t id = (size_t)((a & 1) ? x1 : x0) +
+                      (size_t)kp.nx * ((size_t)((a & 2) ? y1 : y0) + (size_t)kp.ny * ((a & 4) ? z1 : z0));
+    c[0][a] = F[id];
+    c[1][a] = F[N + id];
+    c[2][a] = F[2 * N + id];
+  }
+}
+
+// curl of the cube: (dy Fz - dz Fy, dz Fx - dx Fz, dx Fy - dy Fx)
+template <int DIM>
+__device__ __forceinline__ void cube_curl(const KParams &kp, const double c[3][8], double out[3]) {
+  const double ax = kp.inv_dx / (DIM == 3 ? 4.0 : 2.0);
+  const double ay = kp.inv_dy / (DIM == 3 ? 4.0 : 2.0);
+  const double az = kp.inv_dz / 4.0;
+  double d[3][3];  // d[comp][dim]
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    if constexpr (DIM == 2) {
+      d[q][0] = ax * ((c[q][1] - c[q][0]) + (c[q][3] - c[q][2]));
+      d[q][1] = ay * ((c[q][2] - c[q][0]) + (c[q][3] - c[q][1]));
+      d[q][2] = 0.0;
+    } else {
+      d[q][0] = ax * ((c[q][1] - c[q][0]) + (c[q][3] - c[q][2]) + (c[q][5] - c[q][4]) + (c[q][7] - c[q][6]));
+      d[q][1] = ay * ((c[q][2] - c[q][0]) + (c[q][3] - c[q][1]) + (c[q][6] - c[q][4]) + (c[q][7] - c[q][5]));
+      d[q][2] = az * ((c[q][4] - c[q][0]) + (c[q][5] - c[q][1]) + (c[q][6] - c[q][2]) + (c[q][7] - c[q][3]));
+    }
+  }
+  out[0] = d[2][1] - d[1][2];
+  out[1] = d[0][2] - d[2][0];
+  out[2] = d[1][0] - d[0][1];
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_curl(KParams kp, const double *__restrict__ in, double *__restrict__ out,
+                                              int shift) {
+  const int g = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (g >= kp.ncells) return;
+  const int i = g % kp.nx, j = (g / kp.nx) % kp.ny, k = g / (kp.nx * kp.ny);
+  double c[3][8], r[3];
+  load_cube<DIM>(kp, in, i - shift, j - shift, k - shift, c);
+  cube_curl<DIM>(kp, c, r);
+  const size_t N = (size_t)kp.ncells;
+  out[g] = r[0];
+  out[N + g] = r[1];
+  out[2 * N + g] = r[2];
+}
+
+// out = x + a^2 C_CN t + b M x, with t = C_NC x precomputed
+template <int DIM>
+__global__ __launch_bounds__(256) void k_apply_A_tail(KParams kp, const double *__restrict__ M,
+                                                      const double *__restrict__ x, const double *__restrict__ t,
+                                                      double *__restrict__ out) {
+  constexpr int NOFF = DIM == 3 ? 27 : 9;
+  const int g = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (g >= kp.ncells) return;
+  const size_t N = (size_t)kp.ncells;
+  const int i = g % kp.nx, j = (g / kp.nx) % kp.ny, k = g / (kp.nx * kp.ny);
+  double c[3][8], cc[3];
+  load_cube<DIM>(kp, t, i - 1, j - 1, k - 1, c);
+  cube_curl<DIM>(kp, c, cc);
+  const double a = kp.c * kp.theta * kp.dt;
+  const double b = 4.0 * M_PI * kp.theta * kp.dt;
+  double mx[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int off = 0; off < NOFF; ++off) {
+    const int ii = wrapi(i + off % 3 - 1, kp.nx);
+    const int jj = wrapi(j + (off / 3) % 3 - 1, kp.ny);
+    const int kk = DIM == 3 ? wrapi(k + off / 9 - 1, kp.nz) : 0;
+    const size_t id = (size_t)ii + (size_t)kp.nx * ((size_t)jj + (size_t)kp.ny * kk);
+    const double x0 = x[id], x1 = x[N + id], x2 = x[2 * N + id];
+    const double *Mo = M + (size_t)off * 9 * N + g;
+    mx[0] += Mo[0] * x0 + Mo[N] * x1 + Mo[2 * N] * x2;
+    mx[1] += Mo[3 * N] * x0 + Mo[4 * N] * x1 + Mo[5 * N] * x2;
+    mx[2] += Mo[6 * N] * x0 + Mo[7 * N] * x1 + Mo[8 * N] * x2;
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) out[q * N + g] = x[q * N + g] + a * a * cc[q] + b * mx[q];
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_rhs(KParams kp, const double *__restrict__ En, const double *__restrict__ Bn,
+                                             const double *__restrict__ J, double *__restrict__ out) {
+  const int g = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (g >= kp.ncells) return;
+  const size_t N = (size_t)kp.ncells;
+  const int i = g % kp.nx, j = (g / kp.nx) % kp.ny, k = g / (kp.nx * kp.ny);
+  double c[3][8], cc[3];
+  load_cube<DIM>(kp, Bn, i - 1, j - 1, k - 1, c);
+  cube_curl<DIM>(kp, c, cc);
+  const double a = kp.c * kp.theta * kp.dt;
+  const double b = 4.0 * M_PI * kp.theta * kp.dt;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) out[q * N + g] = En[q * N + g] + a * cc[q] - b * J[q * N + g];
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_field_update(KParams kp, const double *__restrict__ En,
+                                                      const double *__restrict__ Bn, const double *__restrict__ Eth,
+                                                      double *__restrict__ En1, double *__restrict__ Bn1) {
+  const int g = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  if (g >= kp.ncells) return;
+  const size_t N = (size_t)kp.ncells;
+  const int i = g % kp.nx, j = (g / kp.nx) % kp.ny, k = g / (kp.nx * kp.ny);
+  double c[3][8], cc[3];
+  load_cube<DIM>(kp, Eth, i, j, k, c);
+  cube_curl<DIM>(kp, c, cc);
+  const double th = kp.theta;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    Bn1[q * N + g] = Bn[q * N + g] - kp.c * kp.dt * cc[q];
+    En1[q * N + g] = (Eth[q * N + g] - (1.0 - th) * En[q * N + g]) / th;
+  }
+}
+
+// ---- BLAS-1 with fixed-order reductions ----
+__device__ __forceinline__ double block_sum_256(double v, double *lds) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_mdot(const double *__restrict__ V, size_t ld, int nvec,
+                                              const double *__restrict__ w, size_t n, double *__restrict__ partials) {
+  __shared__ double lds[4];
+  const size_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const size_t beg = (size_t)blockIdx.x * chunk;
+  const size_t end = beg + chunk < n ? beg + chunk : n;
+  for (int kv = 0; kv < nvec; ++kv) {
+    const double *v = V + (size_t)kv * ld;
+    double acc = 0.0;
+    for (size_t i = beg + threadIdx.x; i < end; i += 256) acc += v[i] * w[i];
+    const double s = block_sum_256(acc, lds);
+    if (threadIdx.x == 0) partials[(size_t)blockIdx.x * nvec + kv] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_partials(const double *__restrict__ partials, int nparts, int nvec,
+                                                         double *__restrict__ res) {
+  __shared__ double lds[4];
+  const int kv = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += 256) acc += partials[(size_t)b * nvec + kv];
+  const double s = block_sum_256(acc, lds);
+  if (threadIdx.x == 0) res[kv] = s;
+}
+
+__global__ __launch_bounds__(256) void k_maxpy(const double *__restrict__ V, size_t ld, int nvec,
+                                               const double *__restrict__ h, double *__restrict__ w, size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double acc = w[i];
+  for (int kv = 0; kv < nvec; ++kv) acc -= h[kv] * V[(size_t)kv * ld + i];
+  w[i] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_axpby(double a, const double *__restrict__ x, double b, double *__restrict__ y,
+                                               size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];
+}
+
+__global__ __launch_bounds__(256) void k_sumsq(const double *__restrict__ x, size_t n, double *__restrict__ partials) {
+  __shared__ double lds[4];
+  const size_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const size_t beg = (size_t)blockIdx.x * chunk;
+  const size_t end = beg + chunk < n ? beg + chunk : n;
+  double acc = 0.0;
+  for (size_t i = beg + threadIdx.x; i < end; i += 256) acc += x[i] * x[i];
+  const double s = block_sum_256(acc, lds);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+inline int grid_of(size_t n) { return (int)((n + 255) / 256); }
+
+}  // namespace
+
+void launch_curl(const KParams &kp, const double *in, double *out, int to_centres, hipStream_t st) {
+  const int shift = to_centres ? 0 : 1;
+  if (kp.dim == 2)
+    hipLaunchKernelGGL(k_curl<2>, dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, in, out, shift);
+  else
+    hipLaunchKernelGGL(k_curl<3>, dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, in, out, shift);
+}
+
+void launch_apply_A_tail(const KParams &kp, const double *M, const double *x, const double *t, double *out,
+                         hipStream_t st) {
+  if (kp.dim == 2)
+    hipLaunchKernelGGL(k_apply_A_tail<2>, dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, M, x, t, out);
+  else
+    hipLaunchKernelGGL(k_apply_A_tail<3>, dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, M, x, t, out);
+}
+
+void launch_rhs(const KParams &kp, const double *En, const double *Bn, const double *J, double *out, hipStream_t st) {
+  if (kp.dim == 2)
+    hipLaunchKernelGGL(k_rhs<2>, dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, En, Bn, J, out);
+  else
+    hipLaunchKernelGGL(k_rhs<3>, dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, En, Bn, J, out);
+}
+
+void launch_field_update(const KParams &kp, const double *En, const double *Bn, const double *Eth, double *En1,
+                         double *Bn1, hipStream_t st) {
+  if (kp.dim == 2)
+    hipLaunchKernelGGL(k_field_update<2>, dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, En, Bn, Eth, En1, Bn1);
+  else
+    hipLaunchKernelGGL(k_field_update<3>, dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, En, Bn, Eth, En1, Bn1);
+}
+
+void launch_mdot(const double *V, size_t ld, int nvec, const double *w, size_t n, double *partials, double *res,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks), dim3(256), 0, st, V, ld, nvec, w, n, partials);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(nvec), dim3(256), 0, st, partials, kDotBlocks, nvec, res);
+}
+
+void launch_maxpy(const double *V, size_t ld, int nvec, const double *h, double *w, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_maxpy, dim3(grid_of(n)), dim3(256), 0, st, V, ld, nvec, h, w, n);
+}
+
+void launch_axpby(double a, const double *x, double b, double *y, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpby, dim3(grid_of(n)), dim3(256), 0, st, a, x, b, y, n);
+}
+
+void launch_sumsq_partials(const double *x, size_t n, double *partials, hipStream_t st) {
+  hipLaunchKernelGGL(k_sumsq, dim3(kRedBlocks), dim3(256), 0, st, x, n, partials);
+}
+
+void launch_reduce_partials(const double *partials, int nparts, int nvec, double *res, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(nvec), dim3(256), 0, st, partials, nparts, nvec, res);
+}
+
+}  // namespace relsim

@@ -1,0 +1,843 @@
+// Particle kernels of the semi-implicit step for gfx950: moment deposit
+// (S1-S3), node assembly of J-hat and M, push (S6), the incremental stable
+// re-sort by bin, and the kinetic-energy reduction (S7).
+//
+// Work decomposition shared by the particle kernels: a 64-lane wavefront is
+// split into 64/G lane groups; each group owns one cell and walks that
+// cell's particles (both species, contiguous because particles are sorted
+// by bin = cell * nspecies + species) G at a time, so loads are coalesced
+// and every particle of a group sees the same neighbourhood of grid values.
+//
+// Deposit formulation.  For a particle with in-cell offsets f_d, the CIC
+// node weights are products of (1 - f_d) or f_d, so the weight product of an
+// ordered node pair (a, b) of the cell's corners depends only on the per-dim
+// monomial type t_d = a_d + b_d in {0,1,2}: (1-f)^2, f(1-f), f^2.  Hence
+//   M_{g,g'} = sum over cells c containing g and g' of S_c[t(g,g',c)],
+//   S_c[t][k] = V^-1 sum_{p in c} (w q beta / gbar) prod_d mono_{t_d}(f_d) alpha_k,
+// and J-hat likewise from per-corner sums.  The particle kernel reduces the
+// per-cell moments S_c within its lane group (registers, then one LDS
+// transpose); a second kernel assembles every node's J-hat and 9/27 M blocks
+// from the 4/8 surrounding cells by a fixed-order gather.  No float atomics:
+// results are deterministic, and M_{g,g'} == M_{g',g} bit for bit.
+#include <climits>
+
+#include "relsim_internal.h"
+
+namespace relsim {
+namespace {
+
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  // Consecutive workgroups are dispatched to the 8 XCDs round robin; remap so
+  // that each XCD (and its L2) works on one contiguous slice of the grid.
+  const int q = nb >> 3;
+  if (b >= (q << 3)) return b;
+  return (b & 7) * q + (b >> 3);
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+template <typename T>
+__device__ __forceinline__ T sqrt_t(T x);
+template <>
+__device__ __forceinline__ float sqrt_t<float>(float x) { return sqrtf(x); }
+template <>
+__device__ __forceinline__ double sqrt_t<double>(double x) { return sqrt(x); }
+
+// CIC weights of the three cell centres at relative positions -1/2, 1/2,
+// 3/2 (cell units) seen from a particle at offset f in [0,1).
+template <typename T>
+__device__ __forceinline__ void centre_w3(T f, T w[3]) {
+  const bool hi = f >= T(0.5);
+  w[0] = hi ? T(0) : T(0.5) - f;
+  w[1] = hi ? T(1.5) - f : T(0.5) + f;
+  w[2] = hi ? f - T(0.5) : T(0);
+}
+
+// alpha = (I - [b]x + b b^T) / (1 + |b|^2), row-major.
+template <typename T>
+__device__ __forceinline__ void make_alpha(T bx, T by, T bz, T a[9]) {
+  const T inv = T(1) / (T(1) + bx * bx + by * by + bz * bz);
+  a[0] = (T(1) + bx * bx) * inv;
+  a[1] = (bz + bx * by) * inv;
+  a[2] = (bx * bz - by) * inv;
+  a[3] = (bx * by - bz) * inv;
+  a[4] = (T(1) + by * by) * inv;
+  a[5] = (bx + by * bz) * inv;
+  a[6] = (by + bx * bz) * inv;
+  a[7] = (by * bz - bx) * inv;
+  a[8] = (T(1) + bz * bz) * inv;
+}
+
+// Particle-side view of the kernel constants in the arithmetic type T.
+template <typename T>
+struct PC {
+  T dt, invc, invc2, invV, idx, idy, idz;
+  __device__ explicit PC(const KParams &kp)
+      : dt(T(kp.dt)), invc(T(1.0 / kp.c)), invc2(T(1.0 / (kp.c * kp.c))), invV(T(1.0 / kp.V)),
+        idx(T(kp.inv_dx)), idy(T(kp.inv_dy)), idz(T(kp.inv_dz)) {}
+};
+
+// Block of 3x3 (2D) cell-centre B values around cell (ci, cj) in registers.
+template <typename T>
+__device__ __forceinline__ void load_B_block_2d(const KParams &kp, const double *__restrict__ B, int ci, int cj,
+                                                T Bc[3][9]) {
+  const size_t N = (size_t)kp.ncells;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int ii = wrapi(ci + (t % 3) - 1, kp.nx);
+    const int jj = wrapi(cj + (t / 3) - 1, kp.ny);
+    const size_t id = (size_t)ii + (size_t)kp.nx * jj;
+    Bc[0][t] = (T)B[id];
+    Bc[1][t] = (T)B[N + id];
+    Bc[2][t] = (T)B[2 * N + id];
+  }
+}
+
+// B at the particle: 2D from the register block, 3D by a direct 8-centre
+// gather (the 27-centre block would not fit the register budget in FP64).
+template <typename T, int DIM>
+__device__ __forceinline__ void gather_B(const KParams &kp, const double *__restrict__ B, const T (&Bc)[3][9], int ci,
+                                         int cj, int ck, T fx, T fy, T fz, T &Bx, T &By, T &Bz) {
+  if constexpr (DIM == 2) {
+    T wx[3], wy[3];
+    centre_w3(fx, wx);
+    centre_w3(fy, wy);
+    Bx = By = Bz = T(0);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const T wt = wx[t % 3] * wy[t / 3];
+      Bx += wt * Bc[0][t];
+      By += wt * Bc[1][t];
+      Bz += wt * Bc[2][t];
+    }
+  } else {
+    const size_t N = (size_t)kp.ncells;
+    const bool hx = fx >= T(0.5), hy = fy >= T(0.5), hz = fz >= T(0.5);
+    const int ix = hx ? ci : ci - 1, iy = hy ? cj : cj - 1, iz = hz ? ck : ck - 1;
+    const T gx = hx ? fx - T(0.5) : fx + T(0.5);
+    const T gy = hy ? fy - T(0.5) : fy + T(0.5);
+    const T gz = hz ? fz - T(0.5) : fz + T(0.5);
+    const int x0 = wrapi(ix, kp.nx), x1 = wrapi(ix + 1, kp.nx);
+    const int y0 = wrapi(iy, kp.ny), y1 = wrapi(iy + 1, kp.ny);
+    const int z0 = wrapi(iz, kp.nz), z1 = wrapi(iz + 1, kp.nz);
+    Bx = By = Bz = T(0);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int xx = (a & 1) ? x1 : x0, yy = (a & 2) ? y1 : y0, zz = (a & 4) ? z1 : z0;
+      const T wt = ((a & 1) ? gx : T(1) - gx) * ((a & 2) ? gy : T(1) - gy) * ((a & 4) ? gz : T(1) - gz);
+      const size_t id = (size_t)xx + (size_t)kp.nx * ((size_t)yy + (size_t)kp.ny * zz);
+      Bx += wt * (T)B[id];
+      By += wt * (T)B[N + id];
+      Bz += wt * (T)B[2 * N + id];
+    }
+  }
+}
+
+// Per-lane cell bookkeeping shared by the particle kernels.
+struct CellSpan {
+  int cell, ci, cj, ck, pbeg, pend;
+  int bound[8];  // first particle of species s (INT_MAX beyond nspecies)
+  bool valid;
+};
+
+__device__ __forceinline__ CellSpan cell_span(const KParams &kp, const int32_t *__restrict__ bin_start, int cell) {
+  CellSpan cs;
+  cs.valid = cell < kp.ncells;
+  cs.cell = cs.valid ? cell : 0;
+  cs.ci = cs.cell % kp.nx;
+  cs.cj = (cs.cell / kp.nx) % kp.ny;
+  cs.ck = cs.cell / (kp.nx * kp.ny);
+  const int S = kp.nspecies;
+  cs.pbeg = cs.valid ? bin_start[cs.cell * S] : 0;
+  cs.pend = cs.valid ? bin_start[cs.cell * S + S] : 0;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) cs.bound[s] = (cs.valid && s < S) ? bin_start[cs.cell * S + s] : INT_MAX;
+  return cs;
+}
+
+// Wave-uniform number of rounds: max over the wave of ceil(count / G).
+template <int G>
+__device__ __forceinline__ int wave_rounds(int count) {
+  int r = (count + G - 1) / G;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) r = max(r, __shfl_xor(r, o));
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ int species_of(const KParams &kp, const CellSpan &cs, int p, T &q, T &beta) {
+  int s = 0;
+  q = (T)kp.q[0];
+  beta = (T)kp.beta[0];
+#pragma unroll
+  for (int s2 = 1; s2 < 8; ++s2)
+    if (p >= cs.bound[s2]) {
+      s = s2;
+      q = (T)kp.q[s2];
+      beta = (T)kp.beta[s2];
+    }
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// S1-S3: per-cell moments
+// ---------------------------------------------------------------------------
+template <typename T, int DIM, int G>
+__global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t *__restrict__ bin_start,
+                                                      const T *__restrict__ o0, const T *__restrict__ o1,
+                                                      const T *__restrict__ o2, const T *__restrict__ u0,
+                                                      const T *__restrict__ u1, const T *__restrict__ u2,
+                                                      const T *__restrict__ wt, const double *__restrict__ B,
+                                                      T *__restrict__ S) {
+  constexpr int NACC = 93;  // 81 mass moments + 12 current moments per pass
+  constexpr int NPASS = DIM == 3 ? 3 : 1;
+  __shared__ T red[64 * NACC];
+  const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const CellSpan cs = cell_span(kp, bin_start, blk * (64 / G) + grp);
+  const PC<T> pc(kp);
+  const size_t NC = (size_t)kp.ncells;
+
+  T Bc[3][9];
+  if constexpr (DIM == 2) load_B_block_2d<T>(kp, B, cs.ci, cs.cj, Bc);
+  const int rounds = wave_rounds<G>(cs.pend - cs.pbeg);
+
+#pragma unroll 1
+  for (int pass = 0; pass < NPASS; ++pass) {
+    T acc[NACC];
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) acc[k] = T(0);
+#pragma unroll 1
+    for (int r = 0; r < rounds; ++r) {
+      const int p = cs.pbeg + gl + r * G;
+      if (p < cs.pend) {
+        const T fx = o0[p], fy = o1[p];
+        const T fz = DIM == 3 ? o2[p] : T(0);
+        const T ux = u0[p], uy = u1[p], uz = u2[p], wp = wt[p];
+        T qs, bs;
+        species_of<T>(kp, cs, p, qs, bs);
+        T Bx, By, Bz;
+        gather_B<T, DIM>(kp, B, Bc, cs.ci, cs.cj, cs.ck, fx, fy, fz, Bx, By, Bz);
+        const T gb = kp.nonrel ? T(1) : sqrt_t<T>(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
+        const T igb = T(1) / gb;
+        const T kb = bs * igb * pc.invc;
+        T a[9];
+        make_alpha<T>(kb * Bx, kb * By, kb * Bz, a);
+        const T cM = wp * qs * bs * igb * pc.invV;
+        const T cJ = wp * qs * pc.invV * igb;
+        T psiM[9], psiJ[3];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) psiM[k] = cM * a[k];
+        psiJ[0] = cJ * (a[0] * ux + a[1] * uy + a[2] * uz);
+        psiJ[1] = cJ * (a[3] * ux + a[4] * uy + a[5] * uz);
+        psiJ[2] = cJ * (a[6] * ux + a[7] * uy + a[8] * uz);
+        const T nx0 = T(1) - fx, ny0 = T(1) - fy, nz0 = T(1) - fz;
+        const T mx[3] = {nx0 * nx0, nx0 * fx, fx * fx};
+        const T my[3] = {ny0 * ny0, ny0 * fy, fy * fy};
+        T mzf = T(1), jzf = T(1);
+        if constexpr (DIM == 3) {
+          mzf = pass == 0 ? nz0 * nz0 : (pass == 1 ? nz0 * fz : fz * fz);
+          jzf = pass == 0 ? nz0 : fz;
+        }
+#pragma unroll
+        for (int m = 0; m < 9; ++m) {
+          const T wgt = mx[m % 3] * my[m / 3] * mzf;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) acc[m * 9 + k] += wgt * psiM[k];
+        }
+        if (DIM == 2 || pass < 2) {
+#pragma unroll
+          for (int cxy = 0; cxy < 4; ++cxy) {
+            const T wgt = ((cxy & 1) ? fx : nx0) * ((cxy & 2) ? fy : ny0) * jzf;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) acc[81 + cxy * 3 + k] += wgt * psiJ[k];
+          }
+        }
+      }
+    }
+    // group reduction: registers -> LDS transpose -> G-term sums in fixed order
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) red[lane * NACC + k] = acc[k];
+    __syncthreads();
+    const int nk = (DIM == 3 && pass == 2) ? 81 : NACC;
+    for (int k = gl; k < nk; k += G) {
+      T s = T(0);
+#pragma unroll 8
+      for (int j = 0; j < G; ++j) s += red[(grp * G + j) * NACC + k];
+      if (cs.valid) {
+        const int sidx = DIM == 3 ? (k < 81 ? pass * 81 + k : 243 + pass * 12 + (k - 81)) : k;
+        S[(size_t)sidx * NC + cs.cell] = s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// J-hat and M at nodes from the per-cell moments (fixed-order gather)
+// ---------------------------------------------------------------------------
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_assemble(KParams kp, const T *__restrict__ S, double *__restrict__ J,
+                                                  double *__restrict__ M) {
+  constexpr int NOFF = DIM == 3 ? 27 : 9;
+  constexpr int NCORN = DIM == 3 ? 8 : 4;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int g = blk * blockDim.x + threadIdx.x;
+  if (g >= kp.ncells) return;
+  const size_t N = (size_t)kp.ncells;
+  const int i = g % kp.nx, j = (g / kp.nx) % kp.ny, k = g / (kp.nx * kp.ny);
+  // cells having node g as corner a: c = g - a
+  int cidx[NCORN];
+#pragma unroll
+  for (int a = 0; a < NCORN; ++a) {
+    const int ii = wrapi(i - (a & 1), kp.nx);
+    const int jj = wrapi(j - ((a >> 1) & 1), kp.ny);
+    const int kk = DIM == 3 ? wrapi(k - ((a >> 2) & 1), kp.nz) : 0;
+    cidx[a] = ii + kp.nx * (jj + kp.ny * kk);
+  }
+#pragma unroll
+  for (int off = 0; off < NOFF; ++off) {
+    const int dx = off % 3 - 1, dy = (off / 3) % 3 - 1, dz = off / 9 - 1;
+    double acc[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int a = 0; a < NCORN; ++a) {
+      const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+      const int bx = ax + dx, by = ay + dy, bz = az + dz;
+      if (bx < 0 || bx > 1 || by < 0 || by > 1) continue;
+      if (DIM == 3 && (bz < 0 || bz > 1)) continue;
+      const int mono = (ax + bx) + 3 * (ay + by);
+      const int base = DIM == 3 ? (az + bz) * 81 + mono * 9 : mono * 9;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) acc[q] += (double)S[(size_t)(base + q) * N + cidx[a]];
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) M[((size_t)off * 9 + q) * N + g] = acc[q];
+  }
+  double jacc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < NCORN; ++a) {
+    const int cxy = (a & 1) + 2 * ((a >> 1) & 1);
+    const int base = DIM == 3 ? 243 + ((a >> 2) & 1) * 12 + cxy * 3 : 81 + cxy * 3;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) jacc[q] += (double)S[(size_t)(base + q) * N + cidx[a]];
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) J[(size_t)q * N + g] = jacc[q];
+}
+
+// ---------------------------------------------------------------------------
+// S6: push, cell crossing, and per-(bin, move) counts for the re-sort
+// ---------------------------------------------------------------------------
+template <typename T, int DIM>
+__device__ __forceinline__ int cross_cell(T &f, int32_t *err) {
+  // f is the new offset in cell units; bring it back into [0,1) with one
+  // cell move.  A value rounding to exactly 1 after the correction from
+  // below is the left face of the cell (offset 0, no move).
+  int m = 0;
+  if (f >= T(1)) {
+    f -= T(1);
+    m = 1;
+  } else if (f < T(0)) {
+    f += T(1);
+    m = -1;
+  }
+  if (!(f >= T(0) && f < T(1))) {
+    if (m == -1 && f == T(1)) {
+      f = T(0);
+      m = 0;
+    } else {
+      atomicOr(err, 1);  // moved more than one cell, or non-finite
+      f = T(0);
+    }
+  }
+  return m;
+}
+
+template <typename T, int DIM, int G>
+__global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restrict__ bin_start, T *__restrict__ o0,
+                                             T *__restrict__ o1, T *__restrict__ o2, T *__restrict__ u0,
+                                             T *__restrict__ u1, T *__restrict__ u2, const double *__restrict__ Eth,
+                                             const double *__restrict__ B, uint8_t *__restrict__ dirc,
+                                             uint16_t *__restrict__ cnt, int32_t *__restrict__ err, int count_moves) {
+  constexpr int NDIR = DIM == 3 ? 27 : 9;
+  constexpr int NK = 8 * NDIR;  // (species, move) keys per group
+  constexpr int NGRP = 64 / G;
+  __shared__ uint32_t lcnt[NGRP * NK];
+  const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const CellSpan cs = cell_span(kp, bin_start, blk * NGRP + grp);
+  const PC<T> pc(kp);
+  const size_t N = (size_t)kp.ncells;
+  if (count_moves) {
+    for (int t = lane; t < NGRP * NK; t += 64) lcnt[t] = 0u;
+    __syncthreads();
+    if (cs.valid && gl == 0) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int hi = (s + 1 < 8 && cs.bound[s + 1] < INT_MAX) ? cs.bound[(s + 1) & 7] : cs.pend;
+        if (cs.bound[s] < INT_MAX && hi - cs.bound[s] > 65535) atomicOr(err, 2);
+      }
+    }
+  }
+
+  T Bc[3][9];
+  if constexpr (DIM == 2) load_B_block_2d<T>(kp, B, cs.ci, cs.cj, Bc);
+  // E_theta at the 2^DIM corner nodes of the cell
+  constexpr int NCORN = DIM == 3 ? 8 : 4;
+  T Ec[3][NCORN];
+#pragma unroll
+  for (int a = 0; a < NCORN; ++a) {
+    const int ii = wrapi(cs.ci + (a & 1), kp.nx);
+    const int jj = wrapi(cs.cj + ((a >> 1) & 1), kp.ny);
+    const int kk = DIM == 3 ? wrapi(cs.ck + ((a >> 2) & 1), kp.nz) : 0;
+    const size_t id = (size_t)ii + (size_t)kp.nx * ((size_t)jj + (size_t)kp.ny * kk);
+    Ec[0][a] = (T)Eth[id];
+    Ec[1][a] = (T)Eth[N + id];
+    Ec[2][a] = (T)Eth[2 * N + id];
+  }
+  const int rounds = wave_rounds<G>(cs.pend - cs.pbeg);
+
+#pragma unroll 1
+  for (int r = 0; r < rounds; ++r) {
+    const int p = cs.pbeg + gl + r * G;
+    const bool pv = p < cs.pend;
+    int key = 0;
+    if (pv) {
+      T fx = o0[p], fy = o1[p];
+      T fz = DIM == 3 ? o2[p] : T(0);
+      const T ux = u0[p], uy = u1[p], uz = u2[p];
+      T qs, bs;
+      const int s = species_of<T>(kp, cs, p, qs, bs);
+      T Bx, By, Bz;
+      gather_B<T, DIM>(kp, B, Bc, cs.ci, cs.cj, cs.ck, fx, fy, fz, Bx, By, Bz);
+      const T gb = kp.nonrel ? T(1) : sqrt_t<T>(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
+      const T kb = bs / gb * pc.invc;
+      T a[9];
+      make_alpha<T>(kb * Bx, kb * By, kb * Bz, a);
+      T Ex = T(0), Ey = T(0), Ez = T(0);
+#pragma unroll
+      for (int c = 0; c < NCORN; ++c) {
+        T wgt = ((c & 1) ? fx : T(1) - fx) * ((c & 2) ? fy : T(1) - fy);
+        if constexpr (DIM == 3) wgt *= (c & 4) ? fz : T(1) - fz;
+        Ex += wgt * Ec[0][c];
+        Ey += wgt * Ec[1][c];
+        Ez += wgt * Ec[2][c];
+      }
+      const T vx = ux + bs * Ex, vy = uy + bs * Ey, vz = uz + bs * Ez;
+      const T ubx = a[0] * vx + a[1] * vy + a[2] * vz;
+      const T uby = a[3] * vx + a[4] * vy + a[5] * vz;
+      const T ubz = a[6] * vx + a[7] * vy + a[8] * vz;
+      const T nx = T(2) * ubx - ux, ny = T(2) * uby - uy, nz = T(2) * ubz - uz;
+      const T gn = kp.nonrel ? T(1) : sqrt_t<T>(T(1) + (nx * nx + ny * ny + nz * nz) * pc.invc2);
+      const T dtg = pc.dt / gn;
+      fx += dtg * nx * pc.idx;
+      fy += dtg * ny * pc.idy;
+      if constexpr (DIM == 3) fz += dtg * nz * pc.idz;
+      int mx = 0, my = 0, mz = 0;
+      if (count_moves) {
+        mx = cross_cell<T, DIM>(fx, err);
+        my = cross_cell<T, DIM>(fy, err);
+        if constexpr (DIM == 3) mz = cross_cell<T, DIM>(fz, err);
+      } else {
+        // no re-sort: offsets stay relative to the old cell, in [-1, 2)
+        bool ok = fx >= T(-1) && fx < T(2) && fy >= T(-1) && fy < T(2);
+        if constexpr (DIM == 3) ok = ok && fz >= T(-1) && fz < T(2);
+        if (!ok) atomicOr(err, 1);
+      }
+      o0[p] = fx;
+      o1[p] = fy;
+      if constexpr (DIM == 3) o2[p] = fz;
+      u0[p] = nx;
+      u1[p] = ny;
+      u2[p] = nz;
+      const int dir = (mx + 1) + 3 * (my + 1) + (DIM == 3 ? 9 * (mz + 1) : 0);
+      if (count_moves) dirc[p] = (uint8_t)dir;
+      key = grp * NK + s * NDIR + dir;
+    }
+    if (count_moves) {
+      // wave-level aggregation of identical (group, species, move) keys
+      unsigned long long active = __ballot(pv);
+      while (active) {
+        const int leader = __ffsll((long long)active) - 1;
+        const int lk = __builtin_amdgcn_readlane(key, leader);
+        const unsigned long long m = __ballot(pv && key == lk);
+        if (lane == leader) lcnt[lk] += (uint32_t)__popcll(m);
+        active &= ~m;
+      }
+    }
+  }
+  if (count_moves) {
+    __syncthreads();
+    if (cs.valid) {
+      const int S = kp.nspecies;
+      for (int t = gl; t < S * NDIR; t += G) {
+        const int s = t / NDIR, dir = t % NDIR;
+        const uint32_t v = lcnt[grp * NK + s * NDIR + dir];
+        cnt[(size_t)dir * kp.nbins + (size_t)cs.cell * S + s] = (uint16_t)(v > 65535u ? 65535u : v);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// re-sort, step 2: per destination bin, the offset of each incoming move
+// class in source order (sources are earlier in the old order iff their cell
+// index is smaller), and the bin total.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int source_shift(int r, int c, int n) {
+  // r-th smallest of the wrapped coordinates {c-1, c, c+1} -> its shift
+  if (c == 0) return r == 0 ? 0 : (r == 1 ? 1 : -1);
+  if (c == n - 1) return r == 0 ? 1 : (r == 1 ? -1 : 0);
+  return r - 1;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_sort_offsets(KParams kp, const uint16_t *__restrict__ cnt,
+                                                      uint16_t *__restrict__ pre, int32_t *__restrict__ total,
+                                                      int32_t *__restrict__ err) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= kp.nbins) return;
+  const int S = kp.nspecies;
+  const int cell = d / S, s = d % S;
+  const int ci = cell % kp.nx, cj = (cell / kp.nx) % kp.ny, ck = cell / (kp.nx * kp.ny);
+  const size_t nb = (size_t)kp.nbins;
+  int run = 0;
+  const int NZ = DIM == 3 ? 3 : 1;
+  for (int rz = 0; rz < NZ; ++rz) {
+    const int sz = DIM == 3 ? source_shift(rz, ck, kp.nz) : 0;
+    for (int ry = 0; ry < 3; ++ry) {
+      const int sy = source_shift(ry, cj, kp.ny);
+      for (int rx = 0; rx < 3; ++rx) {
+        const int sx = source_shift(rx, ci, kp.nx);
+        const int src = wrapi(ci + sx, kp.nx) + kp.nx * (wrapi(cj + sy, kp.ny) + kp.ny * (DIM == 3 ? wrapi(ck + sz, kp.nz) : 0));
+        const int dir = (1 - sx) + 3 * (1 - sy) + (DIM == 3 ? 9 * (1 - sz) : 0);
+        const int c16 = cnt[(size_t)dir * nb + (size_t)src * S + s];
+        pre[(size_t)dir * nb + d] = (uint16_t)(run > 65535 ? 65535 : run);
+        run += c16;
+      }
+    }
+  }
+  if (run > 65535) atomicOr(err, 2);
+  total[d] = run;
+}
+
+// ---------------------------------------------------------------------------
+// re-sort, step 3: stable scatter into the back buffers
+// ---------------------------------------------------------------------------
+template <typename T, int DIM, int G>
+__global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *__restrict__ bin_start,
+                                                     const T *__restrict__ o0, const T *__restrict__ o1,
+                                                     const T *__restrict__ o2, const T *__restrict__ u0,
+                                                     const T *__restrict__ u1, const T *__restrict__ u2,
+                                                     const T *__restrict__ wt, const uint8_t *__restrict__ dirc,
+                                                     const uint16_t *__restrict__ pre,
+                                                     const int32_t *__restrict__ bsn, int32_t *__restrict__ cell_out,
+                                                     T *__restrict__ q0, T *__restrict__ q1, T *__restrict__ q2,
+                                                     T *__restrict__ v0, T *__restrict__ v1, T *__restrict__ v2,
+                                                     T *__restrict__ wo, int ntot, int32_t *__restrict__ err) {
+  constexpr int NDIR = DIM == 3 ? 27 : 9;
+  constexpr int NK = 8 * NDIR;
+  constexpr int NGRP = 64 / G;
+  __shared__ uint32_t lbase[NGRP * NK];
+  const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const CellSpan cs = cell_span(kp, bin_start, blk * NGRP + grp);
+  for (int t = lane; t < NGRP * NK; t += 64) lbase[t] = 0u;
+  __syncthreads();
+  const int S = kp.nspecies;
+  const size_t nb = (size_t)kp.nbins;
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int rounds = wave_rounds<G>(cs.pend - cs.pbeg);
+#pragma unroll 1
+  for (int r = 0; r < rounds; ++r) {
+    const int p = cs.pbeg + gl + r * G;
+    const bool pv = p < cs.pend;
+    int key = 0, dir = 0, s = 0;
+    if (pv) {
+      dir = dirc[p];
+#pragma unroll
+      for (int s2 = 1; s2 < 8; ++s2)
+        if (p >= cs.bound[s2]) s = s2;
+      key = grp * NK + s * NDIR + dir;
+    }
+    int rank = 0;
+    unsigned long long active = __ballot(pv);
+    while (active) {
+      const int leader = __ffsll((long long)active) - 1;
+      const int lk = __builtin_amdgcn_readlane(key, leader);
+      const bool mine = pv && key == lk;
+      const unsigned long long m = __ballot(mine);
+      if (mine) rank = (int)lbase[lk] + __popcll(m & lt);
+      __builtin_amdgcn_wave_barrier();
+      if (lane == leader) lbase[lk] += (uint32_t)__popcll(m);
+      active &= ~m;
+    }
+    if (pv) {
+      const int mx = dir % 3 - 1, my = (dir / 3) % 3 - 1, mz = dir / 9 - 1;
+      const int dc = wrapi(cs.ci + mx, kp.nx) +
+                     kp.nx * (wrapi(cs.cj + my, kp.ny) + kp.ny * (DIM == 3 ? wrapi(cs.ck + mz, kp.nz) : 0));
+      const int d = dc * S + s;
+      const int pos = bsn[d] + (int)pre[(size_t)dir * nb + d] + rank;
+      if (pos < 0 || pos >= ntot) {
+        // only reachable when a bin overflowed the 16-bit counters (flagged)
+        atomicOr(err, 2);
+        continue;
+      }
+      q0[pos] = o0[p];
+      q1[pos] = o1[p];
+      if constexpr (DIM == 3) q2[pos] = o2[p];
+      v0[pos] = u0[p];
+      v1[pos] = u1[p];
+      v2[pos] = u2[p];
+      wo[pos] = wt[p];
+      cell_out[pos] = dc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// S7 kinetic part: per-block FP64 partial sums (fixed order)
+// ---------------------------------------------------------------------------
+template <typename T, int DIM, int G>
+__global__ __launch_bounds__(64) void k_kinetic(KParams kp, const int32_t *__restrict__ bin_start,
+                                                const T *__restrict__ u0, const T *__restrict__ u1,
+                                                const T *__restrict__ u2, const T *__restrict__ wt,
+                                                double *__restrict__ partials) {
+  constexpr int NGRP = 64 / G;
+  __shared__ double red[64];
+  const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
+  const double c2 = kp.c * kp.c;
+  double acc = 0.0;
+  const int ncg = (kp.ncells + NGRP - 1) / NGRP;
+  for (int cg = blockIdx.x; cg < ncg; cg += gridDim.x) {
+    const CellSpan cs = cell_span(kp, bin_start, cg * NGRP + grp);
+    for (int p = cs.pbeg + gl; p < cs.pend; p += G) {
+      int s = 0;
+#pragma unroll
+      for (int s2 = 1; s2 < 8; ++s2)
+        if (p >= cs.bound[s2]) s = s2;
+      const double ux = u0[p], uy = u1[p], uz = u2[p];
+      const double uu = ux * ux + uy * uy + uz * uz;
+      double m = kp.m[0];
+#pragma unroll
+      for (int s2 = 1; s2 < 8; ++s2)
+        if (s == s2) m = kp.m[s2];
+      const double w = wt[p];
+      acc += kp.nonrel ? 0.5 * w * m * uu : w * m * uu / (sqrt(1.0 + uu / c2) + 1.0);
+    }
+  }
+  red[lane] = acc;
+  __syncthreads();
+  for (int o = 32; o >= 1; o >>= 1) {
+    if (lane < o) red[lane] += red[lane + o];
+    __syncthreads();
+  }
+  if (lane == 0) partials[blockIdx.x] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of int32 (three-phase: block scans, scan of block sums, add)
+// ---------------------------------------------------------------------------
+constexpr int kScanBlock = 1024;
+constexpr int kScanItems = 2 * kScanBlock;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int *lds, int &total) {
+  // inclusive warp scan via shuffles, then across waves through LDS
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds[wid] = x;
+  __syncthreads();
+  if (wid == 0) {
+    const int nw = blockDim.x >> 6;
+    int t = lane < nw ? lds[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(t, o);
+      if (lane >= o) t += y;
+    }
+    if (lane < nw) lds[64 + lane] = t;
+  }
+  __syncthreads();
+  const int wprefix = wid > 0 ? lds[64 + wid - 1] : 0;
+  total = lds[64 + (blockDim.x >> 6) - 1];
+  __syncthreads();
+  return wprefix + x - v;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_blocks(const int32_t *__restrict__ in, int32_t *__restrict__ out,
+                                                            int n, int32_t *__restrict__ bsum) {
+  __shared__ int lds[128];
+  const size_t base = (size_t)blockIdx.x * kScanItems;
+  const size_t i0 = base + 2 * threadIdx.x;
+  const int a = i0 < (size_t)n ? in[i0] : 0;
+  const int b = i0 + 1 < (size_t)n ? in[i0 + 1] : 0;
+  int total;
+  const int ex = block_exclusive_scan(a + b, lds, total);
+  if (i0 < (size_t)n) out[i0] = ex;
+  if (i0 + 1 < (size_t)n) out[i0 + 1] = ex + a;
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_top(int32_t *__restrict__ bsum, int nb, int32_t *__restrict__ out,
+                                                         int n) {
+  __shared__ int lds[128];
+  int carry = 0;
+  for (int base = 0; base < nb; base += kScanBlock) {
+    const int i = base + threadIdx.x;
+    const int v = i < nb ? bsum[i] : 0;
+    int total;
+    const int ex = block_exclusive_scan(v, lds, total);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(int32_t *__restrict__ out, int n, const int32_t *__restrict__ bsum) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < (size_t)n) out[i] += bsum[i / kScanItems];
+}
+
+template <typename T>
+const T *cp(const void *p) {
+  return static_cast<const T *>(p);
+}
+template <typename T>
+T *mp(void *p) {
+  return static_cast<T *>(p);
+}
+
+template <typename T, int DIM, int G>
+void deposit_impl(const KParams &kp, const PartPtrs &pp, const double *B, void *S, hipStream_t st) {
+  const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
+  hipLaunchKernelGGL((k_deposit_cells<T, DIM, G>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, cp<T>(pp.off[0]),
+                     cp<T>(pp.off[1]), cp<T>(pp.off[2]), cp<T>(pp.u[0]), cp<T>(pp.u[1]), cp<T>(pp.u[2]), cp<T>(pp.w),
+                     B, mp<T>(S));
+}
+
+template <typename T, int DIM, int G>
+void push_impl(const KParams &kp, const PartPtrs &pp, const double *Eth, const double *B, uint8_t *dirc,
+               uint16_t *cnt, int32_t *err, int count_moves, hipStream_t st) {
+  const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
+  hipLaunchKernelGGL((k_push<T, DIM, G>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, mp<T>(pp.off[0]),
+                     mp<T>(pp.off[1]), mp<T>(pp.off[2]), mp<T>(pp.u[0]), mp<T>(pp.u[1]), mp<T>(pp.u[2]), Eth, B, dirc,
+                     cnt, err, count_moves);
+}
+
+template <typename T, int DIM, int G>
+void scatter_impl(const KParams &kp, const PartPtrs &src, const uint8_t *dirc, const uint16_t *pre, const int32_t *bsn,
+                  int32_t *cell_out, void *const off_out[3], void *const u_out[3], void *w_out, int ntot, int32_t *err,
+                  hipStream_t st) {
+  const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
+  hipLaunchKernelGGL((k_sort_scatter<T, DIM, G>), dim3(nblk), dim3(64), 0, st, kp, src.bin_start, cp<T>(src.off[0]),
+                     cp<T>(src.off[1]), cp<T>(src.off[2]), cp<T>(src.u[0]), cp<T>(src.u[1]), cp<T>(src.u[2]),
+                     cp<T>(src.w), dirc, pre, bsn, cell_out, mp<T>(off_out[0]), mp<T>(off_out[1]), mp<T>(off_out[2]),
+                     mp<T>(u_out[0]), mp<T>(u_out[1]), mp<T>(u_out[2]), mp<T>(w_out), ntot, err);
+}
+
+template <typename T, int DIM, int G>
+void kinetic_impl(const KParams &kp, const PartPtrs &pp, double *partials, hipStream_t st) {
+  hipLaunchKernelGGL((k_kinetic<T, DIM, G>), dim3(kRedBlocks), dim3(64), 0, st, kp, pp.bin_start, cp<T>(pp.u[0]),
+                     cp<T>(pp.u[1]), cp<T>(pp.u[2]), cp<T>(pp.w), partials);
+}
+
+// Dispatch over (precision, dim, group) to the template instances.
+template <template <typename, int, int> class F, typename... A>
+void dispatch(int prec, int dim, int group, A &&...args) {
+#define RELSIM_CASE(TT, DD, GG) \
+  if (dim == DD && group == GG) return F<TT, DD, GG>::run(args...);
+  if (prec == RELSIM_MIXED) {
+    RELSIM_CASE(float, 2, 8) RELSIM_CASE(float, 2, 16) RELSIM_CASE(float, 2, 32) RELSIM_CASE(float, 2, 64)
+    RELSIM_CASE(float, 3, 8) RELSIM_CASE(float, 3, 16) RELSIM_CASE(float, 3, 32) RELSIM_CASE(float, 3, 64)
+  } else {
+    RELSIM_CASE(double, 2, 8) RELSIM_CASE(double, 2, 16) RELSIM_CASE(double, 2, 32) RELSIM_CASE(double, 2, 64)
+    RELSIM_CASE(double, 3, 8) RELSIM_CASE(double, 3, 16) RELSIM_CASE(double, 3, 32) RELSIM_CASE(double, 3, 64)
+  }
+#undef RELSIM_CASE
+}
+
+template <typename T, int D, int G>
+struct DepositF {
+  template <typename... A>
+  static void run(A &&...a) { deposit_impl<T, D, G>(a...); }
+};
+template <typename T, int D, int G>
+struct PushF {
+  template <typename... A>
+  static void run(A &&...a) { push_impl<T, D, G>(a...); }
+};
+template <typename T, int D, int G>
+struct ScatterF {
+  template <typename... A>
+  static void run(A &&...a) { scatter_impl<T, D, G>(a...); }
+};
+template <typename T, int D, int G>
+struct KineticF {
+  template <typename... A>
+  static void run(A &&...a) { kinetic_impl<T, D, G>(a...); }
+};
+
+}  // namespace
+
+void launch_deposit_cells(const KParams &kp, int prec, int group, const PartPtrs &pp, const double *B, void *S,
+                          hipStream_t st) {
+  dispatch<DepositF>(prec, kp.dim, group, kp, pp, B, S, st);
+}
+
+void launch_assemble(const KParams &kp, int prec, const void *S, double *J, double *M, hipStream_t st) {
+  const int nblk = (kp.ncells + 255) / 256;
+  if (prec == RELSIM_MIXED) {
+    if (kp.dim == 2)
+      hipLaunchKernelGGL((k_assemble<float, 2>), dim3(nblk), dim3(256), 0, st, kp, cp<float>(S), J, M);
+    else
+      hipLaunchKernelGGL((k_assemble<float, 3>), dim3(nblk), dim3(256), 0, st, kp, cp<float>(S), J, M);
+  } else {
+    if (kp.dim == 2)
+      hipLaunchKernelGGL((k_assemble<double, 2>), dim3(nblk), dim3(256), 0, st, kp, cp<double>(S), J, M);
+    else
+      hipLaunchKernelGGL((k_assemble<double, 3>), dim3(nblk), dim3(256), 0, st, kp, cp<double>(S), J, M);
+  }
+}
+
+void launch_push(const KParams &kp, int prec, int group, const PartPtrs &pp, const double *Eth, const double *B,
+                 uint8_t *dirc, uint16_t *cnt, int32_t *err, int count_moves, hipStream_t st) {
+  dispatch<PushF>(prec, kp.dim, group, kp, pp, Eth, B, dirc, cnt, err, count_moves, st);
+}
+
+void launch_sort_offsets(const KParams &kp, const uint16_t *cnt, uint16_t *pre, int32_t *total, int32_t *err,
+                         hipStream_t st) {
+  const int nblk = (kp.nbins + 255) / 256;
+  if (kp.dim == 2)
+    hipLaunchKernelGGL((k_sort_offsets<2>), dim3(nblk), dim3(256), 0, st, kp, cnt, pre, total, err);
+  else
+    hipLaunchKernelGGL((k_sort_offsets<3>), dim3(nblk), dim3(256), 0, st, kp, cnt, pre, total, err);
+}
+
+size_t scan_tmp_elems(int n) { return (size_t)(n + kScanItems - 1) / kScanItems + 1; }
+
+void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream_t st) {
+  const int nb = (n + kScanItems - 1) / kScanItems;
+  if (nb > 0) hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(kScanBlock), 0, st, in, out, n, tmp);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, st, tmp, nb, out, n);
+  if (nb > 1) hipLaunchKernelGGL(k_scan_add, dim3((n + 255) / 256), dim3(256), 0, st, out, n, tmp);
+}
+
+void launch_sort_scatter(const KParams &kp, int prec, int group, const PartPtrs &src, const uint8_t *dirc,
+                         const uint16_t *pre, const int32_t *bin_start_new, int32_t *cell_out, void *const off_out[3],
+                         void *const u_out[3], void *w_out, int ntot, int32_t *err, hipStream_t st) {
+  dispatch<ScatterF>(prec, kp.dim, group, kp, src, dirc, pre, bin_start_new, cell_out, off_out, u_out, w_out, ntot, err,
+                     st);
+}
+
+void launch_kinetic(const KParams &kp, int prec, int group, const PartPtrs &pp, double *partials, hipStream_t st) {
+  dispatch<KineticF>(prec, kp.dim, group, kp, pp, partials, st);
+}
+
+}  // namespace relsim

@@ -1,0 +1,84 @@
+// Internal declarations shared by the HIP translation units of librelsim.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "relsim.h"
+
+namespace relsim {
+
+// Constants handed to every particle/grid kernel by value.
+struct KParams {
+  int dim, nx, ny, nz, ncells, nspecies, nbins, nonrel;
+  double dx, dy, dz, dt, c, theta, V;
+  double inv_dx, inv_dy, inv_dz;
+  double q[8], m[8], beta[8];
+};
+
+// Offsets (in bytes) of the regions carved out of the caller's workspace.
+struct Layout {
+  size_t S, cnt, pre, total, scan_tmp, dirc, err, gm_V, gm_t, gm_b, gm_r, gm_part, gm_small, red_part;
+  size_t gs_k0, gs_k1, gs_v0, gs_v1, gs_hist, end;
+};
+
+constexpr int kMaxRestart = 64;
+constexpr int kDotBlocks = 512;     // blocks of the multi-dot reduction
+constexpr int kRedBlocks = 1024;    // blocks of the energy reductions
+
+// Moments per cell: 2D 81 mass moments + 12 current moments; 3D three passes
+// of 81 mass moments plus 2 x 12 current moments.
+inline int n_cell_moments(int dim) { return dim == 3 ? 3 * 81 + 2 * 12 : 81 + 12; }
+inline int n_dirs(int dim) { return dim == 3 ? 27 : 9; }
+
+// ---- particle kernels (particles.hip) ----
+struct PartPtrs {
+  const int32_t *bin_start;
+  void *off[3];
+  void *u[3];
+  void *w;
+};
+
+void launch_deposit_cells(const KParams &kp, int prec, int group, const PartPtrs &pp, const double *B, void *S,
+                          hipStream_t st);
+void launch_assemble(const KParams &kp, int prec, const void *S, double *J, double *M, hipStream_t st);
+void launch_push(const KParams &kp, int prec, int group, const PartPtrs &pp, const double *Eth, const double *B,
+                 uint8_t *dirc, uint16_t *cnt, int32_t *err, int count_moves, hipStream_t st);
+void launch_sort_offsets(const KParams &kp, const uint16_t *cnt, uint16_t *pre, int32_t *total, int32_t *err,
+                         hipStream_t st);
+void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream_t st);
+size_t scan_tmp_elems(int n);
+void launch_sort_scatter(const KParams &kp, int prec, int group, const PartPtrs &src, const uint8_t *dirc,
+                         const uint16_t *pre, const int32_t *bin_start_new, int32_t *cell_out, void *const off_out[3],
+                         void *const u_out[3], void *w_out, int ntot, int32_t *err, hipStream_t st);
+void launch_kinetic(const KParams &kp, int prec, int group, const PartPtrs &pp, double *partials, hipStream_t st);
+
+// ---- general stable sort by bin (sort.hip) ----
+size_t gsort_tmp_elems(int64_t n);  // int32 elements of scratch for the histograms
+void launch_gsort(const KParams &kp, int prec, int64_t n, const int32_t *cell, const uint8_t *species, const PartPtrs &src,
+                  int32_t *keys0, int32_t *keys1, int32_t *vals0, int32_t *vals1, int32_t *hist, int32_t *scan_tmp,
+                  int32_t *err, int32_t *bin_start_out, int32_t *cell_out, void *const off_out[3], void *const u_out[3],
+                  void *w_out, hipStream_t st);
+
+// ---- field kernels (field.hip) ----
+void launch_curl(const KParams &kp, const double *in, double *out, int to_centres, hipStream_t st);
+void launch_apply_A_tail(const KParams &kp, const double *M, const double *x, const double *t, double *out,
+                         hipStream_t st);
+void launch_rhs(const KParams &kp, const double *En, const double *Bn, const double *J, double *out, hipStream_t st);
+void launch_field_update(const KParams &kp, const double *En, const double *Bn, const double *Eth, double *En1,
+                         double *Bn1, hipStream_t st);
+// out[k] = sum_i V[k][i] * w[i] for k < nvec (V rows of length n with stride ld)
+// written to partials[blocks][nvec]; then reduced into res[nvec] (device).
+void launch_mdot(const double *V, size_t ld, int nvec, const double *w, size_t n, double *partials, double *res,
+                 hipStream_t st);
+// w -= sum_k h[k] V[k]  (h on the device)
+void launch_maxpy(const double *V, size_t ld, int nvec, const double *h, double *w, size_t n, hipStream_t st);
+// y = a * x + b * y  (scalars from the host)
+void launch_axpby(double a, const double *x, double b, double *y, size_t n, hipStream_t st);
+void launch_sumsq_partials(const double *x, size_t n, double *partials, hipStream_t st);
+void launch_reduce_partials(const double *partials, int nparts, int nvec, double *res, hipStream_t st);
+
+}  // namespace relsim

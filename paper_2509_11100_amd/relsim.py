@@ -1,0 +1,320 @@
+"""Thin Python binding of librelsim over torch device tensors.
+
+Each function carries the name of the C entry point it calls and only
+marshals arguments: every step of the path runs in the library's HIP kernels.
+PyTorch provides the device memory and the stream (the stream current at
+context creation is the one every call enqueues on).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import RelsimError
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Context:
+    """A librelsim context: parameters, caller-owned workspace, stream."""
+
+    def __init__(self, *, dim: int, nx: int, ny: int, nz: int = 1, dx: float, dy: Optional[float] = None,
+                 dz: Optional[float] = None, dt: float, c: float = 1.0, theta: float = 0.5,
+                 precision: str = "fp64", q: Sequence[float] = (1.0, -1.0), m: Sequence[float] = (1.0, 1.0),
+                 max_particles: int, gmres_rtol: float = 1e-10, gmres_restart: int = 30, gmres_maxit: int = 3000,
+                 nonrelativistic: bool = False, group: int = 0, device: str = "cuda"):
+        self.lib = _lib.load()
+        p = _lib.relsim_params()
+        p.dim, p.nx, p.ny, p.nz = dim, nx, ny, (nz if dim == 3 else 1)
+        p.dx = dx
+        p.dy = dx if dy is None else dy
+        p.dz = dx if dz is None else dz
+        p.dt, p.c, p.theta = dt, c, theta
+        if precision not in ("fp64", "mixed"):
+            raise ValueError("precision must be 'fp64' or 'mixed'")
+        p.precision = _lib.RELSIM_FP64 if precision == "fp64" else _lib.RELSIM_MIXED
+        p.nspecies = len(q)
+        for i, (qq, mm) in enumerate(zip(q, m)):
+            p.q[i] = qq
+            p.m[i] = mm
+        p.max_particles = int(max_particles)
+        p.gmres_rtol, p.gmres_restart, p.gmres_maxit = gmres_rtol, gmres_restart, gmres_maxit
+        p.nonrelativistic = 1 if nonrelativistic else 0
+        p.group = group
+        self.params = p
+        self.precision = precision
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        nbytes = self.lib.relsim_workspace_bytes(C.byref(p))
+        if nbytes == 0:
+            raise RelsimError(_lib.RELSIM_EINVAL, "invalid parameters")
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        rc = self.lib.relsim_init(C.byref(p), C.c_void_p(self.stream.cuda_stream), C.c_void_p(self.workspace.data_ptr()),
+                                  C.c_size_t(int(nbytes)), C.byref(h))
+        if rc != 0:
+            raise RelsimError(rc, self.lib.relsim_strerror(rc).decode())
+        self.handle = h
+
+    # ---- shapes ----
+    @property
+    def dim(self) -> int:
+        return self.params.dim
+
+    @property
+    def ncells(self) -> int:
+        return self.params.nx * self.params.ny * (self.params.nz if self.params.dim == 3 else 1)
+
+    @property
+    def nspecies(self) -> int:
+        return self.params.nspecies
+
+    @property
+    def noff(self) -> int:
+        return 27 if self.params.dim == 3 else 9
+
+    @property
+    def dtype(self) -> torch.dtype:
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    def check(self, rc: int) -> int:
+        if rc != 0:
+            raise RelsimError(rc, "%s: %s" % (self.lib.relsim_strerror(rc).decode(),
+                                              self.lib.relsim_last_error(self.handle).decode()))
+        return rc
+
+    def grid(self) -> torch.Tensor:
+        return torch.zeros((3, self.ncells), dtype=torch.float64, device=self.device)
+
+    def mass_matrix(self) -> torch.Tensor:
+        return torch.empty((self.noff, 9, self.ncells), dtype=torch.float64, device=self.device)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.relsim_finalize(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Particles:
+    """Double-buffered structure-of-arrays particle state on the device."""
+
+    def __init__(self, ctx: Context, capacity: Optional[int] = None):
+        self.ctx = ctx
+        cap = int(ctx.params.max_particles if capacity is None else capacity)
+        if cap > ctx.params.max_particles:
+            raise ValueError("capacity exceeds the context's max_particles")
+        dev, dt = ctx.device, ctx.dtype
+        nb = ctx.ncells * ctx.nspecies
+        self.capacity = cap
+        self.sets = []
+        for _ in range(2):
+            self.sets.append({
+                "bin_start": torch.zeros(nb + 1, dtype=torch.int32, device=dev),
+                "cell": torch.zeros(max(cap, 1), dtype=torch.int32, device=dev),
+                "off": [torch.zeros(max(cap, 1), dtype=dt, device=dev) for _ in range(3)],
+                "u": [torch.zeros(max(cap, 1), dtype=dt, device=dev) for _ in range(3)],
+                "w": torch.zeros(max(cap, 1), dtype=dt, device=dev),
+            })
+        self.species_in = torch.zeros(max(cap, 1), dtype=torch.uint8, device=dev)
+        self.s = _lib.relsim_particles()
+        self.front = 0
+        self.n = 0
+        self._bind()
+
+    def _bind(self):
+        f, b = self.sets[self.front], self.sets[1 - self.front]
+        s = self.s
+        s.n = self.n
+        s.bin_start, s.cell, s.w = f["bin_start"].data_ptr(), f["cell"].data_ptr(), f["w"].data_ptr()
+        s.bin_start_back, s.cell_back, s.w_back = b["bin_start"].data_ptr(), b["cell"].data_ptr(), b["w"].data_ptr()
+        for d in range(3):
+            s.off[d], s.u[d] = f["off"][d].data_ptr(), f["u"][d].data_ptr()
+            s.off_back[d], s.u_back[d] = b["off"][d].data_ptr(), b["u"][d].data_ptr()
+        s.species = self.species_in.data_ptr()
+
+    def _sync_front(self):
+        """After a call that may have swapped the sets inside the C struct."""
+        self.front = 0 if self.s.off[0] == self.sets[0]["off"][0].data_ptr() else 1
+        self._bind()
+
+    def load(self, cell, species, off, u, w, bin_start=None):
+        """Copy host (numpy) particles in; sorts on the device unless bin_start is given."""
+        n = int(np.asarray(w).shape[0])
+        if n > self.capacity:
+            raise ValueError("too many particles for this buffer")
+        f = self.sets[self.front]
+        dt = self.ctx.dtype
+        dev = self.ctx.device
+        self.n = n
+        f["cell"][:n].copy_(torch.as_tensor(np.asarray(cell, dtype=np.int32)).to(dev))
+        self.species_in[:n].copy_(torch.as_tensor(np.asarray(species, dtype=np.uint8)).to(dev))
+        offs = np.asarray(off)
+        for d in range(3):
+            if d < offs.shape[0]:
+                f["off"][d][:n].copy_(torch.as_tensor(offs[d]).to(dev, dt))
+            else:
+                f["off"][d][:n].zero_()
+            f["u"][d][:n].copy_(torch.as_tensor(np.asarray(u)[d]).to(dev, dt))
+        f["w"][:n].copy_(torch.as_tensor(np.asarray(w)).to(dev, dt))
+        self._bind()
+        if bin_start is None:
+            sort(self.ctx, self)
+        else:
+            f["bin_start"].copy_(torch.as_tensor(np.asarray(bin_start, dtype=np.int32)).to(dev))
+        return self
+
+    # front views (first n entries)
+    @property
+    def bin_start(self) -> torch.Tensor:
+        return self.sets[self.front]["bin_start"]
+
+    @property
+    def cell(self) -> torch.Tensor:
+        return self.sets[self.front]["cell"][: self.n]
+
+    @property
+    def off(self):
+        return [t[: self.n] for t in self.sets[self.front]["off"][: self.ctx.dim]]
+
+    @property
+    def u(self):
+        return [t[: self.n] for t in self.sets[self.front]["u"]]
+
+    @property
+    def w(self) -> torch.Tensor:
+        return self.sets[self.front]["w"][: self.n]
+
+    def species(self) -> torch.Tensor:
+        """Species id of every front particle, from the bin layout."""
+        bs = self.bin_start.long()
+        counts = bs[1:] - bs[:-1]
+        ids = torch.arange(counts.numel(), device=bs.device) % self.ctx.nspecies
+        return torch.repeat_interleave(ids, counts)
+
+    def to_host(self):
+        """Front state as numpy (cell, species, off, u, w, bin_start)."""
+        return (self.cell.cpu().numpy(), self.species().cpu().numpy().astype(np.uint8),
+                np.stack([t.cpu().numpy() for t in self.off]), np.stack([t.cpu().numpy() for t in self.u]),
+                self.w.cpu().numpy(), self.bin_start.cpu().numpy())
+
+
+# ---------------------------------------------------------------------------
+# entry points (names follow include/relsim.h)
+# ---------------------------------------------------------------------------
+def _grid_ok(ctx: Context, *ts):
+    for t in ts:
+        if t is None:
+            continue
+        if t.device != ctx.device or t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError("grid arrays must be contiguous float64 tensors on the context device")
+
+
+def sort(ctx: Context, parts: Particles) -> None:
+    """relsim_sort"""
+    parts.s.n = parts.n
+    ctx.check(ctx.lib.relsim_sort(ctx.handle, C.byref(parts.s)))
+    parts._sync_front()
+
+
+def deposit_moments(ctx: Context, parts: Particles, B: torch.Tensor, J: Optional[torch.Tensor] = None,
+                    M: Optional[torch.Tensor] = None):
+    """relsim_deposit_moments -> (Jhat [3][N], M [noff][9][N])"""
+    J = ctx.grid() if J is None else J
+    M = ctx.mass_matrix() if M is None else M
+    _grid_ok(ctx, B, J, M)
+    parts.s.n = parts.n
+    ctx.check(ctx.lib.relsim_deposit_moments(ctx.handle, C.byref(parts.s), _ptr(B), _ptr(J), _ptr(M)))
+    return J, M
+
+
+def field_solve(ctx: Context, M, J, E, B, E_theta=None, E1=None, B1=None, allow_unconverged: bool = False):
+    """relsim_field_solve -> (E_theta, E^{n+1}, B^{n+1}, iterations, relative residual)"""
+    E_theta = ctx.grid() if E_theta is None else E_theta
+    E1 = ctx.grid() if E1 is None else E1
+    B1 = ctx.grid() if B1 is None else B1
+    _grid_ok(ctx, M, J, E, B, E_theta, E1, B1)
+    it = C.c_int32(0)
+    rr = C.c_double(0.0)
+    rc = ctx.lib.relsim_field_solve(ctx.handle, _ptr(M), _ptr(J), _ptr(E), _ptr(B), _ptr(E_theta), _ptr(E1), _ptr(B1),
+                                    C.byref(it), C.byref(rr))
+    if not (allow_unconverged and rc == _lib.RELSIM_ENOTCONVERGED):
+        ctx.check(rc)
+    return E_theta, E1, B1, it.value, rr.value
+
+
+def push(ctx: Context, parts: Particles, E_theta: torch.Tensor, B: torch.Tensor, resort: bool = True) -> None:
+    """relsim_push (re-sorts into the back buffers and swaps when resort)"""
+    _grid_ok(ctx, E_theta, B)
+    parts.s.n = parts.n
+    ctx.check(ctx.lib.relsim_push(ctx.handle, C.byref(parts.s), _ptr(E_theta), _ptr(B), 1 if resort else 0))
+    parts._sync_front()
+
+
+def energy(ctx: Context, parts: Particles, E: torch.Tensor, B: torch.Tensor) -> np.ndarray:
+    """relsim_energy -> (kinetic, electric, magnetic, total)"""
+    _grid_ok(ctx, E, B)
+    out = (C.c_double * 4)()
+    parts.s.n = parts.n
+    ctx.check(ctx.lib.relsim_energy(ctx.handle, C.byref(parts.s), _ptr(E), _ptr(B), out))
+    return np.array(list(out))
+
+
+def curl_nc(ctx: Context, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """relsim_curl_nc"""
+    out = ctx.grid() if out is None else out
+    _grid_ok(ctx, x, out)
+    ctx.check(ctx.lib.relsim_curl_nc(ctx.handle, _ptr(x), _ptr(out)))
+    return out
+
+
+def curl_cn(ctx: Context, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """relsim_curl_cn"""
+    out = ctx.grid() if out is None else out
+    _grid_ok(ctx, x, out)
+    ctx.check(ctx.lib.relsim_curl_cn(ctx.handle, _ptr(x), _ptr(out)))
+    return out
+
+
+def apply_A(ctx: Context, M: torch.Tensor, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """relsim_apply_A"""
+    out = ctx.grid() if out is None else out
+    _grid_ok(ctx, M, x, out)
+    ctx.check(ctx.lib.relsim_apply_A(ctx.handle, _ptr(M), _ptr(x), _ptr(out)))
+    return out
+
+
+def timing_enable(ctx: Context, on: bool = True) -> None:
+    """relsim_timing_enable"""
+    ctx.check(ctx.lib.relsim_timing_enable(ctx.handle, 1 if on else 0))
+
+
+def timing_reset(ctx: Context) -> None:
+    """relsim_timing_reset"""
+    ctx.check(ctx.lib.relsim_timing_reset(ctx.handle))
+
+
+def timing_read(ctx: Context) -> dict:
+    """relsim_timing_read -> {kernel: (total_ms, launches)}"""
+    cap = 64
+    names = (C.c_char * 48 * cap)()
+    ms = (C.c_double * cap)()
+    cnt = (C.c_int64 * cap)()
+    n = ctx.lib.relsim_timing_read(ctx.handle, cap, C.cast(names, C.c_void_p), ms, cnt)
+    if n < 0:
+        ctx.check(n)
+    return {names[i].value.decode(): (ms[i], cnt[i]) for i in range(n)}
