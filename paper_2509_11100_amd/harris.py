@@ -154,6 +154,12 @@ def boost_z(rng: np.random.Generator, u: np.ndarray, beta: np.ndarray) -> np.nda
 # ----------------------------------------------------------------------------
 # Particles and fields
 # ----------------------------------------------------------------------------
+def _sech2(x: np.ndarray) -> np.ndarray:
+    """sech^2 without overflow: 4 e^{-2|x|} / (1 + e^{-2|x|})^2."""
+    e = np.exp(-2.0 * np.abs(x))
+    return 4.0 * e / (1.0 + e) ** 2
+
+
 def make_particles(wl: Workload, seed: Optional[int] = None) -> Dict[str, np.ndarray]:
     """Generate the bin-sorted particle state in FP64.
 
@@ -186,7 +192,7 @@ def make_particles(wl: Workload, seed: Optional[int] = None) -> Dict[str, np.nda
     j = (cell.astype(np.int64) // wl.nx) % wl.ny
     y = (j + off[1]) * dx - 0.5 * Y           # physical y in [-Y/2, Y/2)
 
-    dens_sheet = N0 * (1.0 / np.cosh((y - 0.5 * Ly) / hp.a) ** 2 + 1.0 / np.cosh((y + 0.5 * Ly) / hp.a) ** 2)
+    dens_sheet = N0 * (_sech2((y - 0.5 * Ly) / hp.a) + _sech2((y + 0.5 * Ly) / hp.a))
     w = np.where(is_sheet, dens_sheet * V / n_sheet, wl.nb_over_n0 * N0 * V / n_bg)
 
     u = np.empty((3, n))
