@@ -135,10 +135,14 @@ int relsim_field_solve(relsim_ctx *ctx, const double *M, const double *Jhat, con
  * B^n, move it across at most one cell face per dimension (periodic), and,
  * if resort, re-sort it into the back set by a stable counting sort over the
  * neighbour moves and swap.  With resort == 0 the particles stay in their
- * old bins (their offsets may then lie in [-1, 2)), which is only valid as
- * the last call on that state.  Returns RELSIM_ERANGE if a particle moved
- * more than one cell (the state is then undefined). */
-int relsim_push(relsim_ctx *ctx, relsim_particles *part, const double *E_theta, const double *B_n, int32_t resort);
+ * old bins and their offsets, still relative to the old cell, may lie in
+ * [-1, 2); the state is then only good for reading out.  new_index (device,
+ * [n], may be NULL; used only with resort) receives, for every particle in
+ * the old order, its position in the new order.  A particle that moves more
+ * than one cell is reported as RELSIM_ERANGE by the next synchronous call
+ * (the state is then undefined). */
+int relsim_push(relsim_ctx *ctx, relsim_particles *part, const double *E_theta, const double *B_n, int32_t resort,
+                int32_t *new_index);
 
 /* a7 (S7): out[0..3] = kinetic, electric, magnetic, total energy (host
  * array), accumulated in FP64 in both precisions.  Synchronous. */
@@ -150,6 +154,45 @@ int relsim_energy(relsim_ctx *ctx, const relsim_particles *part, const double *E
 int relsim_curl_nc(relsim_ctx *ctx, const double *in, double *out);
 int relsim_curl_cn(relsim_ctx *ctx, const double *in, double *out);
 int relsim_apply_A(relsim_ctx *ctx, const double *M, const double *x, double *out);
+
+/* out = A^T x, the transposed S4 operator (block transpose of M, mirrored
+ * offsets; the curl-curl term is symmetric). */
+int relsim_apply_AT(relsim_ctx *ctx, const double *M, const double *x, double *out);
+
+/* a8: reverse-mode adjoint of one step, RELSIM_FP64 contexts only.  All
+ * cotangent arrays are FP64 device arrays: particle ones [dim][n] for
+ * positions (per unit of physical length) and [3][n] for momenta, in the
+ * particle order of `state_n`; grid ones [3][N].  The step is
+ *   (x^{n+1/2}, u^n, E^n, B^n) -> (x^{n+3/2}, u^{n+1}, E^{n+1}, B^{n+1}).
+ * Call order for one step backwards: relsim_push_adjoint, then
+ * relsim_field_solve_adjoint, then relsim_deposit_adjoint, with the grid
+ * accumulators zeroed by the caller first.
+ *
+ * relsim_push_adjoint (adjoint of S1, S2, S6): state_n is the particle state
+ * before the push (bin-sorted, with cell ids); new_index maps it to the
+ * order of lam_x_in / lam_u_in (the cotangents of x^{n+3/2}, u^{n+1}; NULL =
+ * same order).  Writes lam_x_out, lam_u_out (cotangents of x^{n+1/2}, u^n
+ * through the push) and ADDS into lam_E_theta and lam_B_n. */
+int relsim_push_adjoint(relsim_ctx *ctx, const relsim_particles *state_n, const double *E_theta, const double *B_n,
+                        const int32_t *new_index, const double *lam_x_in, const double *lam_u_in, double *lam_x_out,
+                        double *lam_u_out, double *lam_E_theta, double *lam_B_n);
+
+/* relsim_field_solve_adjoint (adjoint of S4, S5): given lam_E_theta (from the
+ * push adjoint) and the cotangents of E^{n+1}, B^{n+1}, solves
+ * A^T mu = lam_E_theta + lam_E_np1/theta - c dt C_NC^T lam_B_np1 by GMRES
+ * (same tolerance as the forward solve, initial guess 0), writes mu, and ADDS
+ * -(1-theta)/theta lam_E_np1 + mu into lam_E_n and lam_B_np1 +
+ * c theta dt C_CN^T mu into lam_B_n.  M is the step's mass matrix.
+ * Synchronous; RELSIM_ENOTCONVERGED as for relsim_field_solve. */
+int relsim_field_solve_adjoint(relsim_ctx *ctx, const double *M, const double *lam_E_theta, const double *lam_E_np1,
+                               const double *lam_B_np1, double *mu, double *lam_E_n, double *lam_B_n, int32_t *iters,
+                               double *rel_resid);
+
+/* relsim_deposit_adjoint (adjoint of S1-S3 through J-bar = Jhat + M E_th):
+ * with mu from relsim_field_solve_adjoint, ADDS the particle cotangents into
+ * lam_x, lam_u and the field cotangent into lam_B_n. */
+int relsim_deposit_adjoint(relsim_ctx *ctx, const relsim_particles *state_n, const double *B_n, const double *E_theta,
+                           const double *mu, double *lam_x, double *lam_u, double *lam_B_n);
 
 /* Per-kernel timing with HIP events on the context's stream.  When enabled,
  * every kernel launch is bracketed by events; relsim_timing_read

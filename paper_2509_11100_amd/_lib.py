@@ -74,7 +74,11 @@ def load() -> C.CDLL:
         "relsim_sort": (C.c_int, [vp, pt]),
         "relsim_deposit_moments": (C.c_int, [vp, pt, vp, vp, vp]),
         "relsim_field_solve": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i32), dp]),
-        "relsim_push": (C.c_int, [vp, pt, vp, vp, i32]),
+        "relsim_push": (C.c_int, [vp, pt, vp, vp, i32, vp]),
+        "relsim_apply_AT": (C.c_int, [vp, vp, vp, vp]),
+        "relsim_push_adjoint": (C.c_int, [vp, pt, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "relsim_field_solve_adjoint": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i32), dp]),
+        "relsim_deposit_adjoint": (C.c_int, [vp, pt, vp, vp, vp, vp, vp, vp]),
         "relsim_energy": (C.c_int, [vp, pt, vp, vp, dp]),
         "relsim_curl_nc": (C.c_int, [vp, vp, vp]),
         "relsim_curl_cn": (C.c_int, [vp, vp, vp]),
@@ -98,6 +102,7 @@ def exported_symbols():
     return [
         "relsim_workspace_bytes", "relsim_init", "relsim_finalize", "relsim_sort", "relsim_deposit_moments",
         "relsim_field_solve", "relsim_push", "relsim_energy", "relsim_curl_nc", "relsim_curl_cn",
-        "relsim_apply_A", "relsim_timing_enable", "relsim_timing_reset", "relsim_timing_read",
+        "relsim_apply_A", "relsim_apply_AT", "relsim_push_adjoint", "relsim_field_solve_adjoint",
+        "relsim_deposit_adjoint", "relsim_timing_enable", "relsim_timing_reset", "relsim_timing_read",
         "relsim_strerror", "relsim_last_error",
     ]

@@ -280,6 +280,13 @@ void apply_A(relsim_ctx *c, const double *M, const double *x, double *out) {
   timed(c, "apply_A", [&] { launch_apply_A_tail(c->kp, M, x, t, out, c->st); });
 }
 
+// out = A^T x
+void apply_AT(relsim_ctx *c, const double *M, const double *x, double *out) {
+  double *t = c->at<double>(c->L.gm_t);
+  timed(c, "curl_nc", [&] { launch_curl(c->kp, x, t, 1, c->st); });
+  timed(c, "apply_AT", [&] { launch_apply_AT_tail(c->kp, M, x, t, out, c->st); });
+}
+
 int norm2(relsim_ctx *c, const double *x, size_t n, double *out) {
   double *part = c->at<double>(c->L.red_part);
   double *res = c->at<double>(c->L.gm_small) + 3 * (kMaxRestart + 2);
@@ -383,7 +390,8 @@ int relsim_deposit_moments(relsim_ctx *c, const relsim_particles *pt, const doub
   return launch_status(c, "relsim_deposit_moments");
 }
 
-int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, const double *B_n, int32_t resort) {
+int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, const double *B_n, int32_t resort,
+                int32_t *new_index) {
   if (!c) return RELSIM_EINVAL;
   int rc = check_particles(c, pt, resort != 0);
   if (rc) return rc;
@@ -406,7 +414,7 @@ int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, cons
     void *ub[3] = {pt->u_back[0], pt->u_back[1], pt->u_back[2]};
     timed(c, "sort_scatter", [&] {
       launch_sort_scatter(c->kp, c->p.precision, G, front(pt), dirc, pre, pt->bin_start_back, pt->cell_back, offb, ub,
-                          pt->w_back, (int)pt->n, err, c->st);
+                          pt->w_back, (int)pt->n, err, new_index, c->st);
     });
     rc = launch_status(c, "relsim_push");
     if (rc) return rc;
@@ -470,13 +478,12 @@ int relsim_apply_A(relsim_ctx *c, const double *M, const double *x, double *out)
   return launch_status(c, "relsim_apply_A");
 }
 
-int relsim_field_solve(relsim_ctx *c, const double *M, const double *Jhat, const double *E_n, const double *B_n,
-                       double *E_theta, double *E_np1, double *B_np1, int32_t *iters, double *rel_resid) {
-  if (!c) return RELSIM_EINVAL;
-  if (!M || !Jhat || !E_n || !B_n || !E_theta || !E_np1 || !B_np1) return fail(c, RELSIM_EINVAL, "null grid array");
-  if (E_theta == E_n || E_theta == E_np1 || B_np1 == B_n) return fail(c, RELSIM_EINVAL, "aliased solve arguments");
-  int rc = check_flags(c);
-  if (rc) return rc;
+}  // extern "C"
+
+// Restarted GMRES for A x = b (or A^T x = b) from the initial guess in x.
+// b must live in the workspace slot gm_b.  Returns RELSIM_OK, or
+// RELSIM_ENOTCONVERGED with the last iterate in x.
+static int gmres_solve(relsim_ctx *c, const double *M, bool transpose, double *x, int32_t *iters, double *rel_resid) {
   const size_t n3 = 3 * (size_t)c->kp.ncells;
   const int m = c->p.gmres_restart;
   double *V = c->at<double>(c->L.gm_V);
@@ -485,9 +492,13 @@ int relsim_field_solve(relsim_ctx *c, const double *M, const double *Jhat, const
   double *part = c->at<double>(c->L.gm_part);
   double *hdev = c->at<double>(c->L.gm_small);
   double *ydev = hdev + (kMaxRestart + 2);
-  double *x = E_theta;
-  timed(c, "rhs", [&] { launch_rhs(c->kp, E_n, B_n, Jhat, b, c->st); });
-  HIP_CHECK(c, hipMemcpyAsync(x, E_n, n3 * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  auto op = [&](const double *in, double *out) {
+    if (transpose)
+      apply_AT(c, M, in, out);
+    else
+      apply_A(c, M, in, out);
+  };
+  int rc;
   double bnorm;
   rc = norm2(c, b, n3, &bnorm);
   if (rc) return rc;
@@ -499,7 +510,7 @@ int relsim_field_solve(relsim_ctx *c, const double *M, const double *Jhat, const
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   for (;;) {
     // true residual r = b - A x
-    apply_A(c, M, x, r);
+    op(x, r);
     timed(c, "axpby", [&] { launch_axpby(1.0, b, -1.0, r, n3, c->st); });
     double beta;
     rc = norm2(c, r, n3, &beta);
@@ -519,7 +530,7 @@ int relsim_field_solve(relsim_ctx *c, const double *M, const double *Jhat, const
     for (int j = 0; j < m; ++j) {
       double *vj = V + (size_t)j * n3;
       double *w = V + (size_t)(j + 1) * n3;
-      apply_A(c, M, vj, w);
+      op(vj, w);
       // classical Gram-Schmidt, twice; the second pass also returns |w|^2
       timed(c, "mdot", [&] { launch_mdot(V, n3, j + 1, w, n3, part, hdev, c->st); });
       rc = fetch(c, hdev, j + 1);
@@ -578,13 +589,110 @@ int relsim_field_solve(relsim_ctx *c, const double *M, const double *Jhat, const
     // the copy reads c->host; make sure it finished before the host buffer is reused
     HIP_CHECK(c, hipStreamSynchronize(c->st));
   }
-  timed(c, "field_update", [&] { launch_field_update(c->kp, E_n, B_n, x, E_np1, B_np1, c->st); });
-  rc = launch_status(c, "relsim_field_solve");
-  if (rc) return rc;
   if (iters) *iters = total_it;
   if (rel_resid) *rel_resid = rel;
   if (!converged) return fail(c, RELSIM_ENOTCONVERGED, "GMRES reached gmres_maxit before gmres_rtol");
   return RELSIM_OK;
+}
+
+extern "C" {
+
+int relsim_field_solve(relsim_ctx *c, const double *M, const double *Jhat, const double *E_n, const double *B_n,
+                       double *E_theta, double *E_np1, double *B_np1, int32_t *iters, double *rel_resid) {
+  if (!c) return RELSIM_EINVAL;
+  if (!M || !Jhat || !E_n || !B_n || !E_theta || !E_np1 || !B_np1) return fail(c, RELSIM_EINVAL, "null grid array");
+  if (E_theta == E_n || E_theta == E_np1 || B_np1 == B_n) return fail(c, RELSIM_EINVAL, "aliased solve arguments");
+  int rc = check_flags(c);
+  if (rc) return rc;
+  const size_t n3 = 3 * (size_t)c->kp.ncells;
+  double *b = c->at<double>(c->L.gm_b);
+  timed(c, "rhs", [&] { launch_rhs(c->kp, E_n, B_n, Jhat, b, c->st); });
+  HIP_CHECK(c, hipMemcpyAsync(E_theta, E_n, n3 * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  const int solved = gmres_solve(c, M, false, E_theta, iters, rel_resid);
+  if (solved != RELSIM_OK && solved != RELSIM_ENOTCONVERGED) return solved;
+  timed(c, "field_update", [&] { launch_field_update(c->kp, E_n, B_n, E_theta, E_np1, B_np1, c->st); });
+  rc = launch_status(c, "relsim_field_solve");
+  if (rc) return rc;
+  return solved;
+}
+
+int relsim_apply_AT(relsim_ctx *c, const double *M, const double *x, double *out) {
+  if (!c || !M || !x || !out) return RELSIM_EINVAL;
+  if (x == out) return fail(c, RELSIM_EINVAL, "relsim_apply_AT cannot work in place");
+  apply_AT(c, M, x, out);
+  return launch_status(c, "relsim_apply_AT");
+}
+
+static AdjInPtrs adj_inputs(const relsim_particles *pt) {
+  AdjInPtrs a;
+  a.bin_start = pt->bin_start;
+  a.cell = pt->cell;
+  for (int d = 0; d < 3; ++d) {
+    a.off[d] = (const double *)pt->off[d];
+    a.u[d] = (const double *)pt->u[d];
+  }
+  a.w = (const double *)pt->w;
+  return a;
+}
+
+int relsim_push_adjoint(relsim_ctx *c, const relsim_particles *state_n, const double *E_theta, const double *B_n,
+                        const int32_t *new_index, const double *lam_x_in, const double *lam_u_in, double *lam_x_out,
+                        double *lam_u_out, double *lam_E_theta, double *lam_B_n) {
+  if (!c) return RELSIM_EINVAL;
+  if (c->p.precision != RELSIM_FP64) return fail(c, RELSIM_EINVAL, "the adjoint needs RELSIM_FP64");
+  int rc = check_particles(c, state_n, false);
+  if (rc) return rc;
+  if (!state_n->cell || !E_theta || !B_n || !lam_x_in || !lam_u_in || !lam_x_out || !lam_u_out || !lam_E_theta ||
+      !lam_B_n)
+    return fail(c, RELSIM_EINVAL, "null argument");
+  timed(c, "push_adjoint", [&] {
+    launch_push_adjoint(c->kp, adj_inputs(state_n), (int)state_n->n, E_theta, B_n, new_index, lam_x_in, lam_u_in,
+                        lam_x_out, lam_u_out, lam_E_theta, lam_B_n, c->st);
+  });
+  return launch_status(c, "relsim_push_adjoint");
+}
+
+int relsim_field_solve_adjoint(relsim_ctx *c, const double *M, const double *lam_E_theta, const double *lam_E_np1,
+                               const double *lam_B_np1, double *mu, double *lam_E_n, double *lam_B_n, int32_t *iters,
+                               double *rel_resid) {
+  if (!c) return RELSIM_EINVAL;
+  if (!M || !lam_E_theta || !lam_E_np1 || !lam_B_np1 || !mu || !lam_E_n || !lam_B_n)
+    return fail(c, RELSIM_EINVAL, "null grid array");
+  int rc = check_flags(c);
+  if (rc) return rc;
+  const size_t n3 = 3 * (size_t)c->kp.ncells;
+  const double th = c->kp.theta;
+  double *b = c->at<double>(c->L.gm_b);
+  double *t = c->at<double>(c->L.gm_t);
+  // rhs = l_th + l_E1/theta - c dt C_NC^T l_B1, with C_NC^T = C_CN
+  timed(c, "curl_cn", [&] { launch_curl(c->kp, lam_B_np1, t, 0, c->st); });
+  timed(c, "adj_rhs", [&] { launch_adj_rhs(n3, th, c->kp.c * c->kp.dt, lam_E_theta, lam_E_np1, t, b, c->st); });
+  HIP_CHECK(c, hipMemsetAsync(mu, 0, n3 * sizeof(double), c->st));
+  const int solved = gmres_solve(c, M, true, mu, iters, rel_resid);
+  if (solved != RELSIM_OK && solved != RELSIM_ENOTCONVERGED) return solved;
+  // l_En += -(1-theta)/theta l_E1 + mu ; l_Bn += l_B1 + c theta dt C_CN^T mu, with C_CN^T = C_NC
+  timed(c, "curl_nc", [&] { launch_curl(c->kp, mu, t, 1, c->st); });
+  timed(c, "adj_finish", [&] {
+    launch_adj_finish(n3, th, c->kp.c * th * c->kp.dt, lam_E_np1, lam_B_np1, mu, t, lam_E_n, lam_B_n, c->st);
+  });
+  rc = launch_status(c, "relsim_field_solve_adjoint");
+  if (rc) return rc;
+  return solved;
+}
+
+int relsim_deposit_adjoint(relsim_ctx *c, const relsim_particles *state_n, const double *B_n, const double *E_theta,
+                           const double *mu, double *lam_x, double *lam_u, double *lam_B_n) {
+  if (!c) return RELSIM_EINVAL;
+  if (c->p.precision != RELSIM_FP64) return fail(c, RELSIM_EINVAL, "the adjoint needs RELSIM_FP64");
+  int rc = check_particles(c, state_n, false);
+  if (rc) return rc;
+  if (!state_n->cell || !B_n || !E_theta || !mu || !lam_x || !lam_u || !lam_B_n)
+    return fail(c, RELSIM_EINVAL, "null argument");
+  timed(c, "deposit_adjoint", [&] {
+    launch_deposit_adjoint(c->kp, adj_inputs(state_n), (int)state_n->n, B_n, E_theta, mu, lam_x, lam_u, lam_B_n,
+                           c->st);
+  });
+  return launch_status(c, "relsim_deposit_adjoint");
 }
 
 int relsim_timing_enable(relsim_ctx *c, int32_t on) {

@@ -536,7 +536,8 @@ __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *
                                                      const int32_t *__restrict__ bsn, int32_t *__restrict__ cell_out,
                                                      T *__restrict__ q0, T *__restrict__ q1, T *__restrict__ q2,
                                                      T *__restrict__ v0, T *__restrict__ v1, T *__restrict__ v2,
-                                                     T *__restrict__ wo, int ntot, int32_t *__restrict__ err) {
+                                                     T *__restrict__ wo, int ntot, int32_t *__restrict__ err,
+                                                     int32_t *__restrict__ perm) {
   constexpr int NDIR = DIM == 3 ? 27 : 9;
   constexpr int NK = 8 * NDIR;
   constexpr int NGRP = 64 / G;
@@ -593,6 +594,7 @@ __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *
       v2[pos] = u2[p];
       wo[pos] = wt[p];
       cell_out[pos] = dc;
+      if (perm) perm[p] = pos;
     }
   }
 }
@@ -734,12 +736,12 @@ void push_impl(const KParams &kp, const PartPtrs &pp, const double *Eth, const d
 template <typename T, int DIM, int G>
 void scatter_impl(const KParams &kp, const PartPtrs &src, const uint8_t *dirc, const uint16_t *pre, const int32_t *bsn,
                   int32_t *cell_out, void *const off_out[3], void *const u_out[3], void *w_out, int ntot, int32_t *err,
-                  hipStream_t st) {
+                  int32_t *perm, hipStream_t st) {
   const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
   hipLaunchKernelGGL((k_sort_scatter<T, DIM, G>), dim3(nblk), dim3(64), 0, st, kp, src.bin_start, cp<T>(src.off[0]),
                      cp<T>(src.off[1]), cp<T>(src.off[2]), cp<T>(src.u[0]), cp<T>(src.u[1]), cp<T>(src.u[2]),
                      cp<T>(src.w), dirc, pre, bsn, cell_out, mp<T>(off_out[0]), mp<T>(off_out[1]), mp<T>(off_out[2]),
-                     mp<T>(u_out[0]), mp<T>(u_out[1]), mp<T>(u_out[2]), mp<T>(w_out), ntot, err);
+                     mp<T>(u_out[0]), mp<T>(u_out[1]), mp<T>(u_out[2]), mp<T>(w_out), ntot, err, perm);
 }
 
 template <typename T, int DIM, int G>
@@ -831,9 +833,9 @@ void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream
 
 void launch_sort_scatter(const KParams &kp, int prec, int group, const PartPtrs &src, const uint8_t *dirc,
                          const uint16_t *pre, const int32_t *bin_start_new, int32_t *cell_out, void *const off_out[3],
-                         void *const u_out[3], void *w_out, int ntot, int32_t *err, hipStream_t st) {
+                         void *const u_out[3], void *w_out, int ntot, int32_t *err, int32_t *perm, hipStream_t st) {
   dispatch<ScatterF>(prec, kp.dim, group, kp, src, dirc, pre, bin_start_new, cell_out, off_out, u_out, w_out, ntot, err,
-                     st);
+                     perm, st);
 }
 
 void launch_kinetic(const KParams &kp, int prec, int group, const PartPtrs &pp, double *partials, hipStream_t st) {

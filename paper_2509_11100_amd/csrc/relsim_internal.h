@@ -53,7 +53,7 @@ void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream
 size_t scan_tmp_elems(int n);
 void launch_sort_scatter(const KParams &kp, int prec, int group, const PartPtrs &src, const uint8_t *dirc,
                          const uint16_t *pre, const int32_t *bin_start_new, int32_t *cell_out, void *const off_out[3],
-                         void *const u_out[3], void *w_out, int ntot, int32_t *err, hipStream_t st);
+                         void *const u_out[3], void *w_out, int ntot, int32_t *err, int32_t *perm, hipStream_t st);
 void launch_kinetic(const KParams &kp, int prec, int group, const PartPtrs &pp, double *partials, hipStream_t st);
 
 // ---- general stable sort by bin (sort.hip) ----
@@ -62,6 +62,26 @@ void launch_gsort(const KParams &kp, int prec, int64_t n, const int32_t *cell, c
                   int32_t *keys0, int32_t *keys1, int32_t *vals0, int32_t *vals1, int32_t *hist, int32_t *scan_tmp,
                   int32_t *err, int32_t *bin_start_out, int32_t *cell_out, void *const off_out[3], void *const u_out[3],
                   void *w_out, hipStream_t st);
+
+// ---- adjoint kernels (adjoint.hip), FP64 particle state ----
+struct AdjInPtrs {
+  const int32_t *bin_start = nullptr;
+  const int32_t *cell = nullptr;
+  const double *off[3] = {nullptr, nullptr, nullptr};
+  const double *u[3] = {nullptr, nullptr, nullptr};
+  const double *w = nullptr;
+};
+void launch_push_adjoint(const KParams &kp, const AdjInPtrs &in, int n, const double *Eth, const double *B,
+                         const int32_t *new_index, const double *lx_in, const double *lu_in, double *lx_out,
+                         double *lu_out, double *lEth, double *lB, hipStream_t st);
+void launch_deposit_adjoint(const KParams &kp, const AdjInPtrs &in, int n, const double *B, const double *Eth,
+                            const double *mu, double *lx_out, double *lu_out, double *lB, hipStream_t st);
+void launch_apply_AT_tail(const KParams &kp, const double *M, const double *x, const double *t, double *out,
+                          hipStream_t st);
+void launch_adj_rhs(size_t n3, double theta, double cdt, const double *lth, const double *lE1, const double *ccn_lB1,
+                    double *out, hipStream_t st);
+void launch_adj_finish(size_t n3, double theta, double ctdt, const double *lE1, const double *lB1, const double *mu,
+                       const double *cnc_mu, double *lEn, double *lBn, hipStream_t st);
 
 // ---- field kernels (field.hip) ----
 void launch_curl(const KParams &kp, const double *in, double *out, int to_centres, hipStream_t st);

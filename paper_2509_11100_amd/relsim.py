@@ -257,12 +257,59 @@ def field_solve(ctx: Context, M, J, E, B, E_theta=None, E1=None, B1=None, allow_
     return E_theta, E1, B1, it.value, rr.value
 
 
-def push(ctx: Context, parts: Particles, E_theta: torch.Tensor, B: torch.Tensor, resort: bool = True) -> None:
-    """relsim_push (re-sorts into the back buffers and swaps when resort)"""
+def push(ctx: Context, parts: Particles, E_theta: torch.Tensor, B: torch.Tensor, resort: bool = True,
+         new_index: Optional[torch.Tensor] = None) -> None:
+    """relsim_push (re-sorts into the back buffers and swaps when resort;
+    new_index, int32 [n], receives each old particle's new position)"""
     _grid_ok(ctx, E_theta, B)
+    if new_index is not None and (new_index.dtype != torch.int32 or new_index.numel() < parts.n):
+        raise ValueError("new_index must be an int32 tensor of at least n elements")
     parts.s.n = parts.n
-    ctx.check(ctx.lib.relsim_push(ctx.handle, C.byref(parts.s), _ptr(E_theta), _ptr(B), 1 if resort else 0))
+    ctx.check(ctx.lib.relsim_push(ctx.handle, C.byref(parts.s), _ptr(E_theta), _ptr(B), 1 if resort else 0,
+                                  _ptr(new_index)))
     parts._sync_front()
+
+
+def apply_AT(ctx: Context, M: torch.Tensor, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """relsim_apply_AT"""
+    out = ctx.grid() if out is None else out
+    _grid_ok(ctx, M, x, out)
+    ctx.check(ctx.lib.relsim_apply_AT(ctx.handle, _ptr(M), _ptr(x), _ptr(out)))
+    return out
+
+
+def _f64(ctx: Context, *ts):
+    for t in ts:
+        if t.device != ctx.device or t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError("adjoint arrays must be contiguous float64 tensors on the context device")
+
+
+def push_adjoint(ctx: Context, state: Particles, E_theta, B, new_index, lam_x_in, lam_u_in, lam_x_out, lam_u_out,
+                 lam_E_theta, lam_B) -> None:
+    """relsim_push_adjoint (lam_E_theta and lam_B are accumulated into)"""
+    _f64(ctx, E_theta, B, lam_x_in, lam_u_in, lam_x_out, lam_u_out, lam_E_theta, lam_B)
+    state.s.n = state.n
+    ctx.check(ctx.lib.relsim_push_adjoint(ctx.handle, C.byref(state.s), _ptr(E_theta), _ptr(B), _ptr(new_index),
+                                          _ptr(lam_x_in), _ptr(lam_u_in), _ptr(lam_x_out), _ptr(lam_u_out),
+                                          _ptr(lam_E_theta), _ptr(lam_B)))
+
+
+def field_solve_adjoint(ctx: Context, M, lam_E_theta, lam_E1, lam_B1, mu, lam_E, lam_B):
+    """relsim_field_solve_adjoint -> (iterations, relative residual); lam_E, lam_B accumulated into"""
+    _f64(ctx, M, lam_E_theta, lam_E1, lam_B1, mu, lam_E, lam_B)
+    it = C.c_int32(0)
+    rr = C.c_double(0.0)
+    ctx.check(ctx.lib.relsim_field_solve_adjoint(ctx.handle, _ptr(M), _ptr(lam_E_theta), _ptr(lam_E1), _ptr(lam_B1),
+                                                 _ptr(mu), _ptr(lam_E), _ptr(lam_B), C.byref(it), C.byref(rr)))
+    return it.value, rr.value
+
+
+def deposit_adjoint(ctx: Context, state: Particles, B, E_theta, mu, lam_x, lam_u, lam_B) -> None:
+    """relsim_deposit_adjoint (all three outputs accumulated into)"""
+    _f64(ctx, B, E_theta, mu, lam_x, lam_u, lam_B)
+    state.s.n = state.n
+    ctx.check(ctx.lib.relsim_deposit_adjoint(ctx.handle, C.byref(state.s), _ptr(B), _ptr(E_theta), _ptr(mu),
+                                             _ptr(lam_x), _ptr(lam_u), _ptr(lam_B)))
 
 
 def energy(ctx: Context, parts: Particles, E: torch.Tensor, B: torch.Tensor) -> np.ndarray:
