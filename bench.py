@@ -88,7 +88,7 @@ def measured_traffic(tag, kernel):
     return None if k is None else k["hbm_bytes"]
 
 
-def run_precision(prec, wl, host, steps, warmup, rtol, want_kernels=True):
+def run_precision(prec, wl, host, steps, warmup, rtol, want_kernels=True, group=0):
     import numpy as np
     import torch
 
@@ -97,7 +97,7 @@ def run_precision(prec, wl, host, steps, warmup, rtol, want_kernels=True):
     n = host["w"].shape[0]
     ctx = relsim.Context(dim=wl.dim, nx=wl.nx, ny=wl.ny, nz=wl.nz if wl.dim == 3 else 1, dx=wl.dx, dt=wl.dt,
                          precision=prec, q=wl.q, m=wl.m, max_particles=n, gmres_rtol=rtol, gmres_restart=30,
-                         gmres_maxit=5000)
+                         gmres_maxit=5000, group=group)
     parts = relsim.Particles(ctx).load(host["cell"], host["species"], host["off"], host["u"], host["w"],
                                        host["bin_start"])
     E = torch.as_tensor(host["E"]).cuda()
@@ -205,6 +205,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="harris2d_1024x512")
     ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"])
+    ap.add_argument("--group", type=int, default=0, help="lanes per cell in the particle kernels (0 = automatic)")
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--cpu-sample", type=int, default=10_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -241,7 +242,7 @@ def main():
     results = {}
     for p in precs:
         log("running %s: %d warmup + %d timed steps" % (p, args.warmup, args.steps))
-        results[p] = run_precision(p, wl, host, args.steps, args.warmup, args.rtol)
+        results[p] = run_precision(p, wl, host, args.steps, args.warmup, args.rtol, group=args.group)
         log("%s: %.4g particle-steps/s, hot %.3f ms/step, solve %.3f ms/step" % (
             p, results[p]["value"], results[p]["hot_ms_per_step"], results[p]["solve_ms_per_step"]))
 

@@ -172,6 +172,10 @@ Layout make_layout(const relsim_params *p) {
   L.gs_v0 = take(np * 4);
   L.gs_v1 = take(np * 4);
   L.gs_hist = take(gsort_tmp_elems(np) * 4);
+  L.slotmap = take(nc * 16);
+  const size_t ng = (size_t)(p->nx + 2) * (p->ny + 2) * (p->dim == 3 ? p->nz + 2 : 1);
+  L.stB = take(ng * 4 * es);
+  L.stE = take(ng * 4 * es);
   L.end = o;
   return L;
 }
@@ -186,6 +190,16 @@ KParams make_kparams(const relsim_params *p) {
   k.nspecies = p->nspecies;
   k.nbins = k.ncells * k.nspecies;
   k.nonrel = p->nonrelativistic ? 1 : 0;
+  // largest power-of-two tile extents (up to 16 x 8 in 2D, 8 x 4 x 4 in 3D)
+  // that divide the grid
+  auto tile = [](int n, int cap) {
+    int t = cap;
+    while (t > 1 && n % t != 0) t >>= 1;
+    return t;
+  };
+  k.tx = tile(k.nx, p->dim == 3 ? 8 : 16);
+  k.ty = tile(k.ny, p->dim == 3 ? 4 : 8);
+  k.tz = p->dim == 3 ? tile(k.nz, 4) : 1;
   k.dx = p->dx;
   k.dy = p->dy;
   k.dz = p->dim == 3 ? p->dz : 1.0;
@@ -196,19 +210,42 @@ KParams make_kparams(const relsim_params *p) {
   k.inv_dx = 1.0 / k.dx;
   k.inv_dy = 1.0 / k.dy;
   k.inv_dz = 1.0 / k.dz;
+  k.inv_c = 1.0 / k.c;
+  k.inv_c2 = 1.0 / (k.c * k.c);
+  k.inv_V = 1.0 / k.V;
+  k.gx = k.nx + 2;
+  k.gxy = k.gx * (k.ny + 2);
+  k.nghost = k.gxy * (p->dim == 3 ? k.nz + 2 : 1);
   for (int s = 0; s < 8; ++s) {
     k.q[s] = s < p->nspecies ? p->q[s] : 0.0;
     k.m[s] = s < p->nspecies ? p->m[s] : 1.0;
     k.beta[s] = s < p->nspecies ? p->q[s] * p->dt / (2.0 * p->m[s]) : 0.0;
+    k.f_q[s] = (float)k.q[s];
+    k.f_beta[s] = (float)k.beta[s];
   }
+  k.f_dt = (float)k.dt;
+  k.f_inv_c = (float)k.inv_c;
+  k.f_inv_c2 = (float)k.inv_c2;
+  k.f_inv_V = (float)k.inv_V;
+  k.f_inv_dx = (float)k.inv_dx;
+  k.f_inv_dy = (float)k.inv_dy;
+  k.f_inv_dz = (float)k.inv_dz;
   return k;
 }
 
-int choose_group(const relsim_ctx *c, int64_t n) {
+// Lanes per cell for a particle kernel: the largest power of two in [8, 64]
+// not above mean_occupancy / rounds, where `rounds` is the number of G-wide
+// rounds per cell the kernel wants.  The deposit amortises its per-cell
+// reduction over many rounds (16), the push over a few (4), while the
+// scatter writes whole runs per instruction (2).  Measured on the
+// 1024 x 512 Harris sheet (128 particles per cell).
+enum KernelKind { K_DEPOSIT = 16, K_PUSH = 4, K_SCATTER = 2, K_OTHER = 4 };
+
+int choose_group(const relsim_ctx *c, int64_t n, KernelKind k = K_OTHER) {
   if (c->p.group) return c->p.group;
   const double mean = (double)n / (double)c->kp.ncells;
   int g = 8;
-  while (g < 64 && 2.0 * g <= 0.5 * mean) g *= 2;
+  while (g < 64 && 2.0 * g <= mean / (double)k) g *= 2;
   return g;
 }
 
@@ -340,6 +377,13 @@ int relsim_init(const relsim_params *p, void *hip_stream, void *workspace, size_
     relsim_finalize(c);
     return RELSIM_EHIP;
   }
+  // processing order of the particle kernels: tile-major slot -> cell table
+  c->kp.slotmap = c->at<int4>(L.slotmap);
+  launch_fill_slotmap(c->kp, c->at<int4>(L.slotmap), c->st);
+  if (hipGetLastError() != hipSuccess) {
+    relsim_finalize(c);
+    return RELSIM_EHIP;
+  }
   *out = c;
   return RELSIM_OK;
 }
@@ -383,9 +427,11 @@ int relsim_deposit_moments(relsim_ctx *c, const relsim_particles *pt, const doub
   int rc = check_particles(c, pt, false);
   if (rc) return rc;
   if (!B_n || !Jhat || !M) return fail(c, RELSIM_EINVAL, "null grid array");
-  const int G = choose_group(c, pt->n);
+  const int G = choose_group(c, pt->n, K_DEPOSIT);
   void *S = c->at<char>(c->L.S);
-  timed(c, "deposit_cells", [&] { launch_deposit_cells(c->kp, c->p.precision, G, front(pt), B_n, S, c->st); });
+  void *stB = c->at<char>(c->L.stB);
+  timed(c, "stage_fields", [&] { launch_stage_field(c->kp, c->p.precision, B_n, stB, c->st); });
+  timed(c, "deposit_cells", [&] { launch_deposit_cells(c->kp, c->p.precision, G, front(pt), stB, S, c->st); });
   timed(c, "assemble_nodes", [&] { launch_assemble(c->kp, c->p.precision, S, Jhat, M, c->st); });
   return launch_status(c, "relsim_deposit_moments");
 }
@@ -396,14 +442,21 @@ int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, cons
   int rc = check_particles(c, pt, resort != 0);
   if (rc) return rc;
   if (!E_theta || !B_n) return fail(c, RELSIM_EINVAL, "null grid array");
-  const int G = choose_group(c, pt->n);
+  const int G = choose_group(c, pt->n, K_PUSH);
+  const int Gs = choose_group(c, pt->n, K_SCATTER);
   uint8_t *dirc = c->at<uint8_t>(c->L.dirc);
   uint16_t *cnt = c->at<uint16_t>(c->L.cnt);
   uint16_t *pre = c->at<uint16_t>(c->L.pre);
   int32_t *total = c->at<int32_t>(c->L.total);
   int32_t *err = c->at<int32_t>(c->L.err);
+  void *stB = c->at<char>(c->L.stB);
+  void *stE = c->at<char>(c->L.stE);
+  timed(c, "stage_fields", [&] {
+    launch_stage_field(c->kp, c->p.precision, B_n, stB, c->st);
+    launch_stage_field(c->kp, c->p.precision, E_theta, stE, c->st);
+  });
   timed(c, "push", [&] {
-    launch_push(c->kp, c->p.precision, G, front(pt), E_theta, B_n, dirc, cnt, err, resort ? 1 : 0, c->st);
+    launch_push(c->kp, c->p.precision, G, front(pt), stE, stB, dirc, cnt, err, resort ? 1 : 0, c->st);
   });
   if (resort) {
     timed(c, "sort_offsets", [&] { launch_sort_offsets(c->kp, cnt, pre, total, err, c->st); });
@@ -413,7 +466,7 @@ int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, cons
     void *offb[3] = {pt->off_back[0], pt->off_back[1], pt->off_back[2]};
     void *ub[3] = {pt->u_back[0], pt->u_back[1], pt->u_back[2]};
     timed(c, "sort_scatter", [&] {
-      launch_sort_scatter(c->kp, c->p.precision, G, front(pt), dirc, pre, pt->bin_start_back, pt->cell_back, offb, ub,
+      launch_sort_scatter(c->kp, c->p.precision, Gs, front(pt), dirc, pre, pt->bin_start_back, pt->cell_back, offb, ub,
                           pt->w_back, (int)pt->n, err, new_index, c->st);
     });
     rc = launch_status(c, "relsim_push");

@@ -7,6 +7,12 @@
 // cell's particles (both species, contiguous because particles are sorted
 // by bin = cell * nspecies + species) G at a time, so loads are coalesced
 // and every particle of a group sees the same neighbourhood of grid values.
+// Groups visit the cells tile by tile (2D tiles of up to 16 x 8 cells, 3D of
+// up to 8 x 4 x 4), so that neighbouring cells, whose particles exchange
+// places in the re-sort, are processed close together in time; workgroups
+// are remapped so that each XCD (and its L2) works on one contiguous band.
+// The next round's particle loads are issued before the current round is
+// computed.
 //
 // Deposit formulation.  For a particle with in-cell offsets f_d, the CIC
 // node weights are products of (1 - f_d) or f_d, so the weight product of an
@@ -36,12 +42,23 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-template <typename T>
-__device__ __forceinline__ T sqrt_t(T x);
-template <>
-__device__ __forceinline__ float sqrt_t<float>(float x) { return sqrtf(x); }
-template <>
-__device__ __forceinline__ double sqrt_t<double>(double x) { return sqrt(x); }
+// Cell visited by processing slot `slot` (tile-major order; the tile extents
+// divide the grid extents).
+__device__ __forceinline__ int slot_cell(const KParams &kp, int slot) {
+  const int tcell = kp.tx * kp.ty * kp.tz;
+  const int tile = slot / tcell, r = slot - tile * tcell;
+  const int ntx = kp.nx / kp.tx, nty = kp.ny / kp.ty;
+  const int tix = tile % ntx, tiy = (tile / ntx) % nty, tiz = tile / (ntx * nty);
+  const int lx = r % kp.tx, ly = (r / kp.tx) % kp.ty, lz = r / (kp.tx * kp.ty);
+  return (tix * kp.tx + lx) + kp.nx * ((tiy * kp.ty + ly) + kp.ny * (tiz * kp.tz + lz));
+}
+
+// Reciprocal and reciprocal square root: the hardware instructions (1 ulp)
+// in FP32, correctly rounded in FP64.
+__device__ __forceinline__ float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
 
 // CIC weights of the three cell centres at relative positions -1/2, 1/2,
 // 3/2 (cell units) seen from a particle at offset f in [0,1).
@@ -56,7 +73,7 @@ __device__ __forceinline__ void centre_w3(T f, T w[3]) {
 // alpha = (I - [b]x + b b^T) / (1 + |b|^2), row-major.
 template <typename T>
 __device__ __forceinline__ void make_alpha(T bx, T by, T bz, T a[9]) {
-  const T inv = T(1) / (T(1) + bx * bx + by * by + bz * bz);
+  const T inv = rcp_t(T(1) + bx * bx + by * by + bz * bz);
   a[0] = (T(1) + bx * bx) * inv;
   a[1] = (bz + bx * by) * inv;
   a[2] = (bx * bz - by) * inv;
@@ -68,37 +85,79 @@ __device__ __forceinline__ void make_alpha(T bx, T by, T bz, T a[9]) {
   a[8] = (T(1) + bz * bz) * inv;
 }
 
-// Particle-side view of the kernel constants in the arithmetic type T.
+// Particle-side view of the kernel constants in the arithmetic type T
+// (precomputed on the host: no divisions or conversions in the kernels).
 template <typename T>
-struct PC {
-  T dt, invc, invc2, invV, idx, idy, idz;
+struct PC;
+template <>
+struct PC<float> {
+  float dt, invc, invc2, invV, idx, idy, idz;
+  const float *q, *beta;
   __device__ explicit PC(const KParams &kp)
-      : dt(T(kp.dt)), invc(T(1.0 / kp.c)), invc2(T(1.0 / (kp.c * kp.c))), invV(T(1.0 / kp.V)),
-        idx(T(kp.inv_dx)), idy(T(kp.inv_dy)), idz(T(kp.inv_dz)) {}
+      : dt(kp.f_dt), invc(kp.f_inv_c), invc2(kp.f_inv_c2), invV(kp.f_inv_V), idx(kp.f_inv_dx), idy(kp.f_inv_dy),
+        idz(kp.f_inv_dz), q(kp.f_q), beta(kp.f_beta) {}
+};
+template <>
+struct PC<double> {
+  double dt, invc, invc2, invV, idx, idy, idz;
+  const double *q, *beta;
+  __device__ explicit PC(const KParams &kp)
+      : dt(kp.dt), invc(kp.inv_c), invc2(kp.inv_c2), invV(kp.inv_V), idx(kp.inv_dx), idy(kp.inv_dy),
+        idz(kp.inv_dz), q(kp.q), beta(kp.beta) {}
 };
 
-// Block of 3x3 (2D) cell-centre B values around cell (ci, cj) in registers.
+// One point of a ghosted field copy: three components and a pad.
 template <typename T>
-__device__ __forceinline__ void load_B_block_2d(const KParams &kp, const double *__restrict__ B, int ci, int cj,
+struct alignas(4 * sizeof(T)) V4 {
+  T x, y, z, w;
+};
+
+// Ghosted copy of a SoA FP64 grid field (one thread per ghosted point).
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_stage_field(KParams kp, const double *__restrict__ F,
+                                                     V4<T> *__restrict__ out) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  if (g >= kp.nghost) return;
+  const int gi = g % kp.gx, gj = (g / kp.gx) % (kp.ny + 2);
+  const int i = wrapi(gi - 1, kp.nx), j = wrapi(gj - 1, kp.ny);
+  const int k = DIM == 3 ? wrapi(g / kp.gxy - 1, kp.nz) : 0;
+  const size_t N = (size_t)kp.ncells, id = (size_t)i + (size_t)kp.nx * ((size_t)j + (size_t)kp.ny * k);
+  V4<T> v;
+  v.x = (T)F[id];
+  v.y = (T)F[N + id];
+  v.z = (T)F[2 * N + id];
+  v.w = T(0);
+  out[g] = v;
+}
+
+// Index of grid point (i, j, k) in a ghosted copy, i in [-1, nx] etc.
+template <int DIM>
+__device__ __forceinline__ int gidx(const KParams &kp, int i, int j, int k) {
+  return (i + 1) + kp.gx * (j + 1) + (DIM == 3 ? kp.gxy * (k + 1) : 0);
+}
+
+// Block of 3x3 (2D) cell-centre B values around the cell with ghosted index
+// gc in registers.
+template <typename T>
+__device__ __forceinline__ void load_B_block_2d(const KParams &kp, const V4<T> *__restrict__ Bs, int gc,
                                                 T Bc[3][9]) {
-  const size_t N = (size_t)kp.ncells;
 #pragma unroll
   for (int t = 0; t < 9; ++t) {
-    const int ii = wrapi(ci + (t % 3) - 1, kp.nx);
-    const int jj = wrapi(cj + (t / 3) - 1, kp.ny);
-    const size_t id = (size_t)ii + (size_t)kp.nx * jj;
-    Bc[0][t] = (T)B[id];
-    Bc[1][t] = (T)B[N + id];
-    Bc[2][t] = (T)B[2 * N + id];
+    const V4<T> b = Bs[gc + (t % 3 - 1) + kp.gx * (t / 3 - 1)];
+    Bc[0][t] = b.x;
+    Bc[1][t] = b.y;
+    Bc[2][t] = b.z;
   }
 }
 
-// B at the particle: 2D from the register block, 3D by a direct 8-centre
-// gather (the 27-centre block would not fit the register budget in FP64).
-template <typename T, int DIM>
-__device__ __forceinline__ void gather_B(const KParams &kp, const double *__restrict__ B, const T (&Bc)[3][9], int ci,
-                                         int cj, int ck, T fx, T fy, T fz, T &Bx, T &By, T &Bz) {
-  if constexpr (DIM == 2) {
+// B at the particle.  With BLK (2D only) from the 3x3 register block of the
+// cell; otherwise by a direct gather of the 2^DIM centres around the
+// particle from the ghosted copy (lower corner at shift -1 or 0 per
+// dimension).
+template <typename T, int DIM, bool BLK>
+__device__ __forceinline__ void gather_B(const KParams &kp, const V4<T> *__restrict__ Bs, const T (&Bc)[3][9],
+                                         int gc, T fx, T fy, T fz, T &Bx, T &By, T &Bz) {
+  if constexpr (DIM == 2 && BLK) {
     T wx[3], wy[3];
     centre_w3(fx, wx);
     centre_w3(fy, wy);
@@ -111,24 +170,21 @@ __device__ __forceinline__ void gather_B(const KParams &kp, const double *__rest
       Bz += wt * Bc[2][t];
     }
   } else {
-    const size_t N = (size_t)kp.ncells;
-    const bool hx = fx >= T(0.5), hy = fy >= T(0.5), hz = fz >= T(0.5);
-    const int ix = hx ? ci : ci - 1, iy = hy ? cj : cj - 1, iz = hz ? ck : ck - 1;
+    constexpr int NCEN = DIM == 3 ? 8 : 4;
+    const bool hx = fx >= T(0.5), hy = fy >= T(0.5), hz = DIM == 3 && fz >= T(0.5);
+    const int g0 = gc - (hx ? 0 : 1) - (hy ? 0 : kp.gx) - ((DIM == 2 || hz) ? 0 : kp.gxy);
     const T gx = hx ? fx - T(0.5) : fx + T(0.5);
     const T gy = hy ? fy - T(0.5) : fy + T(0.5);
     const T gz = hz ? fz - T(0.5) : fz + T(0.5);
-    const int x0 = wrapi(ix, kp.nx), x1 = wrapi(ix + 1, kp.nx);
-    const int y0 = wrapi(iy, kp.ny), y1 = wrapi(iy + 1, kp.ny);
-    const int z0 = wrapi(iz, kp.nz), z1 = wrapi(iz + 1, kp.nz);
     Bx = By = Bz = T(0);
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      const int xx = (a & 1) ? x1 : x0, yy = (a & 2) ? y1 : y0, zz = (a & 4) ? z1 : z0;
-      const T wt = ((a & 1) ? gx : T(1) - gx) * ((a & 2) ? gy : T(1) - gy) * ((a & 4) ? gz : T(1) - gz);
-      const size_t id = (size_t)xx + (size_t)kp.nx * ((size_t)yy + (size_t)kp.ny * zz);
-      Bx += wt * (T)B[id];
-      By += wt * (T)B[N + id];
-      Bz += wt * (T)B[2 * N + id];
+    for (int a = 0; a < NCEN; ++a) {
+      const V4<T> b = Bs[g0 + (a & 1) + ((a & 2) ? kp.gx : 0) + ((a & 4) ? kp.gxy : 0)];
+      T wt = ((a & 1) ? gx : T(1) - gx) * ((a & 2) ? gy : T(1) - gy);
+      if constexpr (DIM == 3) wt *= (a & 4) ? gz : T(1) - gz;
+      Bx += wt * b.x;
+      By += wt * b.y;
+      Bz += wt * b.z;
     }
   }
 }
@@ -136,23 +192,60 @@ __device__ __forceinline__ void gather_B(const KParams &kp, const double *__rest
 // Per-lane cell bookkeeping shared by the particle kernels.
 struct CellSpan {
   int cell, ci, cj, ck, pbeg, pend;
-  int bound[8];  // first particle of species s (INT_MAX beyond nspecies)
+  int gc;        // ghosted field index of the cell's lower node / its centre
+  int bound[8];  // first particle of species s (the cell's end for s >= nspecies)
   bool valid;
 };
 
-__device__ __forceinline__ CellSpan cell_span(const KParams &kp, const int32_t *__restrict__ bin_start, int cell) {
+__device__ __forceinline__ CellSpan cell_span(const KParams &kp, const int32_t *__restrict__ bin_start, int cell,
+                                              bool valid) {
   CellSpan cs;
-  cs.valid = cell < kp.ncells;
-  cs.cell = cs.valid ? cell : 0;
+  cs.valid = valid;
+  cs.cell = valid ? cell : 0;
   cs.ci = cs.cell % kp.nx;
   cs.cj = (cs.cell / kp.nx) % kp.ny;
   cs.ck = cs.cell / (kp.nx * kp.ny);
-  const int S = kp.nspecies;
-  cs.pbeg = cs.valid ? bin_start[cs.cell * S] : 0;
-  cs.pend = cs.valid ? bin_start[cs.cell * S + S] : 0;
+  cs.gc = (cs.ci + 1) + kp.gx * (cs.cj + 1) + kp.gxy * (kp.dim == 3 ? cs.ck + 1 : 0);
+  const int S = kp.nspecies, b0 = cs.cell * S;
 #pragma unroll
-  for (int s = 0; s < 8; ++s) cs.bound[s] = (cs.valid && s < S) ? bin_start[cs.cell * S + s] : INT_MAX;
+  for (int s = 0; s < 8; ++s) cs.bound[s] = valid ? bin_start[b0 + (s < S ? s : S)] : 0;
+  cs.pbeg = cs.bound[0];
+  cs.pend = valid ? bin_start[b0 + S] : 0;
   return cs;
+}
+
+__device__ __forceinline__ CellSpan cell_span(const KParams &kp, const int32_t *__restrict__ bin_start, int cell) {
+  return cell_span(kp, bin_start, cell, cell < kp.ncells);
+}
+
+// The cell of processing slot blk * (64/G) + grp, from the precomputed slot
+// table {cell, i, j, k} (no integer division in the kernels).
+template <int G>
+__device__ __forceinline__ CellSpan slot_span(const KParams &kp, const int32_t *__restrict__ bin_start, int blk,
+                                              int grp) {
+  const int slot = blk * (64 / G) + grp;
+  const bool valid = slot < kp.ncells;
+  const int4 c = kp.slotmap[valid ? slot : 0];
+  CellSpan cs;
+  cs.valid = valid;
+  cs.cell = c.x;
+  cs.ci = c.y;
+  cs.cj = c.z;
+  cs.ck = c.w;
+  cs.gc = (cs.ci + 1) + kp.gx * (cs.cj + 1) + kp.gxy * (kp.dim == 3 ? cs.ck + 1 : 0);
+  const int S = kp.nspecies, b0 = cs.cell * S;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) cs.bound[s] = valid ? bin_start[b0 + (s < S ? s : S)] : 0;
+  cs.pbeg = cs.bound[0];
+  cs.pend = valid ? bin_start[b0 + S] : 0;
+  return cs;
+}
+
+__global__ __launch_bounds__(256) void k_fill_slotmap(KParams kp, int4 *__restrict__ map) {
+  const int slot = blockIdx.x * 256 + threadIdx.x;
+  if (slot >= kp.ncells) return;
+  const int c = slot_cell(kp, slot);
+  map[slot] = make_int4(c, c % kp.nx, (c / kp.nx) % kp.ny, c / (kp.nx * kp.ny));
 }
 
 // Wave-uniform number of rounds: max over the wave of ceil(count / G).
@@ -164,42 +257,76 @@ __device__ __forceinline__ int wave_rounds(int count) {
   return r;
 }
 
+// Species of particle p of the cell (particles of a cell are ordered by
+// species), with its charge and beta.
 template <typename T>
-__device__ __forceinline__ int species_of(const KParams &kp, const CellSpan &cs, int p, T &q, T &beta) {
+__device__ __forceinline__ int species_of(const KParams &kp, const PC<T> &pc, const CellSpan &cs, int p, T &q,
+                                         T &beta) {
+  if (kp.nspecies == 2) {
+    const bool s1 = p >= cs.bound[1];
+    q = s1 ? pc.q[1] : pc.q[0];
+    beta = s1 ? pc.beta[1] : pc.beta[0];
+    return s1 ? 1 : 0;
+  }
   int s = 0;
-  q = (T)kp.q[0];
-  beta = (T)kp.beta[0];
+  q = pc.q[0];
+  beta = pc.beta[0];
 #pragma unroll
   for (int s2 = 1; s2 < 8; ++s2)
     if (p >= cs.bound[s2]) {
       s = s2;
-      q = (T)kp.q[s2];
-      beta = (T)kp.beta[s2];
+      q = pc.q[s2];
+      beta = pc.beta[s2];
     }
   return s;
+}
+
+// One particle's state as loaded from the SoA arrays.
+template <typename T>
+struct PRec {
+  T fx, fy, fz, ux, uy, uz, w;
+};
+
+template <typename T, int DIM, bool WITH_W>
+__device__ __forceinline__ void load_rec(int p, int pend, const T *__restrict__ o0, const T *__restrict__ o1,
+                                         const T *__restrict__ o2, const T *__restrict__ u0,
+                                         const T *__restrict__ u1, const T *__restrict__ u2,
+                                         const T *__restrict__ wt, PRec<T> &r) {
+  if (p < pend) {
+    r.fx = o0[p];
+    r.fy = o1[p];
+    if constexpr (DIM == 3) r.fz = o2[p];
+    r.ux = u0[p];
+    r.uy = u1[p];
+    r.uz = u2[p];
+    if constexpr (WITH_W) r.w = wt[p];
+  }
 }
 
 // ---------------------------------------------------------------------------
 // S1-S3: per-cell moments
 // ---------------------------------------------------------------------------
 template <typename T, int DIM, int G>
-__global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t *__restrict__ bin_start,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_deposit_cells(KParams kp, const int32_t *__restrict__ bin_start,
                                                       const T *__restrict__ o0, const T *__restrict__ o1,
                                                       const T *__restrict__ o2, const T *__restrict__ u0,
                                                       const T *__restrict__ u1, const T *__restrict__ u2,
-                                                      const T *__restrict__ wt, const double *__restrict__ B,
+                                                      const T *__restrict__ wt, const V4<T> *__restrict__ Bs,
                                                       T *__restrict__ S) {
   constexpr int NACC = 93;  // 81 mass moments + 12 current moments per pass
   constexpr int NPASS = DIM == 3 ? 3 : 1;
-  __shared__ T red[64 * NACC];
+  constexpr int CH = 32;    // moments per LDS transpose chunk (keeps LDS off the occupancy limit)
+  // FP32 keeps the cell's 3x3 B block in registers; FP64 gathers per particle
+  constexpr bool BLK = DIM == 2 && sizeof(T) == 4;
+  __shared__ T red[64 * (CH + 1)];
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const CellSpan cs = cell_span(kp, bin_start, blk * (64 / G) + grp);
+  const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
   const PC<T> pc(kp);
   const size_t NC = (size_t)kp.ncells;
 
   T Bc[3][9];
-  if constexpr (DIM == 2) load_B_block_2d<T>(kp, B, cs.ci, cs.cj, Bc);
+  if constexpr (BLK) load_B_block_2d<T>(kp, Bs, cs.gc, Bc);
   const int rounds = wave_rounds<G>(cs.pend - cs.pbeg);
 
 #pragma unroll 1
@@ -207,24 +334,26 @@ __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t 
     T acc[NACC];
 #pragma unroll
     for (int k = 0; k < NACC; ++k) acc[k] = T(0);
+    PRec<T> cur{}, nxt{};
+    int p = cs.pbeg + gl;
+    load_rec<T, DIM, true>(p, cs.pend, o0, o1, o2, u0, u1, u2, wt, cur);
 #pragma unroll 1
     for (int r = 0; r < rounds; ++r) {
-      const int p = cs.pbeg + gl + r * G;
+      const int pn = p + G;
+      load_rec<T, DIM, true>(pn, cs.pend, o0, o1, o2, u0, u1, u2, wt, nxt);
       if (p < cs.pend) {
-        const T fx = o0[p], fy = o1[p];
-        const T fz = DIM == 3 ? o2[p] : T(0);
-        const T ux = u0[p], uy = u1[p], uz = u2[p], wp = wt[p];
+        const T fx = cur.fx, fy = cur.fy, fz = DIM == 3 ? cur.fz : T(0);
+        const T ux = cur.ux, uy = cur.uy, uz = cur.uz, wp = cur.w;
         T qs, bs;
-        species_of<T>(kp, cs, p, qs, bs);
+        species_of<T>(kp, pc, cs, p, qs, bs);
         T Bx, By, Bz;
-        gather_B<T, DIM>(kp, B, Bc, cs.ci, cs.cj, cs.ck, fx, fy, fz, Bx, By, Bz);
-        const T gb = kp.nonrel ? T(1) : sqrt_t<T>(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
-        const T igb = T(1) / gb;
+        gather_B<T, DIM, BLK>(kp, Bs, Bc, cs.gc, fx, fy, fz, Bx, By, Bz);
+        const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
         const T kb = bs * igb * pc.invc;
         T a[9];
         make_alpha<T>(kb * Bx, kb * By, kb * Bz, a);
-        const T cM = wp * qs * bs * igb * pc.invV;
-        const T cJ = wp * qs * pc.invV * igb;
+        const T cJ = wp * qs * igb * pc.invV;
+        const T cM = cJ * bs;
         T psiM[9], psiJ[3];
 #pragma unroll
         for (int k = 0; k < 9; ++k) psiM[k] = cM * a[k];
@@ -254,22 +383,33 @@ __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t 
           }
         }
       }
+      cur = nxt;
+      p = pn;
     }
-    // group reduction: registers -> LDS transpose -> G-term sums in fixed order
-#pragma unroll
-    for (int k = 0; k < NACC; ++k) red[lane * NACC + k] = acc[k];
-    __syncthreads();
+    // group reduction, CH moments at a time: registers -> LDS transpose ->
+    // G-term sums in fixed lane order
     const int nk = (DIM == 3 && pass == 2) ? 81 : NACC;
-    for (int k = gl; k < nk; k += G) {
-      T s = T(0);
+#pragma unroll
+    for (int c0 = 0; c0 < NACC; c0 += CH) {
+      if (c0 < nk) {
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+          if (c0 + k < NACC) red[lane * (CH + 1) + k] = acc[c0 + k];
+        __syncthreads();
+        const int kend = nk - c0 < CH ? nk - c0 : CH;
+        for (int k = gl; k < kend; k += G) {
+          T s = T(0);
 #pragma unroll 8
-      for (int j = 0; j < G; ++j) s += red[(grp * G + j) * NACC + k];
-      if (cs.valid) {
-        const int sidx = DIM == 3 ? (k < 81 ? pass * 81 + k : 243 + pass * 12 + (k - 81)) : k;
-        S[(size_t)sidx * NC + cs.cell] = s;
+          for (int j = 0; j < G; ++j) s += red[(grp * G + j) * (CH + 1) + k];
+          if (cs.valid) {
+            const int m = c0 + k;
+            const int sidx = DIM == 3 ? (m < 81 ? pass * 81 + m : 243 + pass * 12 + (m - 81)) : m;
+            S[(size_t)sidx * NC + cs.cell] = s;
+          }
+        }
+        __syncthreads();
       }
     }
-    __syncthreads();
   }
 }
 
@@ -358,8 +498,8 @@ __device__ __forceinline__ int cross_cell(T &f, int32_t *err) {
 template <typename T, int DIM, int G>
 __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restrict__ bin_start, T *__restrict__ o0,
                                              T *__restrict__ o1, T *__restrict__ o2, T *__restrict__ u0,
-                                             T *__restrict__ u1, T *__restrict__ u2, const double *__restrict__ Eth,
-                                             const double *__restrict__ B, uint8_t *__restrict__ dirc,
+                                             T *__restrict__ u1, T *__restrict__ u2, const V4<T> *__restrict__ Es,
+                                             const V4<T> *__restrict__ Bs, uint8_t *__restrict__ dirc,
                                              uint16_t *__restrict__ cnt, int32_t *__restrict__ err, int count_moves) {
   constexpr int NDIR = DIM == 3 ? 27 : 9;
   constexpr int NK = 8 * NDIR;  // (species, move) keys per group
@@ -367,53 +507,44 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
   __shared__ uint32_t lcnt[NGRP * NK];
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const CellSpan cs = cell_span(kp, bin_start, blk * NGRP + grp);
+  const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
   const PC<T> pc(kp);
-  const size_t N = (size_t)kp.ncells;
   if (count_moves) {
     for (int t = lane; t < NGRP * NK; t += 64) lcnt[t] = 0u;
     __syncthreads();
-    if (cs.valid && gl == 0) {
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const int hi = (s + 1 < 8 && cs.bound[s + 1] < INT_MAX) ? cs.bound[(s + 1) & 7] : cs.pend;
-        if (cs.bound[s] < INT_MAX && hi - cs.bound[s] > 65535) atomicOr(err, 2);
-      }
-    }
   }
 
   T Bc[3][9];
-  if constexpr (DIM == 2) load_B_block_2d<T>(kp, B, cs.ci, cs.cj, Bc);
+  if constexpr (DIM == 2) load_B_block_2d<T>(kp, Bs, cs.gc, Bc);
   // E_theta at the 2^DIM corner nodes of the cell
   constexpr int NCORN = DIM == 3 ? 8 : 4;
   T Ec[3][NCORN];
 #pragma unroll
   for (int a = 0; a < NCORN; ++a) {
-    const int ii = wrapi(cs.ci + (a & 1), kp.nx);
-    const int jj = wrapi(cs.cj + ((a >> 1) & 1), kp.ny);
-    const int kk = DIM == 3 ? wrapi(cs.ck + ((a >> 2) & 1), kp.nz) : 0;
-    const size_t id = (size_t)ii + (size_t)kp.nx * ((size_t)jj + (size_t)kp.ny * kk);
-    Ec[0][a] = (T)Eth[id];
-    Ec[1][a] = (T)Eth[N + id];
-    Ec[2][a] = (T)Eth[2 * N + id];
+    const V4<T> e = Es[cs.gc + (a & 1) + ((a & 2) ? kp.gx : 0) + ((a & 4) ? kp.gxy : 0)];
+    Ec[0][a] = e.x;
+    Ec[1][a] = e.y;
+    Ec[2][a] = e.z;
   }
   const int rounds = wave_rounds<G>(cs.pend - cs.pbeg);
+  PRec<T> cur{}, nxt{};
+  int p = cs.pbeg + gl;
+  load_rec<T, DIM, false>(p, cs.pend, o0, o1, o2, u0, u1, u2, nullptr, cur);
 
 #pragma unroll 1
   for (int r = 0; r < rounds; ++r) {
-    const int p = cs.pbeg + gl + r * G;
-    const bool pv = p < cs.pend;
-    int key = 0;
-    if (pv) {
-      T fx = o0[p], fy = o1[p];
-      T fz = DIM == 3 ? o2[p] : T(0);
-      const T ux = u0[p], uy = u1[p], uz = u2[p];
+    const int pn = p + G;
+    load_rec<T, DIM, false>(pn, cs.pend, o0, o1, o2, u0, u1, u2, nullptr, nxt);
+    if (p < cs.pend) {
+      T fx = cur.fx, fy = cur.fy;
+      T fz = DIM == 3 ? cur.fz : T(0);
+      const T ux = cur.ux, uy = cur.uy, uz = cur.uz;
       T qs, bs;
-      const int s = species_of<T>(kp, cs, p, qs, bs);
+      const int s = species_of<T>(kp, pc, cs, p, qs, bs);
       T Bx, By, Bz;
-      gather_B<T, DIM>(kp, B, Bc, cs.ci, cs.cj, cs.ck, fx, fy, fz, Bx, By, Bz);
-      const T gb = kp.nonrel ? T(1) : sqrt_t<T>(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
-      const T kb = bs / gb * pc.invc;
+      gather_B<T, DIM, true>(kp, Bs, Bc, cs.gc, fx, fy, fz, Bx, By, Bz);
+      const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
+      const T kb = bs * igb * pc.invc;
       T a[9];
       make_alpha<T>(kb * Bx, kb * By, kb * Bz, a);
       T Ex = T(0), Ey = T(0), Ez = T(0);
@@ -430,8 +561,8 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
       const T uby = a[3] * vx + a[4] * vy + a[5] * vz;
       const T ubz = a[6] * vx + a[7] * vy + a[8] * vz;
       const T nx = T(2) * ubx - ux, ny = T(2) * uby - uy, nz = T(2) * ubz - uz;
-      const T gn = kp.nonrel ? T(1) : sqrt_t<T>(T(1) + (nx * nx + ny * ny + nz * nz) * pc.invc2);
-      const T dtg = pc.dt / gn;
+      const T ign = kp.nonrel ? T(1) : rsqrt_t(T(1) + (nx * nx + ny * ny + nz * nz) * pc.invc2);
+      const T dtg = pc.dt * ign;
       fx += dtg * nx * pc.idx;
       fy += dtg * ny * pc.idy;
       if constexpr (DIM == 3) fz += dtg * nz * pc.idz;
@@ -452,21 +583,14 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
       u0[p] = nx;
       u1[p] = ny;
       u2[p] = nz;
-      const int dir = (mx + 1) + 3 * (my + 1) + (DIM == 3 ? 9 * (mz + 1) : 0);
-      if (count_moves) dirc[p] = (uint8_t)dir;
-      key = grp * NK + s * NDIR + dir;
-    }
-    if (count_moves) {
-      // wave-level aggregation of identical (group, species, move) keys
-      unsigned long long active = __ballot(pv);
-      while (active) {
-        const int leader = __ffsll((long long)active) - 1;
-        const int lk = __builtin_amdgcn_readlane(key, leader);
-        const unsigned long long m = __ballot(pv && key == lk);
-        if (lane == leader) lcnt[lk] += (uint32_t)__popcll(m);
-        active &= ~m;
+      if (count_moves) {
+        const int dir = (mx + 1) + 3 * (my + 1) + (DIM == 3 ? 9 * (mz + 1) : 0);
+        dirc[p] = (uint8_t)dir;
+        atomicAdd(&lcnt[grp * NK + s * NDIR + dir], 1u);  // integer: order-independent
       }
     }
+    cur = nxt;
+    p = pn;
   }
   if (count_moves) {
     __syncthreads();
@@ -475,6 +599,7 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
       for (int t = gl; t < S * NDIR; t += G) {
         const int s = t / NDIR, dir = t % NDIR;
         const uint32_t v = lcnt[grp * NK + s * NDIR + dir];
+        if (v > 65535u) atomicOr(err, 2);  // a move class beyond the 16-bit counters
         cnt[(size_t)dir * kp.nbins + (size_t)cs.cell * S + s] = (uint16_t)(v > 65535u ? 65535u : v);
       }
     }
@@ -541,41 +666,54 @@ __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *
   constexpr int NDIR = DIM == 3 ? 27 : 9;
   constexpr int NK = 8 * NDIR;
   constexpr int NGRP = 64 / G;
+  // bits of the key grp * NK + species * NDIR + move
+  constexpr int KBITS = NGRP * NK <= 256 ? 8 : (NGRP * NK <= 512 ? 9 : (NGRP * NK <= 1024 ? 10 : 11));
   __shared__ uint32_t lbase[NGRP * NK];
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const CellSpan cs = cell_span(kp, bin_start, blk * NGRP + grp);
+  const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
   for (int t = lane; t < NGRP * NK; t += 64) lbase[t] = 0u;
   __syncthreads();
   const int S = kp.nspecies;
   const size_t nb = (size_t)kp.nbins;
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int rounds = wave_rounds<G>(cs.pend - cs.pbeg);
+  PRec<T> cur{}, nxt{};
+  int p = cs.pbeg + gl;
+  int dcur = 0, dnxt = 0;
+  load_rec<T, DIM, true>(p, cs.pend, o0, o1, o2, u0, u1, u2, wt, cur);
+  if (p < cs.pend) dcur = dirc[p];
 #pragma unroll 1
   for (int r = 0; r < rounds; ++r) {
-    const int p = cs.pbeg + gl + r * G;
+    const int pn = p + G;
+    load_rec<T, DIM, true>(pn, cs.pend, o0, o1, o2, u0, u1, u2, wt, nxt);
+    if (pn < cs.pend) dnxt = dirc[pn];
     const bool pv = p < cs.pend;
-    int key = 0, dir = 0, s = 0;
+    int s = 0;
     if (pv) {
-      dir = dirc[p];
+      if (S == 2) {
+        s = p >= cs.bound[1] ? 1 : 0;
+      } else {
 #pragma unroll
-      for (int s2 = 1; s2 < 8; ++s2)
-        if (p >= cs.bound[s2]) s = s2;
-      key = grp * NK + s * NDIR + dir;
+        for (int s2 = 1; s2 < 8; ++s2)
+          if (p >= cs.bound[s2]) s = s2;
+      }
+    }
+    const int key = grp * NK + s * NDIR + dcur;
+    // lanes of the wave holding the same key, from one ballot per key bit
+    unsigned long long same = __ballot(pv);
+#pragma unroll
+    for (int b = 0; b < KBITS; ++b) {
+      const unsigned long long ones = __ballot(pv && ((key >> b) & 1));
+      same &= ((key >> b) & 1) ? ones : ~ones;
     }
     int rank = 0;
-    unsigned long long active = __ballot(pv);
-    while (active) {
-      const int leader = __ffsll((long long)active) - 1;
-      const int lk = __builtin_amdgcn_readlane(key, leader);
-      const bool mine = pv && key == lk;
-      const unsigned long long m = __ballot(mine);
-      if (mine) rank = (int)lbase[lk] + __popcll(m & lt);
-      __builtin_amdgcn_wave_barrier();
-      if (lane == leader) lbase[lk] += (uint32_t)__popcll(m);
-      active &= ~m;
-    }
+    if (pv) rank = (int)lbase[key] + __popcll(same & lt);
+    __builtin_amdgcn_wave_barrier();
+    // the highest lane of each key advances that key's running count
+    if (pv && (same >> lane) == 1ull) lbase[key] += (uint32_t)__popcll(same);
     if (pv) {
+      const int dir = dcur;
       const int mx = dir % 3 - 1, my = (dir / 3) % 3 - 1, mz = dir / 9 - 1;
       const int dc = wrapi(cs.ci + mx, kp.nx) +
                      kp.nx * (wrapi(cs.cj + my, kp.ny) + kp.ny * (DIM == 3 ? wrapi(cs.ck + mz, kp.nz) : 0));
@@ -584,18 +722,22 @@ __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *
       if (pos < 0 || pos >= ntot) {
         // only reachable when a bin overflowed the 16-bit counters (flagged)
         atomicOr(err, 2);
-        continue;
+      } else {
+        q0[pos] = cur.fx;
+        q1[pos] = cur.fy;
+        if constexpr (DIM == 3) q2[pos] = cur.fz;
+        v0[pos] = cur.ux;
+        v1[pos] = cur.uy;
+        v2[pos] = cur.uz;
+        wo[pos] = cur.w;
+        cell_out[pos] = dc;
+        if (perm) perm[p] = pos;
       }
-      q0[pos] = o0[p];
-      q1[pos] = o1[p];
-      if constexpr (DIM == 3) q2[pos] = o2[p];
-      v0[pos] = u0[p];
-      v1[pos] = u1[p];
-      v2[pos] = u2[p];
-      wo[pos] = wt[p];
-      cell_out[pos] = dc;
-      if (perm) perm[p] = pos;
     }
+    __builtin_amdgcn_wave_barrier();
+    cur = nxt;
+    dcur = dnxt;
+    p = pn;
   }
 }
 
@@ -717,20 +859,20 @@ T *mp(void *p) {
 }
 
 template <typename T, int DIM, int G>
-void deposit_impl(const KParams &kp, const PartPtrs &pp, const double *B, void *S, hipStream_t st) {
+void deposit_impl(const KParams &kp, const PartPtrs &pp, const void *Bst, void *S, hipStream_t st) {
   const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
   hipLaunchKernelGGL((k_deposit_cells<T, DIM, G>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, cp<T>(pp.off[0]),
                      cp<T>(pp.off[1]), cp<T>(pp.off[2]), cp<T>(pp.u[0]), cp<T>(pp.u[1]), cp<T>(pp.u[2]), cp<T>(pp.w),
-                     B, mp<T>(S));
+                     cp<V4<T>>(Bst), mp<T>(S));
 }
 
 template <typename T, int DIM, int G>
-void push_impl(const KParams &kp, const PartPtrs &pp, const double *Eth, const double *B, uint8_t *dirc,
+void push_impl(const KParams &kp, const PartPtrs &pp, const void *Est, const void *Bst, uint8_t *dirc,
                uint16_t *cnt, int32_t *err, int count_moves, hipStream_t st) {
   const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
   hipLaunchKernelGGL((k_push<T, DIM, G>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, mp<T>(pp.off[0]),
-                     mp<T>(pp.off[1]), mp<T>(pp.off[2]), mp<T>(pp.u[0]), mp<T>(pp.u[1]), mp<T>(pp.u[2]), Eth, B, dirc,
-                     cnt, err, count_moves);
+                     mp<T>(pp.off[1]), mp<T>(pp.off[2]), mp<T>(pp.u[0]), mp<T>(pp.u[1]), mp<T>(pp.u[2]),
+                     cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, cnt, err, count_moves);
 }
 
 template <typename T, int DIM, int G>
@@ -788,9 +930,28 @@ struct KineticF {
 
 }  // namespace
 
-void launch_deposit_cells(const KParams &kp, int prec, int group, const PartPtrs &pp, const double *B, void *S,
+void launch_stage_field(const KParams &kp, int prec, const double *F, void *out, hipStream_t st) {
+  const int nblk = (kp.nghost + 255) / 256;
+  if (prec == RELSIM_MIXED) {
+    if (kp.dim == 2)
+      hipLaunchKernelGGL((k_stage_field<float, 2>), dim3(nblk), dim3(256), 0, st, kp, F, mp<V4<float>>(out));
+    else
+      hipLaunchKernelGGL((k_stage_field<float, 3>), dim3(nblk), dim3(256), 0, st, kp, F, mp<V4<float>>(out));
+  } else {
+    if (kp.dim == 2)
+      hipLaunchKernelGGL((k_stage_field<double, 2>), dim3(nblk), dim3(256), 0, st, kp, F, mp<V4<double>>(out));
+    else
+      hipLaunchKernelGGL((k_stage_field<double, 3>), dim3(nblk), dim3(256), 0, st, kp, F, mp<V4<double>>(out));
+  }
+}
+
+void launch_deposit_cells(const KParams &kp, int prec, int group, const PartPtrs &pp, const void *Bst, void *S,
                           hipStream_t st) {
-  dispatch<DepositF>(prec, kp.dim, group, kp, pp, B, S, st);
+  dispatch<DepositF>(prec, kp.dim, group, kp, pp, Bst, S, st);
+}
+
+void launch_fill_slotmap(const KParams &kp, int4 *map, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_slotmap, dim3((kp.ncells + 255) / 256), dim3(256), 0, st, kp, map);
 }
 
 void launch_assemble(const KParams &kp, int prec, const void *S, double *J, double *M, hipStream_t st) {
@@ -808,9 +969,9 @@ void launch_assemble(const KParams &kp, int prec, const void *S, double *J, doub
   }
 }
 
-void launch_push(const KParams &kp, int prec, int group, const PartPtrs &pp, const double *Eth, const double *B,
+void launch_push(const KParams &kp, int prec, int group, const PartPtrs &pp, const void *Est, const void *Bst,
                  uint8_t *dirc, uint16_t *cnt, int32_t *err, int count_moves, hipStream_t st) {
-  dispatch<PushF>(prec, kp.dim, group, kp, pp, Eth, B, dirc, cnt, err, count_moves, st);
+  dispatch<PushF>(prec, kp.dim, group, kp, pp, Est, Bst, dirc, cnt, err, count_moves, st);
 }
 
 void launch_sort_offsets(const KParams &kp, const uint16_t *cnt, uint16_t *pre, int32_t *total, int32_t *err,

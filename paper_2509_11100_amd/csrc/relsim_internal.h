@@ -14,15 +14,22 @@ namespace relsim {
 // Constants handed to every particle/grid kernel by value.
 struct KParams {
   int dim, nx, ny, nz, ncells, nspecies, nbins, nonrel;
+  int tx, ty, tz;  // tile extents of the particle kernels' cell order (divide nx, ny, nz)
+  int gx, gxy;     // strides of the ghosted field copies: nx + 2, (nx + 2)(ny + 2)
+  int nghost;      // points of a ghosted field copy
+  const int4 *slotmap;  // [ncells] {cell, i, j, k} of each processing slot (workspace)
   double dx, dy, dz, dt, c, theta, V;
-  double inv_dx, inv_dy, inv_dz;
+  double inv_dx, inv_dy, inv_dz, inv_c, inv_c2, inv_V;
   double q[8], m[8], beta[8];
+  // the same constants rounded to FP32 once on the host (mixed precision)
+  float f_dt, f_inv_c, f_inv_c2, f_inv_V, f_inv_dx, f_inv_dy, f_inv_dz;
+  float f_q[8], f_beta[8];
 };
 
 // Offsets (in bytes) of the regions carved out of the caller's workspace.
 struct Layout {
   size_t S, cnt, pre, total, scan_tmp, dirc, err, gm_V, gm_t, gm_b, gm_r, gm_part, gm_small, red_part;
-  size_t gs_k0, gs_k1, gs_v0, gs_v1, gs_hist, end;
+  size_t gs_k0, gs_k1, gs_v0, gs_v1, gs_hist, slotmap, stB, stE, end;
 };
 
 constexpr int kMaxRestart = 64;
@@ -42,10 +49,15 @@ struct PartPtrs {
   void *w;
 };
 
-void launch_deposit_cells(const KParams &kp, int prec, int group, const PartPtrs &pp, const double *B, void *S,
+// Ghosted, component-interleaved copy of a grid vector field (SoA FP64 on
+// nodes or centres) in the particle arithmetic type: point (i, j, k) with
+// i in [-1, nx], ... at (i + 1) + gx (j + 1) [+ gxy (k + 1)], 4 values each.
+void launch_stage_field(const KParams &kp, int prec, const double *F, void *out, hipStream_t st);
+void launch_deposit_cells(const KParams &kp, int prec, int group, const PartPtrs &pp, const void *Bst, void *S,
                           hipStream_t st);
 void launch_assemble(const KParams &kp, int prec, const void *S, double *J, double *M, hipStream_t st);
-void launch_push(const KParams &kp, int prec, int group, const PartPtrs &pp, const double *Eth, const double *B,
+void launch_fill_slotmap(const KParams &kp, int4 *map, hipStream_t st);
+void launch_push(const KParams &kp, int prec, int group, const PartPtrs &pp, const void *Est, const void *Bst,
                  uint8_t *dirc, uint16_t *cnt, int32_t *err, int count_moves, hipStream_t st);
 void launch_sort_offsets(const KParams &kp, const uint16_t *cnt, uint16_t *pre, int32_t *total, int32_t *err,
                          hipStream_t st);
