@@ -176,6 +176,7 @@ Layout make_layout(const relsim_params *p) {
   const size_t ng = (size_t)(p->nx + 2) * (p->ny + 2) * (p->dim == 3 ? p->nz + 2 : 1);
   L.stB = take(ng * 4 * es);
   L.stE = take(ng * 4 * es);
+  L.sink = take((size_t)kSinkSlots * 64 * 8);
   L.end = o;
   return L;
 }
@@ -236,16 +237,18 @@ KParams make_kparams(const relsim_params *p) {
 // Lanes per cell for a particle kernel: the largest power of two in [8, 64]
 // not above mean_occupancy / rounds, where `rounds` is the number of G-wide
 // rounds per cell the kernel wants.  The deposit amortises its per-cell
-// reduction over many rounds (16), the push over a few (4), while the
+// reduction over several rounds (8 in FP32; 16 in FP64, whose register-bound
+// occupancy favours narrower groups), the push over a few (4), while the
 // scatter writes whole runs per instruction (2).  Measured on the
 // 1024 x 512 Harris sheet (128 particles per cell).
-enum KernelKind { K_DEPOSIT = 16, K_PUSH = 4, K_SCATTER = 2, K_OTHER = 4 };
+enum KernelKind { K_DEPOSIT = 8, K_PUSH = 4, K_SCATTER = 2, K_OTHER = 4 };
 
 int choose_group(const relsim_ctx *c, int64_t n, KernelKind k = K_OTHER) {
   if (c->p.group) return c->p.group;
+  const double rounds = (k == K_DEPOSIT && c->p.precision == RELSIM_FP64) ? 16.0 : (double)k;
   const double mean = (double)n / (double)c->kp.ncells;
   int g = 8;
-  while (g < 64 && 2.0 * g <= mean / (double)k) g *= 2;
+  while (g < 64 && 2.0 * g <= mean / rounds) g *= 2;
   return g;
 }
 
@@ -456,7 +459,8 @@ int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, cons
     launch_stage_field(c->kp, c->p.precision, E_theta, stE, c->st);
   });
   timed(c, "push", [&] {
-    launch_push(c->kp, c->p.precision, G, front(pt), stE, stB, dirc, cnt, err, resort ? 1 : 0, c->st);
+    launch_push(c->kp, c->p.precision, G, front(pt), stE, stB, dirc, cnt, err, resort ? 1 : 0,
+                c->at<char>(c->L.sink), c->st);
   });
   if (resort) {
     timed(c, "sort_offsets", [&] { launch_sort_offsets(c->kp, cnt, pre, total, err, c->st); });
@@ -467,7 +471,7 @@ int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, cons
     void *ub[3] = {pt->u_back[0], pt->u_back[1], pt->u_back[2]};
     timed(c, "sort_scatter", [&] {
       launch_sort_scatter(c->kp, c->p.precision, Gs, front(pt), dirc, pre, pt->bin_start_back, pt->cell_back, offb, ub,
-                          pt->w_back, (int)pt->n, err, new_index, c->st);
+                          pt->w_back, (int)pt->n, err, new_index, c->at<char>(c->L.sink), c->st);
     });
     rc = launch_status(c, "relsim_push");
     if (rc) return rc;

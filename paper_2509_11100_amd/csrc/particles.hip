@@ -287,20 +287,34 @@ struct PRec {
   T fx, fy, fz, ux, uy, uz, w;
 };
 
+// Index a lane loads for particle p of a cell ending at pend: lanes past
+// the end read a valid neighbour instead of branching, so that the loads stay
+// unconditional and the next round's loads are in flight while the current
+// round computes.  Only used when the wave has particles (n > 0).
+__device__ __forceinline__ int load_index(int p, int pend) { return p < pend ? p : (pend > 0 ? pend - 1 : 0); }
+
+// Rounds start on 64-byte boundaries (lanes before the cell's first particle
+// idle), so that each load or store instruction of a lane group covers whole
+// 32-byte memory sectors: a sector split between two instructions is
+// transferred twice.
+template <typename T, int G>
+constexpr int round_align() {
+  return (64 / (int)sizeof(T)) < G ? 64 / (int)sizeof(T) : G;
+}
+
 template <typename T, int DIM, bool WITH_W>
 __device__ __forceinline__ void load_rec(int p, int pend, const T *__restrict__ o0, const T *__restrict__ o1,
                                          const T *__restrict__ o2, const T *__restrict__ u0,
                                          const T *__restrict__ u1, const T *__restrict__ u2,
                                          const T *__restrict__ wt, PRec<T> &r) {
-  if (p < pend) {
-    r.fx = o0[p];
-    r.fy = o1[p];
-    if constexpr (DIM == 3) r.fz = o2[p];
-    r.ux = u0[p];
-    r.uy = u1[p];
-    r.uz = u2[p];
-    if constexpr (WITH_W) r.w = wt[p];
-  }
+  const int q = load_index(p, pend);
+  r.fx = o0[q];
+  r.fy = o1[q];
+  if constexpr (DIM == 3) r.fz = o2[q];
+  r.ux = u0[q];
+  r.uy = u1[q];
+  r.uz = u2[q];
+  if constexpr (WITH_W) r.w = wt[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -327,7 +341,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 
   T Bc[3][9];
   if constexpr (BLK) load_B_block_2d<T>(kp, Bs, cs.gc, Bc);
-  const int rounds = wave_rounds<G>(cs.pend - cs.pbeg);
+  const int pal = cs.pbeg & ~(round_align<T, G>() - 1);
+  const int rounds = wave_rounds<G>(cs.pend - pal);
 
 #pragma unroll 1
   for (int pass = 0; pass < NPASS; ++pass) {
@@ -335,13 +350,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 #pragma unroll
     for (int k = 0; k < NACC; ++k) acc[k] = T(0);
     PRec<T> cur{}, nxt{};
-    int p = cs.pbeg + gl;
-    load_rec<T, DIM, true>(p, cs.pend, o0, o1, o2, u0, u1, u2, wt, cur);
+    int p = pal + gl;
+    if (rounds > 0) load_rec<T, DIM, true>(p, cs.pend, o0, o1, o2, u0, u1, u2, wt, cur);
+    __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll 1
     for (int r = 0; r < rounds; ++r) {
       const int pn = p + G;
       load_rec<T, DIM, true>(pn, cs.pend, o0, o1, o2, u0, u1, u2, wt, nxt);
-      if (p < cs.pend) {
+      if (p >= cs.pbeg && p < cs.pend) {
         const T fx = cur.fx, fy = cur.fy, fz = DIM == 3 ? cur.fz : T(0);
         const T ux = cur.ux, uy = cur.uy, uz = cur.uz, wp = cur.w;
         T qs, bs;
@@ -470,8 +486,8 @@ __global__ __launch_bounds__(256) void k_assemble(KParams kp, const T *__restric
 // ---------------------------------------------------------------------------
 // S6: push, cell crossing, and per-(bin, move) counts for the re-sort
 // ---------------------------------------------------------------------------
-template <typename T, int DIM>
-__device__ __forceinline__ int cross_cell(T &f, int32_t *err) {
+template <typename T>
+__device__ __forceinline__ int cross_cell(T &f, int &bad) {
   // f is the new offset in cell units; bring it back into [0,1) with one
   // cell move.  A value rounding to exactly 1 after the correction from
   // below is the left face of the cell (offset 0, no move).
@@ -488,19 +504,29 @@ __device__ __forceinline__ int cross_cell(T &f, int32_t *err) {
       f = T(0);
       m = 0;
     } else {
-      atomicOr(err, 1);  // moved more than one cell, or non-finite
+      bad = 1;  // moved more than one cell, or non-finite
       f = T(0);
     }
   }
   return m;
 }
 
-template <typename T, int DIM, int G>
+// Lanes past their cell's end store into a per-lane slot of a small sink in
+// the workspace instead of branching around the stores: with unconditional
+// stores the compiler can count them, and the wait for the next round's
+// loads does not also wait for this round's stores to complete.
+template <typename T>
+__device__ __forceinline__ T *sink_slot(void *sink, int lane) {
+  return reinterpret_cast<T *>(sink) + (((blockIdx.x & (kSinkSlots - 1)) << 6) + lane);
+}
+
+template <typename T, int DIM, int G, bool COUNT>
 __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restrict__ bin_start, T *__restrict__ o0,
                                              T *__restrict__ o1, T *__restrict__ o2, T *__restrict__ u0,
                                              T *__restrict__ u1, T *__restrict__ u2, const V4<T> *__restrict__ Es,
                                              const V4<T> *__restrict__ Bs, uint8_t *__restrict__ dirc,
-                                             uint16_t *__restrict__ cnt, int32_t *__restrict__ err, int count_moves) {
+                                             uint16_t *__restrict__ cnt, int32_t *__restrict__ err,
+                                             void *__restrict__ sink) {
   constexpr int NDIR = DIM == 3 ? 27 : 9;
   constexpr int NK = 8 * NDIR;  // (species, move) keys per group
   constexpr int NGRP = 64 / G;
@@ -509,7 +535,9 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
   const PC<T> pc(kp);
-  if (count_moves) {
+  T *const sinkT = sink_slot<T>(sink, lane);
+  uint8_t *const sinkB = sink_slot<uint8_t>(sink, lane);
+  if constexpr (COUNT) {
     for (int t = lane; t < NGRP * NK; t += 64) lcnt[t] = 0u;
     __syncthreads();
   }
@@ -526,73 +554,81 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
     Ec[1][a] = e.y;
     Ec[2][a] = e.z;
   }
-  const int rounds = wave_rounds<G>(cs.pend - cs.pbeg);
+  const int pal = cs.pbeg & ~(round_align<T, G>() - 1);
+  const int rounds = wave_rounds<G>(cs.pend - pal);
   PRec<T> cur{}, nxt{};
-  int p = cs.pbeg + gl;
-  load_rec<T, DIM, false>(p, cs.pend, o0, o1, o2, u0, u1, u2, nullptr, cur);
+  int p = pal + gl;
+  int bad = 0;
+  if (rounds > 0) load_rec<T, DIM, false>(p, cs.pend, o0, o1, o2, u0, u1, u2, nullptr, cur);
+  // enter the loop with nothing in flight, so the loop's waits only count
+  // its own loads and stores
+  __builtin_amdgcn_s_waitcnt(0);
 
 #pragma unroll 1
   for (int r = 0; r < rounds; ++r) {
     const int pn = p + G;
     load_rec<T, DIM, false>(pn, cs.pend, o0, o1, o2, u0, u1, u2, nullptr, nxt);
-    if (p < cs.pend) {
-      T fx = cur.fx, fy = cur.fy;
-      T fz = DIM == 3 ? cur.fz : T(0);
-      const T ux = cur.ux, uy = cur.uy, uz = cur.uz;
-      T qs, bs;
-      const int s = species_of<T>(kp, pc, cs, p, qs, bs);
-      T Bx, By, Bz;
-      gather_B<T, DIM, true>(kp, Bs, Bc, cs.gc, fx, fy, fz, Bx, By, Bz);
-      const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
-      const T kb = bs * igb * pc.invc;
-      T a[9];
-      make_alpha<T>(kb * Bx, kb * By, kb * Bz, a);
-      T Ex = T(0), Ey = T(0), Ez = T(0);
+    // lanes past the end compute on a copy of a valid particle (finite
+    // values) and store into the sink
+    const bool pv = p >= cs.pbeg && p < cs.pend;
+    T fx = cur.fx, fy = cur.fy;
+    T fz = DIM == 3 ? cur.fz : T(0);
+    const T ux = cur.ux, uy = cur.uy, uz = cur.uz;
+    T qs, bs;
+    const int s = species_of<T>(kp, pc, cs, p, qs, bs);
+    T Bx, By, Bz;
+    gather_B<T, DIM, true>(kp, Bs, Bc, cs.gc, fx, fy, fz, Bx, By, Bz);
+    const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
+    const T kb = bs * igb * pc.invc;
+    T a[9];
+    make_alpha<T>(kb * Bx, kb * By, kb * Bz, a);
+    T Ex = T(0), Ey = T(0), Ez = T(0);
 #pragma unroll
-      for (int c = 0; c < NCORN; ++c) {
-        T wgt = ((c & 1) ? fx : T(1) - fx) * ((c & 2) ? fy : T(1) - fy);
-        if constexpr (DIM == 3) wgt *= (c & 4) ? fz : T(1) - fz;
-        Ex += wgt * Ec[0][c];
-        Ey += wgt * Ec[1][c];
-        Ez += wgt * Ec[2][c];
-      }
-      const T vx = ux + bs * Ex, vy = uy + bs * Ey, vz = uz + bs * Ez;
-      const T ubx = a[0] * vx + a[1] * vy + a[2] * vz;
-      const T uby = a[3] * vx + a[4] * vy + a[5] * vz;
-      const T ubz = a[6] * vx + a[7] * vy + a[8] * vz;
-      const T nx = T(2) * ubx - ux, ny = T(2) * uby - uy, nz = T(2) * ubz - uz;
-      const T ign = kp.nonrel ? T(1) : rsqrt_t(T(1) + (nx * nx + ny * ny + nz * nz) * pc.invc2);
-      const T dtg = pc.dt * ign;
-      fx += dtg * nx * pc.idx;
-      fy += dtg * ny * pc.idy;
-      if constexpr (DIM == 3) fz += dtg * nz * pc.idz;
-      int mx = 0, my = 0, mz = 0;
-      if (count_moves) {
-        mx = cross_cell<T, DIM>(fx, err);
-        my = cross_cell<T, DIM>(fy, err);
-        if constexpr (DIM == 3) mz = cross_cell<T, DIM>(fz, err);
-      } else {
-        // no re-sort: offsets stay relative to the old cell, in [-1, 2)
-        bool ok = fx >= T(-1) && fx < T(2) && fy >= T(-1) && fy < T(2);
-        if constexpr (DIM == 3) ok = ok && fz >= T(-1) && fz < T(2);
-        if (!ok) atomicOr(err, 1);
-      }
-      o0[p] = fx;
-      o1[p] = fy;
-      if constexpr (DIM == 3) o2[p] = fz;
-      u0[p] = nx;
-      u1[p] = ny;
-      u2[p] = nz;
-      if (count_moves) {
-        const int dir = (mx + 1) + 3 * (my + 1) + (DIM == 3 ? 9 * (mz + 1) : 0);
-        dirc[p] = (uint8_t)dir;
-        atomicAdd(&lcnt[grp * NK + s * NDIR + dir], 1u);  // integer: order-independent
-      }
+    for (int c = 0; c < NCORN; ++c) {
+      T wgt = ((c & 1) ? fx : T(1) - fx) * ((c & 2) ? fy : T(1) - fy);
+      if constexpr (DIM == 3) wgt *= (c & 4) ? fz : T(1) - fz;
+      Ex += wgt * Ec[0][c];
+      Ey += wgt * Ec[1][c];
+      Ez += wgt * Ec[2][c];
+    }
+    const T vx = ux + bs * Ex, vy = uy + bs * Ey, vz = uz + bs * Ez;
+    const T ubx = a[0] * vx + a[1] * vy + a[2] * vz;
+    const T uby = a[3] * vx + a[4] * vy + a[5] * vz;
+    const T ubz = a[6] * vx + a[7] * vy + a[8] * vz;
+    const T nx = T(2) * ubx - ux, ny = T(2) * uby - uy, nz = T(2) * ubz - uz;
+    const T ign = kp.nonrel ? T(1) : rsqrt_t(T(1) + (nx * nx + ny * ny + nz * nz) * pc.invc2);
+    const T dtg = pc.dt * ign;
+    fx += dtg * nx * pc.idx;
+    fy += dtg * ny * pc.idy;
+    if constexpr (DIM == 3) fz += dtg * nz * pc.idz;
+    int mx = 0, my = 0, mz = 0, flag = 0;
+    if constexpr (COUNT) {
+      mx = cross_cell<T>(fx, flag);
+      my = cross_cell<T>(fy, flag);
+      if constexpr (DIM == 3) mz = cross_cell<T>(fz, flag);
+    } else {
+      // no re-sort: offsets stay relative to the old cell, in [-1, 2)
+      bool ok = fx >= T(-1) && fx < T(2) && fy >= T(-1) && fy < T(2);
+      if constexpr (DIM == 3) ok = ok && fz >= T(-1) && fz < T(2);
+      flag = ok ? 0 : 1;
+    }
+    bad |= pv ? flag : 0;
+    *(pv ? o0 + p : sinkT) = fx;
+    *(pv ? o1 + p : sinkT) = fy;
+    if constexpr (DIM == 3) *(pv ? o2 + p : sinkT) = fz;
+    *(pv ? u0 + p : sinkT) = nx;
+    *(pv ? u1 + p : sinkT) = ny;
+    *(pv ? u2 + p : sinkT) = nz;
+    if constexpr (COUNT) {
+      const int dir = (mx + 1) + 3 * (my + 1) + (DIM == 3 ? 9 * (mz + 1) : 0);
+      *(pv ? dirc + p : sinkB) = (uint8_t)dir;
+      if (pv) atomicAdd(&lcnt[grp * NK + s * NDIR + dir], 1u);  // integer: order-independent
     }
     cur = nxt;
     p = pn;
   }
-  if (count_moves) {
+  if (__ballot(bad) && lane == 0) atomicOr(err, 1);
+  if constexpr (COUNT) {
     __syncthreads();
     if (cs.valid) {
       const int S = kp.nspecies;
@@ -649,9 +685,14 @@ __global__ __launch_bounds__(256) void k_sort_offsets(KParams kp, const uint16_t
 }
 
 // ---------------------------------------------------------------------------
-// re-sort, step 3: stable scatter into the back buffers
+// re-sort, step 3: stable scatter into the back buffers.  Each lane group
+// first resolves, for each (species, move) key of its cell, where that
+// class's run starts in the new order (new bin start + offset of this
+// source cell among the bin's sources); in the loop a particle's place is
+// that base plus its rank among the same-key lanes of earlier rounds and
+// lower lanes of this round, found from one ballot per key bit.
 // ---------------------------------------------------------------------------
-template <typename T, int DIM, int G>
+template <typename T, int DIM, int G, bool PERM>
 __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *__restrict__ bin_start,
                                                      const T *__restrict__ o0, const T *__restrict__ o1,
                                                      const T *__restrict__ o2, const T *__restrict__ u0,
@@ -662,32 +703,47 @@ __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *
                                                      T *__restrict__ q0, T *__restrict__ q1, T *__restrict__ q2,
                                                      T *__restrict__ v0, T *__restrict__ v1, T *__restrict__ v2,
                                                      T *__restrict__ wo, int ntot, int32_t *__restrict__ err,
-                                                     int32_t *__restrict__ perm) {
+                                                     int32_t *__restrict__ perm, void *__restrict__ sink) {
   constexpr int NDIR = DIM == 3 ? 27 : 9;
-  constexpr int NK = 8 * NDIR;
   constexpr int NGRP = 64 / G;
-  // bits of the key grp * NK + species * NDIR + move
-  constexpr int KBITS = NGRP * NK <= 256 ? 8 : (NGRP * NK <= 512 ? 9 : (NGRP * NK <= 1024 ? 10 : 11));
-  __shared__ uint32_t lbase[NGRP * NK];
+  __shared__ int lbase[NGRP * 8 * NDIR];  // next destination of each (group, species, move) key
+  __shared__ int ldc[NGRP * NDIR];        // destination cell of each (group, move)
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
-  for (int t = lane; t < NGRP * NK; t += 64) lbase[t] = 0u;
-  __syncthreads();
-  const int S = kp.nspecies;
+  const int S = kp.nspecies, nkey = S * NDIR;
   const size_t nb = (size_t)kp.nbins;
+  if (cs.valid) {
+    for (int t = gl; t < nkey; t += G) {
+      const int s = t / NDIR, dir = t - s * NDIR;
+      const int mx = dir % 3 - 1, my = (dir / 3) % 3 - 1, mz = dir / 9 - 1;
+      const int dc = wrapi(cs.ci + mx, kp.nx) +
+                     kp.nx * (wrapi(cs.cj + my, kp.ny) + kp.ny * (DIM == 3 ? wrapi(cs.ck + mz, kp.nz) : 0));
+      const int d = dc * S + s;
+      lbase[grp * nkey + t] = bsn[d] + (int)pre[(size_t)dir * nb + d];
+      if (s == 0) ldc[grp * NDIR + dir] = dc;
+    }
+  }
+  __syncthreads();
+  // key bits: keys are grp * nkey + species * NDIR + move < NGRP * nkey
+  const int kbits = 32 - __builtin_clz((unsigned)(NGRP * nkey - 1) | 1u);
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int rounds = wave_rounds<G>(cs.pend - cs.pbeg);
+  T *const sinkT = sink_slot<T>(sink, lane);
+  int32_t *const sinkI = sink_slot<int32_t>(sink, lane);
   PRec<T> cur{}, nxt{};
   int p = cs.pbeg + gl;
-  int dcur = 0, dnxt = 0;
-  load_rec<T, DIM, true>(p, cs.pend, o0, o1, o2, u0, u1, u2, wt, cur);
-  if (p < cs.pend) dcur = dirc[p];
+  int dcur = 0, dnxt = 0, bad = 0;
+  if (rounds > 0) {
+    load_rec<T, DIM, true>(p, cs.pend, o0, o1, o2, u0, u1, u2, wt, cur);
+    dcur = dirc[load_index(p, cs.pend)];
+  }
+  __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll 1
   for (int r = 0; r < rounds; ++r) {
     const int pn = p + G;
     load_rec<T, DIM, true>(pn, cs.pend, o0, o1, o2, u0, u1, u2, wt, nxt);
-    if (pn < cs.pend) dnxt = dirc[pn];
+    dnxt = dirc[load_index(pn, cs.pend)];
     const bool pv = p < cs.pend;
     int s = 0;
     if (pv) {
@@ -699,46 +755,43 @@ __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *
           if (p >= cs.bound[s2]) s = s2;
       }
     }
-    const int key = grp * NK + s * NDIR + dcur;
-    // lanes of the wave holding the same key, from one ballot per key bit
-    unsigned long long same = __ballot(pv);
-#pragma unroll
-    for (int b = 0; b < KBITS; ++b) {
-      const unsigned long long ones = __ballot(pv && ((key >> b) & 1));
-      same &= ((key >> b) & 1) ? ones : ~ones;
+    const int key = pv ? grp * nkey + s * NDIR + dcur : 0;
+    // lanes of this round holding the same key
+    const unsigned long long act = __ballot(pv);
+    uint32_t same_lo = (uint32_t)act, same_hi = (uint32_t)(act >> 32);
+#pragma unroll 1
+    for (int b = 0; b < kbits; ++b) {
+      const bool bit = (key >> b) & 1;
+      const unsigned long long ones = __ballot(bit);
+      const uint32_t lo = (uint32_t)ones, hi = (uint32_t)(ones >> 32);
+      same_lo &= bit ? lo : ~lo;
+      same_hi &= bit ? hi : ~hi;
     }
-    int rank = 0;
-    if (pv) rank = (int)lbase[key] + __popcll(same & lt);
+    const unsigned long long same = ((unsigned long long)same_hi << 32) | same_lo;
+    int pos = 0;
+    if (pv) pos = lbase[key] + __popcll(same & lt);
     __builtin_amdgcn_wave_barrier();
-    // the highest lane of each key advances that key's running count
-    if (pv && (same >> lane) == 1ull) lbase[key] += (uint32_t)__popcll(same);
-    if (pv) {
-      const int dir = dcur;
-      const int mx = dir % 3 - 1, my = (dir / 3) % 3 - 1, mz = dir / 9 - 1;
-      const int dc = wrapi(cs.ci + mx, kp.nx) +
-                     kp.nx * (wrapi(cs.cj + my, kp.ny) + kp.ny * (DIM == 3 ? wrapi(cs.ck + mz, kp.nz) : 0));
-      const int d = dc * S + s;
-      const int pos = bsn[d] + (int)pre[(size_t)dir * nb + d] + rank;
-      if (pos < 0 || pos >= ntot) {
-        // only reachable when a bin overflowed the 16-bit counters (flagged)
-        atomicOr(err, 2);
-      } else {
-        q0[pos] = cur.fx;
-        q1[pos] = cur.fy;
-        if constexpr (DIM == 3) q2[pos] = cur.fz;
-        v0[pos] = cur.ux;
-        v1[pos] = cur.uy;
-        v2[pos] = cur.uz;
-        wo[pos] = cur.w;
-        cell_out[pos] = dc;
-        if (perm) perm[p] = pos;
-      }
-    }
+    // the highest lane of each key advances that key's base
+    if (pv && (same >> lane) == 1ull) lbase[key] += __popcll(same);
+    // only reachable out of range when a bin overflowed the 16-bit
+    // counters (flagged); lanes past the end store into the sink
+    const bool ok = pv && pos >= 0 && pos < ntot;
+    bad |= (pv && !ok) ? 1 : 0;
+    *(ok ? q0 + pos : sinkT) = cur.fx;
+    *(ok ? q1 + pos : sinkT) = cur.fy;
+    if constexpr (DIM == 3) *(ok ? q2 + pos : sinkT) = cur.fz;
+    *(ok ? v0 + pos : sinkT) = cur.ux;
+    *(ok ? v1 + pos : sinkT) = cur.uy;
+    *(ok ? v2 + pos : sinkT) = cur.uz;
+    *(ok ? wo + pos : sinkT) = cur.w;
+    *(ok ? cell_out + pos : sinkI) = ldc[grp * NDIR + dcur];
+    if constexpr (PERM) *(ok ? perm + p : sinkI) = pos;
     __builtin_amdgcn_wave_barrier();
     cur = nxt;
     dcur = dnxt;
     p = pn;
   }
+  if (__ballot(bad) && lane == 0) atomicOr(err, 2);
 }
 
 // ---------------------------------------------------------------------------
@@ -868,22 +921,35 @@ void deposit_impl(const KParams &kp, const PartPtrs &pp, const void *Bst, void *
 
 template <typename T, int DIM, int G>
 void push_impl(const KParams &kp, const PartPtrs &pp, const void *Est, const void *Bst, uint8_t *dirc,
-               uint16_t *cnt, int32_t *err, int count_moves, hipStream_t st) {
+               uint16_t *cnt, int32_t *err, int count_moves, void *sink, hipStream_t st) {
   const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
-  hipLaunchKernelGGL((k_push<T, DIM, G>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, mp<T>(pp.off[0]),
-                     mp<T>(pp.off[1]), mp<T>(pp.off[2]), mp<T>(pp.u[0]), mp<T>(pp.u[1]), mp<T>(pp.u[2]),
-                     cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, cnt, err, count_moves);
+  if (count_moves)
+    hipLaunchKernelGGL((k_push<T, DIM, G, true>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, mp<T>(pp.off[0]),
+                       mp<T>(pp.off[1]), mp<T>(pp.off[2]), mp<T>(pp.u[0]), mp<T>(pp.u[1]), mp<T>(pp.u[2]),
+                       cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, cnt, err, sink);
+  else
+    hipLaunchKernelGGL((k_push<T, DIM, G, false>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, mp<T>(pp.off[0]),
+                       mp<T>(pp.off[1]), mp<T>(pp.off[2]), mp<T>(pp.u[0]), mp<T>(pp.u[1]), mp<T>(pp.u[2]),
+                       cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, cnt, err, sink);
 }
 
 template <typename T, int DIM, int G>
 void scatter_impl(const KParams &kp, const PartPtrs &src, const uint8_t *dirc, const uint16_t *pre, const int32_t *bsn,
                   int32_t *cell_out, void *const off_out[3], void *const u_out[3], void *w_out, int ntot, int32_t *err,
-                  int32_t *perm, hipStream_t st) {
+                  int32_t *perm, void *sink, hipStream_t st) {
   const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
-  hipLaunchKernelGGL((k_sort_scatter<T, DIM, G>), dim3(nblk), dim3(64), 0, st, kp, src.bin_start, cp<T>(src.off[0]),
-                     cp<T>(src.off[1]), cp<T>(src.off[2]), cp<T>(src.u[0]), cp<T>(src.u[1]), cp<T>(src.u[2]),
-                     cp<T>(src.w), dirc, pre, bsn, cell_out, mp<T>(off_out[0]), mp<T>(off_out[1]), mp<T>(off_out[2]),
-                     mp<T>(u_out[0]), mp<T>(u_out[1]), mp<T>(u_out[2]), mp<T>(w_out), ntot, err, perm);
+  if (perm)
+    hipLaunchKernelGGL((k_sort_scatter<T, DIM, G, true>), dim3(nblk), dim3(64), 0, st, kp, src.bin_start,
+                       cp<T>(src.off[0]), cp<T>(src.off[1]), cp<T>(src.off[2]), cp<T>(src.u[0]), cp<T>(src.u[1]),
+                       cp<T>(src.u[2]), cp<T>(src.w), dirc, pre, bsn, cell_out, mp<T>(off_out[0]), mp<T>(off_out[1]),
+                       mp<T>(off_out[2]), mp<T>(u_out[0]), mp<T>(u_out[1]), mp<T>(u_out[2]), mp<T>(w_out), ntot, err,
+                       perm, sink);
+  else
+    hipLaunchKernelGGL((k_sort_scatter<T, DIM, G, false>), dim3(nblk), dim3(64), 0, st, kp, src.bin_start,
+                       cp<T>(src.off[0]), cp<T>(src.off[1]), cp<T>(src.off[2]), cp<T>(src.u[0]), cp<T>(src.u[1]),
+                       cp<T>(src.u[2]), cp<T>(src.w), dirc, pre, bsn, cell_out, mp<T>(off_out[0]), mp<T>(off_out[1]),
+                       mp<T>(off_out[2]), mp<T>(u_out[0]), mp<T>(u_out[1]), mp<T>(u_out[2]), mp<T>(w_out), ntot, err,
+                       perm, sink);
 }
 
 template <typename T, int DIM, int G>
@@ -970,8 +1036,8 @@ void launch_assemble(const KParams &kp, int prec, const void *S, double *J, doub
 }
 
 void launch_push(const KParams &kp, int prec, int group, const PartPtrs &pp, const void *Est, const void *Bst,
-                 uint8_t *dirc, uint16_t *cnt, int32_t *err, int count_moves, hipStream_t st) {
-  dispatch<PushF>(prec, kp.dim, group, kp, pp, Est, Bst, dirc, cnt, err, count_moves, st);
+                 uint8_t *dirc, uint16_t *cnt, int32_t *err, int count_moves, void *sink, hipStream_t st) {
+  dispatch<PushF>(prec, kp.dim, group, kp, pp, Est, Bst, dirc, cnt, err, count_moves, sink, st);
 }
 
 void launch_sort_offsets(const KParams &kp, const uint16_t *cnt, uint16_t *pre, int32_t *total, int32_t *err,
@@ -994,9 +1060,10 @@ void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream
 
 void launch_sort_scatter(const KParams &kp, int prec, int group, const PartPtrs &src, const uint8_t *dirc,
                          const uint16_t *pre, const int32_t *bin_start_new, int32_t *cell_out, void *const off_out[3],
-                         void *const u_out[3], void *w_out, int ntot, int32_t *err, int32_t *perm, hipStream_t st) {
+                         void *const u_out[3], void *w_out, int ntot, int32_t *err, int32_t *perm, void *sink,
+                         hipStream_t st) {
   dispatch<ScatterF>(prec, kp.dim, group, kp, src, dirc, pre, bin_start_new, cell_out, off_out, u_out, w_out, ntot, err,
-                     perm, st);
+                     perm, sink, st);
 }
 
 void launch_kinetic(const KParams &kp, int prec, int group, const PartPtrs &pp, double *partials, hipStream_t st) {

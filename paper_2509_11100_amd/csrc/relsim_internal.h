@@ -29,12 +29,13 @@ struct KParams {
 // Offsets (in bytes) of the regions carved out of the caller's workspace.
 struct Layout {
   size_t S, cnt, pre, total, scan_tmp, dirc, err, gm_V, gm_t, gm_b, gm_r, gm_part, gm_small, red_part;
-  size_t gs_k0, gs_k1, gs_v0, gs_v1, gs_hist, slotmap, stB, stE, end;
+  size_t gs_k0, gs_k1, gs_v0, gs_v1, gs_hist, slotmap, stB, stE, sink, end;
 };
 
 constexpr int kMaxRestart = 64;
 constexpr int kDotBlocks = 512;     // blocks of the multi-dot reduction
 constexpr int kRedBlocks = 1024;    // blocks of the energy reductions
+constexpr int kSinkSlots = 512;     // per-lane store sinks of the particle kernels (power of two)
 
 // Moments per cell: 2D 81 mass moments + 12 current moments; 3D three passes
 // of 81 mass moments plus 2 x 12 current moments.
@@ -57,15 +58,18 @@ void launch_deposit_cells(const KParams &kp, int prec, int group, const PartPtrs
                           hipStream_t st);
 void launch_assemble(const KParams &kp, int prec, const void *S, double *J, double *M, hipStream_t st);
 void launch_fill_slotmap(const KParams &kp, int4 *map, hipStream_t st);
+// `sink`: kSinkSlots * 64 * 8 bytes of workspace that lanes without a
+// particle store into (contents meaningless)
 void launch_push(const KParams &kp, int prec, int group, const PartPtrs &pp, const void *Est, const void *Bst,
-                 uint8_t *dirc, uint16_t *cnt, int32_t *err, int count_moves, hipStream_t st);
+                 uint8_t *dirc, uint16_t *cnt, int32_t *err, int count_moves, void *sink, hipStream_t st);
 void launch_sort_offsets(const KParams &kp, const uint16_t *cnt, uint16_t *pre, int32_t *total, int32_t *err,
                          hipStream_t st);
 void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream_t st);
 size_t scan_tmp_elems(int n);
 void launch_sort_scatter(const KParams &kp, int prec, int group, const PartPtrs &src, const uint8_t *dirc,
                          const uint16_t *pre, const int32_t *bin_start_new, int32_t *cell_out, void *const off_out[3],
-                         void *const u_out[3], void *w_out, int ntot, int32_t *err, int32_t *perm, hipStream_t st);
+                         void *const u_out[3], void *w_out, int ntot, int32_t *err, int32_t *perm, void *sink,
+                         hipStream_t st);
 void launch_kinetic(const KParams &kp, int prec, int group, const PartPtrs &pp, double *partials, hipStream_t st);
 
 // ---- general stable sort by bin (sort.hip) ----
