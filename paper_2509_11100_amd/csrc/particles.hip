@@ -321,7 +321,7 @@ __device__ __forceinline__ void load_rec(int p, int pend, const T *__restrict__ 
 // S1-S3: per-cell moments
 // ---------------------------------------------------------------------------
 template <typename T, int DIM, int G>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_deposit_cells(KParams kp, const int32_t *__restrict__ bin_start,
+__global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t *__restrict__ bin_start,
                                                       const T *__restrict__ o0, const T *__restrict__ o1,
                                                       const T *__restrict__ o2, const T *__restrict__ u0,
                                                       const T *__restrict__ u1, const T *__restrict__ u2,
