@@ -7,8 +7,8 @@ particles per cell per species (67,108,864 particles), FP32-mixed (headline)
 and FP64.  Every timed step is a full step of the scheme: deposit, FP64 GMRES
 field solve (relative tolerance 1e-10), push + re-sort, FP64 energy.  The
 metric's time is the GPU time of the deposit and push calls (HIP events on
-the library's stream); the field solve and the energy diagnostic are timed
-and reported separately.  Inputs are generated on the host, copied to HBM,
+the stream the library launches on); the field solve and the energy
+diagnostic are timed and reported separately.  Inputs are generated on the host, copied to HBM,
 and are resident before the timed region starts.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -125,7 +125,10 @@ def run_precision(prec, wl, host, steps, warmup, rtol, want_kernels=True, group=
         relsim.timing_enable(ctx, False)
         if ev is not None:
             ev[3].record(st)
-        return it, rr
+        W = relsim.energy(ctx, parts, E1, B1)
+        if ev is not None:
+            ev[4].record(st)
+        return it, rr, W
 
     for _ in range(warmup):
         one_step(E, B, nb[0], nb[1])
@@ -133,13 +136,15 @@ def run_precision(prec, wl, host, steps, warmup, rtol, want_kernels=True, group=
         B, nb[1] = nb[1], B
     relsim.timing_reset(ctx)
     Wstart = relsim.energy(ctx, parts, E, B)
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
     iters = []
+    energies = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        it, rr = one_step(E, B, nb[0], nb[1], evs[k])
+        it, rr, W = one_step(E, B, nb[0], nb[1], evs[k])
         iters.append(it)
+        energies.append(W)
         E, nb[0] = nb[0], E
         B, nb[1] = nb[1], B
     torch.cuda.synchronize()
@@ -148,6 +153,7 @@ def run_precision(prec, wl, host, steps, warmup, rtol, want_kernels=True, group=
     dep = sum(e[0].elapsed_time(e[1]) for e in evs)
     sol = sum(e[1].elapsed_time(e[2]) for e in evs)
     pus = sum(e[2].elapsed_time(e[3]) for e in evs)
+    ene = sum(e[3].elapsed_time(e[4]) for e in evs)
     kern = relsim.timing_read(ctx)
     hot = dep + pus
     res = {
@@ -158,11 +164,14 @@ def run_precision(prec, wl, host, steps, warmup, rtol, want_kernels=True, group=
         "deposit_ms_per_step": dep / steps,
         "push_sort_ms_per_step": pus / steps,
         "solve_ms_per_step": sol / steps,
+        "energy_ms_per_step": ene / steps,
         "wall_ms_per_step": 1e3 * wall / steps,
         "gmres_iters_per_step": sum(iters) / steps,
         "energy_start": list(map(float, Wstart)),
         "energy_end": list(map(float, Wend)),
         "energy_drift_per_step": float((Wend[3] - Wstart[3]) / W0[3] / steps),
+        "energy_drift_max_abs_per_step": float(max(abs(b[3] - a[3]) for a, b in zip([Wstart] + energies[:-1],
+                                                                                        energies)) / W0[3]),
         "kernels": {k: {"ms_per_launch": v[0] / max(v[1], 1), "launches": v[1]} for k, v in kern.items()},
     }
     del parts, ctx, E, B, nb, Eth, J, M

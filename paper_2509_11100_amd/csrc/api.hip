@@ -177,6 +177,7 @@ Layout make_layout(const relsim_params *p) {
   L.stB = take(ng * 4 * es);
   L.stE = take(ng * 4 * es);
   L.sink = take((size_t)kSinkSlots * 64 * 8);
+  L.kin_part = take(nc * 8);
   L.end = o;
   return L;
 }
@@ -493,8 +494,9 @@ int relsim_energy(relsim_ctx *c, const relsim_particles *pt, const double *E, co
   double *res = c->at<double>(c->L.gm_small);
   const size_t n3 = 3 * (size_t)c->kp.ncells;
   timed(c, "kinetic", [&] {
-    launch_kinetic(c->kp, c->p.precision, G, front(pt), part, c->st);
-    launch_reduce_partials(part, kRedBlocks, 1, res, c->st);
+    double *kpart = c->at<double>(c->L.kin_part);
+    launch_kinetic(c->kp, c->p.precision, G, front(pt), kpart, c->st);
+    launch_reduce_long(kpart, (c->kp.ncells + (64 / G) - 1) / (64 / G), part, res, c->st);
   });
   timed(c, "field_energy", [&] {
     launch_sumsq_partials(E, n3, part + kRedBlocks, c->st);

@@ -182,6 +182,19 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double *__restric
   if (threadIdx.x == 0) res[kv] = s;
 }
 
+// Sums of consecutive chunks of a long array of partial sums, one block per
+// chunk, in a fixed order.
+__global__ __launch_bounds__(256) void k_reduce_chunks(const double *__restrict__ in, int n, int chunk,
+                                                       double *__restrict__ out) {
+  __shared__ double lds[4];
+  const int b0 = blockIdx.x * chunk;
+  const int b1 = b0 + chunk < n ? b0 + chunk : n;
+  double acc = 0.0;
+  for (int i = b0 + threadIdx.x; i < b1; i += 256) acc += in[i];
+  const double s = block_sum_256(acc, lds);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
 __global__ __launch_bounds__(256) void k_maxpy(const double *__restrict__ V, size_t ld, int nvec,
                                                const double *__restrict__ h, double *__restrict__ w, size_t n) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -264,6 +277,12 @@ void launch_sumsq_partials(const double *x, size_t n, double *partials, hipStrea
 
 void launch_reduce_partials(const double *partials, int nparts, int nvec, double *res, hipStream_t st) {
   hipLaunchKernelGGL(k_reduce_partials, dim3(nvec), dim3(256), 0, st, partials, nparts, nvec, res);
+}
+
+void launch_reduce_long(const double *in, int n, double *tmp, double *res, hipStream_t st) {
+  const int chunk = (n + kRedBlocks - 1) / kRedBlocks;
+  hipLaunchKernelGGL(k_reduce_chunks, dim3(kRedBlocks), dim3(256), 0, st, in, n, chunk > 0 ? chunk : 1, tmp);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, st, tmp, kRedBlocks, 1, res);
 }
 
 }  // namespace relsim

@@ -197,27 +197,6 @@ struct CellSpan {
   bool valid;
 };
 
-__device__ __forceinline__ CellSpan cell_span(const KParams &kp, const int32_t *__restrict__ bin_start, int cell,
-                                              bool valid) {
-  CellSpan cs;
-  cs.valid = valid;
-  cs.cell = valid ? cell : 0;
-  cs.ci = cs.cell % kp.nx;
-  cs.cj = (cs.cell / kp.nx) % kp.ny;
-  cs.ck = cs.cell / (kp.nx * kp.ny);
-  cs.gc = (cs.ci + 1) + kp.gx * (cs.cj + 1) + kp.gxy * (kp.dim == 3 ? cs.ck + 1 : 0);
-  const int S = kp.nspecies, b0 = cs.cell * S;
-#pragma unroll
-  for (int s = 0; s < 8; ++s) cs.bound[s] = valid ? bin_start[b0 + (s < S ? s : S)] : 0;
-  cs.pbeg = cs.bound[0];
-  cs.pend = valid ? bin_start[b0 + S] : 0;
-  return cs;
-}
-
-__device__ __forceinline__ CellSpan cell_span(const KParams &kp, const int32_t *__restrict__ bin_start, int cell) {
-  return cell_span(kp, bin_start, cell, cell < kp.ncells);
-}
-
 // The cell of processing slot blk * (64/G) + grp, from the precomputed slot
 // table {cell, i, j, k} (no integer division in the kernels).
 template <int G>
@@ -802,28 +781,28 @@ __global__ __launch_bounds__(64) void k_kinetic(KParams kp, const int32_t *__res
                                                 const T *__restrict__ u0, const T *__restrict__ u1,
                                                 const T *__restrict__ u2, const T *__restrict__ wt,
                                                 double *__restrict__ partials) {
-  constexpr int NGRP = 64 / G;
+  // one block per 64/G cells in slot order; block b writes partials[b]
   __shared__ double red[64];
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
-  const double c2 = kp.c * kp.c;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
+  const double invc2 = kp.inv_c2;
+  const int S = kp.nspecies;
   double acc = 0.0;
-  const int ncg = (kp.ncells + NGRP - 1) / NGRP;
-  for (int cg = blockIdx.x; cg < ncg; cg += gridDim.x) {
-    const CellSpan cs = cell_span(kp, bin_start, cg * NGRP + grp);
-    for (int p = cs.pbeg + gl; p < cs.pend; p += G) {
-      int s = 0;
+  for (int p = cs.pbeg + gl; p < cs.pend; p += G) {
+    int s = 0;
+    if (S == 2) {
+      s = p >= cs.bound[1] ? 1 : 0;
+    } else {
 #pragma unroll
       for (int s2 = 1; s2 < 8; ++s2)
         if (p >= cs.bound[s2]) s = s2;
-      const double ux = u0[p], uy = u1[p], uz = u2[p];
-      const double uu = ux * ux + uy * uy + uz * uz;
-      double m = kp.m[0];
-#pragma unroll
-      for (int s2 = 1; s2 < 8; ++s2)
-        if (s == s2) m = kp.m[s2];
-      const double w = wt[p];
-      acc += kp.nonrel ? 0.5 * w * m * uu : w * m * uu / (sqrt(1.0 + uu / c2) + 1.0);
     }
+    const double ux = u0[p], uy = u1[p], uz = u2[p];
+    const double uu = ux * ux + uy * uy + uz * uz;
+    const double wm = (double)wt[p] * kp.m[s];
+    // (gamma - 1) c^2 = |u|^2 / (sqrt(1 + |u|^2/c^2) + 1), without cancellation
+    acc += kp.nonrel ? 0.5 * wm * uu : wm * uu / (sqrt(1.0 + uu * invc2) + 1.0);
   }
   red[lane] = acc;
   __syncthreads();
@@ -831,7 +810,7 @@ __global__ __launch_bounds__(64) void k_kinetic(KParams kp, const int32_t *__res
     if (lane < o) red[lane] += red[lane + o];
     __syncthreads();
   }
-  if (lane == 0) partials[blockIdx.x] = red[0];
+  if (lane == 0) partials[blk] = red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -954,7 +933,8 @@ void scatter_impl(const KParams &kp, const PartPtrs &src, const uint8_t *dirc, c
 
 template <typename T, int DIM, int G>
 void kinetic_impl(const KParams &kp, const PartPtrs &pp, double *partials, hipStream_t st) {
-  hipLaunchKernelGGL((k_kinetic<T, DIM, G>), dim3(kRedBlocks), dim3(64), 0, st, kp, pp.bin_start, cp<T>(pp.u[0]),
+  const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
+  hipLaunchKernelGGL((k_kinetic<T, DIM, G>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, cp<T>(pp.u[0]),
                      cp<T>(pp.u[1]), cp<T>(pp.u[2]), cp<T>(pp.w), partials);
 }
 

@@ -29,7 +29,7 @@ struct KParams {
 // Offsets (in bytes) of the regions carved out of the caller's workspace.
 struct Layout {
   size_t S, cnt, pre, total, scan_tmp, dirc, err, gm_V, gm_t, gm_b, gm_r, gm_part, gm_small, red_part;
-  size_t gs_k0, gs_k1, gs_v0, gs_v1, gs_hist, slotmap, stB, stE, sink, end;
+  size_t gs_k0, gs_k1, gs_v0, gs_v1, gs_hist, slotmap, stB, stE, sink, kin_part, end;
 };
 
 constexpr int kMaxRestart = 64;
@@ -70,6 +70,8 @@ void launch_sort_scatter(const KParams &kp, int prec, int group, const PartPtrs 
                          const uint16_t *pre, const int32_t *bin_start_new, int32_t *cell_out, void *const off_out[3],
                          void *const u_out[3], void *w_out, int ntot, int32_t *err, int32_t *perm, void *sink,
                          hipStream_t st);
+// partials: one double per block of 64/group cells (at most ncells)
+// partials: one double per block of 64/group cells (at most ncells)
 void launch_kinetic(const KParams &kp, int prec, int group, const PartPtrs &pp, double *partials, hipStream_t st);
 
 // ---- general stable sort by bin (sort.hip) ----
@@ -116,5 +118,7 @@ void launch_maxpy(const double *V, size_t ld, int nvec, const double *h, double 
 void launch_axpby(double a, const double *x, double b, double *y, size_t n, hipStream_t st);
 void launch_sumsq_partials(const double *x, size_t n, double *partials, hipStream_t st);
 void launch_reduce_partials(const double *partials, int nparts, int nvec, double *res, hipStream_t st);
+// res[0] = sum of in[0..n) in a fixed order (tmp: kRedBlocks doubles)
+void launch_reduce_long(const double *in, int n, double *tmp, double *res, hipStream_t st);
 
 }  // namespace relsim
