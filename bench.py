@@ -35,7 +35,8 @@ def log(*a):
 
 
 def kernel_bytes(name, wl, prec, n, nbins, ncells):
-    """Algorithmic bytes of one launch of a particle kernel."""
+    """Algorithmic bytes of one launch of a kernel: what it must read and
+    write at least once (particle state, grid fields, per-cell moments)."""
     T = 4 if prec == "mixed" else 8
     d = wl.dim
     noff = 27 if d == 3 else 9
@@ -154,6 +155,7 @@ def run_precision(prec, wl, host, steps, warmup, rtol, want_kernels=True, group=
     sol = sum(e[1].elapsed_time(e[2]) for e in evs)
     pus = sum(e[2].elapsed_time(e[3]) for e in evs)
     ene = sum(e[3].elapsed_time(e[4]) for e in evs)
+    hot_steps = sorted(e[0].elapsed_time(e[1]) + e[2].elapsed_time(e[3]) for e in evs)
     kern = relsim.timing_read(ctx)
     hot = dep + pus
     res = {
@@ -161,6 +163,7 @@ def run_precision(prec, wl, host, steps, warmup, rtol, want_kernels=True, group=
         "particles": n,
         "value": n * steps / (hot * 1e-3),
         "hot_ms_per_step": hot / steps,
+        "hot_ms_median_step": hot_steps[len(hot_steps) // 2],
         "deposit_ms_per_step": dep / steps,
         "push_sort_ms_per_step": pus / steps,
         "solve_ms_per_step": sol / steps,
@@ -177,6 +180,42 @@ def run_precision(prec, wl, host, steps, warmup, rtol, want_kernels=True, group=
     del parts, ctx, E, B, nb, Eth, J, M
     torch.cuda.empty_cache()
     return res
+
+
+def device_copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Achievable HBM bandwidth on this GPU: a device-to-device copy of 1 GiB
+    (read + write bytes over time), the practical ceiling beside the 8 TB/s
+    specification."""
+    import torch
+
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def path_bytes_per_particle(wl, prec, n, nbins, ncells):
+    """Algorithmic bytes per particle-step of this design (deposit + push +
+    re-sort, as separate kernels) and the single-pass minimum (one read and
+    one write of the particle state plus the per-step grid traffic: M and
+    J-hat written once, E_theta and B^n read once)."""
+    T = 4 if prec == "mixed" else 8
+    d = wl.dim
+    noff = 27 if d == 3 else 9
+    this = sum(kernel_bytes(k, wl, prec, n, nbins, ncells) for k in
+               ("deposit_cells", "assemble_nodes", "push", "sort_scatter")) / n
+    state = 4 + (d + 4) * T
+    grid = ncells * (8 * 9 * noff + 3 * 24) / n
+    return this, 2 * state + grid
 
 
 def cpu_baseline(wl, host, nsample):
@@ -222,8 +261,7 @@ def main():
                     help="also run one device copy of this size (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, 'How the path would "
-              "shard'); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU; the multi-GPU path is not built. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -246,6 +284,7 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    copy_gbs = device_copy_bandwidth()
 
     precs = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
     results = {}
@@ -274,6 +313,16 @@ def main():
             b = kernel_bytes(k, wl, head["precision"], n, nbins, wl.ncells)
             per_kernel[k] = round(b / (v["ms_per_launch"] * 1e-3) / 1e9, 1)
         roof["achieved_by_kernel_GBs"] = per_kernel
+        roof["measured_copy_GBs"] = round(copy_gbs, 1)
+        roof["frac_of_measured_copy"] = round(ach / copy_gbs, 4)
+        this, fused = path_bytes_per_particle(wl, head["precision"], n, nbins, wl.ncells)
+        roof["path"] = {
+            "bytes_per_particle_step": round(this, 2),
+            "achieved_GBs": round(head["value"] * this / 1e9, 1),
+            "frac": round(head["value"] * this / 1e9 / PEAK_HBM_GBS, 4),
+            "single_pass_min_bytes_per_particle_step": round(fused, 2),
+            "frac_single_pass_min": round(head["value"] * fused / 1e9 / PEAK_HBM_GBS, 4),
+        }
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -294,8 +343,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if head["precision"] == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": "%s: 2D double Harris sheet %dx%d cells, %d particles/cell/species, %d particles, "
-                               "dt = 0.5 dx/c, GMRES rtol %g" % (wl.name, wl.nx, wl.ny, wl.ppc, n, args.rtol),
+        "config": {"workload": "%s: %dD double Harris sheet %s cells, %d particles/cell/species, %d particles, "
+                               "dt = 0.5 dx/c, GMRES rtol %g" % (
+                                   wl.name, wl.dim, "x".join(str(v) for v in (wl.nx, wl.ny, wl.nz)[:wl.dim]), wl.ppc,
+                                   n, args.rtol),
                    "precision": head["precision"], "parallelism": "single GPU"},
         "results": results,
         "roofline": roof,
