@@ -24,6 +24,10 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
+    # fuse a*b + c only inside one source expression: which products the
+    # backend would otherwise fuse depends on each instance's scheduling, so
+    # kernels computing the same formula could round differently
+    "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
     "-I", CSRC,

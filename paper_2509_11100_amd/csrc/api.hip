@@ -172,7 +172,6 @@ Layout make_layout(const relsim_params *p) {
   L.gs_v0 = take(np * 4);
   L.gs_v1 = take(np * 4);
   L.gs_hist = take(gsort_tmp_elems(np) * 4);
-  L.slotmap = take(nc * 16);
   const size_t ng = (size_t)(p->nx + 2) * (p->ny + 2) * (p->dim == 3 ? p->nz + 2 : 1);
   L.stB = take(ng * 4 * es);
   L.stE = take(ng * 4 * es);
@@ -202,6 +201,16 @@ KParams make_kparams(const relsim_params *p) {
   k.tx = tile(k.nx, p->dim == 3 ? 8 : 16);
   k.ty = tile(k.ny, p->dim == 3 ? 4 : 8);
   k.tz = p->dim == 3 ? tile(k.nz, 4) : 1;
+  auto lg = [](int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+  };
+  k.ltx = lg(k.tx);
+  k.lty = lg(k.ty);
+  k.ltz = lg(k.tz);
+  k.ntx = k.nx / k.tx;
+  k.nty = k.ny / k.ty;
   k.dx = p->dx;
   k.dy = p->dy;
   k.dz = p->dim == 3 ? p->dz : 1.0;
@@ -382,8 +391,6 @@ int relsim_init(const relsim_params *p, void *hip_stream, void *workspace, size_
     return RELSIM_EHIP;
   }
   // processing order of the particle kernels: tile-major slot -> cell table
-  c->kp.slotmap = c->at<int4>(L.slotmap);
-  launch_fill_slotmap(c->kp, c->at<int4>(L.slotmap), c->st);
   if (hipGetLastError() != hipSuccess) {
     relsim_finalize(c);
     return RELSIM_EHIP;

@@ -42,15 +42,18 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// Cell visited by processing slot `slot` (tile-major order; the tile extents
-// divide the grid extents).
-__device__ __forceinline__ int slot_cell(const KParams &kp, int slot) {
-  const int tcell = kp.tx * kp.ty * kp.tz;
-  const int tile = slot / tcell, r = slot - tile * tcell;
-  const int ntx = kp.nx / kp.tx, nty = kp.ny / kp.ty;
-  const int tix = tile % ntx, tiy = (tile / ntx) % nty, tiz = tile / (ntx * nty);
-  const int lx = r % kp.tx, ly = (r / kp.tx) % kp.ty, lz = r / (kp.tx * kp.ty);
-  return (tix * kp.tx + lx) + kp.nx * ((tiy * kp.ty + ly) + kp.ny * (tiz * kp.tz + lz));
+// Grid coordinates of the cell visited by processing slot `slot`: tiles in
+// row-major order, cells row-major inside a tile (power-of-two tile extents
+// dividing the grid).
+__device__ __forceinline__ void slot_coords(const KParams &kp, int slot, int &i, int &j, int &k) {
+  const int lt = kp.ltx + kp.lty + kp.ltz;
+  const int tile = slot >> lt, r = slot & ((1 << lt) - 1);
+  const int lx = r & (kp.tx - 1), ly = (r >> kp.ltx) & (kp.ty - 1), lz = r >> (kp.ltx + kp.lty);
+  const int t2 = tile / kp.ntx;
+  const int tiz = t2 / kp.nty;
+  i = ((tile - t2 * kp.ntx) << kp.ltx) + lx;
+  j = ((t2 - tiz * kp.nty) << kp.lty) + ly;
+  k = (tiz << kp.ltz) + lz;
 }
 
 // Reciprocal and reciprocal square root: the hardware instructions (1 ulp)
@@ -197,20 +200,16 @@ struct CellSpan {
   bool valid;
 };
 
-// The cell of processing slot blk * (64/G) + grp, from the precomputed slot
-// table {cell, i, j, k} (no integer division in the kernels).
+// The cell of processing slot blk * (64/G) + grp and its particle range.
 template <int G>
 __device__ __forceinline__ CellSpan slot_span(const KParams &kp, const int32_t *__restrict__ bin_start, int blk,
                                               int grp) {
   const int slot = blk * (64 / G) + grp;
   const bool valid = slot < kp.ncells;
-  const int4 c = kp.slotmap[valid ? slot : 0];
   CellSpan cs;
   cs.valid = valid;
-  cs.cell = c.x;
-  cs.ci = c.y;
-  cs.cj = c.z;
-  cs.ck = c.w;
+  slot_coords(kp, valid ? slot : 0, cs.ci, cs.cj, cs.ck);
+  cs.cell = cs.ci + kp.nx * (cs.cj + kp.ny * cs.ck);
   cs.gc = (cs.ci + 1) + kp.gx * (cs.cj + 1) + kp.gxy * (kp.dim == 3 ? cs.ck + 1 : 0);
   const int S = kp.nspecies, b0 = cs.cell * S;
 #pragma unroll
@@ -218,13 +217,6 @@ __device__ __forceinline__ CellSpan slot_span(const KParams &kp, const int32_t *
   cs.pbeg = cs.bound[0];
   cs.pend = valid ? bin_start[b0 + S] : 0;
   return cs;
-}
-
-__global__ __launch_bounds__(256) void k_fill_slotmap(KParams kp, int4 *__restrict__ map) {
-  const int slot = blockIdx.x * 256 + threadIdx.x;
-  if (slot >= kp.ncells) return;
-  const int c = slot_cell(kp, slot);
-  map[slot] = make_int4(c, c % kp.nx, (c / kp.nx) % kp.ny, c / (kp.nx * kp.ny));
 }
 
 // Wave-uniform number of rounds: max over the wave of ceil(count / G).
@@ -994,10 +986,6 @@ void launch_stage_field(const KParams &kp, int prec, const double *F, void *out,
 void launch_deposit_cells(const KParams &kp, int prec, int group, const PartPtrs &pp, const void *Bst, void *S,
                           hipStream_t st) {
   dispatch<DepositF>(prec, kp.dim, group, kp, pp, Bst, S, st);
-}
-
-void launch_fill_slotmap(const KParams &kp, int4 *map, hipStream_t st) {
-  hipLaunchKernelGGL(k_fill_slotmap, dim3((kp.ncells + 255) / 256), dim3(256), 0, st, kp, map);
 }
 
 void launch_assemble(const KParams &kp, int prec, const void *S, double *J, double *M, hipStream_t st) {

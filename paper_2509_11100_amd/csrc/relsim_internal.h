@@ -14,10 +14,11 @@ namespace relsim {
 // Constants handed to every particle/grid kernel by value.
 struct KParams {
   int dim, nx, ny, nz, ncells, nspecies, nbins, nonrel;
-  int tx, ty, tz;  // tile extents of the particle kernels' cell order (divide nx, ny, nz)
-  int gx, gxy;     // strides of the ghosted field copies: nx + 2, (nx + 2)(ny + 2)
-  int nghost;      // points of a ghosted field copy
-  const int4 *slotmap;  // [ncells] {cell, i, j, k} of each processing slot (workspace)
+  int tx, ty, tz;     // tile extents of the particle kernels' cell order (powers of two dividing nx, ny, nz)
+  int ltx, lty, ltz;  // their base-2 logarithms
+  int ntx, nty;       // tiles along x and y
+  int gx, gxy;        // strides of the ghosted field copies: nx + 2, (nx + 2)(ny + 2)
+  int nghost;         // points of a ghosted field copy
   double dx, dy, dz, dt, c, theta, V;
   double inv_dx, inv_dy, inv_dz, inv_c, inv_c2, inv_V;
   double q[8], m[8], beta[8];
@@ -29,7 +30,7 @@ struct KParams {
 // Offsets (in bytes) of the regions carved out of the caller's workspace.
 struct Layout {
   size_t S, cnt, pre, total, scan_tmp, dirc, err, gm_V, gm_t, gm_b, gm_r, gm_part, gm_small, red_part;
-  size_t gs_k0, gs_k1, gs_v0, gs_v1, gs_hist, slotmap, stB, stE, sink, kin_part, end;
+  size_t gs_k0, gs_k1, gs_v0, gs_v1, gs_hist, stB, stE, sink, kin_part, end;
 };
 
 constexpr int kMaxRestart = 64;
@@ -57,7 +58,6 @@ void launch_stage_field(const KParams &kp, int prec, const double *F, void *out,
 void launch_deposit_cells(const KParams &kp, int prec, int group, const PartPtrs &pp, const void *Bst, void *S,
                           hipStream_t st);
 void launch_assemble(const KParams &kp, int prec, const void *S, double *J, double *M, hipStream_t st);
-void launch_fill_slotmap(const KParams &kp, int4 *map, hipStream_t st);
 // `sink`: kSinkSlots * 64 * 8 bytes of workspace that lanes without a
 // particle store into (contents meaningless)
 void launch_push(const KParams &kp, int prec, int group, const PartPtrs &pp, const void *Est, const void *Bst,
