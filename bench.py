@@ -54,8 +54,8 @@ def kernel_bytes(name, wl, prec, n, nbins, ncells):
         # in: offsets + momentum, E_theta, B^n; out: offsets + momentum + 1-byte move code
         return n * (2 * (d + 3) * T + 1) + 2 * ncells * grid
     if name == "sort_scatter":
-        # in: full state + move code; out: full state + cell id
-        return n * (2 * (d + 4) * T + 1 + 4)
+        # in: offsets, momentum, weight + move code; out: offsets, momentum, weight
+        return n * (2 * (d + 4) * T + 1)
     return None
 
 

@@ -88,7 +88,12 @@ typedef struct {
 typedef struct {
   int64_t n;                   /* particles in use                                */
   int32_t *bin_start;          /* [ncells*nspecies + 1]                           */
-  int32_t *cell;               /* [capacity] linear cell index (kept by sorts)    */
+  int32_t *cell;               /* [capacity] linear cell index: input of
+                                  relsim_sort, written by relsim_sort and
+                                  relsim_fill_cells; relsim_push leaves it
+                                  stale (the bins already say where each
+                                  particle is, and the re-sort saves the
+                                  4-byte write per particle)                    */
   void *off[3];
   void *u[3];
   void *w;
@@ -144,6 +149,11 @@ int relsim_field_solve(relsim_ctx *ctx, const double *M, const double *Jhat, con
 int relsim_push(relsim_ctx *ctx, relsim_particles *part, const double *E_theta, const double *B_n, int32_t resort,
                 int32_t *new_index);
 
+/* Write part->cell (front set) from bin_start: particle p of bin b gets cell
+ * b / nspecies.  Needed after relsim_push before anything reads the cell
+ * ids (the adjoint entry points read state_n->cell). */
+int relsim_fill_cells(relsim_ctx *ctx, relsim_particles *part);
+
 /* a7 (S7): out[0..3] = kinetic, electric, magnetic, total energy (host
  * array), accumulated in FP64 in both precisions.  Synchronous. */
 int relsim_energy(relsim_ctx *ctx, const relsim_particles *part, const double *E, const double *B, double out[4]);
@@ -169,7 +179,8 @@ int relsim_apply_AT(relsim_ctx *ctx, const double *M, const double *x, double *o
  * accumulators zeroed by the caller first.
  *
  * relsim_push_adjoint (adjoint of S1, S2, S6): state_n is the particle state
- * before the push (bin-sorted, with cell ids); new_index maps it to the
+ * before the push (bin-sorted, with its cell ids written, e.g. by
+ * relsim_fill_cells); new_index maps it to the
  * order of lam_x_in / lam_u_in (the cotangents of x^{n+3/2}, u^{n+1}; NULL =
  * same order).  Writes lam_x_out, lam_u_out (cotangents of x^{n+1/2}, u^n
  * through the push) and ADDS into lam_E_theta and lam_B_n. */

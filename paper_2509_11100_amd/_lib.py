@@ -80,6 +80,7 @@ def load() -> C.CDLL:
         "relsim_field_solve_adjoint": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i32), dp]),
         "relsim_deposit_adjoint": (C.c_int, [vp, pt, vp, vp, vp, vp, vp, vp]),
         "relsim_energy": (C.c_int, [vp, pt, vp, vp, dp]),
+        "relsim_fill_cells": (C.c_int, [vp, pt]),
         "relsim_curl_nc": (C.c_int, [vp, vp, vp]),
         "relsim_curl_cn": (C.c_int, [vp, vp, vp]),
         "relsim_apply_A": (C.c_int, [vp, vp, vp, vp]),
@@ -101,7 +102,7 @@ def exported_symbols():
     """Names of the C functions this binding expects the library to export."""
     return [
         "relsim_workspace_bytes", "relsim_init", "relsim_finalize", "relsim_sort", "relsim_deposit_moments",
-        "relsim_field_solve", "relsim_push", "relsim_energy", "relsim_curl_nc", "relsim_curl_cn",
+        "relsim_field_solve", "relsim_push", "relsim_fill_cells", "relsim_energy", "relsim_curl_nc", "relsim_curl_cn",
         "relsim_apply_A", "relsim_apply_AT", "relsim_push_adjoint", "relsim_field_solve_adjoint",
         "relsim_deposit_adjoint", "relsim_timing_enable", "relsim_timing_reset", "relsim_timing_read",
         "relsim_strerror", "relsim_last_error",

@@ -478,8 +478,8 @@ int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, cons
     void *offb[3] = {pt->off_back[0], pt->off_back[1], pt->off_back[2]};
     void *ub[3] = {pt->u_back[0], pt->u_back[1], pt->u_back[2]};
     timed(c, "sort_scatter", [&] {
-      launch_sort_scatter(c->kp, c->p.precision, Gs, front(pt), dirc, pre, pt->bin_start_back, pt->cell_back, offb, ub,
-                          pt->w_back, (int)pt->n, err, new_index, c->at<char>(c->L.sink), c->st);
+      launch_sort_scatter(c->kp, c->p.precision, Gs, front(pt), dirc, pre, pt->bin_start_back, offb, ub, pt->w_back,
+                          (int)pt->n, err, new_index, c->at<char>(c->L.sink), c->st);
     });
     rc = launch_status(c, "relsim_push");
     if (rc) return rc;
@@ -487,6 +487,15 @@ int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, cons
     return RELSIM_OK;
   }
   return launch_status(c, "relsim_push");
+}
+
+int relsim_fill_cells(relsim_ctx *c, relsim_particles *pt) {
+  if (!c) return RELSIM_EINVAL;
+  int rc = check_particles(c, pt, false);
+  if (rc) return rc;
+  if (!pt->cell) return fail(c, RELSIM_EINVAL, "null cell array");
+  launch_fill_cells(c->kp, pt->bin_start, pt->cell, c->st);
+  return launch_status(c, "relsim_fill_cells");
 }
 
 int relsim_energy(relsim_ctx *c, const relsim_particles *pt, const double *E, const double *B, double out[4]) {

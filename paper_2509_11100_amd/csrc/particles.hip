@@ -670,7 +670,7 @@ __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *
                                                      const T *__restrict__ u1, const T *__restrict__ u2,
                                                      const T *__restrict__ wt, const uint8_t *__restrict__ dirc,
                                                      const uint16_t *__restrict__ pre,
-                                                     const int32_t *__restrict__ bsn, int32_t *__restrict__ cell_out,
+                                                     const int32_t *__restrict__ bsn,
                                                      T *__restrict__ q0, T *__restrict__ q1, T *__restrict__ q2,
                                                      T *__restrict__ v0, T *__restrict__ v1, T *__restrict__ v2,
                                                      T *__restrict__ wo, int ntot, int32_t *__restrict__ err,
@@ -678,7 +678,6 @@ __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *
   constexpr int NDIR = DIM == 3 ? 27 : 9;
   constexpr int NGRP = 64 / G;
   __shared__ int lbase[NGRP * 8 * NDIR];  // next destination of each (group, species, move) key
-  __shared__ int ldc[NGRP * NDIR];        // destination cell of each (group, move)
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
@@ -692,7 +691,6 @@ __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *
                      kp.nx * (wrapi(cs.cj + my, kp.ny) + kp.ny * (DIM == 3 ? wrapi(cs.ck + mz, kp.nz) : 0));
       const int d = dc * S + s;
       lbase[grp * nkey + t] = bsn[d] + (int)pre[(size_t)dir * nb + d];
-      if (s == 0) ldc[grp * NDIR + dir] = dc;
     }
   }
   __syncthreads();
@@ -755,7 +753,6 @@ __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *
     *(ok ? v1 + pos : sinkT) = cur.uy;
     *(ok ? v2 + pos : sinkT) = cur.uz;
     *(ok ? wo + pos : sinkT) = cur.w;
-    *(ok ? cell_out + pos : sinkI) = ldc[grp * NDIR + dcur];
     if constexpr (PERM) *(ok ? perm + p : sinkI) = pos;
     __builtin_amdgcn_wave_barrier();
     cur = nxt;
@@ -763,6 +760,16 @@ __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *
     p = pn;
   }
   if (__ballot(bad) && lane == 0) atomicOr(err, 2);
+}
+
+// ---------------------------------------------------------------------------
+// cell id of every particle from the bin ranges (one wave per cell)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_fill_cells(KParams kp, const int32_t *__restrict__ bin_start,
+                                                   int32_t *__restrict__ cell) {
+  const int c = blockIdx.x;
+  const int b = bin_start[c * kp.nspecies], e = bin_start[(c + 1) * kp.nspecies];
+  for (int p = b + (int)threadIdx.x; p < e; p += 64) cell[p] = c;
 }
 
 // ---------------------------------------------------------------------------
@@ -906,19 +913,19 @@ void push_impl(const KParams &kp, const PartPtrs &pp, const void *Est, const voi
 
 template <typename T, int DIM, int G>
 void scatter_impl(const KParams &kp, const PartPtrs &src, const uint8_t *dirc, const uint16_t *pre, const int32_t *bsn,
-                  int32_t *cell_out, void *const off_out[3], void *const u_out[3], void *w_out, int ntot, int32_t *err,
+                  void *const off_out[3], void *const u_out[3], void *w_out, int ntot, int32_t *err,
                   int32_t *perm, void *sink, hipStream_t st) {
   const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
   if (perm)
     hipLaunchKernelGGL((k_sort_scatter<T, DIM, G, true>), dim3(nblk), dim3(64), 0, st, kp, src.bin_start,
                        cp<T>(src.off[0]), cp<T>(src.off[1]), cp<T>(src.off[2]), cp<T>(src.u[0]), cp<T>(src.u[1]),
-                       cp<T>(src.u[2]), cp<T>(src.w), dirc, pre, bsn, cell_out, mp<T>(off_out[0]), mp<T>(off_out[1]),
+                       cp<T>(src.u[2]), cp<T>(src.w), dirc, pre, bsn, mp<T>(off_out[0]), mp<T>(off_out[1]),
                        mp<T>(off_out[2]), mp<T>(u_out[0]), mp<T>(u_out[1]), mp<T>(u_out[2]), mp<T>(w_out), ntot, err,
                        perm, sink);
   else
     hipLaunchKernelGGL((k_sort_scatter<T, DIM, G, false>), dim3(nblk), dim3(64), 0, st, kp, src.bin_start,
                        cp<T>(src.off[0]), cp<T>(src.off[1]), cp<T>(src.off[2]), cp<T>(src.u[0]), cp<T>(src.u[1]),
-                       cp<T>(src.u[2]), cp<T>(src.w), dirc, pre, bsn, cell_out, mp<T>(off_out[0]), mp<T>(off_out[1]),
+                       cp<T>(src.u[2]), cp<T>(src.w), dirc, pre, bsn, mp<T>(off_out[0]), mp<T>(off_out[1]),
                        mp<T>(off_out[2]), mp<T>(u_out[0]), mp<T>(u_out[1]), mp<T>(u_out[2]), mp<T>(w_out), ntot, err,
                        perm, sink);
 }
@@ -1027,11 +1034,15 @@ void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream
 }
 
 void launch_sort_scatter(const KParams &kp, int prec, int group, const PartPtrs &src, const uint8_t *dirc,
-                         const uint16_t *pre, const int32_t *bin_start_new, int32_t *cell_out, void *const off_out[3],
+                         const uint16_t *pre, const int32_t *bin_start_new, void *const off_out[3],
                          void *const u_out[3], void *w_out, int ntot, int32_t *err, int32_t *perm, void *sink,
                          hipStream_t st) {
-  dispatch<ScatterF>(prec, kp.dim, group, kp, src, dirc, pre, bin_start_new, cell_out, off_out, u_out, w_out, ntot, err,
+  dispatch<ScatterF>(prec, kp.dim, group, kp, src, dirc, pre, bin_start_new, off_out, u_out, w_out, ntot, err,
                      perm, sink, st);
+}
+
+void launch_fill_cells(const KParams &kp, const int32_t *bin_start, int32_t *cell, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_cells, dim3(kp.ncells), dim3(64), 0, st, kp, bin_start, cell);
 }
 
 void launch_kinetic(const KParams &kp, int prec, int group, const PartPtrs &pp, double *partials, hipStream_t st) {

@@ -67,10 +67,14 @@ void launch_sort_offsets(const KParams &kp, const uint16_t *cnt, uint16_t *pre, 
 void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream_t st);
 size_t scan_tmp_elems(int n);
 void launch_sort_scatter(const KParams &kp, int prec, int group, const PartPtrs &src, const uint8_t *dirc,
-                         const uint16_t *pre, const int32_t *bin_start_new, int32_t *cell_out, void *const off_out[3],
+                         const uint16_t *pre, const int32_t *bin_start_new, void *const off_out[3],
                          void *const u_out[3], void *w_out, int ntot, int32_t *err, int32_t *perm, void *sink,
                          hipStream_t st);
+// cell[p] for every particle from the bin ranges
+void launch_fill_cells(const KParams &kp, const int32_t *bin_start, int32_t *cell, hipStream_t st);
 // partials: one double per block of 64/group cells (at most ncells)
+// cell[p] for every particle from the bin ranges
+void launch_fill_cells(const KParams &kp, const int32_t *bin_start, int32_t *cell, hipStream_t st);
 // partials: one double per block of 64/group cells (at most ncells)
 void launch_kinetic(const KParams &kp, int prec, int group, const PartPtrs &pp, double *partials, hipStream_t st);
 

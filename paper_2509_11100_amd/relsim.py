@@ -185,6 +185,10 @@ class Particles:
 
     @property
     def cell(self) -> torch.Tensor:
+        """Cell id per particle, written from the bin ranges on access
+        (relsim_fill_cells): the push does not maintain it."""
+        self.s.n = self.n
+        self.ctx.check(self.ctx.lib.relsim_fill_cells(self.ctx.handle, C.byref(self.s)))
         return self.sets[self.front]["cell"][: self.n]
 
     @property
