@@ -213,7 +213,7 @@ def path_bytes_per_particle(wl, prec, n, nbins, ncells):
     noff = 27 if d == 3 else 9
     this = sum(kernel_bytes(k, wl, prec, n, nbins, ncells) for k in
                ("deposit_cells", "assemble_nodes", "push", "sort_scatter")) / n
-    state = 4 + (d + 4) * T
+    state = (d + 4) * T
     grid = ncells * (8 * 9 * noff + 3 * 24) / n
     return this, 2 * state + grid
 
