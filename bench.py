@@ -51,8 +51,9 @@ def kernel_bytes(name, wl, prec, n, nbins, ncells):
         nmom = 93 if d == 2 else 267
         return ncells * nmom * T + ncells * (grid + 8 * 9 * noff)
     if name == "push":
-        # in: offsets + momentum, E_theta, B^n; out: offsets + momentum + 1-byte move code
-        return n * (2 * (d + 3) * T + 1) + 2 * ncells * grid
+        # in: offsets + (momentum, weight) records, E_theta, B^n; out: the
+        # same records (whole, weight unchanged) + 1-byte move code
+        return n * (2 * (d + 4) * T + 1) + 2 * ncells * grid
     if name == "sort_scatter":
         # in: offsets, momentum, weight + move code; out: offsets, momentum, weight
         return n * (2 * (d + 4) * T + 1)

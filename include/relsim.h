@@ -77,14 +77,16 @@ typedef struct {
                                   8, 16, 32 or 64                                 */
 } relsim_params;
 
-/* Particle state: structure of arrays, sorted by bin = cell * nspecies + s,
- * so that the particles of (cell, species) occupy
- * [bin_start[bin], bin_start[bin+1]).  Each array exists twice ("front" and
+/* Particle state, sorted by bin = cell * nspecies + s, so that the
+ * particles of (cell, species) occupy [bin_start[bin], bin_start[bin+1]).
+ * Element type T is double for RELSIM_FP64 and float for RELSIM_MIXED.  The
+ * record of particle p is split over three packed arrays (structure of small
+ * arrays): xy[p] = (off_x, off_y) (2 T, aligned to 2 T), uw[p] = (u_x, u_y,
+ * u_z, w) (4 T, aligned to 4 T) and, in 3D, z[p] = off_z.  off in [0,1) is the
+ * position inside the cell in units of the cell size; u = gamma v; w = number
+ * of physical particles represented.  Each array exists twice ("front" and
  * "back"); the re-sort writes into the back set and then swaps the two sets
- * (and the two bin_start arrays) inside this struct.  off[d] in [0,1) is the
- * position inside the cell in units of the cell size; u[k] = gamma v_k;
- * w = number of physical particles represented.  Element type is double for
- * RELSIM_FP64 and float for RELSIM_MIXED; off[2] is unused in 2D. */
+ * (and the two bin_start arrays) inside this struct. */
 typedef struct {
   int64_t n;                   /* particles in use                                */
   int32_t *bin_start;          /* [ncells*nspecies + 1]                           */
@@ -94,14 +96,14 @@ typedef struct {
                                   stale (the bins already say where each
                                   particle is, and the re-sort saves the
                                   4-byte write per particle)                    */
-  void *off[3];
-  void *u[3];
-  void *w;
+  void *xy;                    /* [capacity][2] T                                 */
+  void *uw;                    /* [capacity][4] T                                 */
+  void *z;                     /* [capacity] T, 3D only (NULL in 2D)              */
   int32_t *bin_start_back;
   int32_t *cell_back;
-  void *off_back[3];
-  void *u_back[3];
-  void *w_back;
+  void *xy_back;
+  void *uw_back;
+  void *z_back;
   const uint8_t *species;      /* [n] species id, read only by relsim_sort        */
 } relsim_particles;
 

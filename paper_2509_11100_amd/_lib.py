@@ -38,9 +38,9 @@ class relsim_particles(C.Structure):
     _fields_ = [
         ("n", C.c_int64),
         ("bin_start", C.c_void_p), ("cell", C.c_void_p),
-        ("off", C.c_void_p * 3), ("u", C.c_void_p * 3), ("w", C.c_void_p),
+        ("xy", C.c_void_p), ("uw", C.c_void_p), ("z", C.c_void_p),
         ("bin_start_back", C.c_void_p), ("cell_back", C.c_void_p),
-        ("off_back", C.c_void_p * 3), ("u_back", C.c_void_p * 3), ("w_back", C.c_void_p),
+        ("xy_back", C.c_void_p), ("uw_back", C.c_void_p), ("z_back", C.c_void_p),
         ("species", C.c_void_p),
     ]
 

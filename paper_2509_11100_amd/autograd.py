@@ -41,11 +41,13 @@ class Stepper:
             raise ValueError("state larger than the context's max_particles")
         f = p.sets[p.front]
         p.n = n
-        for d in range(self.ctx.dim):
-            f["off"][d][:n].copy_(off[d])
+        for d in range(2):
+            f["xy"][:n, d].copy_(off[d])
+        if self.ctx.dim == 3:
+            f["z"][:n].copy_(off[2])
         for k in range(3):
-            f["u"][k][:n].copy_(u[k])
-        f["w"][:n].copy_(w)
+            f["uw"][:n, k].copy_(u[k])
+        f["uw"][:n, 3].copy_(w)
         f["cell"][:n].copy_(cell)
         f["bin_start"].copy_(bin_start)
         p._bind()

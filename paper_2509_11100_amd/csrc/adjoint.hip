@@ -31,8 +31,8 @@ struct PState {
 
 template <int DIM>
 __device__ __forceinline__ PState load_particle(const KParams &kp, const int32_t *__restrict__ bin_start,
-                                                const int32_t *__restrict__ cell, const double *const *off,
-                                                const double *const *uu, const double *__restrict__ w, int p) {
+                                                const int32_t *__restrict__ cell, const double *__restrict__ xy,
+                                                const double *__restrict__ uw, const double *__restrict__ zz, int p) {
   PState st;
   const int c = cell[p];
   const int S = kp.nspecies;
@@ -53,13 +53,13 @@ __device__ __forceinline__ PState load_particle(const KParams &kp, const int32_t
   st.ci = c % kp.nx;
   st.cj = (c / kp.nx) % kp.ny;
   st.ck = c / (kp.nx * kp.ny);
-  st.f[0] = off[0][p];
-  st.f[1] = off[1][p];
-  st.f[2] = DIM == 3 ? off[2][p] : 0.0;
-  st.u[0] = uu[0][p];
-  st.u[1] = uu[1][p];
-  st.u[2] = uu[2][p];
-  st.w = w[p];
+  st.f[0] = xy[2 * (size_t)p];
+  st.f[1] = xy[2 * (size_t)p + 1];
+  st.f[2] = DIM == 3 ? zz[p] : 0.0;
+  st.u[0] = uw[4 * (size_t)p];
+  st.u[1] = uw[4 * (size_t)p + 1];
+  st.u[2] = uw[4 * (size_t)p + 2];
+  st.w = uw[4 * (size_t)p + 3];
   return st;
 }
 
@@ -155,7 +155,7 @@ __device__ __forceinline__ void atomic_add3(double *g, size_t N, int idx, double
 
 struct AdjIn {
   const int32_t *bin_start, *cell;
-  const double *off[3], *u[3], *w;
+  const double *xy, *uw, *z;  // packed (off_x, off_y), (u_x, u_y, u_z, w); off_z
 };
 
 template <int DIM>
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(256) void k_push_adjoint(KParams kp, AdjIn in, int 
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= n) return;
   const size_t N = (size_t)kp.ncells;
-  const PState st = load_particle<DIM>(kp, in.bin_start, in.cell, in.off, in.u, in.w, p);
+  const PState st = load_particle<DIM>(kp, in.bin_start, in.cell, in.xy, in.uw, in.z, p);
   const double c2 = kp.c * kp.c;
   Stencil<DIM> sc, sn;
   stencil<DIM>(kp, st, true, sc);
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(256) void k_deposit_adjoint(KParams kp, AdjIn in, i
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p >= n) return;
   const size_t N = (size_t)kp.ncells;
-  const PState st = load_particle<DIM>(kp, in.bin_start, in.cell, in.off, in.u, in.w, p);
+  const PState st = load_particle<DIM>(kp, in.bin_start, in.cell, in.xy, in.uw, in.z, p);
   const double c2 = kp.c * kp.c;
   Stencil<DIM> sc, sn;
   stencil<DIM>(kp, st, true, sc);
@@ -425,7 +425,7 @@ void launch_push_adjoint(const KParams &kp, const AdjInPtrs &in, int n, const do
                          const int32_t *new_index, const double *lx_in, const double *lu_in, double *lx_out,
                          double *lu_out, double *lEth, double *lB, hipStream_t st) {
   if (n <= 0) return;
-  AdjIn a{in.bin_start, in.cell, {in.off[0], in.off[1], in.off[2]}, {in.u[0], in.u[1], in.u[2]}, in.w};
+  AdjIn a{in.bin_start, in.cell, in.xy, in.uw, in.z};
   const int nb = (n + 255) / 256;
   if (kp.dim == 2)
     hipLaunchKernelGGL(k_push_adjoint<2>, dim3(nb), dim3(256), 0, st, kp, a, n, Eth, B, new_index, lx_in, lu_in, lx_out,
@@ -438,7 +438,7 @@ void launch_push_adjoint(const KParams &kp, const AdjInPtrs &in, int n, const do
 void launch_deposit_adjoint(const KParams &kp, const AdjInPtrs &in, int n, const double *B, const double *Eth,
                             const double *mu, double *lx_out, double *lu_out, double *lB, hipStream_t st) {
   if (n <= 0) return;
-  AdjIn a{in.bin_start, in.cell, {in.off[0], in.off[1], in.off[2]}, {in.u[0], in.u[1], in.u[2]}, in.w};
+  AdjIn a{in.bin_start, in.cell, in.xy, in.uw, in.z};
   const int nb = (n + 255) / 256;
   if (kp.dim == 2)
     hipLaunchKernelGGL(k_deposit_adjoint<2>, dim3(nb), dim3(256), 0, st, kp, a, n, B, Eth, mu, lx_out, lu_out, lB);

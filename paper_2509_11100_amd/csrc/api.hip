@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <new>
@@ -175,7 +176,7 @@ Layout make_layout(const relsim_params *p) {
   const size_t ng = (size_t)(p->nx + 2) * (p->ny + 2) * (p->dim == 3 ? p->nz + 2 : 1);
   L.stB = take(ng * 4 * es);
   L.stE = take(ng * 4 * es);
-  L.sink = take((size_t)kSinkSlots * 64 * 8);
+  L.sink = take((size_t)kSinkSlots * 64 * 32);
   L.kin_part = take(nc * 8);
   L.end = o;
   return L;
@@ -265,34 +266,44 @@ int choose_group(const relsim_ctx *c, int64_t n, KernelKind k = K_OTHER) {
 PartPtrs front(const relsim_particles *pt) {
   PartPtrs pp;
   pp.bin_start = pt->bin_start;
-  for (int d = 0; d < 3; ++d) {
-    pp.off[d] = pt->off[d];
-    pp.u[d] = pt->u[d];
-  }
-  pp.w = pt->w;
+  pp.xy = pt->xy;
+  pp.uw = pt->uw;
+  pp.z = pt->z;
+  return pp;
+}
+
+PartPtrs back(const relsim_particles *pt) {
+  PartPtrs pp;
+  pp.bin_start = pt->bin_start_back;
+  pp.xy = pt->xy_back;
+  pp.uw = pt->uw_back;
+  pp.z = pt->z_back;
   return pp;
 }
 
 void swap_sets(relsim_particles *pt) {
   std::swap(pt->bin_start, pt->bin_start_back);
   std::swap(pt->cell, pt->cell_back);
-  for (int d = 0; d < 3; ++d) {
-    std::swap(pt->off[d], pt->off_back[d]);
-    std::swap(pt->u[d], pt->u_back[d]);
-  }
-  std::swap(pt->w, pt->w_back);
+  std::swap(pt->xy, pt->xy_back);
+  std::swap(pt->uw, pt->uw_back);
+  std::swap(pt->z, pt->z_back);
 }
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 int check_particles(relsim_ctx *c, const relsim_particles *pt, bool need_back) {
   if (!pt) return fail(c, RELSIM_EINVAL, "null particles");
   if (pt->n < 0 || pt->n > c->p.max_particles) return fail(c, RELSIM_EINVAL, "particle count outside [0, max_particles]");
-  if (!pt->bin_start || !pt->off[0] || !pt->off[1] || (c->p.dim == 3 && !pt->off[2]) || !pt->u[0] || !pt->u[1] ||
-      !pt->u[2] || !pt->w)
+  if (!pt->bin_start || !pt->xy || !pt->uw || (c->p.dim == 3 && !pt->z))
     return fail(c, RELSIM_EINVAL, "null particle array");
-  if (need_back && (!pt->bin_start_back || !pt->cell_back || !pt->off_back[0] || !pt->off_back[1] ||
-                    (c->p.dim == 3 && !pt->off_back[2]) || !pt->u_back[0] || !pt->u_back[1] || !pt->u_back[2] ||
-                    !pt->w_back))
+  const size_t es = c->p.precision == RELSIM_MIXED ? 4 : 8;
+  if (!aligned(pt->xy, 2 * es) || !aligned(pt->uw, 4 * es))
+    return fail(c, RELSIM_EINVAL, "particle records not aligned to their size");
+  if (need_back && (!pt->bin_start_back || !pt->cell_back || !pt->xy_back || !pt->uw_back ||
+                    (c->p.dim == 3 && !pt->z_back)))
     return fail(c, RELSIM_EINVAL, "null back-buffer particle array");
+  if (need_back && (!aligned(pt->xy_back, 2 * es) || !aligned(pt->uw_back, 4 * es)))
+    return fail(c, RELSIM_EINVAL, "particle records not aligned to their size");
   return RELSIM_OK;
 }
 
@@ -417,13 +428,11 @@ int relsim_sort(relsim_ctx *c, relsim_particles *pt) {
   if (rc) return rc;
   if (!pt->cell) return fail(c, RELSIM_EINVAL, "relsim_sort needs the cell array");
   if (c->p.nspecies > 1 && !pt->species) return fail(c, RELSIM_EINVAL, "relsim_sort needs species ids");
-  void *offb[3] = {pt->off_back[0], pt->off_back[1], pt->off_back[2]};
-  void *ub[3] = {pt->u_back[0], pt->u_back[1], pt->u_back[2]};
   timed(c, "general_sort", [&] {
     launch_gsort(c->kp, c->p.precision, pt->n, pt->cell, pt->species, front(pt), c->at<int32_t>(c->L.gs_k0),
                  c->at<int32_t>(c->L.gs_k1), c->at<int32_t>(c->L.gs_v0), c->at<int32_t>(c->L.gs_v1),
                  c->at<int32_t>(c->L.gs_hist), c->at<int32_t>(c->L.scan_tmp), c->at<int32_t>(c->L.err),
-                 pt->bin_start_back, pt->cell_back, offb, ub, pt->w_back, c->st);
+                 pt->bin_start_back, pt->cell_back, back(pt), c->st);
   });
   rc = launch_status(c, "relsim_sort");
   if (rc) return rc;
@@ -475,11 +484,9 @@ int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, cons
     timed(c, "sort_scan", [&] {
       launch_scan(total, pt->bin_start_back, c->kp.nbins, c->at<int32_t>(c->L.scan_tmp), c->st);
     });
-    void *offb[3] = {pt->off_back[0], pt->off_back[1], pt->off_back[2]};
-    void *ub[3] = {pt->u_back[0], pt->u_back[1], pt->u_back[2]};
     timed(c, "sort_scatter", [&] {
-      launch_sort_scatter(c->kp, c->p.precision, Gs, front(pt), dirc, pre, pt->bin_start_back, offb, ub, pt->w_back,
-                          (int)pt->n, err, new_index, c->at<char>(c->L.sink), c->st);
+      launch_sort_scatter(c->kp, c->p.precision, Gs, front(pt), dirc, pre, pt->bin_start_back, back(pt), (int)pt->n,
+                          err, new_index, c->at<char>(c->L.sink), c->st);
     });
     rc = launch_status(c, "relsim_push");
     if (rc) return rc;
@@ -702,11 +709,9 @@ static AdjInPtrs adj_inputs(const relsim_particles *pt) {
   AdjInPtrs a;
   a.bin_start = pt->bin_start;
   a.cell = pt->cell;
-  for (int d = 0; d < 3; ++d) {
-    a.off[d] = (const double *)pt->off[d];
-    a.u[d] = (const double *)pt->u[d];
-  }
-  a.w = (const double *)pt->w;
+  a.xy = (const double *)pt->xy;
+  a.uw = (const double *)pt->uw;
+  a.z = (const double *)pt->z;
   return a;
 }
 

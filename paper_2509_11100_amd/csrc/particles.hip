@@ -109,11 +109,7 @@ struct PC<double> {
         idz(kp.inv_dz), q(kp.q), beta(kp.beta) {}
 };
 
-// One point of a ghosted field copy: three components and a pad.
-template <typename T>
-struct alignas(4 * sizeof(T)) V4 {
-  T x, y, z, w;
-};
+
 
 // Ghosted copy of a SoA FP64 grid field (one thread per ghosted point).
 template <typename T, int DIM>
@@ -273,19 +269,19 @@ constexpr int round_align() {
   return (64 / (int)sizeof(T)) < G ? 64 / (int)sizeof(T) : G;
 }
 
-template <typename T, int DIM, bool WITH_W>
-__device__ __forceinline__ void load_rec(int p, int pend, const T *__restrict__ o0, const T *__restrict__ o1,
-                                         const T *__restrict__ o2, const T *__restrict__ u0,
-                                         const T *__restrict__ u1, const T *__restrict__ u2,
-                                         const T *__restrict__ wt, PRec<T> &r) {
+template <typename T, int DIM>
+__device__ __forceinline__ void load_rec(int p, int pend, const V2<T> *__restrict__ xy, const V4<T> *__restrict__ uw,
+                                         const T *__restrict__ zz, PRec<T> &r) {
   const int q = load_index(p, pend);
-  r.fx = o0[q];
-  r.fy = o1[q];
-  if constexpr (DIM == 3) r.fz = o2[q];
-  r.ux = u0[q];
-  r.uy = u1[q];
-  r.uz = u2[q];
-  if constexpr (WITH_W) r.w = wt[q];
+  const V2<T> a = xy[q];
+  const V4<T> b = uw[q];
+  r.fx = a.x;
+  r.fy = a.y;
+  if constexpr (DIM == 3) r.fz = zz[q];
+  r.ux = b.x;
+  r.uy = b.y;
+  r.uz = b.z;
+  r.w = b.w;
 }
 
 // ---------------------------------------------------------------------------
@@ -293,11 +289,9 @@ __device__ __forceinline__ void load_rec(int p, int pend, const T *__restrict__ 
 // ---------------------------------------------------------------------------
 template <typename T, int DIM, int G>
 __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t *__restrict__ bin_start,
-                                                      const T *__restrict__ o0, const T *__restrict__ o1,
-                                                      const T *__restrict__ o2, const T *__restrict__ u0,
-                                                      const T *__restrict__ u1, const T *__restrict__ u2,
-                                                      const T *__restrict__ wt, const V4<T> *__restrict__ Bs,
-                                                      T *__restrict__ S) {
+                                                      const V2<T> *__restrict__ xy,
+                                                      const V4<T> *__restrict__ uw, const T *__restrict__ zz,
+                                                      const V4<T> *__restrict__ Bs, T *__restrict__ S) {
   constexpr int NACC = 93;  // 81 mass moments + 12 current moments per pass
   constexpr int NPASS = DIM == 3 ? 3 : 1;
   constexpr int CH = 32;    // moments per LDS transpose chunk (keeps LDS off the occupancy limit)
@@ -322,12 +316,12 @@ __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t 
     for (int k = 0; k < NACC; ++k) acc[k] = T(0);
     PRec<T> cur{}, nxt{};
     int p = pal + gl;
-    if (rounds > 0) load_rec<T, DIM, true>(p, cs.pend, o0, o1, o2, u0, u1, u2, wt, cur);
+    if (rounds > 0) load_rec<T, DIM>(p, cs.pend, xy, uw, zz, cur);
     __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll 1
     for (int r = 0; r < rounds; ++r) {
       const int pn = p + G;
-      load_rec<T, DIM, true>(pn, cs.pend, o0, o1, o2, u0, u1, u2, wt, nxt);
+      load_rec<T, DIM>(pn, cs.pend, xy, uw, zz, nxt);
       if (p >= cs.pbeg && p < cs.pend) {
         const T fx = cur.fx, fy = cur.fy, fz = DIM == 3 ? cur.fz : T(0);
         const T ux = cur.ux, uy = cur.uy, uz = cur.uz, wp = cur.w;
@@ -492,9 +486,9 @@ __device__ __forceinline__ T *sink_slot(void *sink, int lane) {
 }
 
 template <typename T, int DIM, int G, bool COUNT>
-__global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restrict__ bin_start, T *__restrict__ o0,
-                                             T *__restrict__ o1, T *__restrict__ o2, T *__restrict__ u0,
-                                             T *__restrict__ u1, T *__restrict__ u2, const V4<T> *__restrict__ Es,
+__global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restrict__ bin_start,
+                                             V2<T> *__restrict__ xy, V4<T> *__restrict__ uw, T *__restrict__ zz,
+                                             const V4<T> *__restrict__ Es,
                                              const V4<T> *__restrict__ Bs, uint8_t *__restrict__ dirc,
                                              uint16_t *__restrict__ cnt, int32_t *__restrict__ err,
                                              void *__restrict__ sink) {
@@ -530,7 +524,7 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
   PRec<T> cur{}, nxt{};
   int p = pal + gl;
   int bad = 0;
-  if (rounds > 0) load_rec<T, DIM, false>(p, cs.pend, o0, o1, o2, u0, u1, u2, nullptr, cur);
+  if (rounds > 0) load_rec<T, DIM>(p, cs.pend, xy, uw, zz, cur);
   // enter the loop with nothing in flight, so the loop's waits only count
   // its own loads and stores
   __builtin_amdgcn_s_waitcnt(0);
@@ -538,7 +532,7 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
 #pragma unroll 1
   for (int r = 0; r < rounds; ++r) {
     const int pn = p + G;
-    load_rec<T, DIM, false>(pn, cs.pend, o0, o1, o2, u0, u1, u2, nullptr, nxt);
+    load_rec<T, DIM>(pn, cs.pend, xy, uw, zz, nxt);
     // lanes past the end compute on a copy of a valid particle (finite
     // values) and store into the sink
     const bool pv = p >= cs.pbeg && p < cs.pend;
@@ -584,12 +578,17 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
       flag = ok ? 0 : 1;
     }
     bad |= pv ? flag : 0;
-    *(pv ? o0 + p : sinkT) = fx;
-    *(pv ? o1 + p : sinkT) = fy;
-    if constexpr (DIM == 3) *(pv ? o2 + p : sinkT) = fz;
-    *(pv ? u0 + p : sinkT) = nx;
-    *(pv ? u1 + p : sinkT) = ny;
-    *(pv ? u2 + p : sinkT) = nz;
+    V2<T> xo;
+    xo.x = fx;
+    xo.y = fy;
+    V4<T> uo;
+    uo.x = nx;
+    uo.y = ny;
+    uo.z = nz;
+    uo.w = cur.w;
+    *(pv ? xy + p : sink_slot<V2<T>>(sink, lane)) = xo;
+    *(pv ? uw + p : sink_slot<V4<T>>(sink, lane)) = uo;
+    if constexpr (DIM == 3) *(pv ? zz + p : sinkT) = fz;
     if constexpr (COUNT) {
       const int dir = (mx + 1) + 3 * (my + 1) + (DIM == 3 ? 9 * (mz + 1) : 0);
       *(pv ? dirc + p : sinkB) = (uint8_t)dir;
@@ -665,15 +664,13 @@ __global__ __launch_bounds__(256) void k_sort_offsets(KParams kp, const uint16_t
 // ---------------------------------------------------------------------------
 template <typename T, int DIM, int G, bool PERM>
 __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *__restrict__ bin_start,
-                                                     const T *__restrict__ o0, const T *__restrict__ o1,
-                                                     const T *__restrict__ o2, const T *__restrict__ u0,
-                                                     const T *__restrict__ u1, const T *__restrict__ u2,
-                                                     const T *__restrict__ wt, const uint8_t *__restrict__ dirc,
+                                                     const V2<T> *__restrict__ xy,
+                                                     const V4<T> *__restrict__ uw, const T *__restrict__ zz,
+                                                     const uint8_t *__restrict__ dirc,
                                                      const uint16_t *__restrict__ pre,
-                                                     const int32_t *__restrict__ bsn,
-                                                     T *__restrict__ q0, T *__restrict__ q1, T *__restrict__ q2,
-                                                     T *__restrict__ v0, T *__restrict__ v1, T *__restrict__ v2,
-                                                     T *__restrict__ wo, int ntot, int32_t *__restrict__ err,
+                                                     const int32_t *__restrict__ bsn, V2<T> *__restrict__ xo,
+                                                     V4<T> *__restrict__ uo, T *__restrict__ zo, int ntot,
+                                                     int32_t *__restrict__ err,
                                                      int32_t *__restrict__ perm, void *__restrict__ sink) {
   constexpr int NDIR = DIM == 3 ? 27 : 9;
   constexpr int NGRP = 64 / G;
@@ -704,14 +701,14 @@ __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *
   int p = cs.pbeg + gl;
   int dcur = 0, dnxt = 0, bad = 0;
   if (rounds > 0) {
-    load_rec<T, DIM, true>(p, cs.pend, o0, o1, o2, u0, u1, u2, wt, cur);
+    load_rec<T, DIM>(p, cs.pend, xy, uw, zz, cur);
     dcur = dirc[load_index(p, cs.pend)];
   }
   __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll 1
   for (int r = 0; r < rounds; ++r) {
     const int pn = p + G;
-    load_rec<T, DIM, true>(pn, cs.pend, o0, o1, o2, u0, u1, u2, wt, nxt);
+    load_rec<T, DIM>(pn, cs.pend, xy, uw, zz, nxt);
     dnxt = dirc[load_index(pn, cs.pend)];
     const bool pv = p < cs.pend;
     int s = 0;
@@ -746,13 +743,17 @@ __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *
     // counters (flagged); lanes past the end store into the sink
     const bool ok = pv && pos >= 0 && pos < ntot;
     bad |= (pv && !ok) ? 1 : 0;
-    *(ok ? q0 + pos : sinkT) = cur.fx;
-    *(ok ? q1 + pos : sinkT) = cur.fy;
-    if constexpr (DIM == 3) *(ok ? q2 + pos : sinkT) = cur.fz;
-    *(ok ? v0 + pos : sinkT) = cur.ux;
-    *(ok ? v1 + pos : sinkT) = cur.uy;
-    *(ok ? v2 + pos : sinkT) = cur.uz;
-    *(ok ? wo + pos : sinkT) = cur.w;
+    V2<T> xv;
+    xv.x = cur.fx;
+    xv.y = cur.fy;
+    V4<T> uv;
+    uv.x = cur.ux;
+    uv.y = cur.uy;
+    uv.z = cur.uz;
+    uv.w = cur.w;
+    *(ok ? xo + pos : sink_slot<V2<T>>(sink, lane)) = xv;
+    *(ok ? uo + pos : sink_slot<V4<T>>(sink, lane)) = uv;
+    if constexpr (DIM == 3) *(ok ? zo + pos : sinkT) = cur.fz;
     if constexpr (PERM) *(ok ? perm + p : sinkI) = pos;
     __builtin_amdgcn_wave_barrier();
     cur = nxt;
@@ -777,9 +778,7 @@ __global__ __launch_bounds__(64) void k_fill_cells(KParams kp, const int32_t *__
 // ---------------------------------------------------------------------------
 template <typename T, int DIM, int G>
 __global__ __launch_bounds__(64) void k_kinetic(KParams kp, const int32_t *__restrict__ bin_start,
-                                                const T *__restrict__ u0, const T *__restrict__ u1,
-                                                const T *__restrict__ u2, const T *__restrict__ wt,
-                                                double *__restrict__ partials) {
+                                                const V4<T> *__restrict__ uw, double *__restrict__ partials) {
   // one block per 64/G cells in slot order; block b writes partials[b]
   __shared__ double red[64];
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
@@ -797,9 +796,10 @@ __global__ __launch_bounds__(64) void k_kinetic(KParams kp, const int32_t *__res
       for (int s2 = 1; s2 < 8; ++s2)
         if (p >= cs.bound[s2]) s = s2;
     }
-    const double ux = u0[p], uy = u1[p], uz = u2[p];
+    const V4<T> r = uw[p];
+    const double ux = r.x, uy = r.y, uz = r.z;
     const double uu = ux * ux + uy * uy + uz * uz;
-    const double wm = (double)wt[p] * kp.m[s];
+    const double wm = (double)r.w * kp.m[s];
     // (gamma - 1) c^2 = |u|^2 / (sqrt(1 + |u|^2/c^2) + 1), without cancellation
     acc += kp.nonrel ? 0.5 * wm * uu : wm * uu / (sqrt(1.0 + uu * invc2) + 1.0);
   }
@@ -892,9 +892,8 @@ T *mp(void *p) {
 template <typename T, int DIM, int G>
 void deposit_impl(const KParams &kp, const PartPtrs &pp, const void *Bst, void *S, hipStream_t st) {
   const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
-  hipLaunchKernelGGL((k_deposit_cells<T, DIM, G>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, cp<T>(pp.off[0]),
-                     cp<T>(pp.off[1]), cp<T>(pp.off[2]), cp<T>(pp.u[0]), cp<T>(pp.u[1]), cp<T>(pp.u[2]), cp<T>(pp.w),
-                     cp<V4<T>>(Bst), mp<T>(S));
+  hipLaunchKernelGGL((k_deposit_cells<T, DIM, G>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, cp<V2<T>>(pp.xy),
+                     cp<V4<T>>(pp.uw), cp<T>(pp.z), cp<V4<T>>(Bst), mp<T>(S));
 }
 
 template <typename T, int DIM, int G>
@@ -902,39 +901,32 @@ void push_impl(const KParams &kp, const PartPtrs &pp, const void *Est, const voi
                uint16_t *cnt, int32_t *err, int count_moves, void *sink, hipStream_t st) {
   const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
   if (count_moves)
-    hipLaunchKernelGGL((k_push<T, DIM, G, true>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, mp<T>(pp.off[0]),
-                       mp<T>(pp.off[1]), mp<T>(pp.off[2]), mp<T>(pp.u[0]), mp<T>(pp.u[1]), mp<T>(pp.u[2]),
-                       cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, cnt, err, sink);
+    hipLaunchKernelGGL((k_push<T, DIM, G, true>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, mp<V2<T>>(pp.xy),
+                       mp<V4<T>>(pp.uw), mp<T>(pp.z), cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, cnt, err, sink);
   else
-    hipLaunchKernelGGL((k_push<T, DIM, G, false>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, mp<T>(pp.off[0]),
-                       mp<T>(pp.off[1]), mp<T>(pp.off[2]), mp<T>(pp.u[0]), mp<T>(pp.u[1]), mp<T>(pp.u[2]),
-                       cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, cnt, err, sink);
+    hipLaunchKernelGGL((k_push<T, DIM, G, false>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, mp<V2<T>>(pp.xy),
+                       mp<V4<T>>(pp.uw), mp<T>(pp.z), cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, cnt, err, sink);
 }
 
 template <typename T, int DIM, int G>
 void scatter_impl(const KParams &kp, const PartPtrs &src, const uint8_t *dirc, const uint16_t *pre, const int32_t *bsn,
-                  void *const off_out[3], void *const u_out[3], void *w_out, int ntot, int32_t *err,
-                  int32_t *perm, void *sink, hipStream_t st) {
+                  const PartPtrs &out, int ntot, int32_t *err, int32_t *perm, void *sink, hipStream_t st) {
   const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
   if (perm)
     hipLaunchKernelGGL((k_sort_scatter<T, DIM, G, true>), dim3(nblk), dim3(64), 0, st, kp, src.bin_start,
-                       cp<T>(src.off[0]), cp<T>(src.off[1]), cp<T>(src.off[2]), cp<T>(src.u[0]), cp<T>(src.u[1]),
-                       cp<T>(src.u[2]), cp<T>(src.w), dirc, pre, bsn, mp<T>(off_out[0]), mp<T>(off_out[1]),
-                       mp<T>(off_out[2]), mp<T>(u_out[0]), mp<T>(u_out[1]), mp<T>(u_out[2]), mp<T>(w_out), ntot, err,
-                       perm, sink);
+                       cp<V2<T>>(src.xy), cp<V4<T>>(src.uw), cp<T>(src.z), dirc, pre, bsn, mp<V2<T>>(out.xy),
+                       mp<V4<T>>(out.uw), mp<T>(out.z), ntot, err, perm, sink);
   else
     hipLaunchKernelGGL((k_sort_scatter<T, DIM, G, false>), dim3(nblk), dim3(64), 0, st, kp, src.bin_start,
-                       cp<T>(src.off[0]), cp<T>(src.off[1]), cp<T>(src.off[2]), cp<T>(src.u[0]), cp<T>(src.u[1]),
-                       cp<T>(src.u[2]), cp<T>(src.w), dirc, pre, bsn, mp<T>(off_out[0]), mp<T>(off_out[1]),
-                       mp<T>(off_out[2]), mp<T>(u_out[0]), mp<T>(u_out[1]), mp<T>(u_out[2]), mp<T>(w_out), ntot, err,
-                       perm, sink);
+                       cp<V2<T>>(src.xy), cp<V4<T>>(src.uw), cp<T>(src.z), dirc, pre, bsn, mp<V2<T>>(out.xy),
+                       mp<V4<T>>(out.uw), mp<T>(out.z), ntot, err, perm, sink);
 }
 
 template <typename T, int DIM, int G>
 void kinetic_impl(const KParams &kp, const PartPtrs &pp, double *partials, hipStream_t st) {
   const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
-  hipLaunchKernelGGL((k_kinetic<T, DIM, G>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, cp<T>(pp.u[0]),
-                     cp<T>(pp.u[1]), cp<T>(pp.u[2]), cp<T>(pp.w), partials);
+  hipLaunchKernelGGL((k_kinetic<T, DIM, G>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, cp<V4<T>>(pp.uw),
+                     partials);
 }
 
 // Dispatch over (precision, dim, group) to the template instances.
@@ -1034,11 +1026,9 @@ void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream
 }
 
 void launch_sort_scatter(const KParams &kp, int prec, int group, const PartPtrs &src, const uint8_t *dirc,
-                         const uint16_t *pre, const int32_t *bin_start_new, void *const off_out[3],
-                         void *const u_out[3], void *w_out, int ntot, int32_t *err, int32_t *perm, void *sink,
-                         hipStream_t st) {
-  dispatch<ScatterF>(prec, kp.dim, group, kp, src, dirc, pre, bin_start_new, off_out, u_out, w_out, ntot, err,
-                     perm, sink, st);
+                         const uint16_t *pre, const int32_t *bin_start_new, const PartPtrs &out, int ntot,
+                         int32_t *err, int32_t *perm, void *sink, hipStream_t st) {
+  dispatch<ScatterF>(prec, kp.dim, group, kp, src, dirc, pre, bin_start_new, out, ntot, err, perm, sink, st);
 }
 
 void launch_fill_cells(const KParams &kp, const int32_t *bin_start, int32_t *cell, hipStream_t st) {

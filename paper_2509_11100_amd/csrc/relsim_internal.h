@@ -36,19 +36,32 @@ struct Layout {
 constexpr int kMaxRestart = 64;
 constexpr int kDotBlocks = 512;     // blocks of the multi-dot reduction
 constexpr int kRedBlocks = 1024;    // blocks of the energy reductions
-constexpr int kSinkSlots = 512;     // per-lane store sinks of the particle kernels (power of two)
+constexpr int kSinkSlots = 512;     // per-lane store sinks of the particle kernels (power of two), 32 B each
 
 // Moments per cell: 2D 81 mass moments + 12 current moments; 3D three passes
 // of 81 mass moments plus 2 x 12 current moments.
 inline int n_cell_moments(int dim) { return dim == 3 ? 3 * 81 + 2 * 12 : 81 + 12; }
 inline int n_dirs(int dim) { return dim == 3 ? 27 : 9; }
 
+// Packed records: a ghosted field point (three components and a pad) or a
+// particle's (u_x, u_y, u_z, w); a particle's (off_x, off_y).
+template <typename T>
+struct alignas(4 * sizeof(T)) V4 {
+  T x, y, z, w;
+};
+template <typename T>
+struct alignas(2 * sizeof(T)) V2 {
+  T x, y;
+};
+
 // ---- particle kernels (particles.hip) ----
+// Particle arrays of one buffer set (element type T = float or double):
+// xy [n] of (off_x, off_y), uw [n] of (u_x, u_y, u_z, w), z [n] of off_z (3D).
 struct PartPtrs {
   const int32_t *bin_start;
-  void *off[3];
-  void *u[3];
-  void *w;
+  void *xy;
+  void *uw;
+  void *z;
 };
 
 // Ghosted, component-interleaved copy of a grid vector field (SoA FP64 on
@@ -58,7 +71,7 @@ void launch_stage_field(const KParams &kp, int prec, const double *F, void *out,
 void launch_deposit_cells(const KParams &kp, int prec, int group, const PartPtrs &pp, const void *Bst, void *S,
                           hipStream_t st);
 void launch_assemble(const KParams &kp, int prec, const void *S, double *J, double *M, hipStream_t st);
-// `sink`: kSinkSlots * 64 * 8 bytes of workspace that lanes without a
+// `sink`: kSinkSlots * 64 * 32 bytes of workspace that lanes without a
 // particle store into (contents meaningless)
 void launch_push(const KParams &kp, int prec, int group, const PartPtrs &pp, const void *Est, const void *Bst,
                  uint8_t *dirc, uint16_t *cnt, int32_t *err, int count_moves, void *sink, hipStream_t st);
@@ -67,12 +80,8 @@ void launch_sort_offsets(const KParams &kp, const uint16_t *cnt, uint16_t *pre, 
 void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream_t st);
 size_t scan_tmp_elems(int n);
 void launch_sort_scatter(const KParams &kp, int prec, int group, const PartPtrs &src, const uint8_t *dirc,
-                         const uint16_t *pre, const int32_t *bin_start_new, void *const off_out[3],
-                         void *const u_out[3], void *w_out, int ntot, int32_t *err, int32_t *perm, void *sink,
-                         hipStream_t st);
-// cell[p] for every particle from the bin ranges
-void launch_fill_cells(const KParams &kp, const int32_t *bin_start, int32_t *cell, hipStream_t st);
-// partials: one double per block of 64/group cells (at most ncells)
+                         const uint16_t *pre, const int32_t *bin_start_new, const PartPtrs &out, int ntot,
+                         int32_t *err, int32_t *perm, void *sink, hipStream_t st);
 // cell[p] for every particle from the bin ranges
 void launch_fill_cells(const KParams &kp, const int32_t *bin_start, int32_t *cell, hipStream_t st);
 // partials: one double per block of 64/group cells (at most ncells)
@@ -82,16 +91,15 @@ void launch_kinetic(const KParams &kp, int prec, int group, const PartPtrs &pp, 
 size_t gsort_tmp_elems(int64_t n);  // int32 elements of scratch for the histograms
 void launch_gsort(const KParams &kp, int prec, int64_t n, const int32_t *cell, const uint8_t *species, const PartPtrs &src,
                   int32_t *keys0, int32_t *keys1, int32_t *vals0, int32_t *vals1, int32_t *hist, int32_t *scan_tmp,
-                  int32_t *err, int32_t *bin_start_out, int32_t *cell_out, void *const off_out[3], void *const u_out[3],
-                  void *w_out, hipStream_t st);
+                  int32_t *err, int32_t *bin_start_out, int32_t *cell_out, const PartPtrs &out, hipStream_t st);
 
 // ---- adjoint kernels (adjoint.hip), FP64 particle state ----
 struct AdjInPtrs {
   const int32_t *bin_start = nullptr;
   const int32_t *cell = nullptr;
-  const double *off[3] = {nullptr, nullptr, nullptr};
-  const double *u[3] = {nullptr, nullptr, nullptr};
-  const double *w = nullptr;
+  const double *xy = nullptr;  // [n] (off_x, off_y)
+  const double *uw = nullptr;  // [n] (u_x, u_y, u_z, w)
+  const double *z = nullptr;   // [n] off_z (3D)
 };
 void launch_push_adjoint(const KParams &kp, const AdjInPtrs &in, int n, const double *Eth, const double *B,
                          const int32_t *new_index, const double *lx_in, const double *lu_in, double *lx_out,

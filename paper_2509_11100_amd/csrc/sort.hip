@@ -86,23 +86,16 @@ __global__ __launch_bounds__(256) void k_bin_bounds(const int32_t *__restrict__ 
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_gather(KParams kp, int n, const int32_t *__restrict__ idx,
-                                                const int32_t *__restrict__ keys, const T *__restrict__ o0,
-                                                const T *__restrict__ o1, const T *__restrict__ o2,
-                                                const T *__restrict__ u0, const T *__restrict__ u1,
-                                                const T *__restrict__ u2, const T *__restrict__ w,
-                                                int32_t *__restrict__ cell_out, T *__restrict__ q0, T *__restrict__ q1,
-                                                T *__restrict__ q2, T *__restrict__ v0, T *__restrict__ v1,
-                                                T *__restrict__ v2, T *__restrict__ wo) {
+                                                const int32_t *__restrict__ keys, const V2<T> *__restrict__ xy,
+                                                const V4<T> *__restrict__ uw, const T *__restrict__ zz,
+                                                int32_t *__restrict__ cell_out, V2<T> *__restrict__ xo,
+                                                V4<T> *__restrict__ uo, T *__restrict__ zo) {
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= n) return;
   const int i = idx[j];
-  q0[j] = o0[i];
-  q1[j] = o1[i];
-  if (kp.dim == 3) q2[j] = o2[i];
-  v0[j] = u0[i];
-  v1[j] = u1[i];
-  v2[j] = u2[i];
-  wo[j] = w[i];
+  xo[j] = xy[i];
+  uo[j] = uw[i];
+  if (kp.dim == 3) zo[j] = zz[i];
   cell_out[j] = keys[j] / kp.nspecies;
 }
 
@@ -112,8 +105,8 @@ size_t gsort_tmp_elems(int64_t n) { return (size_t)kRsDigits * (size_t)((n + kRs
 
 void launch_gsort(const KParams &kp, int prec, int64_t n64, const int32_t *cell, const uint8_t *species,
                   const PartPtrs &src, int32_t *keys0, int32_t *keys1, int32_t *vals0, int32_t *vals1, int32_t *hist,
-                  int32_t *scan_tmp, int32_t *err, int32_t *bin_start_out, int32_t *cell_out, void *const off_out[3],
-                  void *const u_out[3], void *w_out, hipStream_t st) {
+                  int32_t *scan_tmp, int32_t *err, int32_t *bin_start_out, int32_t *cell_out, const PartPtrs &out,
+                  hipStream_t st) {
   const int n = (int)n64;
   const int g256 = (n + 255) / 256;
   if (n > 0) hipLaunchKernelGGL(k_make_keys, dim3(g256), dim3(256), 0, st, kp, n, cell, species, keys0, vals0, err);
@@ -135,17 +128,13 @@ void launch_gsort(const KParams &kp, int prec, int64_t n64, const int32_t *cell,
   hipLaunchKernelGGL(k_bin_bounds, dim3((n + 1 + 255) / 256), dim3(256), 0, st, ka, n, kp.nbins, bin_start_out);
   if (n == 0) return;
   if (prec == RELSIM_MIXED)
-    hipLaunchKernelGGL(k_gather<float>, dim3(g256), dim3(256), 0, st, kp, n, va, ka, (const float *)src.off[0],
-                       (const float *)src.off[1], (const float *)src.off[2], (const float *)src.u[0],
-                       (const float *)src.u[1], (const float *)src.u[2], (const float *)src.w, cell_out,
-                       (float *)off_out[0], (float *)off_out[1], (float *)off_out[2], (float *)u_out[0],
-                       (float *)u_out[1], (float *)u_out[2], (float *)w_out);
+    hipLaunchKernelGGL(k_gather<float>, dim3(g256), dim3(256), 0, st, kp, n, va, ka, (const V2<float> *)src.xy,
+                       (const V4<float> *)src.uw, (const float *)src.z, cell_out, (V2<float> *)out.xy,
+                       (V4<float> *)out.uw, (float *)out.z);
   else
-    hipLaunchKernelGGL(k_gather<double>, dim3(g256), dim3(256), 0, st, kp, n, va, ka, (const double *)src.off[0],
-                       (const double *)src.off[1], (const double *)src.off[2], (const double *)src.u[0],
-                       (const double *)src.u[1], (const double *)src.u[2], (const double *)src.w, cell_out,
-                       (double *)off_out[0], (double *)off_out[1], (double *)off_out[2], (double *)u_out[0],
-                       (double *)u_out[1], (double *)u_out[2], (double *)w_out);
+    hipLaunchKernelGGL(k_gather<double>, dim3(g256), dim3(256), 0, st, kp, n, va, ka, (const V2<double> *)src.xy,
+                       (const V4<double> *)src.uw, (const double *)src.z, cell_out, (V2<double> *)out.xy,
+                       (V4<double> *)out.uw, (double *)out.z);
 }
 
 }  // namespace relsim

@@ -111,7 +111,9 @@ class Context:
 
 
 class Particles:
-    """Double-buffered structure-of-arrays particle state on the device."""
+    """Double-buffered particle state on the device: per set, xy [cap][2]
+    (offsets x, y), uw [cap][4] (momentum, weight), z [cap] (offset z, 3D),
+    cell ids and bin starts.  `off`, `u` and `w` are strided views."""
 
     def __init__(self, ctx: Context, capacity: Optional[int] = None):
         self.ctx = ctx
@@ -126,9 +128,9 @@ class Particles:
             self.sets.append({
                 "bin_start": torch.zeros(nb + 1, dtype=torch.int32, device=dev),
                 "cell": torch.zeros(max(cap, 1), dtype=torch.int32, device=dev),
-                "off": [torch.zeros(max(cap, 1), dtype=dt, device=dev) for _ in range(3)],
-                "u": [torch.zeros(max(cap, 1), dtype=dt, device=dev) for _ in range(3)],
-                "w": torch.zeros(max(cap, 1), dtype=dt, device=dev),
+                "xy": torch.zeros((max(cap, 1), 2), dtype=dt, device=dev),
+                "uw": torch.zeros((max(cap, 1), 4), dtype=dt, device=dev),
+                "z": torch.zeros(max(cap, 1), dtype=dt, device=dev) if ctx.dim == 3 else None,
             })
         self.species_in = torch.zeros(max(cap, 1), dtype=torch.uint8, device=dev)
         self.s = _lib.relsim_particles()
@@ -140,16 +142,17 @@ class Particles:
         f, b = self.sets[self.front], self.sets[1 - self.front]
         s = self.s
         s.n = self.n
-        s.bin_start, s.cell, s.w = f["bin_start"].data_ptr(), f["cell"].data_ptr(), f["w"].data_ptr()
-        s.bin_start_back, s.cell_back, s.w_back = b["bin_start"].data_ptr(), b["cell"].data_ptr(), b["w"].data_ptr()
-        for d in range(3):
-            s.off[d], s.u[d] = f["off"][d].data_ptr(), f["u"][d].data_ptr()
-            s.off_back[d], s.u_back[d] = b["off"][d].data_ptr(), b["u"][d].data_ptr()
+        s.bin_start, s.cell = f["bin_start"].data_ptr(), f["cell"].data_ptr()
+        s.bin_start_back, s.cell_back = b["bin_start"].data_ptr(), b["cell"].data_ptr()
+        s.xy, s.uw = f["xy"].data_ptr(), f["uw"].data_ptr()
+        s.xy_back, s.uw_back = b["xy"].data_ptr(), b["uw"].data_ptr()
+        s.z = f["z"].data_ptr() if f["z"] is not None else None
+        s.z_back = b["z"].data_ptr() if b["z"] is not None else None
         s.species = self.species_in.data_ptr()
 
     def _sync_front(self):
         """After a call that may have swapped the sets inside the C struct."""
-        self.front = 0 if self.s.off[0] == self.sets[0]["off"][0].data_ptr() else 1
+        self.front = 0 if self.s.xy == self.sets[0]["xy"].data_ptr() else 1
         self._bind()
 
     def load(self, cell, species, off, u, w, bin_start=None):
@@ -164,13 +167,14 @@ class Particles:
         f["cell"][:n].copy_(torch.as_tensor(np.asarray(cell, dtype=np.int32)).to(dev))
         self.species_in[:n].copy_(torch.as_tensor(np.asarray(species, dtype=np.uint8)).to(dev))
         offs = np.asarray(off)
-        for d in range(3):
-            if d < offs.shape[0]:
-                f["off"][d][:n].copy_(torch.as_tensor(offs[d]).to(dev, dt))
-            else:
-                f["off"][d][:n].zero_()
-            f["u"][d][:n].copy_(torch.as_tensor(np.asarray(u)[d]).to(dev, dt))
-        f["w"][:n].copy_(torch.as_tensor(np.asarray(w)).to(dev, dt))
+        uu = np.asarray(u)
+        for d in range(2):
+            f["xy"][:n, d].copy_(torch.as_tensor(offs[d]).to(dev, dt))
+        if f["z"] is not None:
+            f["z"][:n].copy_(torch.as_tensor(offs[2]).to(dev, dt))
+        for k in range(3):
+            f["uw"][:n, k].copy_(torch.as_tensor(uu[k]).to(dev, dt))
+        f["uw"][:n, 3].copy_(torch.as_tensor(np.asarray(w)).to(dev, dt))
         self._bind()
         if bin_start is None:
             sort(self.ctx, self)
@@ -193,15 +197,20 @@ class Particles:
 
     @property
     def off(self):
-        return [t[: self.n] for t in self.sets[self.front]["off"][: self.ctx.dim]]
+        f = self.sets[self.front]
+        views = [f["xy"][: self.n, 0], f["xy"][: self.n, 1]]
+        if f["z"] is not None:
+            views.append(f["z"][: self.n])
+        return views
 
     @property
     def u(self):
-        return [t[: self.n] for t in self.sets[self.front]["u"]]
+        f = self.sets[self.front]
+        return [f["uw"][: self.n, k] for k in range(3)]
 
     @property
     def w(self) -> torch.Tensor:
-        return self.sets[self.front]["w"][: self.n]
+        return self.sets[self.front]["uw"][: self.n, 3]
 
     def species(self) -> torch.Tensor:
         """Species id of every front particle, from the bin layout."""
