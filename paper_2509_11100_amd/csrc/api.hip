@@ -245,21 +245,26 @@ KParams make_kparams(const relsim_params *p) {
   return k;
 }
 
-// Lanes per cell for a particle kernel: the largest power of two in [8, 64]
-// not above mean_occupancy / rounds, where `rounds` is the number of G-wide
-// rounds per cell the kernel wants.  The deposit amortises its per-cell
-// reduction over several rounds (8 in FP32; 16 in FP64, whose register-bound
-// occupancy favours narrower groups), the push over a few (4), while the
-// scatter writes whole runs per instruction (2).  Measured on the
-// 1024 x 512 Harris sheet (128 particles per cell).
-enum KernelKind { K_DEPOSIT = 8, K_PUSH = 4, K_SCATTER = 2, K_OTHER = 4 };
+// Lanes per cell for a particle kernel: the largest power of two in
+// [gmin, 64] not above mean_occupancy / rounds, where `rounds` is the number
+// of G-wide rounds per cell the kernel wants, then widened until the launch
+// has at least 512 waves (2 per CU) on small grids.  The 2D deposit
+// amortises its per-cell reduction over many rounds (16 in FP32; 32 in FP64,
+// whose register-bound occupancy favours narrower groups) and may go down to
+// 4 lanes; the push wants a few rounds (4), while the scatter writes whole
+// runs per instruction (2).  Measured on the 2D Harris sheets with 32, 64
+// and 128 particles per cell.  (The 3D deposit always splits a cell's
+// moments over 4 lanes and takes no group.)
+enum KernelKind { K_DEPOSIT, K_PUSH, K_SCATTER, K_OTHER };
 
 int choose_group(const relsim_ctx *c, int64_t n, KernelKind k = K_OTHER) {
   if (c->p.group) return c->p.group;
-  const double rounds = (k == K_DEPOSIT && c->p.precision == RELSIM_FP64) ? 16.0 : (double)k;
+  const bool fp64 = c->p.precision == RELSIM_FP64;
+  const double rounds = k == K_DEPOSIT ? (fp64 ? 32.0 : 16.0) : (k == K_SCATTER ? 2.0 : 4.0);
   const double mean = (double)n / (double)c->kp.ncells;
-  int g = 8;
+  int g = k == K_DEPOSIT ? 4 : 8;
   while (g < 64 && 2.0 * g <= mean / rounds) g *= 2;
+  while (g < 64 && (double)c->kp.ncells * g < 512.0 * 64.0) g *= 2;
   return g;
 }
 

@@ -20,11 +20,14 @@
 // monomial type t_d = a_d + b_d in {0,1,2}: (1-f)^2, f(1-f), f^2.  Hence
 //   M_{g,g'} = sum over cells c containing g and g' of S_c[t(g,g',c)],
 //   S_c[t][k] = V^-1 sum_{p in c} (w q beta / gbar) prod_d mono_{t_d}(f_d) alpha_k,
-// and J-hat likewise from per-corner sums.  The particle kernel reduces the
-// per-cell moments S_c within its lane group (registers, then one LDS
-// transpose); a second kernel assembles every node's J-hat and 9/27 M blocks
-// from the 4/8 surrounding cells by a fixed-order gather.  No float atomics:
-// results are deterministic, and M_{g,g'} == M_{g',g} bit for bit.
+// and J-hat likewise from per-corner sums.  In 2D (93 moments per cell) the
+// lanes of a group split the cell's particles and their partial moments are
+// then added in fixed lane order (registers, then one LDS transpose); in 3D
+// (267 moments) the 4 lanes of a group split the moments instead and share
+// each particle's quantities through LDS.  A second kernel assembles every
+// node's J-hat and 9/27 M blocks from the 4/8 surrounding cells by a
+// fixed-order gather.  No float atomics: results are deterministic, and
+// M_{g,g'} == M_{g',g} bit for bit.
 #include <climits>
 
 #include "relsim_internal.h"
@@ -287,16 +290,18 @@ __device__ __forceinline__ void load_rec(int p, int pend, const V2<T> *__restric
 // ---------------------------------------------------------------------------
 // S1-S3: per-cell moments
 // ---------------------------------------------------------------------------
-template <typename T, int DIM, int G>
+// 2D: the G lanes of a group split the cell's particles; each lane sums all
+// 93 moments (81 mass, 12 current) of its particles, and the group's G
+// partial sums are then added in fixed lane order.
+template <typename T, int G>
 __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t *__restrict__ bin_start,
                                                       const V2<T> *__restrict__ xy,
-                                                      const V4<T> *__restrict__ uw, const T *__restrict__ zz,
+                                                      const V4<T> *__restrict__ uw,
                                                       const V4<T> *__restrict__ Bs, T *__restrict__ S) {
-  constexpr int NACC = 93;  // 81 mass moments + 12 current moments per pass
-  constexpr int NPASS = DIM == 3 ? 3 : 1;
+  constexpr int NACC = 93;  // 81 mass moments + 12 current moments
   constexpr int CH = 32;    // moments per LDS transpose chunk (keeps LDS off the occupancy limit)
   // FP32 keeps the cell's 3x3 B block in registers; FP64 gathers per particle
-  constexpr bool BLK = DIM == 2 && sizeof(T) == 4;
+  constexpr bool BLK = sizeof(T) == 4;
   __shared__ T red[64 * (CH + 1)];
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -309,88 +314,189 @@ __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t 
   const int pal = cs.pbeg & ~(round_align<T, G>() - 1);
   const int rounds = wave_rounds<G>(cs.pend - pal);
 
+  T acc[NACC];
+#pragma unroll
+  for (int k = 0; k < NACC; ++k) acc[k] = T(0);
+  PRec<T> cur{}, nxt{};
+  int p = pal + gl;
+  if (rounds > 0) load_rec<T, 2>(p, cs.pend, xy, uw, nullptr, cur);
+  __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll 1
-  for (int pass = 0; pass < NPASS; ++pass) {
-    T acc[NACC];
+  for (int r = 0; r < rounds; ++r) {
+    const int pn = p + G;
+    load_rec<T, 2>(pn, cs.pend, xy, uw, nullptr, nxt);
+    if (p >= cs.pbeg && p < cs.pend) {
+      const T fx = cur.fx, fy = cur.fy;
+      const T ux = cur.ux, uy = cur.uy, uz = cur.uz, wp = cur.w;
+      T qs, bs;
+      species_of<T>(kp, pc, cs, p, qs, bs);
+      T Bx, By, Bz;
+      gather_B<T, 2, BLK>(kp, Bs, Bc, cs.gc, fx, fy, T(0), Bx, By, Bz);
+      const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
+      const T kb = bs * igb * pc.invc;
+      T a[9];
+      make_alpha<T>(kb * Bx, kb * By, kb * Bz, a);
+      const T cJ = wp * qs * igb * pc.invV;
+      const T cM = cJ * bs;
+      T psiM[9], psiJ[3];
 #pragma unroll
-    for (int k = 0; k < NACC; ++k) acc[k] = T(0);
-    PRec<T> cur{}, nxt{};
-    int p = pal + gl;
-    if (rounds > 0) load_rec<T, DIM>(p, cs.pend, xy, uw, zz, cur);
-    __builtin_amdgcn_s_waitcnt(0);
-#pragma unroll 1
-    for (int r = 0; r < rounds; ++r) {
-      const int pn = p + G;
-      load_rec<T, DIM>(pn, cs.pend, xy, uw, zz, nxt);
-      if (p >= cs.pbeg && p < cs.pend) {
-        const T fx = cur.fx, fy = cur.fy, fz = DIM == 3 ? cur.fz : T(0);
-        const T ux = cur.ux, uy = cur.uy, uz = cur.uz, wp = cur.w;
-        T qs, bs;
-        species_of<T>(kp, pc, cs, p, qs, bs);
-        T Bx, By, Bz;
-        gather_B<T, DIM, BLK>(kp, Bs, Bc, cs.gc, fx, fy, fz, Bx, By, Bz);
-        const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
-        const T kb = bs * igb * pc.invc;
-        T a[9];
-        make_alpha<T>(kb * Bx, kb * By, kb * Bz, a);
-        const T cJ = wp * qs * igb * pc.invV;
-        const T cM = cJ * bs;
-        T psiM[9], psiJ[3];
+      for (int k = 0; k < 9; ++k) psiM[k] = cM * a[k];
+      psiJ[0] = cJ * (a[0] * ux + a[1] * uy + a[2] * uz);
+      psiJ[1] = cJ * (a[3] * ux + a[4] * uy + a[5] * uz);
+      psiJ[2] = cJ * (a[6] * ux + a[7] * uy + a[8] * uz);
+      const T nx0 = T(1) - fx, ny0 = T(1) - fy;
+      const T mx[3] = {nx0 * nx0, nx0 * fx, fx * fx};
+      const T my[3] = {ny0 * ny0, ny0 * fy, fy * fy};
 #pragma unroll
-        for (int k = 0; k < 9; ++k) psiM[k] = cM * a[k];
-        psiJ[0] = cJ * (a[0] * ux + a[1] * uy + a[2] * uz);
-        psiJ[1] = cJ * (a[3] * ux + a[4] * uy + a[5] * uz);
-        psiJ[2] = cJ * (a[6] * ux + a[7] * uy + a[8] * uz);
-        const T nx0 = T(1) - fx, ny0 = T(1) - fy, nz0 = T(1) - fz;
-        const T mx[3] = {nx0 * nx0, nx0 * fx, fx * fx};
-        const T my[3] = {ny0 * ny0, ny0 * fy, fy * fy};
-        T mzf = T(1), jzf = T(1);
-        if constexpr (DIM == 3) {
-          mzf = pass == 0 ? nz0 * nz0 : (pass == 1 ? nz0 * fz : fz * fz);
-          jzf = pass == 0 ? nz0 : fz;
-        }
+      for (int m = 0; m < 9; ++m) {
+        const T wgt = mx[m % 3] * my[m / 3];
 #pragma unroll
-        for (int m = 0; m < 9; ++m) {
-          const T wgt = mx[m % 3] * my[m / 3] * mzf;
-#pragma unroll
-          for (int k = 0; k < 9; ++k) acc[m * 9 + k] += wgt * psiM[k];
-        }
-        if (DIM == 2 || pass < 2) {
-#pragma unroll
-          for (int cxy = 0; cxy < 4; ++cxy) {
-            const T wgt = ((cxy & 1) ? fx : nx0) * ((cxy & 2) ? fy : ny0) * jzf;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) acc[81 + cxy * 3 + k] += wgt * psiJ[k];
-          }
-        }
+        for (int k = 0; k < 9; ++k) acc[m * 9 + k] += wgt * psiM[k];
       }
-      cur = nxt;
-      p = pn;
+#pragma unroll
+      for (int cxy = 0; cxy < 4; ++cxy) {
+        const T wgt = ((cxy & 1) ? fx : nx0) * ((cxy & 2) ? fy : ny0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc[81 + cxy * 3 + k] += wgt * psiJ[k];
+      }
     }
-    // group reduction, CH moments at a time: registers -> LDS transpose ->
-    // G-term sums in fixed lane order
-    const int nk = (DIM == 3 && pass == 2) ? 81 : NACC;
+    cur = nxt;
+    p = pn;
+  }
+  // group reduction, CH moments at a time: registers -> LDS transpose ->
+  // G-term sums in fixed lane order
 #pragma unroll
-    for (int c0 = 0; c0 < NACC; c0 += CH) {
-      if (c0 < nk) {
+  for (int c0 = 0; c0 < NACC; c0 += CH) {
 #pragma unroll
-        for (int k = 0; k < CH; ++k)
-          if (c0 + k < NACC) red[lane * (CH + 1) + k] = acc[c0 + k];
-        __syncthreads();
-        const int kend = nk - c0 < CH ? nk - c0 : CH;
-        for (int k = gl; k < kend; k += G) {
-          T s = T(0);
+    for (int k = 0; k < CH; ++k)
+      if (c0 + k < NACC) red[lane * (CH + 1) + k] = acc[c0 + k];
+    __syncthreads();
+    const int kend = NACC - c0 < CH ? NACC - c0 : CH;
+    for (int k = gl; k < kend; k += G) {
+      T s = T(0);
 #pragma unroll 8
-          for (int j = 0; j < G; ++j) s += red[(grp * G + j) * (CH + 1) + k];
-          if (cs.valid) {
-            const int m = c0 + k;
-            const int sidx = DIM == 3 ? (m < 81 ? pass * 81 + m : 243 + pass * 12 + (m - 81)) : m;
-            S[(size_t)sidx * NC + cs.cell] = s;
-          }
-        }
-        __syncthreads();
+      for (int j = 0; j < G; ++j) s += red[(grp * G + j) * (CH + 1) + k];
+      if (cs.valid) S[(size_t)(c0 + k) * NC + cs.cell] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// 3D: the cell's 267 moments are split over the 4 lanes of its group rather
+// than its particles: lane t (t = 0, 1, 2) accumulates the 81 mass moments
+// of z-monomial type t over all of the cell's particles, lane 3 the 24
+// current moments (8 corners x 3 components).  Each round, every lane
+// computes the per-particle quantities (offsets, the 9 alpha-weighted mass
+// coefficients and the 3 current coefficients) of one particle and shares
+// them with its group through LDS; each lane then adds the 4 particles of
+// the round to its own moments.  The per-particle work (B gather, alpha) is
+// done once instead of once per z-monomial type, and no cross-lane
+// reduction is needed: each moment is summed by one lane, in particle
+// order.  All lanes run one instruction stream: lane 3 uses 24 of its 81
+// accumulators, with the operand selection
+//   lanes 0-2: weight = X[x] Y[y] Z, X = ((1-f)^2, (1-f) f, f^2), Z = mono_t(f_z),
+//              coefficient = the 9 mass coefficients;
+//   lane 3:    weight = X[x] Y[y], X = (1-f, f, 0), coefficients =
+//              (current x (1-f_z), current x f_z, 0, 0, 0).
+template <typename T>
+__global__ __launch_bounds__(64) void k_deposit_split3(KParams kp, const int32_t *__restrict__ bin_start,
+                                                       const V2<T> *__restrict__ xy,
+                                                       const V4<T> *__restrict__ uw, const T *__restrict__ zz,
+                                                       const V4<T> *__restrict__ Bs, T *__restrict__ S) {
+  constexpr int G = 4;
+  // per lane 4 x V4: (fx, fy, fz, J0), (J1, J2, M0, M1), (M2..M5), (M6..M8, -)
+  __shared__ V4<T> sh[4][64];
+  const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
+  const PC<T> pc(kp);
+  const size_t NC = (size_t)kp.ncells;
+  const bool isJ = gl == 3;
+
+  T acc[81];
+#pragma unroll
+  for (int k = 0; k < 81; ++k) acc[k] = T(0);
+  const T Bc[3][9] = {};
+  const int pal = cs.pbeg & ~(round_align<T, G>() - 1);
+  const int rounds = wave_rounds<G>(cs.pend - pal);
+  PRec<T> cur{}, nxt{};
+  int p = pal + gl;
+  if (rounds > 0) load_rec<T, 3>(p, cs.pend, xy, uw, zz, cur);
+  __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll 1
+  for (int r = 0; r < rounds; ++r) {
+    const int pn = p + G;
+    load_rec<T, 3>(pn, cs.pend, xy, uw, zz, nxt);
+    {
+      // this lane's particle (lanes outside the cell's range contribute 0)
+      const bool pv = p >= cs.pbeg && p < cs.pend;
+      const T fx = cur.fx, fy = cur.fy, fz = cur.fz;
+      const T ux = cur.ux, uy = cur.uy, uz = cur.uz;
+      T qs, bs;
+      species_of<T>(kp, pc, cs, p, qs, bs);
+      T Bx, By, Bz;
+      gather_B<T, 3, false>(kp, Bs, Bc, cs.gc, fx, fy, fz, Bx, By, Bz);
+      const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
+      const T kb = bs * igb * pc.invc;
+      T a[9];
+      make_alpha<T>(kb * Bx, kb * By, kb * Bz, a);
+      const T cJ = pv ? cur.w * qs * igb * pc.invV : T(0);
+      const T cM = cJ * bs;
+      V4<T> v0, v1, v2, v3;
+      v0.x = fx;
+      v0.y = fy;
+      v0.z = fz;
+      v0.w = cJ * (a[0] * ux + a[1] * uy + a[2] * uz);
+      v1.x = cJ * (a[3] * ux + a[4] * uy + a[5] * uz);
+      v1.y = cJ * (a[6] * ux + a[7] * uy + a[8] * uz);
+      v1.z = cM * a[0];
+      v1.w = cM * a[1];
+      v2.x = cM * a[2];
+      v2.y = cM * a[3];
+      v2.z = cM * a[4];
+      v2.w = cM * a[5];
+      v3.x = cM * a[6];
+      v3.y = cM * a[7];
+      v3.z = cM * a[8];
+      v3.w = T(0);
+      __syncthreads();  // the previous round's reads are done
+      sh[0][lane] = v0;
+      sh[1][lane] = v1;
+      sh[2][lane] = v2;
+      sh[3][lane] = v3;
+      __syncthreads();
+    }
+#pragma unroll 1
+    for (int j = 0; j < G; ++j) {
+      const int src = grp * G + j;
+      const V4<T> v0 = sh[0][src], v1 = sh[1][src], v2 = sh[2][src], v3 = sh[3][src];
+      const T fx = v0.x, fy = v0.y, fz = v0.z;
+      const T nx0 = T(1) - fx, ny0 = T(1) - fy, nz0 = T(1) - fz;
+      const T X[3] = {isJ ? nx0 : nx0 * nx0, isJ ? fx : nx0 * fx, isJ ? T(0) : fx * fx};
+      const T Y[3] = {isJ ? ny0 : ny0 * ny0, isJ ? fy : ny0 * fy, isJ ? T(0) : fy * fy};
+      const T Z = gl == 0 ? nz0 * nz0 : (gl == 1 ? nz0 * fz : (gl == 2 ? fz * fz : T(1)));
+      const T P[9] = {isJ ? v0.w * nz0 : v1.z, isJ ? v1.x * nz0 : v1.w, isJ ? v1.y * nz0 : v2.x,
+                      isJ ? v0.w * fz : v2.y,  isJ ? v1.x * fz : v2.z,  isJ ? v1.y * fz : v2.w,
+                      isJ ? T(0) : v3.x,       isJ ? T(0) : v3.y,       isJ ? T(0) : v3.z};
+#pragma unroll
+      for (int m = 0; m < 9; ++m) {
+        const T wgt = X[m % 3] * Y[m / 3] * Z;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[m * 9 + k] += wgt * P[k];
       }
     }
+    cur = nxt;
+    p = pn;
+  }
+  if (!cs.valid) return;
+#pragma unroll
+  for (int e = 0; e < 81; ++e) {
+    // lane 3: accumulator (x + 3 y) * 9 + k holds the current of corner
+    // (x, y, k / 3) along k % 3
+    const int m = e / 9, k = e % 9, x = m % 3, y = m / 3;
+    const bool jv = x < 2 && y < 2 && k < 6;
+    const int jidx = 243 + (k / 3) * 12 + (x + 2 * y) * 3 + k % 3;
+    if (!isJ || jv) S[(size_t)(isJ ? jidx : gl * 81 + e) * NC + cs.cell] = acc[e];
   }
 }
 
@@ -889,10 +995,17 @@ T *mp(void *p) {
   return static_cast<T *>(p);
 }
 
-template <typename T, int DIM, int G>
+template <typename T, int G>
 void deposit_impl(const KParams &kp, const PartPtrs &pp, const void *Bst, void *S, hipStream_t st) {
   const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
-  hipLaunchKernelGGL((k_deposit_cells<T, DIM, G>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, cp<V2<T>>(pp.xy),
+  hipLaunchKernelGGL((k_deposit_cells<T, G>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, cp<V2<T>>(pp.xy),
+                     cp<V4<T>>(pp.uw), cp<V4<T>>(Bst), mp<T>(S));
+}
+
+template <typename T>
+void deposit3_impl(const KParams &kp, const PartPtrs &pp, const void *Bst, void *S, hipStream_t st) {
+  const int nblk = (kp.ncells + 15) / 16;
+  hipLaunchKernelGGL((k_deposit_split3<T>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, cp<V2<T>>(pp.xy),
                      cp<V4<T>>(pp.uw), cp<T>(pp.z), cp<V4<T>>(Bst), mp<T>(S));
 }
 
@@ -945,11 +1058,6 @@ void dispatch(int prec, int dim, int group, A &&...args) {
 }
 
 template <typename T, int D, int G>
-struct DepositF {
-  template <typename... A>
-  static void run(A &&...a) { deposit_impl<T, D, G>(a...); }
-};
-template <typename T, int D, int G>
 struct PushF {
   template <typename... A>
   static void run(A &&...a) { push_impl<T, D, G>(a...); }
@@ -984,7 +1092,15 @@ void launch_stage_field(const KParams &kp, int prec, const double *F, void *out,
 
 void launch_deposit_cells(const KParams &kp, int prec, int group, const PartPtrs &pp, const void *Bst, void *S,
                           hipStream_t st) {
-  dispatch<DepositF>(prec, kp.dim, group, kp, pp, Bst, S, st);
+  const bool f = prec == RELSIM_MIXED;
+  if (kp.dim == 3) return f ? deposit3_impl<float>(kp, pp, Bst, S, st) : deposit3_impl<double>(kp, pp, Bst, S, st);
+  switch (group) {
+    case 4: return f ? deposit_impl<float, 4>(kp, pp, Bst, S, st) : deposit_impl<double, 4>(kp, pp, Bst, S, st);
+    case 8: return f ? deposit_impl<float, 8>(kp, pp, Bst, S, st) : deposit_impl<double, 8>(kp, pp, Bst, S, st);
+    case 16: return f ? deposit_impl<float, 16>(kp, pp, Bst, S, st) : deposit_impl<double, 16>(kp, pp, Bst, S, st);
+    case 32: return f ? deposit_impl<float, 32>(kp, pp, Bst, S, st) : deposit_impl<double, 32>(kp, pp, Bst, S, st);
+    case 64: return f ? deposit_impl<float, 64>(kp, pp, Bst, S, st) : deposit_impl<double, 64>(kp, pp, Bst, S, st);
+  }
 }
 
 void launch_assemble(const KParams &kp, int prec, const void *S, double *J, double *M, hipStream_t st) {
