@@ -76,19 +76,21 @@ __device__ __forceinline__ void centre_w3(T f, T w[3]) {
   w[2] = hi ? f - T(0.5) : T(0);
 }
 
-// alpha = (I - [b]x + b b^T) / (1 + |b|^2), row-major.
+// alpha = (I - [b]x + b b^T) / (1 + |b|^2), row-major, as its numerator
+// (written to a) and the returned scale 1 / (1 + |b|^2); the kernels fold
+// the scale into their per-particle coefficients.
 template <typename T>
-__device__ __forceinline__ void make_alpha(T bx, T by, T bz, T a[9]) {
-  const T inv = rcp_t(T(1) + bx * bx + by * by + bz * bz);
-  a[0] = (T(1) + bx * bx) * inv;
-  a[1] = (bz + bx * by) * inv;
-  a[2] = (bx * bz - by) * inv;
-  a[3] = (bx * by - bz) * inv;
-  a[4] = (T(1) + by * by) * inv;
-  a[5] = (bx + by * bz) * inv;
-  a[6] = (by + bx * bz) * inv;
-  a[7] = (by * bz - bx) * inv;
-  a[8] = (T(1) + bz * bz) * inv;
+__device__ __forceinline__ T alpha_num(T bx, T by, T bz, T a[9]) {
+  a[0] = T(1) + bx * bx;
+  a[1] = bz + bx * by;
+  a[2] = bx * bz - by;
+  a[3] = bx * by - bz;
+  a[4] = T(1) + by * by;
+  a[5] = bx + by * bz;
+  a[6] = by + bx * bz;
+  a[7] = by * bz - bx;
+  a[8] = T(1) + bz * bz;
+  return rcp_t(a[0] + by * by + bz * bz);
 }
 
 // Particle-side view of the kernel constants in the arithmetic type T
@@ -335,23 +337,23 @@ __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t 
       const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
       const T kb = bs * igb * pc.invc;
       T a[9];
-      make_alpha<T>(kb * Bx, kb * By, kb * Bz, a);
-      const T cJ = wp * qs * igb * pc.invV;
+      const T inv = alpha_num<T>(kb * Bx, kb * By, kb * Bz, a);
+      // current and mass coefficients with the alpha scale folded in; the
+      // mass coefficient rides on the x monomials
+      const T cJ = wp * qs * igb * pc.invV * inv;
       const T cM = cJ * bs;
-      T psiM[9], psiJ[3];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) psiM[k] = cM * a[k];
+      T psiJ[3];
       psiJ[0] = cJ * (a[0] * ux + a[1] * uy + a[2] * uz);
       psiJ[1] = cJ * (a[3] * ux + a[4] * uy + a[5] * uz);
       psiJ[2] = cJ * (a[6] * ux + a[7] * uy + a[8] * uz);
       const T nx0 = T(1) - fx, ny0 = T(1) - fy;
-      const T mx[3] = {nx0 * nx0, nx0 * fx, fx * fx};
+      const T mx[3] = {cM * (nx0 * nx0), cM * (nx0 * fx), cM * (fx * fx)};
       const T my[3] = {ny0 * ny0, ny0 * fy, fy * fy};
 #pragma unroll
       for (int m = 0; m < 9; ++m) {
         const T wgt = mx[m % 3] * my[m / 3];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) acc[m * 9 + k] += wgt * psiM[k];
+        for (int k = 0; k < 9; ++k) acc[m * 9 + k] += wgt * a[k];
       }
 #pragma unroll
       for (int cxy = 0; cxy < 4; ++cxy) {
@@ -386,32 +388,35 @@ __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t 
 // than its particles: lane t (t = 0, 1, 2) accumulates the 81 mass moments
 // of z-monomial type t over all of the cell's particles, lane 3 the 24
 // current moments (8 corners x 3 components).  Each round, every lane
-// computes the per-particle quantities (offsets, the 9 alpha-weighted mass
-// coefficients and the 3 current coefficients) of one particle and shares
-// them with its group through LDS; each lane then adds the 4 particles of
-// the round to its own moments.  The per-particle work (B gather, alpha) is
-// done once instead of once per z-monomial type, and no cross-lane
-// reduction is needed: each moment is summed by one lane, in particle
-// order.  All lanes run one instruction stream: lane 3 uses 24 of its 81
-// accumulators, with the operand selection
-//   lanes 0-2: weight = X[x] Y[y] Z, X = ((1-f)^2, (1-f) f, f^2), Z = mono_t(f_z),
-//              coefficient = the 9 mass coefficients;
-//   lane 3:    weight = X[x] Y[y], X = (1-f, f, 0), coefficients =
-//              (current x (1-f_z), current x f_z, 0, 0, 0).
+// computes the per-particle quantities of one particle and shares them with
+// its group through LDS; each lane then adds the 4 particles of the round to
+// its own moments.  The per-particle work (B gather, alpha) is done once
+// instead of once per z-monomial type, and no cross-lane reduction is
+// needed: each moment is summed by one lane, in particle order.  All lanes
+// run one instruction stream, acc[m * 9 + k] += X[m % 3] Z Y[m / 3] P[k],
+// on operands read from a lane-dependent place:
+//   lanes 0-2: X = ((1-f_x)^2, (1-f_x) f_x, f_x^2), Y likewise in y,
+//              Z = mono_t(f_z), P = the 9 alpha-weighted mass coefficients;
+//   lane 3:    X = (1-f_x, f_x, 0), Y = (1-f_y, f_y, 0), Z = 1,
+//              P = (current x (1-f_z), current x f_z, 0, 0, 0),
+// so lane 3 uses 24 of its 81 accumulators.
 template <typename T>
 __global__ __launch_bounds__(64) void k_deposit_split3(KParams kp, const int32_t *__restrict__ bin_start,
                                                        const V2<T> *__restrict__ xy,
                                                        const V4<T> *__restrict__ uw, const T *__restrict__ zz,
                                                        const V4<T> *__restrict__ Bs, T *__restrict__ S) {
   constexpr int G = 4;
-  // per lane 4 x V4: (fx, fy, fz, J0), (J1, J2, M0, M1), (M2..M5), (M6..M8, -)
-  __shared__ V4<T> sh[4][64];
+  // per producing lane: operand blocks (X0 X1 X2 Y0) (Y1 Y2 P0 P1) (P2..P5)
+  // (P6 P7 P8 -) for the mass lanes [0] and the current lane [1], and Z
+  __shared__ V4<T> sh[2][4][64];
+  __shared__ T zsh[4][64];
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
   const PC<T> pc(kp);
   const size_t NC = (size_t)kp.ncells;
   const bool isJ = gl == 3;
+  const V4<T> *const mine = &sh[isJ ? 1 : 0][0][0];
 
   T acc[81];
 #pragma unroll
@@ -439,48 +444,72 @@ __global__ __launch_bounds__(64) void k_deposit_split3(KParams kp, const int32_t
       const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
       const T kb = bs * igb * pc.invc;
       T a[9];
-      make_alpha<T>(kb * Bx, kb * By, kb * Bz, a);
-      const T cJ = pv ? cur.w * qs * igb * pc.invV : T(0);
+      const T inv = alpha_num<T>(kb * Bx, kb * By, kb * Bz, a);
+      const T cJ = pv ? cur.w * qs * igb * pc.invV * inv : T(0);
       const T cM = cJ * bs;
-      V4<T> v0, v1, v2, v3;
-      v0.x = fx;
-      v0.y = fy;
-      v0.z = fz;
-      v0.w = cJ * (a[0] * ux + a[1] * uy + a[2] * uz);
-      v1.x = cJ * (a[3] * ux + a[4] * uy + a[5] * uz);
-      v1.y = cJ * (a[6] * ux + a[7] * uy + a[8] * uz);
-      v1.z = cM * a[0];
-      v1.w = cM * a[1];
-      v2.x = cM * a[2];
-      v2.y = cM * a[3];
-      v2.z = cM * a[4];
-      v2.w = cM * a[5];
-      v3.x = cM * a[6];
-      v3.y = cM * a[7];
-      v3.z = cM * a[8];
-      v3.w = T(0);
+      const T j0 = cJ * (a[0] * ux + a[1] * uy + a[2] * uz);
+      const T j1 = cJ * (a[3] * ux + a[4] * uy + a[5] * uz);
+      const T j2 = cJ * (a[6] * ux + a[7] * uy + a[8] * uz);
+      const T nx0 = T(1) - fx, ny0 = T(1) - fy, nz0 = T(1) - fz;
+      V4<T> m0, m1, m2, m3, c0, c1, c2, c3;
+      m0.x = nx0 * nx0;
+      m0.y = nx0 * fx;
+      m0.z = fx * fx;
+      m0.w = ny0 * ny0;
+      m1.x = ny0 * fy;
+      m1.y = fy * fy;
+      m1.z = cM * a[0];
+      m1.w = cM * a[1];
+      m2.x = cM * a[2];
+      m2.y = cM * a[3];
+      m2.z = cM * a[4];
+      m2.w = cM * a[5];
+      m3.x = cM * a[6];
+      m3.y = cM * a[7];
+      m3.z = cM * a[8];
+      m3.w = T(0);
+      c0.x = nx0;
+      c0.y = fx;
+      c0.z = T(0);
+      c0.w = ny0;
+      c1.x = fy;
+      c1.y = T(0);
+      c1.z = j0 * nz0;
+      c1.w = j1 * nz0;
+      c2.x = j2 * nz0;
+      c2.y = j0 * fz;
+      c2.z = j1 * fz;
+      c2.w = j2 * fz;
+      c3.x = T(0);
+      c3.y = T(0);
+      c3.z = T(0);
+      c3.w = T(0);
       __syncthreads();  // the previous round's reads are done
-      sh[0][lane] = v0;
-      sh[1][lane] = v1;
-      sh[2][lane] = v2;
-      sh[3][lane] = v3;
+      sh[0][0][lane] = m0;
+      sh[0][1][lane] = m1;
+      sh[0][2][lane] = m2;
+      sh[0][3][lane] = m3;
+      sh[1][0][lane] = c0;
+      sh[1][1][lane] = c1;
+      sh[1][2][lane] = c2;
+      sh[1][3][lane] = c3;
+      zsh[0][lane] = nz0 * nz0;
+      zsh[1][lane] = nz0 * fz;
+      zsh[2][lane] = fz * fz;
+      zsh[3][lane] = T(1);
       __syncthreads();
     }
 #pragma unroll 1
     for (int j = 0; j < G; ++j) {
       const int src = grp * G + j;
-      const V4<T> v0 = sh[0][src], v1 = sh[1][src], v2 = sh[2][src], v3 = sh[3][src];
-      const T fx = v0.x, fy = v0.y, fz = v0.z;
-      const T nx0 = T(1) - fx, ny0 = T(1) - fy, nz0 = T(1) - fz;
-      const T X[3] = {isJ ? nx0 : nx0 * nx0, isJ ? fx : nx0 * fx, isJ ? T(0) : fx * fx};
-      const T Y[3] = {isJ ? ny0 : ny0 * ny0, isJ ? fy : ny0 * fy, isJ ? T(0) : fy * fy};
-      const T Z = gl == 0 ? nz0 * nz0 : (gl == 1 ? nz0 * fz : (gl == 2 ? fz * fz : T(1)));
-      const T P[9] = {isJ ? v0.w * nz0 : v1.z, isJ ? v1.x * nz0 : v1.w, isJ ? v1.y * nz0 : v2.x,
-                      isJ ? v0.w * fz : v2.y,  isJ ? v1.x * fz : v2.z,  isJ ? v1.y * fz : v2.w,
-                      isJ ? T(0) : v3.x,       isJ ? T(0) : v3.y,       isJ ? T(0) : v3.z};
+      const V4<T> v0 = mine[src], v1 = mine[64 + src], v2 = mine[128 + src], v3 = mine[192 + src];
+      const T Z = zsh[gl][src];
+      const T XZ[3] = {v0.x * Z, v0.y * Z, v0.z * Z};
+      const T Y[3] = {v0.w, v1.x, v1.y};
+      const T P[9] = {v1.z, v1.w, v2.x, v2.y, v2.z, v2.w, v3.x, v3.y, v3.z};
 #pragma unroll
       for (int m = 0; m < 9; ++m) {
-        const T wgt = X[m % 3] * Y[m / 3] * Z;
+        const T wgt = XZ[m % 3] * Y[m / 3];
 #pragma unroll
         for (int k = 0; k < 9; ++k) acc[m * 9 + k] += wgt * P[k];
       }
@@ -489,14 +518,20 @@ __global__ __launch_bounds__(64) void k_deposit_split3(KParams kp, const int32_t
     p = pn;
   }
   if (!cs.valid) return;
+  T *const base = S + cs.cell;
+  if (!isJ) {
+    T *const q = base + (size_t)(gl * 81) * NC;
 #pragma unroll
-  for (int e = 0; e < 81; ++e) {
-    // lane 3: accumulator (x + 3 y) * 9 + k holds the current of corner
-    // (x, y, k / 3) along k % 3
-    const int m = e / 9, k = e % 9, x = m % 3, y = m / 3;
-    const bool jv = x < 2 && y < 2 && k < 6;
-    const int jidx = 243 + (k / 3) * 12 + (x + 2 * y) * 3 + k % 3;
-    if (!isJ || jv) S[(size_t)(isJ ? jidx : gl * 81 + e) * NC + cs.cell] = acc[e];
+    for (int e = 0; e < 81; ++e) q[(size_t)e * NC] = acc[e];
+  } else {
+    // accumulator (x + 3 y) * 9 + k holds the current of corner (x, y, k / 3)
+    // along k % 3
+    T *const q = base + (size_t)243 * NC;
+#pragma unroll
+    for (int e = 0; e < 81; ++e) {
+      const int m = e / 9, k = e % 9, x = m % 3, y = m / 3;
+      if (x < 2 && y < 2 && k < 6) q[(size_t)((k / 3) * 12 + (x + 2 * y) * 3 + k % 3) * NC] = acc[e];
+    }
   }
 }
 
@@ -652,7 +687,7 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
     const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
     const T kb = bs * igb * pc.invc;
     T a[9];
-    make_alpha<T>(kb * Bx, kb * By, kb * Bz, a);
+    const T inv2 = T(2) * alpha_num<T>(kb * Bx, kb * By, kb * Bz, a);
     T Ex = T(0), Ey = T(0), Ez = T(0);
 #pragma unroll
     for (int c = 0; c < NCORN; ++c) {
@@ -663,10 +698,11 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
       Ez += wgt * Ec[2][c];
     }
     const T vx = ux + bs * Ex, vy = uy + bs * Ey, vz = uz + bs * Ez;
+    // u^{n+1} = 2 alpha v - u^n, alpha = (numerator a) / (1 + |b|^2)
     const T ubx = a[0] * vx + a[1] * vy + a[2] * vz;
     const T uby = a[3] * vx + a[4] * vy + a[5] * vz;
     const T ubz = a[6] * vx + a[7] * vy + a[8] * vz;
-    const T nx = T(2) * ubx - ux, ny = T(2) * uby - uy, nz = T(2) * ubz - uz;
+    const T nx = inv2 * ubx - ux, ny = inv2 * uby - uy, nz = inv2 * ubz - uz;
     const T ign = kp.nonrel ? T(1) : rsqrt_t(T(1) + (nx * nx + ny * ny + nz * nz) * pc.invc2);
     const T dtg = pc.dt * ign;
     fx += dtg * nx * pc.idx;
