@@ -274,7 +274,7 @@ def main():
     wl = harris.workload(args.workload)
     log("generating %s: %d particles" % (wl.name, wl.nparticles))
     t = time.perf_counter()
-    host = harris.make_particles(wl)
+    host = harris.make_particles(wl, workers=min(16, os.cpu_count() or 1))
     host["E"], host["B"] = harris.make_fields(wl)
     log("inputs ready in %.1f s" % (time.perf_counter() - t))
     torch.cuda.set_device(0)

@@ -33,6 +33,8 @@ Zenitani (2015).
 
 Layout of the generated particles: sorted by bin = cell * nspecies + species,
 cells in natural order (i + nx (j + ny k)), so ``bin_start`` is known up front.
+In 3D every z-layer of cells draws from its own stream (PCG64 seeded with
+(seed, layer)), so layers can be generated in parallel or one at a time.
 """
 from __future__ import annotations
 
@@ -100,13 +102,16 @@ class Workload:
 
 
 # The workloads: 2D 64x32 (small, all parities), 2D 1024x512 (throughput),
-# 2D 256x128 (adjoint), 3D 128x64x64 and 3D 256x128x128.
+# 2D 256x128 (adjoint), 3D 128x64x64, 3D 256x128x128 and 3D 512x256x256
+# (536,870,912 particles: the particle count and mass-matrix size stated for
+# the large 3D run).
 WORKLOADS: Dict[str, Workload] = {
     "harris2d_64x32": Workload("harris2d_64x32", 2, 64, 32, 1, 0.5, 16, seed=1, steps=10),
     "harris2d_1024x512": Workload("harris2d_1024x512", 2, 1024, 512, 1, 1.0, 64, seed=2, steps=100),
     "harris2d_256x128": Workload("harris2d_256x128", 2, 256, 128, 1, 0.5, 32, seed=3, steps=20),
     "harris3d_128x64x64": Workload("harris3d_128x64x64", 3, 128, 64, 64, 0.5, 16, seed=4, steps=50),
     "harris3d_256x128x128": Workload("harris3d_256x128x128", 3, 256, 128, 128, 0.5, 8, seed=5, steps=20),
+    "harris3d_512x256x256": Workload("harris3d_512x256x256", 3, 512, 256, 256, 0.5, 8, seed=6, steps=20),
 }
 
 
@@ -160,17 +165,11 @@ def _sech2(x: np.ndarray) -> np.ndarray:
     return 4.0 * e / (1.0 + e) ** 2
 
 
-def make_particles(wl: Workload, seed: Optional[int] = None) -> Dict[str, np.ndarray]:
-    """Generate the bin-sorted particle state in FP64.
-
-    Returns a dict with ``cell`` (int32, natural cell index), ``species``
-    (uint8), ``off`` (dim, n) offsets in [0,1), ``u`` (3, n), ``w`` (n), and
-    ``bin_start`` (int32, ncells * nspecies + 1).
-    """
-    seed = wl.seed if seed is None else seed
-    rng = np.random.Generator(np.random.PCG64(seed))
+def _generate(wl: Workload, rng: np.random.Generator, c0: int, c1: int) -> Dict[str, np.ndarray]:
+    """Particles of cells [c0, c1) drawn from rng (bin order, no bin_start)."""
     hp = wl.harris
-    S, ppc, nc = wl.nspecies, wl.ppc, wl.ncells
+    S, ppc = wl.nspecies, wl.ppc
+    nc = c1 - c0
     n = nc * S * ppc
     n_sheet = ppc // 2
     n_bg = ppc - n_sheet
@@ -180,7 +179,7 @@ def make_particles(wl: Workload, seed: Optional[int] = None) -> Dict[str, np.nda
     V = dx * dx * (dx if wl.dim == 3 else 1.0)
 
     p = np.arange(n, dtype=np.int64)
-    cell = (p // (S * ppc)).astype(np.int32)
+    cell = (c0 + p // (S * ppc)).astype(np.int32)
     species = ((p // ppc) % S).astype(np.uint8)
     k_in = p % ppc
     is_sheet = k_in < n_sheet
@@ -203,18 +202,72 @@ def make_particles(wl: Workload, seed: Optional[int] = None) -> Dict[str, np.nda
     beta[beta == 0] = wl.beta_d
     u[:, is_sheet] = boost_z(rng, us, beta)
     u[:, ~is_sheet] = sample_mj(rng, wl.theta_b, n - ns)
+    return {"cell": cell, "species": species, "off": off, "u": u, "w": w}
 
-    counts = np.full(nc * S, ppc, dtype=np.int64)
-    bin_start = np.zeros(nc * S + 1, dtype=np.int64)
+
+def layer_rng(seed: int, k: int) -> np.random.Generator:
+    """The stream of z-layer k of a 3D workload."""
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, k])))
+
+
+def make_layers(wl: Workload, k0: int, k1: int, seed: Optional[int] = None) -> Dict[str, np.ndarray]:
+    """Particles of the z-layers [k0, k1) of a 3D workload, in bin order.
+
+    ``bin_start`` covers the bins of those layers and starts at 0.
+    """
+    assert wl.dim == 3 and 0 <= k0 <= k1 <= wl.nz
+    seed = wl.seed if seed is None else seed
+    nxy = wl.nx * wl.ny
+    parts = [_generate(wl, layer_rng(seed, k), k * nxy, (k + 1) * nxy) for k in range(k0, k1)]
+    out = {key: np.concatenate([q[key] for q in parts], axis=-1) for key in ("cell", "species", "off", "u", "w")}
+    out["bin_start"] = _uniform_bins((k1 - k0) * nxy * wl.nspecies, wl.ppc)
+    return out
+
+
+def _uniform_bins(nbins: int, ppc: int) -> np.ndarray:
+    counts = np.full(nbins, ppc, dtype=np.int64)
+    bin_start = np.zeros(nbins + 1, dtype=np.int64)
     np.cumsum(counts, out=bin_start[1:])
-    return {
-        "cell": cell,
-        "species": species,
-        "off": off,
-        "u": u,
-        "w": w,
-        "bin_start": bin_start.astype(np.int32),
-    }
+    return bin_start.astype(np.int32)
+
+
+def make_particles(wl: Workload, seed: Optional[int] = None, workers: int = 1) -> Dict[str, np.ndarray]:
+    """Generate the bin-sorted particle state in FP64.
+
+    Returns a dict with ``cell`` (int32, natural cell index), ``species``
+    (uint8), ``off`` (dim, n) offsets in [0,1), ``u`` (3, n), ``w`` (n), and
+    ``bin_start`` (int32, ncells * nspecies + 1).  3D workloads are generated
+    layer by layer (``workers`` > 1: in that many threads; numpy releases the
+    interpreter lock in the array work).
+    """
+    seed = wl.seed if seed is None else seed
+    if wl.dim == 2:
+        out = _generate(wl, np.random.Generator(np.random.PCG64(seed)), 0, wl.ncells)
+        out["bin_start"] = _uniform_bins(wl.ncells * wl.nspecies, wl.ppc)
+        return out
+    n = wl.nparticles
+    out = {"cell": np.empty(n, np.int32), "species": np.empty(n, np.uint8), "off": np.empty((3, n)),
+           "u": np.empty((3, n)), "w": np.empty(n)}
+    per = wl.nx * wl.ny * wl.nspecies * wl.ppc
+
+    def put(k):
+        q = make_layers(wl, k, k + 1, seed)
+        sl = slice(k * per, (k + 1) * per)
+        for key in ("cell", "species", "w"):
+            out[key][sl] = q[key]
+        out["off"][:, sl] = q["off"]
+        out["u"][:, sl] = q["u"]
+
+    if workers > 1:
+        from concurrent.futures import ThreadPoolExecutor
+
+        with ThreadPoolExecutor(workers) as ex:
+            list(ex.map(put, range(wl.nz)))
+    else:
+        for k in range(wl.nz):
+            put(k)
+    out["bin_start"] = _uniform_bins(wl.ncells * wl.nspecies, wl.ppc)
+    return out
 
 
 def make_fields(wl: Workload, eps: Optional[float] = None):

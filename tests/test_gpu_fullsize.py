@@ -11,13 +11,17 @@ oracle computes one by one:
 * energy (S7): the full FP64 diagnostic against the oracle.
 
 Workloads: the 2D double Harris sheet 1024 x 512 cells x 64 particles per
-cell per species (67,108,864 particles) and the 3D sheet 128 x 64 x 64 x 16
-(16,777,216 particles).  Inputs are the seeded generator's; the mixed path
+cell per species (67,108,864 particles) and the 3D sheets 128 x 64 x 64 x 16
+(16,777,216 particles) and 256 x 128 x 128 x 8 (67,108,864 particles), in
+both precisions.  (The 536,870,912-particle 3D sheet is in
+test_gpu_zlarge.py.)  Inputs are the seeded generator's; the mixed path
 is teacher-forced (the oracle receives the FP32-rounded particle state).
 Tolerances as in test_gpu_parity: 1e-12 (FP64) and 1e-5 (mixed), normwise;
 for the energy sums, the rounding bound of the oracle's sequential sums
 (4 x terms x eps relative, about 1e-9 here).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -29,15 +33,16 @@ from tests.helpers import grid_of, normwise, periodic_diff, positions
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-12, "mixed": 1e-5}
-WORKLOADS = ["harris2d_1024x512", "harris3d_128x64x64"]
+WORKLOADS = ["harris2d_1024x512", "harris3d_128x64x64", "harris3d_256x128x128"]
 _CACHE = {}
+WORKERS = min(16, os.cpu_count() or 1)
 
 
 def inputs(name):
+    # kept for the whole module (about 4 GB of host memory per 67M particles)
     if name not in _CACHE:
-        _CACHE.clear()
         wl = harris.workload(name)
-        p = harris.make_particles(wl)
+        p = harris.make_particles(wl, workers=WORKERS)
         E, B = harris.make_fields(wl)
         _CACHE[name] = (wl, p, E, B)
     return _CACHE[name]
@@ -67,17 +72,13 @@ def particles_of_cells(p, cells, S):
     return np.concatenate(idx) if idx else np.zeros(0, np.int64)
 
 
-@pytest.mark.parametrize("precision", ["mixed", "fp64"])
-@pytest.mark.parametrize("name", WORKLOADS)
-def test_fullsize_deposit_sampled_nodes(name, precision):
-    need_gpu()
+def check_deposit(wl, p, B, ctx, parts, precision):
+    """J-hat and M of sampled nodes against the oracle on the particles of
+    the cells around them."""
     from paper_2509_11100_amd import relsim
+    import torch
 
-    wl, p, E, B = inputs(name)
     g = grid_of(wl)
-    n = p["w"].shape[0]
-    ctx = make_ctx(g, precision, n, rtol=1e-10)
-    parts = load(ctx, p["cell"], p["species"], p["off"], p["u"], p["w"], p["bin_start"])
     J, M = relsim.deposit_moments(ctx, parts, cuda_grid(B))
     rng = np.random.default_rng(7)
     # sampled nodes: random ones, the grid corners and the sheet centres
@@ -88,32 +89,25 @@ def test_fullsize_deposit_sampled_nodes(name, precision):
     x = positions(g, p["cell"][sel], off)
     Jr, Mr = oracle.deposit_nodes(g, x, rounded(precision, p["u"][:, sel]), rounded(precision, p["w"][sel]),
                                   p["species"][sel].astype(np.int32), B, nodes)
-    import torch
-
     nt = torch.as_tensor(nodes, device=J.device)
     Jg = J[:, nt].cpu().numpy()
     Mg = M[:, :, nt].cpu().numpy()
     assert normwise(Jg, Jr) < TOL[precision]
     assert normwise(Mg, Mr) < TOL[precision]
-    del J, M, parts, ctx
+    return J, M
 
 
-@pytest.mark.parametrize("precision", ["mixed", "fp64"])
-@pytest.mark.parametrize("name", WORKLOADS)
-def test_fullsize_push_resort_sampled_particles(name, precision):
-    need_gpu()
+def check_push(wl, p, E, B, ctx, parts, J, M, precision):
+    """Sampled particles followed through push + re-sort by their new index
+    against the oracle push; the whole re-sorted state in bin order."""
     import torch
     from paper_2509_11100_amd import relsim
 
-    wl, p, E, B = inputs(name)
     g = grid_of(wl)
     n = p["w"].shape[0]
     S = len(wl.q)
-    ctx = make_ctx(g, precision, n, rtol=1e-10)
-    parts = load(ctx, p["cell"], p["species"], p["off"], p["u"], p["w"], p["bin_start"])
     Bt = cuda_grid(B)
     # E_theta from the GPU's own deposit and solve (the oracle takes it as input)
-    J, M = relsim.deposit_moments(ctx, parts, Bt)
     Eth, _, _, it, rr = relsim.field_solve(ctx, M, J, cuda_grid(E), Bt)
     del J, M
     perm = torch.empty(n, dtype=torch.int32, device=Bt.device)
@@ -121,8 +115,9 @@ def test_fullsize_push_resort_sampled_particles(name, precision):
     rng = np.random.default_rng(11)
     old = np.unique(np.concatenate([rng.integers(0, n, 20000), [0, n - 1]]))
     new = perm[torch.as_tensor(old, device=perm.device)].cpu().numpy().astype(np.int64)
+    del perm
     assert np.unique(new).size == new.size and new.min() >= 0 and new.max() < n
-    newt = torch.as_tensor(new, device=perm.device)
+    newt = torch.as_tensor(new, device=Bt.device)
     cell1 = parts.cell[newt].cpu().numpy()
     off1 = np.stack([parts.off[d][newt].cpu().numpy().astype(np.float64) for d in range(g.dim)])
     u1 = np.stack([parts.u[d][newt].cpu().numpy().astype(np.float64) for d in range(3)])
@@ -139,25 +134,17 @@ def test_fullsize_push_resort_sampled_particles(name, precision):
     np.testing.assert_array_equal(w1, rounded(precision, p["w"][old]))
     assert np.all((off1 >= 0) & (off1 < 1))
     # the whole re-sorted state is in bin order and bin_start matches it
-    cell = parts.cell.cpu().numpy().astype(np.int64)
-    sp = parts.species().cpu().numpy().astype(np.int64)
-    key = cell * S + sp
+    key = parts.cell.cpu().numpy().astype(np.int64) * S + parts.species().cpu().numpy()
     assert np.all(np.diff(key) >= 0)
     np.testing.assert_array_equal(parts.bin_start.cpu().numpy(), np.searchsorted(key, np.arange(g.N * S + 1)))
-    del parts, ctx
 
 
-@pytest.mark.parametrize("precision", ["mixed", "fp64"])
-@pytest.mark.parametrize("name", WORKLOADS)
-def test_fullsize_energy(name, precision):
-    need_gpu()
+def check_energy(wl, p, E, B, ctx, parts, precision):
+    """The FP64 energy diagnostic against the oracle's."""
     from paper_2509_11100_amd import relsim
 
-    wl, p, E, B = inputs(name)
     g = grid_of(wl)
     n = p["w"].shape[0]
-    ctx = make_ctx(g, precision, n, rtol=1e-10)
-    parts = load(ctx, p["cell"], p["species"], p["off"], p["u"], p["w"], p["bin_start"])
     W = relsim.energy(ctx, parts, cuda_grid(E), cuda_grid(B))
     Wr = oracle.energy(g, rounded(precision, p["u"]), rounded(precision, p["w"]), p["species"].astype(np.int32), E,
                        B)
@@ -168,4 +155,40 @@ def test_fullsize_energy(name, precision):
     for k in range(3):
         assert abs(W[k] - Wr[k]) <= tol[k] * abs(Wr[k])
     np.testing.assert_allclose(W[3], W[0] + W[1] + W[2], rtol=4 * eps)
+
+
+def setup(name, precision):
+    wl, p, E, B = inputs(name)
+    g = grid_of(wl)
+    ctx = make_ctx(g, precision, p["w"].shape[0], rtol=1e-10)
+    parts = load(ctx, p["cell"], p["species"], p["off"], p["u"], p["w"], p["bin_start"])
+    return wl, p, E, B, ctx, parts
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_fullsize_deposit_sampled_nodes(name, precision):
+    need_gpu()
+    wl, p, E, B, ctx, parts = setup(name, precision)
+    check_deposit(wl, p, B, ctx, parts, precision)
     del parts, ctx
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_fullsize_push_resort_sampled_particles(name, precision):
+    need_gpu()
+    wl, p, E, B, ctx, parts = setup(name, precision)
+    J, M = check_deposit(wl, p, B, ctx, parts, precision)
+    check_push(wl, p, E, B, ctx, parts, J, M, precision)
+    del J, M, parts, ctx
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("name", WORKLOADS)
+def test_fullsize_energy(name, precision):
+    need_gpu()
+    wl, p, E, B, ctx, parts = setup(name, precision)
+    check_energy(wl, p, E, B, ctx, parts, precision)
+    del parts, ctx
+
