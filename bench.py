@@ -50,19 +50,23 @@ def kernel_bytes(name, wl, prec, n, nbins, ncells):
         # in: per-cell moments; out: J-hat and M at nodes (FP64)
         nmom = 93 if d == 2 else 267
         return ncells * nmom * T + ncells * (grid + 8 * 9 * noff)
-    if name == "push":
-        # in: offsets + (momentum, weight) records, E_theta, B^n; out: the
-        # same records (whole, weight unchanged) + 1-byte move code
+    if name == "push_count":
+        # first pass of push + re-sort: in: offsets + (momentum, weight)
+        # records, E_theta, B^n; out: 1-byte move code (+ per-bin counts)
+        return n * ((d + 4) * T + 1) + 2 * ncells * grid
+    if name == "push_scatter":
+        # second pass: in: the records, move codes, E_theta, B^n; out: the
+        # pushed records in the new order
         return n * (2 * (d + 4) * T + 1) + 2 * ncells * grid
-    if name == "sort_scatter":
-        # in: offsets, momentum, weight + move code; out: offsets, momentum, weight
-        return n * (2 * (d + 4) * T + 1)
+    if name == "push":
+        # push in place without re-sort: in and out the records
+        return n * 2 * (d + 4) * T + 2 * ncells * grid
     return None
 
 
 # library timing names -> HIP kernel symbols (for the committed counter summaries)
-KERNEL_SYMBOL = {"deposit_cells": "k_deposit_cells", "assemble_nodes": "k_assemble", "push": "k_push",
-                 "sort_scatter": "k_sort_scatter", "sort_offsets": "k_sort_offsets"}
+KERNEL_SYMBOL = {"deposit_cells": "k_deposit_cells", "assemble_nodes": "k_assemble", "push_count": "k_push",
+                 "push_scatter": "k_push_scatter", "sort_offsets": "k_sort_offsets"}
 
 
 def source_sha256():
@@ -213,7 +217,7 @@ def path_bytes_per_particle(wl, prec, n, nbins, ncells):
     d = wl.dim
     noff = 27 if d == 3 else 9
     this = sum(kernel_bytes(k, wl, prec, n, nbins, ncells) for k in
-               ("deposit_cells", "assemble_nodes", "push", "sort_scatter")) / n
+               ("deposit_cells", "assemble_nodes", "push_count", "push_scatter")) / n
     state = (d + 4) * T
     grid = ncells * (8 * 9 * noff + 3 * 24) / n
     return this, 2 * state + grid

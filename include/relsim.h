@@ -138,16 +138,20 @@ int relsim_deposit_moments(relsim_ctx *ctx, const relsim_particles *part, const 
 int relsim_field_solve(relsim_ctx *ctx, const double *M, const double *Jhat, const double *E_n, const double *B_n,
                        double *E_theta, double *E_np1, double *B_np1, int32_t *iters, double *rel_resid);
 
-/* a6 (S6, +a1 when resort != 0): push every particle in place with E_th and
- * B^n, move it across at most one cell face per dimension (periodic), and,
- * if resort, re-sort it into the back set by a stable counting sort over the
- * neighbour moves and swap.  With resort == 0 the particles stay in their
- * old bins and their offsets, still relative to the old cell, may lie in
- * [-1, 2); the state is then only good for reading out.  new_index (device,
- * [n], may be NULL; used only with resort) receives, for every particle in
- * the old order, its position in the new order.  A particle that moves more
- * than one cell is reported as RELSIM_ERANGE by the next synchronous call
- * (the state is then undefined). */
+/* a6 (S6, +a1 when resort != 0): push every particle with E_th and B^n and
+ * move it across at most one cell face per dimension (periodic).  With
+ * resort, the pushed state is written into the back set in the new bin
+ * order (a stable counting sort over the neighbour moves: a first pass
+ * reads the particles and counts the moves, a second pushes them again and
+ * writes each one to its new place) and the sets are swapped, so that the
+ * back set then holds the state before the push.  With resort == 0 the
+ * particles are pushed in place and stay in their old bins; their offsets,
+ * still relative to the old cell, may lie in [-1, 2), and the state is then
+ * only good for reading out.  new_index (device, [n], may be NULL; used only
+ * with resort) receives, for every particle in the old order, its position
+ * in the new order.  A particle that moves more than one cell is reported as
+ * RELSIM_ERANGE by the next synchronous call (the state is then
+ * undefined). */
 int relsim_push(relsim_ctx *ctx, relsim_particles *part, const double *E_theta, const double *B_n, int32_t resort,
                 int32_t *new_index);
 

@@ -323,6 +323,7 @@ int check_flags(relsim_ctx *c) {
   HIP_CHECK(c, hipMemsetAsync(c->at<int32_t>(c->L.err), 0, sizeof(int32_t), c->st));
   if (f & 1) return fail(c, RELSIM_ERANGE, "a particle moved more than one cell in a step, or its position is not finite");
   if (f & 2) return fail(c, RELSIM_ERANGE, "a (cell, species) bin holds more than 65535 particles");
+  if (f & 8) return fail(c, RELSIM_EHIP, "the re-sort's second push pass disagreed with its first about a move");
   return fail(c, RELSIM_EINVAL, "cell index or species id out of range in relsim_sort input");
 }
 
@@ -480,7 +481,9 @@ int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, cons
     launch_stage_field(c->kp, c->p.precision, B_n, stB, c->st);
     launch_stage_field(c->kp, c->p.precision, E_theta, stE, c->st);
   });
-  timed(c, "push", [&] {
+  // with resort the first pass only counts the moves, and the second pushes
+  // again, writing the new state straight into its new place
+  timed(c, resort ? "push_count" : "push", [&] {
     launch_push(c->kp, c->p.precision, G, front(pt), stE, stB, dirc, cnt, err, resort ? 1 : 0,
                 c->at<char>(c->L.sink), c->st);
   });
@@ -489,9 +492,9 @@ int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, cons
     timed(c, "sort_scan", [&] {
       launch_scan(total, pt->bin_start_back, c->kp.nbins, c->at<int32_t>(c->L.scan_tmp), c->st);
     });
-    timed(c, "sort_scatter", [&] {
-      launch_sort_scatter(c->kp, c->p.precision, Gs, front(pt), dirc, pre, pt->bin_start_back, back(pt), (int)pt->n,
-                          err, new_index, c->at<char>(c->L.sink), c->st);
+    timed(c, "push_scatter", [&] {
+      launch_push_scatter(c->kp, c->p.precision, Gs, front(pt), stE, stB, dirc, pre, pt->bin_start_back, back(pt),
+                          (int)pt->n, err, new_index, c->at<char>(c->L.sink), c->st);
     });
     rc = launch_status(c, "relsim_push");
     if (rc) return rc;

@@ -422,7 +422,9 @@ __global__ __launch_bounds__(64) void k_deposit_split3(KParams kp, const int32_t
 #pragma unroll
   for (int k = 0; k < 81; ++k) acc[k] = T(0);
   const T Bc[3][9] = {};
-  const int pal = cs.pbeg & ~(round_align<T, G>() - 1);
+  // rounds start at the cell's first particle: with few particles per cell
+  // an aligned start costs more rounds than it saves in memory sectors
+  const int pal = cs.pbeg;
   const int rounds = wave_rounds<G>(cs.pend - pal);
   PRec<T> cur{}, nxt{};
   int p = pal + gl;
@@ -626,6 +628,68 @@ __device__ __forceinline__ T *sink_slot(void *sink, int lane) {
   return reinterpret_cast<T *>(sink) + (((blockIdx.x & (kSinkSlots - 1)) << 6) + lane);
 }
 
+// E_theta at the 2^DIM corner nodes of the cell with ghosted index gc.
+template <typename T, int DIM>
+__device__ __forceinline__ void load_E_corners(const KParams &kp, const V4<T> *__restrict__ Es, int gc,
+                                               T (&Ec)[3][DIM == 3 ? 8 : 4]) {
+#pragma unroll
+  for (int a = 0; a < (DIM == 3 ? 8 : 4); ++a) {
+    const V4<T> e = Es[gc + (a & 1) + ((a & 2) ? kp.gx : 0) + ((a & 4) ? kp.gxy : 0)];
+    Ec[0][a] = e.x;
+    Ec[1][a] = e.y;
+    Ec[2][a] = e.z;
+  }
+}
+
+// S6 for one particle of the cell: u^{n+1} = 2 alpha (u^n + beta E_p) - u^n
+// (alpha from B^n at the particle, E_p from the cell's corner values of
+// E_theta) and the offsets advanced by dt u^{n+1} / gamma^{n+1} in cell
+// units, not yet brought back into [0, 1).  Every kernel that pushes calls
+// this one function, so that they all round identically.
+template <typename T, int DIM>
+__device__ __forceinline__ void push_one(const KParams &kp, const PC<T> &pc, const V4<T> *__restrict__ Bs,
+                                         const T (&Bc)[3][9], const T (&Ec)[3][DIM == 3 ? 8 : 4], int gc, T bs,
+                                         const PRec<T> &cur, T &fx, T &fy, T &fz, T &nx, T &ny, T &nz) {
+  constexpr int NCORN = DIM == 3 ? 8 : 4;
+  fx = cur.fx;
+  fy = cur.fy;
+  fz = DIM == 3 ? cur.fz : T(0);
+  const T ux = cur.ux, uy = cur.uy, uz = cur.uz;
+  T Bx, By, Bz;
+  gather_B<T, DIM, true>(kp, Bs, Bc, gc, fx, fy, fz, Bx, By, Bz);
+  const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
+  const T kb = bs * igb * pc.invc;
+  T a[9];
+  const T inv2 = T(2) * alpha_num<T>(kb * Bx, kb * By, kb * Bz, a);
+  T Ex = T(0), Ey = T(0), Ez = T(0);
+#pragma unroll
+  for (int c = 0; c < NCORN; ++c) {
+    T wgt = ((c & 1) ? fx : T(1) - fx) * ((c & 2) ? fy : T(1) - fy);
+    if constexpr (DIM == 3) wgt *= (c & 4) ? fz : T(1) - fz;
+    Ex += wgt * Ec[0][c];
+    Ey += wgt * Ec[1][c];
+    Ez += wgt * Ec[2][c];
+  }
+  const T vx = ux + bs * Ex, vy = uy + bs * Ey, vz = uz + bs * Ez;
+  // u^{n+1} = 2 alpha v - u^n, alpha = (numerator a) / (1 + |b|^2)
+  const T ubx = a[0] * vx + a[1] * vy + a[2] * vz;
+  const T uby = a[3] * vx + a[4] * vy + a[5] * vz;
+  const T ubz = a[6] * vx + a[7] * vy + a[8] * vz;
+  nx = inv2 * ubx - ux;
+  ny = inv2 * uby - uy;
+  nz = inv2 * ubz - uz;
+  const T ign = kp.nonrel ? T(1) : rsqrt_t(T(1) + (nx * nx + ny * ny + nz * nz) * pc.invc2);
+  const T dtg = pc.dt * ign;
+  fx += dtg * nx * pc.idx;
+  fy += dtg * ny * pc.idy;
+  if constexpr (DIM == 3) fz += dtg * nz * pc.idz;
+}
+
+// Push pass.  COUNT: the first pass of the re-sort; the particles are only
+// read: each one's move (dirc) and the per-(bin, move) counts are written,
+// and k_push_scatter later recomputes the push and writes the new state in
+// the new order.  !COUNT: push in place with no re-sort; offsets stay
+// relative to the old cell, in [-1, 2).
 template <typename T, int DIM, int G, bool COUNT>
 __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restrict__ bin_start,
                                              V2<T> *__restrict__ xy, V4<T> *__restrict__ uw, T *__restrict__ zz,
@@ -636,7 +700,7 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
   constexpr int NDIR = DIM == 3 ? 27 : 9;
   constexpr int NK = 8 * NDIR;  // (species, move) keys per group
   constexpr int NGRP = 64 / G;
-  __shared__ uint32_t lcnt[NGRP * NK];
+  __shared__ uint32_t lcnt[COUNT ? NGRP * NK : 1];
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
@@ -650,16 +714,8 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
 
   T Bc[3][9];
   if constexpr (DIM == 2) load_B_block_2d<T>(kp, Bs, cs.gc, Bc);
-  // E_theta at the 2^DIM corner nodes of the cell
-  constexpr int NCORN = DIM == 3 ? 8 : 4;
-  T Ec[3][NCORN];
-#pragma unroll
-  for (int a = 0; a < NCORN; ++a) {
-    const V4<T> e = Es[cs.gc + (a & 1) + ((a & 2) ? kp.gx : 0) + ((a & 4) ? kp.gxy : 0)];
-    Ec[0][a] = e.x;
-    Ec[1][a] = e.y;
-    Ec[2][a] = e.z;
-  }
+  T Ec[3][DIM == 3 ? 8 : 4];
+  load_E_corners<T, DIM>(kp, Es, cs.gc, Ec);
   const int pal = cs.pbeg & ~(round_align<T, G>() - 1);
   const int rounds = wave_rounds<G>(cs.pend - pal);
   PRec<T> cur{}, nxt{};
@@ -677,64 +733,35 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
     // lanes past the end compute on a copy of a valid particle (finite
     // values) and store into the sink
     const bool pv = p >= cs.pbeg && p < cs.pend;
-    T fx = cur.fx, fy = cur.fy;
-    T fz = DIM == 3 ? cur.fz : T(0);
-    const T ux = cur.ux, uy = cur.uy, uz = cur.uz;
     T qs, bs;
     const int s = species_of<T>(kp, pc, cs, p, qs, bs);
-    T Bx, By, Bz;
-    gather_B<T, DIM, true>(kp, Bs, Bc, cs.gc, fx, fy, fz, Bx, By, Bz);
-    const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
-    const T kb = bs * igb * pc.invc;
-    T a[9];
-    const T inv2 = T(2) * alpha_num<T>(kb * Bx, kb * By, kb * Bz, a);
-    T Ex = T(0), Ey = T(0), Ez = T(0);
-#pragma unroll
-    for (int c = 0; c < NCORN; ++c) {
-      T wgt = ((c & 1) ? fx : T(1) - fx) * ((c & 2) ? fy : T(1) - fy);
-      if constexpr (DIM == 3) wgt *= (c & 4) ? fz : T(1) - fz;
-      Ex += wgt * Ec[0][c];
-      Ey += wgt * Ec[1][c];
-      Ez += wgt * Ec[2][c];
-    }
-    const T vx = ux + bs * Ex, vy = uy + bs * Ey, vz = uz + bs * Ez;
-    // u^{n+1} = 2 alpha v - u^n, alpha = (numerator a) / (1 + |b|^2)
-    const T ubx = a[0] * vx + a[1] * vy + a[2] * vz;
-    const T uby = a[3] * vx + a[4] * vy + a[5] * vz;
-    const T ubz = a[6] * vx + a[7] * vy + a[8] * vz;
-    const T nx = inv2 * ubx - ux, ny = inv2 * uby - uy, nz = inv2 * ubz - uz;
-    const T ign = kp.nonrel ? T(1) : rsqrt_t(T(1) + (nx * nx + ny * ny + nz * nz) * pc.invc2);
-    const T dtg = pc.dt * ign;
-    fx += dtg * nx * pc.idx;
-    fy += dtg * ny * pc.idy;
-    if constexpr (DIM == 3) fz += dtg * nz * pc.idz;
-    int mx = 0, my = 0, mz = 0, flag = 0;
+    T fx, fy, fz, nx, ny, nz;
+    push_one<T, DIM>(kp, pc, Bs, Bc, Ec, cs.gc, bs, cur, fx, fy, fz, nx, ny, nz);
     if constexpr (COUNT) {
-      mx = cross_cell<T>(fx, flag);
-      my = cross_cell<T>(fy, flag);
-      if constexpr (DIM == 3) mz = cross_cell<T>(fz, flag);
+      int flag = 0;
+      const int mx = cross_cell<T>(fx, flag);
+      const int my = cross_cell<T>(fy, flag);
+      const int mz = DIM == 3 ? cross_cell<T>(fz, flag) : 0;
+      bad |= pv ? flag : 0;
+      const int dir = (mx + 1) + 3 * (my + 1) + (DIM == 3 ? 9 * (mz + 1) : 0);
+      *(pv ? dirc + p : sinkB) = (uint8_t)dir;
+      if (pv) atomicAdd(&lcnt[grp * NK + s * NDIR + dir], 1u);  // integer: order-independent
     } else {
       // no re-sort: offsets stay relative to the old cell, in [-1, 2)
       bool ok = fx >= T(-1) && fx < T(2) && fy >= T(-1) && fy < T(2);
       if constexpr (DIM == 3) ok = ok && fz >= T(-1) && fz < T(2);
-      flag = ok ? 0 : 1;
-    }
-    bad |= pv ? flag : 0;
-    V2<T> xo;
-    xo.x = fx;
-    xo.y = fy;
-    V4<T> uo;
-    uo.x = nx;
-    uo.y = ny;
-    uo.z = nz;
-    uo.w = cur.w;
-    *(pv ? xy + p : sink_slot<V2<T>>(sink, lane)) = xo;
-    *(pv ? uw + p : sink_slot<V4<T>>(sink, lane)) = uo;
-    if constexpr (DIM == 3) *(pv ? zz + p : sinkT) = fz;
-    if constexpr (COUNT) {
-      const int dir = (mx + 1) + 3 * (my + 1) + (DIM == 3 ? 9 * (mz + 1) : 0);
-      *(pv ? dirc + p : sinkB) = (uint8_t)dir;
-      if (pv) atomicAdd(&lcnt[grp * NK + s * NDIR + dir], 1u);  // integer: order-independent
+      bad |= (pv && !ok) ? 1 : 0;
+      V2<T> xo;
+      xo.x = fx;
+      xo.y = fy;
+      V4<T> uo;
+      uo.x = nx;
+      uo.y = ny;
+      uo.z = nz;
+      uo.w = cur.w;
+      *(pv ? xy + p : sink_slot<V2<T>>(sink, lane)) = xo;
+      *(pv ? uw + p : sink_slot<V4<T>>(sink, lane)) = uo;
+      if constexpr (DIM == 3) *(pv ? zz + p : sinkT) = fz;
     }
     cur = nxt;
     p = pn;
@@ -797,17 +824,21 @@ __global__ __launch_bounds__(256) void k_sort_offsets(KParams kp, const uint16_t
 }
 
 // ---------------------------------------------------------------------------
-// re-sort, step 3: stable scatter into the back buffers.  Each lane group
-// first resolves, for each (species, move) key of its cell, where that
-// class's run starts in the new order (new bin start + offset of this
-// source cell among the bin's sources); in the loop a particle's place is
-// that base plus its rank among the same-key lanes of earlier rounds and
-// lower lanes of this round, found from one ballot per key bit.
+// re-sort, step 3: push again and scatter, stably, into the back buffers.
+// Each lane group first resolves, for each (species, move) key of its cell,
+// where that class's run starts in the new order (new bin start + offset of
+// this source cell among the bin's sources).  In the loop every particle is
+// pushed once more (push_one, bit for bit as in the counting pass, which is
+// checked against the recorded move), and its new state is written at that
+// base plus its rank among the same-key lanes of earlier rounds and lower
+// lanes of this round, found from one ballot per key bit.  The particle
+// state is thus read twice and written once per step.
 // ---------------------------------------------------------------------------
 template <typename T, int DIM, int G, bool PERM>
-__global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *__restrict__ bin_start,
+__global__ __launch_bounds__(64) void k_push_scatter(KParams kp, const int32_t *__restrict__ bin_start,
                                                      const V2<T> *__restrict__ xy,
                                                      const V4<T> *__restrict__ uw, const T *__restrict__ zz,
+                                                     const V4<T> *__restrict__ Es, const V4<T> *__restrict__ Bs,
                                                      const uint8_t *__restrict__ dirc,
                                                      const uint16_t *__restrict__ pre,
                                                      const int32_t *__restrict__ bsn, V2<T> *__restrict__ xo,
@@ -820,6 +851,7 @@ __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
+  const PC<T> pc(kp);
   const int S = kp.nspecies, nkey = S * NDIR;
   const size_t nb = (size_t)kp.nbins;
   if (cs.valid) {
@@ -832,6 +864,10 @@ __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *
       lbase[grp * nkey + t] = bsn[d] + (int)pre[(size_t)dir * nb + d];
     }
   }
+  T Bc[3][9];
+  if constexpr (DIM == 2) load_B_block_2d<T>(kp, Bs, cs.gc, Bc);
+  T Ec[3][DIM == 3 ? 8 : 4];
+  load_E_corners<T, DIM>(kp, Es, cs.gc, Ec);
   __syncthreads();
   // key bits: keys are grp * nkey + species * NDIR + move < NGRP * nkey
   const int kbits = 32 - __builtin_clz((unsigned)(NGRP * nkey - 1) | 1u);
@@ -853,16 +889,17 @@ __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *
     load_rec<T, DIM>(pn, cs.pend, xy, uw, zz, nxt);
     dnxt = dirc[load_index(pn, cs.pend)];
     const bool pv = p < cs.pend;
-    int s = 0;
-    if (pv) {
-      if (S == 2) {
-        s = p >= cs.bound[1] ? 1 : 0;
-      } else {
-#pragma unroll
-        for (int s2 = 1; s2 < 8; ++s2)
-          if (p >= cs.bound[s2]) s = s2;
-      }
-    }
+    T qs, bs;
+    const int s = species_of<T>(kp, pc, cs, p, qs, bs);
+    T fx, fy, fz, nx, ny, nz;
+    push_one<T, DIM>(kp, pc, Bs, Bc, Ec, cs.gc, bs, cur, fx, fy, fz, nx, ny, nz);
+    int flag = 0;
+    const int mx = cross_cell<T>(fx, flag);
+    const int my = cross_cell<T>(fy, flag);
+    const int mz = DIM == 3 ? cross_cell<T>(fz, flag) : 0;
+    const int dir = (mx + 1) + 3 * (my + 1) + (DIM == 3 ? 9 * (mz + 1) : 0);
+    // the move must be the one counted (a bad move was flagged there)
+    bad |= (pv && !flag && dir != dcur) ? 4 : 0;
     const int key = pv ? grp * nkey + s * NDIR + dcur : 0;
     // lanes of this round holding the same key
     const unsigned long long act = __ballot(pv);
@@ -884,25 +921,27 @@ __global__ __launch_bounds__(64) void k_sort_scatter(KParams kp, const int32_t *
     // only reachable out of range when a bin overflowed the 16-bit
     // counters (flagged); lanes past the end store into the sink
     const bool ok = pv && pos >= 0 && pos < ntot;
-    bad |= (pv && !ok) ? 1 : 0;
+    bad |= (pv && !ok) ? 2 : 0;
     V2<T> xv;
-    xv.x = cur.fx;
-    xv.y = cur.fy;
+    xv.x = fx;
+    xv.y = fy;
     V4<T> uv;
-    uv.x = cur.ux;
-    uv.y = cur.uy;
-    uv.z = cur.uz;
+    uv.x = nx;
+    uv.y = ny;
+    uv.z = nz;
     uv.w = cur.w;
     *(ok ? xo + pos : sink_slot<V2<T>>(sink, lane)) = xv;
     *(ok ? uo + pos : sink_slot<V4<T>>(sink, lane)) = uv;
-    if constexpr (DIM == 3) *(ok ? zo + pos : sinkT) = cur.fz;
+    if constexpr (DIM == 3) *(ok ? zo + pos : sinkT) = fz;
     if constexpr (PERM) *(ok ? perm + p : sinkI) = pos;
     __builtin_amdgcn_wave_barrier();
     cur = nxt;
     dcur = dnxt;
     p = pn;
   }
-  if (__ballot(bad) && lane == 0) atomicOr(err, 2);
+  const int ball = __ballot(bad & 2) ? 2 : 0;
+  const int balm = __ballot(bad & 4) ? 8 : 0;
+  if ((ball | balm) && lane == 0) atomicOr(err, ball | balm);
 }
 
 // ---------------------------------------------------------------------------
@@ -1058,17 +1097,18 @@ void push_impl(const KParams &kp, const PartPtrs &pp, const void *Est, const voi
 }
 
 template <typename T, int DIM, int G>
-void scatter_impl(const KParams &kp, const PartPtrs &src, const uint8_t *dirc, const uint16_t *pre, const int32_t *bsn,
-                  const PartPtrs &out, int ntot, int32_t *err, int32_t *perm, void *sink, hipStream_t st) {
+void scatter_impl(const KParams &kp, const PartPtrs &src, const void *Est, const void *Bst, const uint8_t *dirc,
+                  const uint16_t *pre, const int32_t *bsn, const PartPtrs &out, int ntot, int32_t *err, int32_t *perm,
+                  void *sink, hipStream_t st) {
   const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
   if (perm)
-    hipLaunchKernelGGL((k_sort_scatter<T, DIM, G, true>), dim3(nblk), dim3(64), 0, st, kp, src.bin_start,
-                       cp<V2<T>>(src.xy), cp<V4<T>>(src.uw), cp<T>(src.z), dirc, pre, bsn, mp<V2<T>>(out.xy),
-                       mp<V4<T>>(out.uw), mp<T>(out.z), ntot, err, perm, sink);
+    hipLaunchKernelGGL((k_push_scatter<T, DIM, G, true>), dim3(nblk), dim3(64), 0, st, kp, src.bin_start,
+                       cp<V2<T>>(src.xy), cp<V4<T>>(src.uw), cp<T>(src.z), cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, pre,
+                       bsn, mp<V2<T>>(out.xy), mp<V4<T>>(out.uw), mp<T>(out.z), ntot, err, perm, sink);
   else
-    hipLaunchKernelGGL((k_sort_scatter<T, DIM, G, false>), dim3(nblk), dim3(64), 0, st, kp, src.bin_start,
-                       cp<V2<T>>(src.xy), cp<V4<T>>(src.uw), cp<T>(src.z), dirc, pre, bsn, mp<V2<T>>(out.xy),
-                       mp<V4<T>>(out.uw), mp<T>(out.z), ntot, err, perm, sink);
+    hipLaunchKernelGGL((k_push_scatter<T, DIM, G, false>), dim3(nblk), dim3(64), 0, st, kp, src.bin_start,
+                       cp<V2<T>>(src.xy), cp<V4<T>>(src.uw), cp<T>(src.z), cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, pre,
+                       bsn, mp<V2<T>>(out.xy), mp<V4<T>>(out.uw), mp<T>(out.z), ntot, err, perm, sink);
 }
 
 template <typename T, int DIM, int G>
@@ -1177,10 +1217,11 @@ void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream
   if (nb > 1) hipLaunchKernelGGL(k_scan_add, dim3((n + 255) / 256), dim3(256), 0, st, out, n, tmp);
 }
 
-void launch_sort_scatter(const KParams &kp, int prec, int group, const PartPtrs &src, const uint8_t *dirc,
-                         const uint16_t *pre, const int32_t *bin_start_new, const PartPtrs &out, int ntot,
-                         int32_t *err, int32_t *perm, void *sink, hipStream_t st) {
-  dispatch<ScatterF>(prec, kp.dim, group, kp, src, dirc, pre, bin_start_new, out, ntot, err, perm, sink, st);
+void launch_push_scatter(const KParams &kp, int prec, int group, const PartPtrs &src, const void *Est,
+                         const void *Bst, const uint8_t *dirc, const uint16_t *pre, const int32_t *bin_start_new,
+                         const PartPtrs &out, int ntot, int32_t *err, int32_t *perm, void *sink, hipStream_t st) {
+  dispatch<ScatterF>(prec, kp.dim, group, kp, src, Est, Bst, dirc, pre, bin_start_new, out, ntot, err, perm, sink,
+                     st);
 }
 
 void launch_fill_cells(const KParams &kp, const int32_t *bin_start, int32_t *cell, hipStream_t st) {

@@ -73,15 +73,19 @@ void launch_deposit_cells(const KParams &kp, int prec, int group, const PartPtrs
 void launch_assemble(const KParams &kp, int prec, const void *S, double *J, double *M, hipStream_t st);
 // `sink`: kSinkSlots * 64 * 32 bytes of workspace that lanes without a
 // particle store into (contents meaningless)
+// count_moves: only read the particles and write each one's move (dirc) and
+// the per-(move, bin) counts (first pass of the re-sort); else push in place
 void launch_push(const KParams &kp, int prec, int group, const PartPtrs &pp, const void *Est, const void *Bst,
                  uint8_t *dirc, uint16_t *cnt, int32_t *err, int count_moves, void *sink, hipStream_t st);
 void launch_sort_offsets(const KParams &kp, const uint16_t *cnt, uint16_t *pre, int32_t *total, int32_t *err,
                          hipStream_t st);
 void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream_t st);
 size_t scan_tmp_elems(int n);
-void launch_sort_scatter(const KParams &kp, int prec, int group, const PartPtrs &src, const uint8_t *dirc,
-                         const uint16_t *pre, const int32_t *bin_start_new, const PartPtrs &out, int ntot,
-                         int32_t *err, int32_t *perm, void *sink, hipStream_t st);
+// second pass of the re-sort: push src again and write the new state into
+// out in the new bin order (err bit 4: a recomputed move differs from dirc)
+void launch_push_scatter(const KParams &kp, int prec, int group, const PartPtrs &src, const void *Est,
+                         const void *Bst, const uint8_t *dirc, const uint16_t *pre, const int32_t *bin_start_new,
+                         const PartPtrs &out, int ntot, int32_t *err, int32_t *perm, void *sink, hipStream_t st);
 // cell[p] for every particle from the bin ranges
 void launch_fill_cells(const KParams &kp, const int32_t *bin_start, int32_t *cell, hipStream_t st);
 // partials: one double per block of 64/group cells (at most ncells)

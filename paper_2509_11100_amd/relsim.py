@@ -272,8 +272,9 @@ def field_solve(ctx: Context, M, J, E, B, E_theta=None, E1=None, B1=None, allow_
 
 def push(ctx: Context, parts: Particles, E_theta: torch.Tensor, B: torch.Tensor, resort: bool = True,
          new_index: Optional[torch.Tensor] = None) -> None:
-    """relsim_push (re-sorts into the back buffers and swaps when resort;
-    new_index, int32 [n], receives each old particle's new position)"""
+    """relsim_push (with resort: the pushed state goes into the back buffers
+    in the new order and the sets swap, leaving the old state in the back
+    set; new_index, int32 [n], receives each old particle's new position)"""
     _grid_ok(ctx, E_theta, B)
     if new_index is not None and (new_index.dtype != torch.int32 or new_index.numel() < parts.n):
         raise ValueError("new_index must be an int32 tensor of at least n elements")
