@@ -251,16 +251,20 @@ KParams make_kparams(const relsim_params *p) {
 // has at least 512 waves (2 per CU) on small grids.  The 2D deposit
 // amortises its per-cell reduction over many rounds (16 in FP32; 32 in FP64,
 // whose register-bound occupancy favours narrower groups) and may go down to
-// 4 lanes; the push wants a few rounds (4), while the scatter writes whole
-// runs per instruction (2).  Measured on the 2D Harris sheets with 32, 64
-// and 128 particles per cell.  (The 3D deposit always splits a cell's
-// moments over 4 lanes and takes no group.)
+// 4 lanes; the counting push pass wants 8 (FP32) or 16 (FP64) rounds; the
+// pushing scatter pass 4 (2 in 3D FP32, where its 27 move classes make wide
+// groups write longer runs).  Measured on the 2D Harris sheets with 32, 64
+// and 128 particles per cell and the 3D sheet with 32.  (The 3D deposit
+// always splits a cell's moments over 4 lanes and takes no group.)
 enum KernelKind { K_DEPOSIT, K_PUSH, K_SCATTER, K_OTHER };
 
 int choose_group(const relsim_ctx *c, int64_t n, KernelKind k = K_OTHER) {
   if (c->p.group) return c->p.group;
   const bool fp64 = c->p.precision == RELSIM_FP64;
-  const double rounds = k == K_DEPOSIT ? (fp64 ? 32.0 : 16.0) : (k == K_SCATTER ? 2.0 : 4.0);
+  double rounds = 4.0;
+  if (k == K_DEPOSIT) rounds = fp64 ? 32.0 : 16.0;
+  if (k == K_PUSH) rounds = fp64 ? 16.0 : 8.0;
+  if (k == K_SCATTER) rounds = (!fp64 && c->kp.dim == 3) ? 2.0 : 4.0;
   const double mean = (double)n / (double)c->kp.ncells;
   int g = k == K_DEPOSIT ? 4 : 8;
   while (g < 64 && 2.0 * g <= mean / rounds) g *= 2;
