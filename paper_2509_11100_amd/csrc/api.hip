@@ -586,6 +586,7 @@ static int gmres_solve(relsim_ctx *c, const double *M, bool transpose, double *x
   double *part = c->at<double>(c->L.gm_part);
   double *hdev = c->at<double>(c->L.gm_small);
   double *ydev = hdev + (kMaxRestart + 2);
+  double *h1dev = hdev, *h2dev = hdev + 2 * (kMaxRestart + 2);
   auto op = [&](const double *in, double *out) {
     if (transpose)
       apply_AT(c, M, in, out);
@@ -625,22 +626,23 @@ static int gmres_solve(relsim_ctx *c, const double *M, bool transpose, double *x
       double *vj = V + (size_t)j * n3;
       double *w = V + (size_t)(j + 1) * n3;
       op(vj, w);
-      // classical Gram-Schmidt, twice; the second pass also returns |w|^2
-      timed(c, "mdot", [&] { launch_mdot(V, n3, j + 1, w, n3, part, hdev, c->st); });
-      rc = fetch(c, hdev, j + 1);
+      // classical Gram-Schmidt, twice, with the coefficients staying on the
+      // device (h1, then the correction h2, whose last entry is |w|^2 after
+      // the first pass); one copy to the host per Arnoldi step
+      timed(c, "mdot", [&] { launch_mdot(V, n3, j + 1, w, n3, part, h1dev, c->st); });
+      timed(c, "maxpy", [&] { launch_maxpy(V, n3, j + 1, h1dev, w, n3, c->st); });
+      timed(c, "mdot", [&] { launch_mdot(V, n3, j + 2, w, n3, part, h2dev, c->st); });
+      timed(c, "maxpy", [&] { launch_maxpy(V, n3, j + 1, h2dev, w, n3, c->st); });
+      rc = fetch(c, hdev, (int)(h2dev - hdev) + j + 2);
       if (rc) return rc;
-      std::vector<double> h(c->host, c->host + j + 1);
-      timed(c, "maxpy", [&] { launch_maxpy(V, n3, j + 1, hdev, w, n3, c->st); });
-      timed(c, "mdot", [&] { launch_mdot(V, n3, j + 2, w, n3, part, hdev, c->st); });
-      rc = fetch(c, hdev, j + 2);
-      if (rc) return rc;
+      const double *h1 = c->host, *h2 = c->host + (h2dev - hdev);
+      std::vector<double> h(h1, h1 + j + 1);
       double s2 = 0.0;
       for (int k = 0; k <= j; ++k) {
-        s2 += c->host[k] * c->host[k];
-        h[k] += c->host[k];
+        s2 += h2[k] * h2[k];
+        h[k] += h2[k];
       }
-      double ww = c->host[j + 1];
-      timed(c, "maxpy", [&] { launch_maxpy(V, n3, j + 1, hdev, w, n3, c->st); });
+      double ww = h2[j + 1];
       double hn2 = ww - s2;
       double hn;
       if (hn2 > 1e-4 * ww) {

@@ -223,7 +223,16 @@ def test_push_resort_is_the_stable_sort_of_the_moved_particles(gname, precision)
     p2 = load(ctx2, *parts.to_host())
     relsim.push(ctx2, p2, torch_grid(E), torch_grid(B), resort=False)
     s2 = host_state(g, p2)
+    n = parts.n
+    keys = ["xy", "uw", "bin_start"] + (["z"] if g.dim == 3 else [])
+    before = {k: parts.sets[parts.front][k].clone() for k in keys}
     relsim.push(ctx, parts, torch_grid(E), torch_grid(B), resort=True)
+    # the push with re-sort only reads the front set: after the swap the
+    # back set holds the state before the push
+    back = parts.sets[1 - parts.front]
+    for k in keys:
+        m = None if k == "bin_start" else n
+        np.testing.assert_array_equal(back[k][:m].cpu().numpy(), before[k][:m].cpu().numpy())
     st = host_state(g, parts)
     dt = np.float32 if precision == "mixed" else np.float64
     off = p2.to_host()[2].astype(dt)
