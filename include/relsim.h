@@ -52,6 +52,7 @@ extern "C" {
 #define RELSIM_ENONFINITE (-4)    /* NaN/Inf met in a reduction or the solve    */
 #define RELSIM_ERANGE (-5)        /* a particle moved more than one cell, or a
                                      bin exceeded 65535 particles              */
+#define RELSIM_EINTERNAL (-6)     /* an internal consistency check failed      */
 
 #define RELSIM_FP64 0  /* particle state and particle arithmetic in double    */
 #define RELSIM_MIXED 1 /* particle state/arithmetic in float, per-cell moments

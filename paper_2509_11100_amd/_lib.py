@@ -17,6 +17,7 @@ RELSIM_ENOTCONVERGED = -2
 RELSIM_EHIP = -3
 RELSIM_ENONFINITE = -4
 RELSIM_ERANGE = -5
+RELSIM_EINTERNAL = -6
 RELSIM_FP64 = 0
 RELSIM_MIXED = 1
 

@@ -165,9 +165,12 @@ __device__ __forceinline__ void gather_B(const KParams &kp, const V4<T> *__restr
     T wx[3], wy[3];
     centre_w3(fx, wx);
     centre_w3(fy, wy);
-    Bx = By = Bz = T(0);
+    const T w0 = wx[0] * wy[0];
+    Bx = w0 * Bc[0][0];
+    By = w0 * Bc[1][0];
+    Bz = w0 * Bc[2][0];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
+    for (int t = 1; t < 9; ++t) {
       const T wt = wx[t % 3] * wy[t / 3];
       Bx += wt * Bc[0][t];
       By += wt * Bc[1][t];
@@ -180,15 +183,14 @@ __device__ __forceinline__ void gather_B(const KParams &kp, const V4<T> *__restr
     const T gx = hx ? fx - T(0.5) : fx + T(0.5);
     const T gy = hy ? fy - T(0.5) : fy + T(0.5);
     const T gz = hz ? fz - T(0.5) : fz + T(0.5);
-    Bx = By = Bz = T(0);
 #pragma unroll
     for (int a = 0; a < NCEN; ++a) {
       const V4<T> b = Bs[g0 + (a & 1) + ((a & 2) ? kp.gx : 0) + ((a & 4) ? kp.gxy : 0)];
       T wt = ((a & 1) ? gx : T(1) - gx) * ((a & 2) ? gy : T(1) - gy);
       if constexpr (DIM == 3) wt *= (a & 4) ? gz : T(1) - gz;
-      Bx += wt * b.x;
-      By += wt * b.y;
-      Bz += wt * b.z;
+      Bx = a == 0 ? wt * b.x : Bx + wt * b.x;
+      By = a == 0 ? wt * b.y : By + wt * b.y;
+      Bz = a == 0 ? wt * b.z : Bz + wt * b.z;
     }
   }
 }
@@ -599,23 +601,16 @@ __device__ __forceinline__ int cross_cell(T &f, int &bad) {
   // f is the new offset in cell units; bring it back into [0,1) with one
   // cell move.  A value rounding to exactly 1 after the correction from
   // below is the left face of the cell (offset 0, no move).
-  int m = 0;
-  if (f >= T(1)) {
-    f -= T(1);
-    m = 1;
-  } else if (f < T(0)) {
-    f += T(1);
-    m = -1;
-  }
-  if (!(f >= T(0) && f < T(1))) {
-    if (m == -1 && f == T(1)) {
-      f = T(0);
-      m = 0;
-    } else {
-      bad = 1;  // moved more than one cell, or non-finite
-      f = T(0);
-    }
-  }
+  // (written with selects only: no divergent branches)
+  const bool up = f >= T(1), dn = f < T(0);
+  int m = up ? 1 : (dn ? -1 : 0);
+  f = up ? f - T(1) : (dn ? f + T(1) : f);
+  const bool edge = dn && f == T(1);
+  m = edge ? 0 : m;
+  f = edge ? T(0) : f;
+  const bool out = !(f >= T(0) && f < T(1));  // moved more than one cell, or non-finite
+  bad = out ? 1 : bad;
+  f = out ? T(0) : f;
   return m;
 }
 
@@ -661,14 +656,14 @@ __device__ __forceinline__ void push_one(const KParams &kp, const PC<T> &pc, con
   const T kb = bs * igb * pc.invc;
   T a[9];
   const T inv2 = T(2) * alpha_num<T>(kb * Bx, kb * By, kb * Bz, a);
-  T Ex = T(0), Ey = T(0), Ez = T(0);
+  T Ex, Ey, Ez;
 #pragma unroll
   for (int c = 0; c < NCORN; ++c) {
     T wgt = ((c & 1) ? fx : T(1) - fx) * ((c & 2) ? fy : T(1) - fy);
     if constexpr (DIM == 3) wgt *= (c & 4) ? fz : T(1) - fz;
-    Ex += wgt * Ec[0][c];
-    Ey += wgt * Ec[1][c];
-    Ez += wgt * Ec[2][c];
+    Ex = c == 0 ? wgt * Ec[0][c] : Ex + wgt * Ec[0][c];
+    Ey = c == 0 ? wgt * Ec[1][c] : Ey + wgt * Ec[1][c];
+    Ez = c == 0 ? wgt * Ec[2][c] : Ez + wgt * Ec[2][c];
   }
   const T vx = ux + bs * Ex, vy = uy + bs * Ey, vz = uz + bs * Ez;
   // u^{n+1} = 2 alpha v - u^n, alpha = (numerator a) / (1 + |b|^2)

@@ -76,8 +76,10 @@ def test_workspace_too_small_is_rejected():
 
 def test_error_strings():
     lib = _lib.load()
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -6):
         assert len(lib.relsim_strerror(code)) > 0
+        assert lib.relsim_strerror(code) != b"unknown error"
+    assert lib.relsim_strerror(-99) == b"unknown error"
     assert lib.relsim_last_error(None) == b"no context"
 
 
