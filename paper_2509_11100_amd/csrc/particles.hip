@@ -325,7 +325,7 @@ __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t 
   int p = pal + gl;
   if (rounds > 0) load_rec<T, 2>(p, cs.pend, xy, uw, nullptr, cur);
   __builtin_amdgcn_s_waitcnt(0);
-#pragma unroll 1
+#pragma unroll 2
   for (int r = 0; r < rounds; ++r) {
     const int pn = p + G;
     load_rec<T, 2>(pn, cs.pend, xy, uw, nullptr, nxt);
@@ -721,7 +721,7 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
   // its own loads and stores
   __builtin_amdgcn_s_waitcnt(0);
 
-#pragma unroll 1
+#pragma unroll 2
   for (int r = 0; r < rounds; ++r) {
     const int pn = p + G;
     load_rec<T, DIM>(pn, cs.pend, xy, uw, zz, nxt);
