@@ -38,8 +38,8 @@ constexpr int kDotBlocks = 512;     // blocks of the multi-dot reduction
 constexpr int kRedBlocks = 1024;    // blocks of the energy reductions
 constexpr int kSinkSlots = 512;     // per-lane store sinks of the particle kernels (power of two), 32 B each
 
-// Moments per cell: 2D 81 mass moments + 12 current moments; 3D three passes
-// of 81 mass moments plus 2 x 12 current moments.
+// Moments per cell: 2D 81 mass moments + 12 current moments; 3D 3 x 81 mass
+// moments (one set per z-monomial type) plus 2 x 12 current moments.
 inline int n_cell_moments(int dim) { return dim == 3 ? 3 * 81 + 2 * 12 : 81 + 12; }
 inline int n_dirs(int dim) { return dim == 3 ? 27 : 9; }
 
