@@ -261,6 +261,64 @@ def test_push_resort_is_the_stable_sort_of_the_moved_particles(gname, precision)
     assert np.all((st["off"] >= 0) & (st["off"] < 1))
 
 
+SPECIES = {
+    1: ((-1.0,), (1.0,)),
+    3: ((1.0, -1.0, 2.0), (1.0, 1.0, 25.0)),
+    8: ((1.0, -1.0, 2.0, -2.0, 0.5, -0.5, 1.0, -3.0), (1.0, 1.0, 4.0, 9.0, 0.25, 2.0, 100.0, 7.0)),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("ns", [1, 3, 8])
+@pytest.mark.parametrize("gname", ["2d_7x5", "3d_5x4x3"])
+def test_species_counts_other_than_two(gname, ns, precision):
+    """The kernels special-case two species; 1, 3 and 8 species take the
+    general path of the bin bounds (deposit, push + re-sort, energy)."""
+    need_gpu()
+    import dataclasses
+
+    import torch
+
+    from paper_2509_11100_amd import relsim
+
+    q, m = SPECIES[ns]
+    g = dataclasses.replace(grids()[gname], q=q, m=m)
+    rng = np.random.default_rng(70 + ns)
+    n = 3000
+    cell, sp, off, u, w = random_cells(g, n, rng, umax=2.5, empty_frac=0.2)
+    B = (2 * rng.random((3, g.N)) - 1) * 2.0
+    E = (2 * rng.random((3, g.N)) - 1) * 0.5
+    ctx = make_ctx(g, precision, n)
+    parts = load(ctx, cell, sp, off, u, w)
+    st = host_state(g, parts)
+    J, M = relsim.deposit_moments(ctx, parts, torch_grid(B))
+    Jr, Mr = oracle.deposit(g, st["x"], st["u"], st["w"], st["species"], B)
+    assert normwise(J.cpu().numpy(), Jr) < TOL[precision]
+    assert normwise(M.cpu().numpy(), Mr) < TOL[precision]
+    W = relsim.energy(ctx, parts, torch_grid(E), torch_grid(B))
+    Wr = oracle.energy(g, st["u"], st["w"], st["species"], E, B)
+    np.testing.assert_allclose(W, Wr, rtol=1e-12 if precision == "fp64" else 1e-6)
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    relsim.push(ctx, parts, torch_grid(E), torch_grid(B), resort=True, new_index=perm)
+    s1 = host_state(g, parts)
+    # every particle's pushed state, found through the new index
+    new = perm.cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(new), np.arange(n))
+    xr, ur = oracle.push(g, st["x"], st["u"], st["species"], E, B)
+    assert normwise(s1["u"][:, new], ur) < TOL[precision]
+    disp = periodic_diff(g, xr, st["x"])
+    assert np.linalg.norm(periodic_diff(g, s1["x"][:, new], xr)) / np.linalg.norm(disp) < TOL[precision]
+    np.testing.assert_array_equal(s1["species"][new], st["species"])
+    np.testing.assert_array_equal(s1["w"][new], st["w"])
+    # bin order, bin_start, and stability (equal bins keep their old order)
+    key = s1["cell"].astype(np.int64) * ns + s1["species"]
+    assert np.all(np.diff(key) >= 0)
+    np.testing.assert_array_equal(s1["bin_start"], np.searchsorted(key, np.arange(g.N * ns + 1)))
+    for b in np.unique(key):
+        src = np.nonzero(key[new] == b)[0]
+        assert np.all(np.diff(new[src]) > 0)
+
+
 def test_push_flags_a_move_of_more_than_one_cell():
     need_gpu()
     # |v| < c, so a move of more than one cell needs c dt > dx: here c dt = 2.7 dx
