@@ -340,6 +340,34 @@ def test_push_flags_a_move_of_more_than_one_cell():
     assert ei.value.code == _lib.RELSIM_ERANGE
 
 
+def test_push_flags_a_move_class_beyond_the_16_bit_counters():
+    """70,000 particles of one species resting in one cell: their (bin, move)
+    class exceeds the 16-bit re-sort counters, which is reported (and the
+    scatter stays inside the arrays); the next sort of a smaller state works."""
+    need_gpu()
+    g = oracle.Grid(dim=2, nx=7, ny=5, dx=1.1, dy=0.9, dt=0.4)
+    n = 70000
+    ctx = make_ctx(g, "mixed", n)
+    cell = np.full(n, 3, np.int32)
+    off = np.full((2, n), 0.5)
+    u = np.zeros((3, n))
+    w = np.ones(n)
+    sp = np.zeros(n, np.uint8)
+    from paper_2509_11100_amd import _lib, relsim
+
+    parts = load(ctx, cell, sp, off, u, w)
+    Z = torch_grid(np.zeros((3, g.N)))
+    relsim.push(ctx, parts, Z, Z, resort=True)
+    with pytest.raises(_lib.RelsimError) as ei:
+        relsim.energy(ctx, parts, Z, Z)
+    assert ei.value.code == _lib.RELSIM_ERANGE
+    # the flag is cleared once reported; a valid state pushes cleanly
+    parts = load(ctx, cell[:100], sp[:100], off[:, :100], u[:, :100], w[:100])
+    relsim.push(ctx, parts, Z, Z, resort=True)
+    relsim.energy(ctx, parts, Z, Z)
+    np.testing.assert_array_equal(parts.cell.cpu().numpy(), cell[:100])
+
+
 # ----------------------------------------------------------------------------
 # a7: energy
 # ----------------------------------------------------------------------------
