@@ -83,7 +83,8 @@ int name_index(relsim_ctx *c, const char *name) {
 
 void harvest(relsim_ctx *c) {
   if (c->pending.empty()) return;
-  hipStreamSynchronize(c->st);
+  // a failed synchronisation shows up as failed elapsed-time queries below
+  (void)hipStreamSynchronize(c->st);
   for (auto &t : c->pending) {
     float v = 0.f;
     if (hipEventElapsedTime(&v, t.a, t.b) == hipSuccess) {
@@ -111,9 +112,11 @@ void timed(relsim_ctx *c, const char *name, F &&f) {
   c->pool.pop_back();
   t.a = c->pool.back();
   c->pool.pop_back();
-  hipEventRecord(t.a, c->st);
+  // timing is best effort: a failed record leaves the launch itself intact
+  // (its error, if any, is reported by launch_status)
+  (void)hipEventRecord(t.a, c->st);
   f();
-  hipEventRecord(t.b, c->st);
+  (void)hipEventRecord(t.b, c->st);
   c->pending.push_back(t);
 }
 
@@ -397,8 +400,8 @@ int relsim_init(const relsim_params *p, void *hip_stream, void *workspace, size_
   c->L = L;
   c->st = (hipStream_t)hip_stream;
   c->ws = (char *)workspace;
-  hipGetDevice(&c->device);
-  if (hipHostMalloc((void **)&c->host, 4096, hipHostMallocDefault) != hipSuccess) {
+  if (hipGetDevice(&c->device) != hipSuccess ||
+      hipHostMalloc((void **)&c->host, 4096, hipHostMallocDefault) != hipSuccess) {
     delete c;
     return RELSIM_EHIP;
   }
@@ -422,13 +425,14 @@ int relsim_init(const relsim_params *p, void *hip_stream, void *workspace, size_
 
 void relsim_finalize(relsim_ctx *c) {
   if (!c) return;
-  hipStreamSynchronize(c->st);
+  // teardown is best effort: nothing can be reported after this call
+  (void)hipStreamSynchronize(c->st);
   for (auto &t : c->pending) {
-    hipEventDestroy(t.a);
-    hipEventDestroy(t.b);
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
   }
-  for (auto e : c->pool) hipEventDestroy(e);
-  if (c->host) hipHostFree(c->host);
+  for (auto e : c->pool) (void)hipEventDestroy(e);
+  if (c->host) (void)hipHostFree(c->host);
   delete c;
 }
 
