@@ -1,6 +1,7 @@
 // Particle kernels of the semi-implicit step for gfx950: moment deposit
-// (S1-S3), node assembly of J-hat and M, push (S6), the incremental stable
-// re-sort by bin, and the kinetic-energy reduction (S7).
+// (S1-S3), node assembly of J-hat and M, push (S6) with the stable re-sort
+// by bin in two passes (count the moves; push again and write each particle
+// in its new place), and the kinetic-energy reduction (S7).
 //
 // Work decomposition shared by the particle kernels: a 64-lane wavefront is
 // split into 64/G lane groups; each group owns one cell and walks that
