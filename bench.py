@@ -69,16 +69,30 @@ KERNEL_SYMBOL = {"deposit_cells": "k_deposit_cells", "assemble_nodes": "k_assemb
                  "push_scatter": "k_push_scatter", "sort_offsets": "k_sort_offsets"}
 
 
-def source_sha256():
-    import glob
+def device_code_sha256(lib_path=None):
+    """sha256 of the GPU code objects built into the library (its
+    .hip_fatbin ELF section): identifies the kernels that ran, and does not
+    change with edits that leave the compiled kernels alone."""
     import hashlib
+    import struct
 
-    h = hashlib.sha256()
-    base = os.path.join(ROOT, "paper_2509_11100_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(base, "*.hip"))) + sorted(glob.glob(os.path.join(base, "*.h"))) + \
-            [os.path.join(ROOT, "include", "relsim.h")]:
-        h.update(open(f, "rb").read())
-    return h.hexdigest()
+    if lib_path is None:
+        lib_path = os.path.join(ROOT, "paper_2509_11100_amd", "librelsim.so")
+    data = open(lib_path, "rb").read()
+    shoff = struct.unpack_from("<Q", data, 0x28)[0]
+    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", data, 0x3A)
+
+    def section(i):
+        name, _, _, _, off, size = struct.unpack_from("<IIQQQQ", data, shoff + i * shentsize)
+        return name, off, size
+
+    _, stroff, _ = section(shstrndx)
+    for i in range(shnum):
+        name, off, size = section(i)
+        end = data.index(b"\0", stroff + name)
+        if data[stroff + name:end] == b".hip_fatbin":
+            return hashlib.sha256(data[off:off + size]).hexdigest()
+    return None
 
 
 def measured_traffic(tag, kernel):
@@ -88,7 +102,8 @@ def measured_traffic(tag, kernel):
     if not os.path.exists(path):
         return None
     js = json.load(open(path))
-    if js.get("source_sha256") != source_sha256():
+    code = device_code_sha256()
+    if code is None or js.get("device_code_sha256") != code:
         return None
     k = js["kernels"].get(KERNEL_SYMBOL.get(kernel, kernel))
     return None if k is None else k["hbm_bytes"]
