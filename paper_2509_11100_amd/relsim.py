@@ -335,6 +335,37 @@ def energy(ctx: Context, parts: Particles, E: torch.Tensor, B: torch.Tensor) -> 
     return np.array(list(out))
 
 
+class Step:
+    """Advances a particle state and its fields by whole steps n -> n+1:
+    relsim_deposit_moments (S1-S3), relsim_field_solve (S4-S5) and
+    relsim_push with re-sort (S6 + a1), in that order, on the context's
+    stream.  Holds E^n and B^n (copies of the tensors given) and the per-step
+    grid arrays (J-hat, M, E_theta and the next fields), allocated once."""
+
+    def __init__(self, ctx: Context, parts: Particles, E: torch.Tensor, B: torch.Tensor):
+        _grid_ok(ctx, E, B)
+        self.ctx, self.parts = ctx, parts
+        self.E, self.B = E.clone(), B.clone()
+        self.J, self.M = ctx.grid(), ctx.mass_matrix()
+        self.E_theta = ctx.grid()
+        self._E1, self._B1 = ctx.grid(), ctx.grid()
+        self.iters, self.rel_resid = 0, 0.0
+
+    def __call__(self, steps: int = 1) -> "Step":
+        for _ in range(steps):
+            deposit_moments(self.ctx, self.parts, self.B, self.J, self.M)
+            _, _, _, self.iters, self.rel_resid = field_solve(self.ctx, self.M, self.J, self.E, self.B, self.E_theta,
+                                                              self._E1, self._B1)
+            push(self.ctx, self.parts, self.E_theta, self.B, resort=True)
+            self.E, self._E1 = self._E1, self.E
+            self.B, self._B1 = self._B1, self.B
+        return self
+
+    def energy(self) -> np.ndarray:
+        """relsim_energy of the current state: (kinetic, electric, magnetic, total)"""
+        return energy(self.ctx, self.parts, self.E, self.B)
+
+
 def curl_nc(ctx: Context, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """relsim_curl_nc"""
     out = ctx.grid() if out is None else out

@@ -395,21 +395,17 @@ def harris_inputs(name="harris2d_64x32", **over):
 
 
 def run_gpu_steps(wl, p, E, B, precision, steps, rtol=1e-13):
-    import torch
     from paper_2509_11100_amd import relsim
 
     g = grid_of(wl)
     ctx = make_ctx(g, precision, p["w"].shape[0], rtol=rtol)
     parts = load(ctx, p["cell"], p["species"], p["off"], p["u"], p["w"], p["bin_start"])
-    Et, Bt = torch_grid(E), torch_grid(B)
-    hist = [relsim.energy(ctx, parts, Et, Bt)]
+    step = relsim.Step(ctx, parts, torch_grid(E), torch_grid(B))
+    hist = [step.energy()]
     for _ in range(steps):
-        J, M = relsim.deposit_moments(ctx, parts, Bt)
-        Eth, E1, B1, it, rr = relsim.field_solve(ctx, M, J, Et, Bt)
-        relsim.push(ctx, parts, Eth, Bt, resort=True)
-        Et, Bt = E1, B1
-        hist.append(relsim.energy(ctx, parts, Et, Bt))
-    return ctx, parts, Et.cpu().numpy(), Bt.cpu().numpy(), np.array(hist)
+        step()
+        hist.append(step.energy())
+    return ctx, parts, step.E.cpu().numpy(), step.B.cpu().numpy(), np.array(hist)
 
 
 def run_oracle_steps(g, x, u, w, sp, E, B, steps):
