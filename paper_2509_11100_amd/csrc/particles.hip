@@ -871,19 +871,23 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, const int32_t *
   const int rounds = wave_rounds<G>(cs.pend - cs.pbeg);
   T *const sinkT = sink_slot<T>(sink, lane);
   int32_t *const sinkI = sink_slot<int32_t>(sink, lane);
-  PRec<T> cur{}, nxt{};
+  // two rounds of loads in flight (this pass waits on memory more than on
+  // arithmetic)
+  PRec<T> cur{}, nxt{}, nn{};
   int p = cs.pbeg + gl;
-  int dcur = 0, dnxt = 0, bad = 0;
+  int dcur = 0, dnxt = 0, dnn = 0, bad = 0;
   if (rounds > 0) {
     load_rec<T, DIM>(p, cs.pend, xy, uw, zz, cur);
     dcur = dirc[load_index(p, cs.pend)];
+    load_rec<T, DIM>(p + G, cs.pend, xy, uw, zz, nxt);
+    dnxt = dirc[load_index(p + G, cs.pend)];
   }
   __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll 1
   for (int r = 0; r < rounds; ++r) {
     const int pn = p + G;
-    load_rec<T, DIM>(pn, cs.pend, xy, uw, zz, nxt);
-    dnxt = dirc[load_index(pn, cs.pend)];
+    load_rec<T, DIM>(p + 2 * G, cs.pend, xy, uw, zz, nn);
+    dnn = dirc[load_index(p + 2 * G, cs.pend)];
     const bool pv = p < cs.pend;
     T qs, bs;
     const int s = species_of<T>(kp, pc, cs, p, qs, bs);
@@ -933,6 +937,8 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, const int32_t *
     __builtin_amdgcn_wave_barrier();
     cur = nxt;
     dcur = dnxt;
+    nxt = nn;
+    dnxt = dnn;
     p = pn;
   }
   const int ball = __ballot(bad & 2) ? 2 : 0;
