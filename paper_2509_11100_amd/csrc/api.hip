@@ -330,7 +330,7 @@ int check_flags(relsim_ctx *c) {
   HIP_CHECK(c, hipMemsetAsync(c->at<int32_t>(c->L.err), 0, sizeof(int32_t), c->st));
   if (f & 1) return fail(c, RELSIM_ERANGE, "a particle moved more than one cell in a step, or its position is not finite");
   if (f & 2) return fail(c, RELSIM_ERANGE, "a (cell, species) bin holds more than 65535 particles");
-  if (f & 8) return fail(c, RELSIM_EINTERNAL, "the re-sort's second push pass disagreed with its first about a move");
+  if (f & 8) return fail(c, RELSIM_EINTERNAL, "the re-sort's second push pass put a particle further than rounding outside the cell its first pass counted");
   return fail(c, RELSIM_EINVAL, "cell index or species id out of range in relsim_sort input");
 }
 

@@ -615,6 +615,24 @@ __device__ __forceinline__ int cross_cell(T &f, int &bad) {
   return m;
 }
 
+// Offset along one dimension relative to the cell the counting pass placed
+// the particle in (move m), from its new offset f relative to the old cell:
+// the same arithmetic as cross_cell for that move, so the result is the
+// counting pass's bit for bit when the push is recomputed identically.
+// Should compiled code ever round the recomputation differently, a particle
+// within rounding of a face is put on that face inside the counted cell;
+// anything further off (a disagreement a rounding difference cannot
+// explain) sets off.
+template <typename T>
+__device__ __forceinline__ T place_offset(T f, int m, int &off) {
+  constexpr T below1 = sizeof(T) == 4 ? T(0x1.fffffep-1) : T(0x1.fffffffffffffp-1);
+  constexpr T tol = T(1e-4);
+  T g = m > 0 ? f - T(1) : (m < 0 ? f + T(1) : f);
+  const bool lo = !(g >= T(0)), hi = g >= T(1);  // lo includes NaN
+  off = ((lo && !(g > -tol)) || (hi && !(g < T(1) + tol))) ? 1 : off;
+  return lo ? T(0) : (hi ? below1 : g);
+}
+
 // Lanes past their cell's end store into a per-lane slot of a small sink in
 // the workspace instead of branching around the stores: with unconditional
 // stores the compiler can count them, and the wait for the next round's
@@ -824,11 +842,12 @@ __global__ __launch_bounds__(256) void k_sort_offsets(KParams kp, const uint16_t
 // Each lane group first resolves, for each (species, move) key of its cell,
 // where that class's run starts in the new order (new bin start + offset of
 // this source cell among the bin's sources).  In the loop every particle is
-// pushed once more (push_one, bit for bit as in the counting pass, which is
-// checked against the recorded move), and its new state is written at that
-// base plus its rank among the same-key lanes of earlier rounds and lower
-// lanes of this round, found from one ballot per key bit.  The particle
-// state is thus read twice and written once per step.
+// pushed once more (push_one, as in the counting pass; its offsets are
+// taken relative to the cell of the recorded move, see place_offset), and
+// its new state is written at that base plus its rank among the same-key
+// lanes of earlier rounds and lower lanes of this round, found from one
+// ballot per key bit.  The particle state is thus read twice and written
+// once per step.
 // ---------------------------------------------------------------------------
 template <typename T, int DIM, int G, bool PERM>
 __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, const int32_t *__restrict__ bin_start,
@@ -893,13 +912,13 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, const int32_t *
     const int s = species_of<T>(kp, pc, cs, p, qs, bs);
     T fx, fy, fz, nx, ny, nz;
     push_one<T, DIM>(kp, pc, Bs, Bc, Ec, cs.gc, bs, cur, fx, fy, fz, nx, ny, nz);
-    int flag = 0;
-    const int mx = cross_cell<T>(fx, flag);
-    const int my = cross_cell<T>(fy, flag);
-    const int mz = DIM == 3 ? cross_cell<T>(fz, flag) : 0;
-    const int dir = (mx + 1) + 3 * (my + 1) + (DIM == 3 ? 9 * (mz + 1) : 0);
-    // the move must be the one counted (a bad move was flagged there)
-    bad |= (pv && !flag && dir != dcur) ? 4 : 0;
+    // the new state goes where the counting pass counted it (move dcur),
+    // with its offsets taken relative to that cell
+    int off = 0;
+    fx = place_offset<T>(fx, dcur % 3 - 1, off);
+    fy = place_offset<T>(fy, (dcur / 3) % 3 - 1, off);
+    if constexpr (DIM == 3) fz = place_offset<T>(fz, dcur / 9 - 1, off);
+    bad |= (pv && off) ? 4 : 0;
     const int key = pv ? grp * nkey + s * NDIR + dcur : 0;
     // lanes of this round holding the same key
     const unsigned long long act = __ballot(pv);

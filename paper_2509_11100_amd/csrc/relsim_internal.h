@@ -82,7 +82,8 @@ void launch_sort_offsets(const KParams &kp, const uint16_t *cnt, uint16_t *pre, 
 void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream_t st);
 size_t scan_tmp_elems(int n);
 // second pass of the re-sort: push src again and write the new state into
-// out in the new bin order (err bit 4: a recomputed move differs from dirc)
+// out in the new bin order, each in the cell of its recorded move (err bit
+// 8: a recomputed position further than rounding outside that cell)
 void launch_push_scatter(const KParams &kp, int prec, int group, const PartPtrs &src, const void *Est,
                          const void *Bst, const uint8_t *dirc, const uint16_t *pre, const int32_t *bin_start_new,
                          const PartPtrs &out, int ntot, int32_t *err, int32_t *perm, void *sink, hipStream_t st);
