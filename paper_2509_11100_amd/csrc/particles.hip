@@ -67,16 +67,6 @@ __device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
 
-// CIC weights of the three cell centres at relative positions -1/2, 1/2,
-// 3/2 (cell units) seen from a particle at offset f in [0,1).
-template <typename T>
-__device__ __forceinline__ void centre_w3(T f, T w[3]) {
-  const bool hi = f >= T(0.5);
-  w[0] = hi ? T(0) : T(0.5) - f;
-  w[1] = hi ? T(1.5) - f : T(0.5) + f;
-  w[2] = hi ? f - T(0.5) : T(0);
-}
-
 // alpha = (I - [b]x + b b^T) / (1 + |b|^2), row-major, as its numerator
 // (written to a) and the returned scale 1 / (1 + |b|^2); the kernels fold
 // the scale into their per-particle coefficients.
@@ -96,23 +86,30 @@ __device__ __forceinline__ T alpha_num(T bx, T by, T bz, T a[9]) {
 
 // Particle-side view of the kernel constants in the arithmetic type T
 // (precomputed on the host: no divisions or conversions in the kernels).
+// The charges and betas of species 0 and 1 are also held by value (read
+// once from the kernel arguments): a per-particle load of them inside a
+// round would make the round wait for every load issued before it,
+// prefetches included.
 template <typename T>
 struct PC;
 template <>
 struct PC<float> {
   float dt, invc, invc2, invV, idx, idy, idz;
+  float q0, q1, b0, b1;
   const float *q, *beta;
   __device__ explicit PC(const KParams &kp)
       : dt(kp.f_dt), invc(kp.f_inv_c), invc2(kp.f_inv_c2), invV(kp.f_inv_V), idx(kp.f_inv_dx), idy(kp.f_inv_dy),
-        idz(kp.f_inv_dz), q(kp.f_q), beta(kp.f_beta) {}
+        idz(kp.f_inv_dz), q0(kp.f_q[0]), q1(kp.f_q[1]), b0(kp.f_beta[0]), b1(kp.f_beta[1]), q(kp.f_q),
+        beta(kp.f_beta) {}
 };
 template <>
 struct PC<double> {
   double dt, invc, invc2, invV, idx, idy, idz;
+  double q0, q1, b0, b1;
   const double *q, *beta;
   __device__ explicit PC(const KParams &kp)
       : dt(kp.dt), invc(kp.inv_c), invc2(kp.inv_c2), invV(kp.inv_V), idx(kp.inv_dx), idy(kp.inv_dy),
-        idz(kp.inv_dz), q(kp.q), beta(kp.beta) {}
+        idz(kp.inv_dz), q0(kp.q[0]), q1(kp.q[1]), b0(kp.beta[0]), b1(kp.beta[1]), q(kp.q), beta(kp.beta) {}
 };
 
 
@@ -141,58 +138,47 @@ __device__ __forceinline__ int gidx(const KParams &kp, int i, int j, int k) {
   return (i + 1) + kp.gx * (j + 1) + (DIM == 3 ? kp.gxy * (k + 1) : 0);
 }
 
-// Block of 3x3 (2D) cell-centre B values around the cell with ghosted index
-// gc in registers.
-template <typename T>
-__device__ __forceinline__ void load_B_block_2d(const KParams &kp, const V4<T> *__restrict__ Bs, int gc,
-                                                T Bc[3][9]) {
+// 2D: the 3x3 block of cell-centre B values around the cell with ghosted
+// index gc, staged in LDS by the G lanes of the cell's group (centre t at
+// column t % 3 - 1, row t / 3 - 1 relative to the cell).  The caller
+// synchronises the block before the first gather.
+template <typename T, int G>
+__device__ __forceinline__ void stage_B_block_2d(const KParams &kp, const V4<T> *__restrict__ Bs, int gc, int gl,
+                                                 V4<T> *blk) {
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const V4<T> b = Bs[gc + (t % 3 - 1) + kp.gx * (t / 3 - 1)];
-    Bc[0][t] = b.x;
-    Bc[1][t] = b.y;
-    Bc[2][t] = b.z;
-  }
+  for (int t = gl; t < 9; t += G) blk[t] = Bs[gc + (t % 3 - 1) + kp.gx * (t / 3 - 1)];
 }
 
-// B at the particle.  With BLK (2D only) from the 3x3 register block of the
-// cell; otherwise by a direct gather of the 2^DIM centres around the
-// particle from the ghosted copy (lower corner at shift -1 or 0 per
-// dimension).
-template <typename T, int DIM, bool BLK>
-__device__ __forceinline__ void gather_B(const KParams &kp, const V4<T> *__restrict__ Bs, const T (&Bc)[3][9],
-                                         int gc, T fx, T fy, T fz, T &Bx, T &By, T &Bz) {
-  if constexpr (DIM == 2 && BLK) {
-    T wx[3], wy[3];
-    centre_w3(fx, wx);
-    centre_w3(fy, wy);
-    const T w0 = wx[0] * wy[0];
-    Bx = w0 * Bc[0][0];
-    By = w0 * Bc[1][0];
-    Bz = w0 * Bc[2][0];
-#pragma unroll
-    for (int t = 1; t < 9; ++t) {
-      const T wt = wx[t % 3] * wy[t / 3];
-      Bx += wt * Bc[0][t];
-      By += wt * Bc[1][t];
-      Bz += wt * Bc[2][t];
-    }
+// B at the particle from the 2^DIM cell centres around it (lower corner at
+// shift -1 or 0 per dimension): in 2D from the cell's LDS block, in 3D
+// directly from the ghosted copy.
+template <typename T, int DIM>
+__device__ __forceinline__ void gather_B(const KParams &kp, const V4<T> *__restrict__ Bs, const V4<T> *blk, int gc,
+                                         T fx, T fy, T fz, T &Bx, T &By, T &Bz) {
+  constexpr int NCEN = DIM == 3 ? 8 : 4;
+  const bool hx = fx >= T(0.5), hy = fy >= T(0.5), hz = DIM == 3 && fz >= T(0.5);
+  const T gx = hx ? fx - T(0.5) : fx + T(0.5);
+  const T gy = hy ? fy - T(0.5) : fy + T(0.5);
+  const T gz = hz ? fz - T(0.5) : fz + T(0.5);
+  const V4<T> *b0;
+  int sy, sz;
+  if constexpr (DIM == 2) {
+    b0 = blk + (hx ? 1 : 0) + (hy ? 3 : 0);
+    sy = 3;
+    sz = 0;
   } else {
-    constexpr int NCEN = DIM == 3 ? 8 : 4;
-    const bool hx = fx >= T(0.5), hy = fy >= T(0.5), hz = DIM == 3 && fz >= T(0.5);
-    const int g0 = gc - (hx ? 0 : 1) - (hy ? 0 : kp.gx) - ((DIM == 2 || hz) ? 0 : kp.gxy);
-    const T gx = hx ? fx - T(0.5) : fx + T(0.5);
-    const T gy = hy ? fy - T(0.5) : fy + T(0.5);
-    const T gz = hz ? fz - T(0.5) : fz + T(0.5);
+    b0 = Bs + (gc - (hx ? 0 : 1) - (hy ? 0 : kp.gx) - (hz ? 0 : kp.gxy));
+    sy = kp.gx;
+    sz = kp.gxy;
+  }
 #pragma unroll
-    for (int a = 0; a < NCEN; ++a) {
-      const V4<T> b = Bs[g0 + (a & 1) + ((a & 2) ? kp.gx : 0) + ((a & 4) ? kp.gxy : 0)];
-      T wt = ((a & 1) ? gx : T(1) - gx) * ((a & 2) ? gy : T(1) - gy);
-      if constexpr (DIM == 3) wt *= (a & 4) ? gz : T(1) - gz;
-      Bx = a == 0 ? wt * b.x : Bx + wt * b.x;
-      By = a == 0 ? wt * b.y : By + wt * b.y;
-      Bz = a == 0 ? wt * b.z : Bz + wt * b.z;
-    }
+  for (int a = 0; a < NCEN; ++a) {
+    const V4<T> b = b0[(a & 1) + ((a & 2) ? sy : 0) + ((a & 4) ? sz : 0)];
+    T wt = ((a & 1) ? gx : T(1) - gx) * ((a & 2) ? gy : T(1) - gy);
+    if constexpr (DIM == 3) wt *= (a & 4) ? gz : T(1) - gz;
+    Bx = a == 0 ? wt * b.x : Bx + wt * b.x;
+    By = a == 0 ? wt * b.y : By + wt * b.y;
+    Bz = a == 0 ? wt * b.z : Bz + wt * b.z;
   }
 }
 
@@ -229,31 +215,49 @@ __device__ __forceinline__ int wave_rounds(int count) {
   int r = (count + G - 1) / G;
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) r = max(r, __shfl_xor(r, o));
-  return r;
+  // every lane holds the maximum now; as a scalar, loops over rounds
+  // branch uniformly
+  return __builtin_amdgcn_readfirstlane(r);
 }
 
 // Species of particle p of the cell (particles of a cell are ordered by
-// species), with its charge and beta.
+// species), with its charge and beta.  The two-species case selects between
+// values passed in (q0, q1, b0, b1), not between loads: the compiler may
+// turn a select of two loads into one load from a selected address, which
+// pins the operands in memory.  Other species counts read the tables qt, bt.
 template <typename T>
-__device__ __forceinline__ int species_of(const KParams &kp, const PC<T> &pc, const CellSpan &cs, int p, T &q,
-                                         T &beta) {
+__device__ __forceinline__ int species_sel(const KParams &kp, const CellSpan &cs, int p, T q0, T q1, T b0, T b1,
+                                          const T *qt, const T *bt, T &q, T &beta) {
   if (kp.nspecies == 2) {
     const bool s1 = p >= cs.bound[1];
-    q = s1 ? pc.q[1] : pc.q[0];
-    beta = s1 ? pc.beta[1] : pc.beta[0];
+    q = s1 ? q1 : q0;
+    beta = s1 ? b1 : b0;
     return s1 ? 1 : 0;
   }
   int s = 0;
-  q = pc.q[0];
-  beta = pc.beta[0];
 #pragma unroll
-  for (int s2 = 1; s2 < 8; ++s2)
-    if (p >= cs.bound[s2]) {
-      s = s2;
-      q = pc.q[s2];
-      beta = pc.beta[s2];
-    }
+  for (int s2 = 1; s2 < 8; ++s2) s = p >= cs.bound[s2] ? s2 : s;
+  q = qt[s];
+  beta = bt[s];
   return s;
+}
+
+template <typename T>
+__device__ __forceinline__ int species_of(const KParams &kp, const PC<T> &pc, const CellSpan &cs, int p,
+                                         const T (*tab)[8], T &q, T &beta) {
+  return species_sel<T>(kp, cs, p, pc.q0, pc.q1, pc.b0, pc.b1, tab[0], tab[1], q, beta);
+}
+
+// Per-species charge and beta in LDS (row 0: q, row 1: beta), for species
+// counts other than two: read inside a round from LDS, since a load from
+// memory there would wait for the next rounds' prefetched loads too.  The
+// caller synchronises before the first use.
+template <typename T>
+__device__ __forceinline__ void fill_species_table(const PC<T> &pc, T (*tab)[8], int lane) {
+  if (lane < 8) {
+    tab[0][lane] = pc.q[lane];
+    tab[1][lane] = pc.beta[lane];
+  }
 }
 
 // One particle's state as loaded from the SoA arrays.
@@ -305,17 +309,18 @@ __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t 
                                                       const V4<T> *__restrict__ Bs, T *__restrict__ S) {
   constexpr int NACC = 93;  // 81 mass moments + 12 current moments
   constexpr int CH = 32;    // moments per LDS transpose chunk (keeps LDS off the occupancy limit)
-  // FP32 keeps the cell's 3x3 B block in registers; FP64 gathers per particle
-  constexpr bool BLK = sizeof(T) == 4;
   __shared__ T red[64 * (CH + 1)];
+  __shared__ V4<T> bsh[64 / G][9];
+  __shared__ T stab[2][8];
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
   const PC<T> pc(kp);
   const size_t NC = (size_t)kp.ncells;
 
-  T Bc[3][9];
-  if constexpr (BLK) load_B_block_2d<T>(kp, Bs, cs.gc, Bc);
+  stage_B_block_2d<T, G>(kp, Bs, cs.gc, gl, bsh[grp]);
+  fill_species_table<T>(pc, stab, lane);
+  __syncthreads();
   const int pal = cs.pbeg & ~(round_align<T, G>() - 1);
   const int rounds = wave_rounds<G>(cs.pend - pal);
 
@@ -334,9 +339,9 @@ __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t 
       const T fx = cur.fx, fy = cur.fy;
       const T ux = cur.ux, uy = cur.uy, uz = cur.uz, wp = cur.w;
       T qs, bs;
-      species_of<T>(kp, pc, cs, p, qs, bs);
+      species_of<T>(kp, pc, cs, p, stab, qs, bs);
       T Bx, By, Bz;
-      gather_B<T, 2, BLK>(kp, Bs, Bc, cs.gc, fx, fy, T(0), Bx, By, Bz);
+      gather_B<T, 2>(kp, Bs, bsh[grp], cs.gc, fx, fy, T(0), Bx, By, Bz);
       const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
       const T kb = bs * igb * pc.invc;
       T a[9];
@@ -413,18 +418,20 @@ __global__ __launch_bounds__(64) void k_deposit_split3(KParams kp, const int32_t
   // (P6 P7 P8 -) for the mass lanes [0] and the current lane [1], and Z
   __shared__ V4<T> sh[2][4][64];
   __shared__ T zsh[4][64];
+  __shared__ T stab[2][8];
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
   const PC<T> pc(kp);
   const size_t NC = (size_t)kp.ncells;
+  fill_species_table<T>(pc, stab, lane);
+  __syncthreads();
   const bool isJ = gl == 3;
   const V4<T> *const mine = &sh[isJ ? 1 : 0][0][0];
 
   T acc[81];
 #pragma unroll
   for (int k = 0; k < 81; ++k) acc[k] = T(0);
-  const T Bc[3][9] = {};
   // rounds start at the cell's first particle: with few particles per cell
   // an aligned start costs more rounds than it saves in memory sectors
   const int pal = cs.pbeg;
@@ -443,9 +450,9 @@ __global__ __launch_bounds__(64) void k_deposit_split3(KParams kp, const int32_t
       const T fx = cur.fx, fy = cur.fy, fz = cur.fz;
       const T ux = cur.ux, uy = cur.uy, uz = cur.uz;
       T qs, bs;
-      species_of<T>(kp, pc, cs, p, qs, bs);
+      species_of<T>(kp, pc, cs, p, stab, qs, bs);
       T Bx, By, Bz;
-      gather_B<T, 3, false>(kp, Bs, Bc, cs.gc, fx, fy, fz, Bx, By, Bz);
+      gather_B<T, 3>(kp, Bs, nullptr, cs.gc, fx, fy, fz, Bx, By, Bz);
       const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
       const T kb = bs * igb * pc.invc;
       T a[9];
@@ -662,7 +669,7 @@ __device__ __forceinline__ void load_E_corners(const KParams &kp, const V4<T> *_
 // this one function, so that they all round identically.
 template <typename T, int DIM>
 __device__ __forceinline__ void push_one(const KParams &kp, const PC<T> &pc, const V4<T> *__restrict__ Bs,
-                                         const T (&Bc)[3][9], const T (&Ec)[3][DIM == 3 ? 8 : 4], int gc, T bs,
+                                         const V4<T> *bblk, const T (&Ec)[3][DIM == 3 ? 8 : 4], int gc, T bs,
                                          const PRec<T> &cur, T &fx, T &fy, T &fz, T &nx, T &ny, T &nz) {
   constexpr int NCORN = DIM == 3 ? 8 : 4;
   fx = cur.fx;
@@ -670,7 +677,7 @@ __device__ __forceinline__ void push_one(const KParams &kp, const PC<T> &pc, con
   fz = DIM == 3 ? cur.fz : T(0);
   const T ux = cur.ux, uy = cur.uy, uz = cur.uz;
   T Bx, By, Bz;
-  gather_B<T, DIM, true>(kp, Bs, Bc, gc, fx, fy, fz, Bx, By, Bz);
+  gather_B<T, DIM>(kp, Bs, bblk, gc, fx, fy, fz, Bx, By, Bz);
   const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
   const T kb = bs * igb * pc.invc;
   T a[9];
@@ -715,19 +722,20 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
   constexpr int NK = 8 * NDIR;  // (species, move) keys per group
   constexpr int NGRP = 64 / G;
   __shared__ uint32_t lcnt[COUNT ? NGRP * NK : 1];
+  __shared__ V4<T> bsh[DIM == 2 ? NGRP : 1][9];
+  __shared__ T stab[2][8];
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
   const PC<T> pc(kp);
   T *const sinkT = sink_slot<T>(sink, lane);
   uint8_t *const sinkB = sink_slot<uint8_t>(sink, lane);
-  if constexpr (COUNT) {
+  if constexpr (COUNT)
     for (int t = lane; t < NGRP * NK; t += 64) lcnt[t] = 0u;
-    __syncthreads();
-  }
-
-  T Bc[3][9];
-  if constexpr (DIM == 2) load_B_block_2d<T>(kp, Bs, cs.gc, Bc);
+  const V4<T> *const bblk = DIM == 2 ? bsh[grp] : nullptr;
+  if constexpr (DIM == 2) stage_B_block_2d<T, G>(kp, Bs, cs.gc, gl, bsh[grp]);
+  fill_species_table<T>(pc, stab, lane);
+  __syncthreads();
   T Ec[3][DIM == 3 ? 8 : 4];
   load_E_corners<T, DIM>(kp, Es, cs.gc, Ec);
   const int pal = cs.pbeg & ~(round_align<T, G>() - 1);
@@ -748,9 +756,9 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
     // values) and store into the sink
     const bool pv = p >= cs.pbeg && p < cs.pend;
     T qs, bs;
-    const int s = species_of<T>(kp, pc, cs, p, qs, bs);
+    const int s = species_of<T>(kp, pc, cs, p, stab, qs, bs);
     T fx, fy, fz, nx, ny, nz;
-    push_one<T, DIM>(kp, pc, Bs, Bc, Ec, cs.gc, bs, cur, fx, fy, fz, nx, ny, nz);
+    push_one<T, DIM>(kp, pc, Bs, bblk, Ec, cs.gc, bs, cur, fx, fy, fz, nx, ny, nz);
     if constexpr (COUNT) {
       int flag = 0;
       const int mx = cross_cell<T>(fx, flag);
@@ -837,6 +845,76 @@ __global__ __launch_bounds__(256) void k_sort_offsets(KParams kp, const uint16_t
   total[d] = run;
 }
 
+// One round of the pushing scatter for particle p of the lane's cell, on
+// record buffer (cur, dc), which it then refills with the round three
+// ahead; see k_push_scatter.
+template <typename T, int DIM, int G, bool PERM>
+__device__ __forceinline__ void scatter_round(const KParams &kp, const PC<T> &pc, const CellSpan &cs,
+                                              const V4<T> *__restrict__ Bs, const V4<T> *bblk,
+                                              const T (&Ec)[3][DIM == 3 ? 8 : 4], int lane, int grp, int nkey,
+                                              int kbits, unsigned long long lt, int *lbase, int ntot,
+                                              const V2<T> *__restrict__ xy, const V4<T> *__restrict__ uw,
+                                              const T *__restrict__ zz, const uint8_t *__restrict__ dirc,
+                                              V2<T> *__restrict__ xo, V4<T> *__restrict__ uo, T *__restrict__ zo,
+                                              int32_t *__restrict__ perm, void *__restrict__ sink, T q0, T q1,
+                                              T b0, T b1, const T *qt, const T *bt, int &p, int &bad,
+                                              PRec<T> &cur, uint8_t &dc) {
+  constexpr int NDIR = DIM == 3 ? 27 : 9;
+  T *const sinkT = sink_slot<T>(sink, lane);
+  int32_t *const sinkI = sink_slot<int32_t>(sink, lane);
+  const int dcur = dc;
+  const bool pv = p < cs.pend;
+  T qs, bs;
+  const int s = species_sel<T>(kp, cs, p, q0, q1, b0, b1, qt, bt, qs, bs);
+  T fx, fy, fz, nx, ny, nz;
+  push_one<T, DIM>(kp, pc, Bs, bblk, Ec, cs.gc, bs, cur, fx, fy, fz, nx, ny, nz);
+  // the new state goes where the counting pass counted it (move dcur),
+  // with its offsets taken relative to that cell
+  int off = 0;
+  fx = place_offset<T>(fx, dcur % 3 - 1, off);
+  fy = place_offset<T>(fy, (dcur / 3) % 3 - 1, off);
+  if constexpr (DIM == 3) fz = place_offset<T>(fz, dcur / 9 - 1, off);
+  bad |= (pv && off) ? 4 : 0;
+  const int key = pv ? grp * nkey + s * NDIR + dcur : 0;
+  // lanes of this round holding the same key
+  const unsigned long long act = __ballot(pv);
+  uint32_t same_lo = (uint32_t)act, same_hi = (uint32_t)(act >> 32);
+#pragma unroll 1
+  for (int b = 0; b < kbits; ++b) {
+    const bool bit = (key >> b) & 1;
+    const unsigned long long ones = __ballot(bit);
+    const uint32_t lo = (uint32_t)ones, hi = (uint32_t)(ones >> 32);
+    same_lo &= bit ? lo : ~lo;
+    same_hi &= bit ? hi : ~hi;
+  }
+  const unsigned long long same = ((unsigned long long)same_hi << 32) | same_lo;
+  int pos = 0;
+  if (pv) pos = lbase[key] + __popcll(same & lt);
+  __builtin_amdgcn_wave_barrier();
+  // the highest lane of each key advances that key's base
+  if (pv && (same >> lane) == 1ull) lbase[key] += __popcll(same);
+  // only reachable out of range when a bin overflowed the 16-bit
+  // counters (flagged); lanes past the end store into the sink
+  const bool ok = pv && pos >= 0 && pos < ntot;
+  bad |= (pv && !ok) ? 2 : 0;
+  V2<T> xv;
+  xv.x = fx;
+  xv.y = fy;
+  V4<T> uv;
+  uv.x = nx;
+  uv.y = ny;
+  uv.z = nz;
+  uv.w = cur.w;
+  *(ok ? xo + pos : sink_slot<V2<T>>(sink, lane)) = xv;
+  *(ok ? uo + pos : sink_slot<V4<T>>(sink, lane)) = uv;
+  if constexpr (DIM == 3) *(ok ? zo + pos : sinkT) = fz;
+  if constexpr (PERM) *(ok ? perm + p : sinkI) = pos;
+  __builtin_amdgcn_wave_barrier();
+  load_rec<T, DIM>(p + 3 * G, cs.pend, xy, uw, zz, cur);
+  dc = dirc[load_index(p + 3 * G, cs.pend)];
+  p += G;
+}
+
 // ---------------------------------------------------------------------------
 // re-sort, step 3: push again and scatter, stably, into the back buffers.
 // Each lane group first resolves, for each (species, move) key of its cell,
@@ -863,11 +941,14 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, const int32_t *
   constexpr int NDIR = DIM == 3 ? 27 : 9;
   constexpr int NGRP = 64 / G;
   __shared__ int lbase[NGRP * 8 * NDIR];  // next destination of each (group, species, move) key
+  __shared__ V4<T> bsh[DIM == 2 ? NGRP : 1][9];
+  __shared__ T stab[2][8];
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
   const PC<T> pc(kp);
   const int S = kp.nspecies, nkey = S * NDIR;
+  fill_species_table<T>(pc, stab, lane);
   const size_t nb = (size_t)kp.nbins;
   if (cs.valid) {
     for (int t = gl; t < nkey; t += G) {
@@ -879,8 +960,8 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, const int32_t *
       lbase[grp * nkey + t] = bsn[d] + (int)pre[(size_t)dir * nb + d];
     }
   }
-  T Bc[3][9];
-  if constexpr (DIM == 2) load_B_block_2d<T>(kp, Bs, cs.gc, Bc);
+  const V4<T> *const bblk = DIM == 2 ? bsh[grp] : nullptr;
+  if constexpr (DIM == 2) stage_B_block_2d<T, G>(kp, Bs, cs.gc, gl, bsh[grp]);
   T Ec[3][DIM == 3 ? 8 : 4];
   load_E_corners<T, DIM>(kp, Es, cs.gc, Ec);
   __syncthreads();
@@ -888,78 +969,41 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, const int32_t *
   const int kbits = 32 - __builtin_clz((unsigned)(NGRP * nkey - 1) | 1u);
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int rounds = wave_rounds<G>(cs.pend - cs.pbeg);
-  T *const sinkT = sink_slot<T>(sink, lane);
-  int32_t *const sinkI = sink_slot<int32_t>(sink, lane);
-  // two rounds of loads in flight (this pass waits on memory more than on
-  // arithmetic)
-  PRec<T> cur{}, nxt{}, nn{};
-  int p = cs.pbeg + gl;
-  int dcur = 0, dnxt = 0, dnn = 0, bad = 0;
+  // Three record buffers in rotation: while one round is pushed and
+  // stored, the loads of the next two are in flight.  Each round refills
+  // its own buffer with the round three ahead once it has been used, so no
+  // buffer is ever copied into another (a copy would wait for its loads).
+  // The loop runs whole groups of three rounds, so every pass through it
+  // issues the same loads in the same order and its waits stay exact; the
+  // last one or two rounds follow it.
+  PRec<T> rb0{}, rb1{}, rb2{};
+  uint8_t db0 = 0, db1 = 0, db2 = 0;
+  int p = cs.pbeg + gl, bad = 0;
   if (rounds > 0) {
-    load_rec<T, DIM>(p, cs.pend, xy, uw, zz, cur);
-    dcur = dirc[load_index(p, cs.pend)];
-    load_rec<T, DIM>(p + G, cs.pend, xy, uw, zz, nxt);
-    dnxt = dirc[load_index(p + G, cs.pend)];
+    load_rec<T, DIM>(p, cs.pend, xy, uw, zz, rb0);
+    db0 = dirc[load_index(p, cs.pend)];
+    load_rec<T, DIM>(p + G, cs.pend, xy, uw, zz, rb1);
+    db1 = dirc[load_index(p + G, cs.pend)];
+    load_rec<T, DIM>(p + 2 * G, cs.pend, xy, uw, zz, rb2);
+    db2 = dirc[load_index(p + 2 * G, cs.pend)];
   }
+  // enter the loop with nothing in flight, so that the waits in the loop
+  // count only the loop's own loads and stores
   __builtin_amdgcn_s_waitcnt(0);
+#define RELSIM_SCATTER_ROUND(rb, db)                                                                          \
+  scatter_round<T, DIM, G, PERM>(kp, pc, cs, Bs, bblk, Ec, lane, grp, nkey, kbits, lt, lbase, ntot, xy, uw, zz, \
+                                 dirc, xo, uo, zo, perm, sink, sq0, sq1, sb0, sb1, stab[0], stab[1], p, bad, rb, db)
+  const T sq0 = pc.q0, sq1 = pc.q1, sb0 = pc.b0, sb1 = pc.b1;
+  int r = 0;
 #pragma unroll 1
-  for (int r = 0; r < rounds; ++r) {
-    const int pn = p + G;
-    load_rec<T, DIM>(p + 2 * G, cs.pend, xy, uw, zz, nn);
-    dnn = dirc[load_index(p + 2 * G, cs.pend)];
-    const bool pv = p < cs.pend;
-    T qs, bs;
-    const int s = species_of<T>(kp, pc, cs, p, qs, bs);
-    T fx, fy, fz, nx, ny, nz;
-    push_one<T, DIM>(kp, pc, Bs, Bc, Ec, cs.gc, bs, cur, fx, fy, fz, nx, ny, nz);
-    // the new state goes where the counting pass counted it (move dcur),
-    // with its offsets taken relative to that cell
-    int off = 0;
-    fx = place_offset<T>(fx, dcur % 3 - 1, off);
-    fy = place_offset<T>(fy, (dcur / 3) % 3 - 1, off);
-    if constexpr (DIM == 3) fz = place_offset<T>(fz, dcur / 9 - 1, off);
-    bad |= (pv && off) ? 4 : 0;
-    const int key = pv ? grp * nkey + s * NDIR + dcur : 0;
-    // lanes of this round holding the same key
-    const unsigned long long act = __ballot(pv);
-    uint32_t same_lo = (uint32_t)act, same_hi = (uint32_t)(act >> 32);
-#pragma unroll 1
-    for (int b = 0; b < kbits; ++b) {
-      const bool bit = (key >> b) & 1;
-      const unsigned long long ones = __ballot(bit);
-      const uint32_t lo = (uint32_t)ones, hi = (uint32_t)(ones >> 32);
-      same_lo &= bit ? lo : ~lo;
-      same_hi &= bit ? hi : ~hi;
-    }
-    const unsigned long long same = ((unsigned long long)same_hi << 32) | same_lo;
-    int pos = 0;
-    if (pv) pos = lbase[key] + __popcll(same & lt);
-    __builtin_amdgcn_wave_barrier();
-    // the highest lane of each key advances that key's base
-    if (pv && (same >> lane) == 1ull) lbase[key] += __popcll(same);
-    // only reachable out of range when a bin overflowed the 16-bit
-    // counters (flagged); lanes past the end store into the sink
-    const bool ok = pv && pos >= 0 && pos < ntot;
-    bad |= (pv && !ok) ? 2 : 0;
-    V2<T> xv;
-    xv.x = fx;
-    xv.y = fy;
-    V4<T> uv;
-    uv.x = nx;
-    uv.y = ny;
-    uv.z = nz;
-    uv.w = cur.w;
-    *(ok ? xo + pos : sink_slot<V2<T>>(sink, lane)) = xv;
-    *(ok ? uo + pos : sink_slot<V4<T>>(sink, lane)) = uv;
-    if constexpr (DIM == 3) *(ok ? zo + pos : sinkT) = fz;
-    if constexpr (PERM) *(ok ? perm + p : sinkI) = pos;
-    __builtin_amdgcn_wave_barrier();
-    cur = nxt;
-    dcur = dnxt;
-    nxt = nn;
-    dnxt = dnn;
-    p = pn;
+  for (; r + 3 <= rounds; r += 3) {
+    RELSIM_SCATTER_ROUND(rb0, db0);
+    RELSIM_SCATTER_ROUND(rb1, db1);
+    RELSIM_SCATTER_ROUND(rb2, db2);
   }
+  if (r < rounds) RELSIM_SCATTER_ROUND(rb0, db0);
+  if (r + 1 < rounds) RELSIM_SCATTER_ROUND(rb1, db1);
+#undef RELSIM_SCATTER_ROUND
   const int ball = __ballot(bad & 2) ? 2 : 0;
   const int balm = __ballot(bad & 4) ? 8 : 0;
   if ((ball | balm) && lane == 0) atomicOr(err, ball | balm);
