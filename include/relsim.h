@@ -73,9 +73,10 @@ typedef struct {
   int32_t gmres_restart;       /* Krylov dimension (1..64)                        */
   int32_t gmres_maxit;         /* total Arnoldi steps allowed                     */
   int32_t nonrelativistic;     /* 1: gamma == 1, kinetic energy m|u|^2/2          */
-  int32_t group;               /* lanes per cell in the particle kernels:
-                                  0 = choose from the mean occupancy, else
-                                  8, 16, 32 or 64                                 */
+  int32_t group;               /* lanes per cell in the deposit and kinetic-
+                                  energy kernels: 0 = choose from the mean
+                                  occupancy, else 8, 16, 32 or 64 (the push
+                                  passes size their row segments themselves)     */
 } relsim_params;
 
 /* Particle state, sorted by bin = cell * nspecies + s, so that the

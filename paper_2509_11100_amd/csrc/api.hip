@@ -248,26 +248,39 @@ KParams make_kparams(const relsim_params *p) {
   return k;
 }
 
-// Lanes per cell for a particle kernel: the largest power of two in
-// [gmin, 64] not above mean_occupancy / rounds, where `rounds` is the number
-// of G-wide rounds per cell the kernel wants, then widened until the launch
-// has at least 512 waves (2 per CU) on small grids.  The 2D deposit
-// amortises its per-cell reduction over many rounds (16 in FP32; 32 in FP64,
-// whose register-bound occupancy favours narrower groups) and may go down to
-// 4 lanes; the counting push pass wants 8 (FP32) or 16 (FP64) rounds; the
-// pushing scatter pass 4 (2 in 3D FP32, where its 27 move classes make wide
-// groups write longer runs).  Measured on the 2D Harris sheets with 32, 64
-// and 128 particles per cell and the 3D sheet with 32.  (The 3D deposit
-// always splits a cell's moments over 4 lanes and takes no group.)
 enum KernelKind { K_DEPOSIT, K_PUSH, K_SCATTER, K_OTHER };
 
+// Cells per wave of the push passes: the widest power of two dividing nx
+// whose segment holds about `rounds` rounds of 64 particles, while the grid
+// still gives 2048 waves and the segment's LDS stays within 8 KB (more
+// starts to limit occupancy).  The counting pass wants 8 rounds, the
+// pushing scatter 4: measured on the 1024 x 512 sheet (128 particles per
+// cell: segments of 4 and 2 cells) and the 256 x 128 x 128 sheet (16 per
+// cell: 16 cells, LDS-bound, for both).
+int choose_cells(const relsim_ctx *c, int64_t n, KernelKind k) {
+  const double rounds = k == K_SCATTER ? 4.0 : 8.0;
+  const size_t lds = 8192;
+  const double mean = (double)n / (double)c->kp.ncells;
+  int C = 1;
+  while (C < 64 && 2.0 * C * mean <= rounds * 64.0 && c->kp.nx % (2 * C) == 0 &&
+         c->kp.ncells / (2 * C) >= 2048 && push_lds_bytes(c->kp, c->p.precision, 2 * C) <= lds)
+    C *= 2;
+  return C;
+}
+
+// Lanes per cell for the deposit and the kinetic-energy kernel: the largest
+// power of two in [gmin, 64] not above mean_occupancy / rounds, where
+// `rounds` is the number of G-wide rounds per cell the kernel wants, then
+// widened until the launch has at least 512 waves (2 per CU) on small
+// grids.  The 2D deposit amortises its per-cell reduction over many rounds
+// (16 in FP32; 32 in FP64, whose register-bound occupancy favours narrower
+// groups) and may go down to 4 lanes.  (The 3D deposit always splits a
+// cell's moments over 4 lanes and takes no group.)
 int choose_group(const relsim_ctx *c, int64_t n, KernelKind k = K_OTHER) {
   if (c->p.group) return c->p.group;
   const bool fp64 = c->p.precision == RELSIM_FP64;
   double rounds = 4.0;
   if (k == K_DEPOSIT) rounds = fp64 ? 32.0 : 16.0;
-  if (k == K_PUSH) rounds = fp64 ? 16.0 : 8.0;
-  if (k == K_SCATTER) rounds = (!fp64 && c->kp.dim == 3) ? 2.0 : 4.0;
   const double mean = (double)n / (double)c->kp.ncells;
   int g = k == K_DEPOSIT ? 4 : 8;
   while (g < 64 && 2.0 * g <= mean / rounds) g *= 2;
@@ -476,8 +489,8 @@ int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, cons
   int rc = check_particles(c, pt, resort != 0);
   if (rc) return rc;
   if (!E_theta || !B_n) return fail(c, RELSIM_EINVAL, "null grid array");
-  const int G = choose_group(c, pt->n, K_PUSH);
-  const int Gs = choose_group(c, pt->n, K_SCATTER);
+  const int cells = choose_cells(c, pt->n, K_PUSH);
+  const int cells_s = choose_cells(c, pt->n, K_SCATTER);
   uint8_t *dirc = c->at<uint8_t>(c->L.dirc);
   uint16_t *cnt = c->at<uint16_t>(c->L.cnt);
   uint16_t *pre = c->at<uint16_t>(c->L.pre);
@@ -492,7 +505,7 @@ int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, cons
   // with resort the first pass only counts the moves, and the second pushes
   // again, writing the new state straight into its new place
   timed(c, resort ? "push_count" : "push", [&] {
-    launch_push(c->kp, c->p.precision, G, front(pt), stE, stB, dirc, cnt, err, resort ? 1 : 0,
+    launch_push(c->kp, c->p.precision, cells, front(pt), stE, stB, dirc, cnt, err, resort ? 1 : 0,
                 c->at<char>(c->L.sink), c->st);
   });
   if (resort) {
@@ -501,7 +514,7 @@ int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, cons
       launch_scan(total, pt->bin_start_back, c->kp.nbins, c->at<int32_t>(c->L.scan_tmp), c->st);
     });
     timed(c, "push_scatter", [&] {
-      launch_push_scatter(c->kp, c->p.precision, Gs, front(pt), stE, stB, dirc, pre, pt->bin_start_back, back(pt),
+      launch_push_scatter(c->kp, c->p.precision, cells_s, front(pt), stE, stB, dirc, pre, pt->bin_start_back, back(pt),
                           (int)pt->n, err, new_index, c->at<char>(c->L.sink), c->st);
     });
     rc = launch_status(c, "relsim_push");

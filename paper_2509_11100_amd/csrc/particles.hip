@@ -3,16 +3,20 @@
 // by bin in two passes (count the moves; push again and write each particle
 // in its new place), and the kinetic-energy reduction (S7).
 //
-// Work decomposition shared by the particle kernels: a 64-lane wavefront is
-// split into 64/G lane groups; each group owns one cell and walks that
-// cell's particles (both species, contiguous because particles are sorted
-// by bin = cell * nspecies + species) G at a time, so loads are coalesced
-// and every particle of a group sees the same neighbourhood of grid values.
-// Groups visit the cells tile by tile (2D tiles of up to 16 x 8 cells, 3D of
-// up to 8 x 4 x 4), so that neighbouring cells, whose particles exchange
+// Work decomposition.  The deposit and the kinetic-energy reduction split a
+// 64-lane wavefront into 64/G lane groups; each group owns one cell and walks
+// that cell's particles (both species, contiguous because particles are
+// sorted by bin = cell * nspecies + species) G at a time, so loads are
+// coalesced and every particle of a group sees the same neighbourhood of
+// grid values.  The two push passes instead give a wave a segment of
+// consecutive cells of one grid row and walk its particles 64 at a time
+// across cell boundaries, with the segment's fields staged in LDS (no lane
+// idles because one cell holds more particles than its neighbours).  Cells
+// and segments are visited tile by tile (2D tiles of up to 16 x 8 cells, 3D
+// of up to 8 x 4 x 4), so that neighbouring cells, whose particles exchange
 // places in the re-sort, are processed close together in time; workgroups
 // are remapped so that each XCD (and its L2) works on one contiguous band.
-// The next round's particle loads are issued before the current round is
+// The next rounds' particle loads are issued before the current round is
 // computed.
 //
 // Deposit formulation.  For a particle with in-cell offsets f_d, the CIC
@@ -138,39 +142,31 @@ __device__ __forceinline__ int gidx(const KParams &kp, int i, int j, int k) {
   return (i + 1) + kp.gx * (j + 1) + (DIM == 3 ? kp.gxy * (k + 1) : 0);
 }
 
-// 2D: the 3x3 block of cell-centre B values around the cell with ghosted
+// The 3^DIM block of cell-centre B values around the cell with ghosted
 // index gc, staged in LDS by the G lanes of the cell's group (centre t at
-// column t % 3 - 1, row t / 3 - 1 relative to the cell).  The caller
+// shift (t % 3 - 1, t / 3 % 3 - 1, t / 9 - 1) from the cell).  The caller
 // synchronises the block before the first gather.
-template <typename T, int G>
-__device__ __forceinline__ void stage_B_block_2d(const KParams &kp, const V4<T> *__restrict__ Bs, int gc, int gl,
-                                                 V4<T> *blk) {
+template <typename T, int G, int DIM>
+__device__ __forceinline__ void stage_B_block(const KParams &kp, const V4<T> *__restrict__ Bs, int gc, int gl,
+                                              V4<T> *blk) {
+  constexpr int NB = DIM == 3 ? 27 : 9;
 #pragma unroll
-  for (int t = gl; t < 9; t += G) blk[t] = Bs[gc + (t % 3 - 1) + kp.gx * (t / 3 - 1)];
+  for (int t = gl; t < NB; t += G)
+    blk[t] = Bs[gc + (t % 3 - 1) + kp.gx * ((t / 3) % 3 - 1) + (DIM == 3 ? kp.gxy * (t / 9 - 1) : 0)];
 }
 
 // B at the particle from the 2^DIM cell centres around it (lower corner at
-// shift -1 or 0 per dimension): in 2D from the cell's LDS block, in 3D
-// directly from the ghosted copy.
+// shift -1 or 0 per dimension), read from an LDS block of centres in which
+// bc points at the particle's cell and (sy, sz) are the y and z strides.
 template <typename T, int DIM>
-__device__ __forceinline__ void gather_B(const KParams &kp, const V4<T> *__restrict__ Bs, const V4<T> *blk, int gc,
-                                         T fx, T fy, T fz, T &Bx, T &By, T &Bz) {
+__device__ __forceinline__ void gather_B(const V4<T> *bc, int sy, int sz, T fx, T fy, T fz, T &Bx, T &By,
+                                         T &Bz) {
   constexpr int NCEN = DIM == 3 ? 8 : 4;
   const bool hx = fx >= T(0.5), hy = fy >= T(0.5), hz = DIM == 3 && fz >= T(0.5);
   const T gx = hx ? fx - T(0.5) : fx + T(0.5);
   const T gy = hy ? fy - T(0.5) : fy + T(0.5);
   const T gz = hz ? fz - T(0.5) : fz + T(0.5);
-  const V4<T> *b0;
-  int sy, sz;
-  if constexpr (DIM == 2) {
-    b0 = blk + (hx ? 1 : 0) + (hy ? 3 : 0);
-    sy = 3;
-    sz = 0;
-  } else {
-    b0 = Bs + (gc - (hx ? 0 : 1) - (hy ? 0 : kp.gx) - (hz ? 0 : kp.gxy));
-    sy = kp.gx;
-    sz = kp.gxy;
-  }
+  const V4<T> *const b0 = bc - (hx ? 0 : 1) - (hy ? 0 : sy) - ((DIM == 3 && !hz) ? sz : 0);
 #pragma unroll
   for (int a = 0; a < NCEN; ++a) {
     const V4<T> b = b0[(a & 1) + ((a & 2) ? sy : 0) + ((a & 4) ? sz : 0)];
@@ -318,7 +314,7 @@ __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t 
   const PC<T> pc(kp);
   const size_t NC = (size_t)kp.ncells;
 
-  stage_B_block_2d<T, G>(kp, Bs, cs.gc, gl, bsh[grp]);
+  stage_B_block<T, G, 2>(kp, Bs, cs.gc, gl, bsh[grp]);
   fill_species_table<T>(pc, stab, lane);
   __syncthreads();
   const int pal = cs.pbeg & ~(round_align<T, G>() - 1);
@@ -341,7 +337,7 @@ __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t 
       T qs, bs;
       species_of<T>(kp, pc, cs, p, stab, qs, bs);
       T Bx, By, Bz;
-      gather_B<T, 2>(kp, Bs, bsh[grp], cs.gc, fx, fy, T(0), Bx, By, Bz);
+      gather_B<T, 2>(bsh[grp] + 4, 3, 9, fx, fy, T(0), Bx, By, Bz);
       const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
       const T kb = bs * igb * pc.invc;
       T a[9];
@@ -418,12 +414,14 @@ __global__ __launch_bounds__(64) void k_deposit_split3(KParams kp, const int32_t
   // (P6 P7 P8 -) for the mass lanes [0] and the current lane [1], and Z
   __shared__ V4<T> sh[2][4][64];
   __shared__ T zsh[4][64];
+  __shared__ V4<T> bsh[64 / G][27];
   __shared__ T stab[2][8];
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
   const PC<T> pc(kp);
   const size_t NC = (size_t)kp.ncells;
+  stage_B_block<T, G, 3>(kp, Bs, cs.gc, gl, bsh[grp]);
   fill_species_table<T>(pc, stab, lane);
   __syncthreads();
   const bool isJ = gl == 3;
@@ -452,7 +450,7 @@ __global__ __launch_bounds__(64) void k_deposit_split3(KParams kp, const int32_t
       T qs, bs;
       species_of<T>(kp, pc, cs, p, stab, qs, bs);
       T Bx, By, Bz;
-      gather_B<T, 3>(kp, Bs, nullptr, cs.gc, fx, fy, fz, Bx, By, Bz);
+      gather_B<T, 3>(bsh[grp] + 13, 3, 9, fx, fy, fz, Bx, By, Bz);
       const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
       const T kb = bs * igb * pc.invc;
       T a[9];
@@ -649,27 +647,23 @@ __device__ __forceinline__ T *sink_slot(void *sink, int lane) {
   return reinterpret_cast<T *>(sink) + (((blockIdx.x & (kSinkSlots - 1)) << 6) + lane);
 }
 
-// E_theta at the 2^DIM corner nodes of the cell with ghosted index gc.
-template <typename T, int DIM>
-__device__ __forceinline__ void load_E_corners(const KParams &kp, const V4<T> *__restrict__ Es, int gc,
-                                               T (&Ec)[3][DIM == 3 ? 8 : 4]) {
-#pragma unroll
-  for (int a = 0; a < (DIM == 3 ? 8 : 4); ++a) {
-    const V4<T> e = Es[gc + (a & 1) + ((a & 2) ? kp.gx : 0) + ((a & 4) ? kp.gxy : 0)];
-    Ec[0][a] = e.x;
-    Ec[1][a] = e.y;
-    Ec[2][a] = e.z;
-  }
-}
+// Where a lane finds the fields of its particle's cell: the LDS regions of
+// cell-centre B values and E_theta node values staged for the wave's row
+// segment (see Segment), as pointers to the cell's centre and lower node.
+template <typename T>
+struct CellFields {
+  const V4<T> *bc;  // B at the cell's centre; y and z strides by, bz
+  const V4<T> *e0;  // E_theta at the cell's lower corner node; strides ey, ez
+  int by, bz, ey, ez;
+};
 
-// S6 for one particle of the cell: u^{n+1} = 2 alpha (u^n + beta E_p) - u^n
-// (alpha from B^n at the particle, E_p from the cell's corner values of
-// E_theta) and the offsets advanced by dt u^{n+1} / gamma^{n+1} in cell
-// units, not yet brought back into [0, 1).  Every kernel that pushes calls
-// this one function, so that they all round identically.
+// S6 for one particle: u^{n+1} = 2 alpha (u^n + beta E_p) - u^n (alpha from
+// B^n at the particle, E_p from the cell's corner values of E_theta) and the
+// offsets advanced by dt u^{n+1} / gamma^{n+1} in cell units, not yet brought
+// back into [0, 1).  Every kernel that pushes calls this one function, so
+// that they all round identically.
 template <typename T, int DIM>
-__device__ __forceinline__ void push_one(const KParams &kp, const PC<T> &pc, const V4<T> *__restrict__ Bs,
-                                         const V4<T> *bblk, const T (&Ec)[3][DIM == 3 ? 8 : 4], int gc, T bs,
+__device__ __forceinline__ void push_one(const KParams &kp, const PC<T> &pc, const CellFields<T> &cf, T bs,
                                          const PRec<T> &cur, T &fx, T &fy, T &fz, T &nx, T &ny, T &nz) {
   constexpr int NCORN = DIM == 3 ? 8 : 4;
   fx = cur.fx;
@@ -677,7 +671,7 @@ __device__ __forceinline__ void push_one(const KParams &kp, const PC<T> &pc, con
   fz = DIM == 3 ? cur.fz : T(0);
   const T ux = cur.ux, uy = cur.uy, uz = cur.uz;
   T Bx, By, Bz;
-  gather_B<T, DIM>(kp, Bs, bblk, gc, fx, fy, fz, Bx, By, Bz);
+  gather_B<T, DIM>(cf.bc, cf.by, cf.bz, fx, fy, fz, Bx, By, Bz);
   const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
   const T kb = bs * igb * pc.invc;
   T a[9];
@@ -685,11 +679,12 @@ __device__ __forceinline__ void push_one(const KParams &kp, const PC<T> &pc, con
   T Ex, Ey, Ez;
 #pragma unroll
   for (int c = 0; c < NCORN; ++c) {
+    const V4<T> e = cf.e0[(c & 1) + ((c & 2) ? cf.ey : 0) + ((c & 4) ? cf.ez : 0)];
     T wgt = ((c & 1) ? fx : T(1) - fx) * ((c & 2) ? fy : T(1) - fy);
     if constexpr (DIM == 3) wgt *= (c & 4) ? fz : T(1) - fz;
-    Ex = c == 0 ? wgt * Ec[0][c] : Ex + wgt * Ec[0][c];
-    Ey = c == 0 ? wgt * Ec[1][c] : Ey + wgt * Ec[1][c];
-    Ez = c == 0 ? wgt * Ec[2][c] : Ez + wgt * Ec[2][c];
+    Ex = c == 0 ? wgt * e.x : Ex + wgt * e.x;
+    Ey = c == 0 ? wgt * e.y : Ey + wgt * e.y;
+    Ez = c == 0 ? wgt * e.z : Ez + wgt * e.z;
   }
   const T vx = ux + bs * Ex, vy = uy + bs * Ey, vz = uz + bs * Ez;
   // u^{n+1} = 2 alpha v - u^n, alpha = (numerator a) / (1 + |b|^2)
@@ -706,59 +701,167 @@ __device__ __forceinline__ void push_one(const KParams &kp, const PC<T> &pc, con
   if constexpr (DIM == 3) fz += dtg * nz * pc.idz;
 }
 
+// ---------------------------------------------------------------------------
+// Push passes: a flat walk over a row segment.
+// A wave owns C consecutive cells of one grid row (C divides nx) and walks
+// their particles, contiguous in memory because they are sorted by bin, 64
+// at a time across cell boundaries.  Lanes are not tied to a cell, so a cell
+// holding more particles than the others costs no idle lanes (with a lane
+// group per cell, a wave's rounds are set by its fullest cell).  The wave
+// first stages in LDS what its particles can touch: the starts of the
+// segment's C * nspecies bins, the cell-centre B values around the segment,
+// the E_theta node values of the segment and the species table; a lane
+// finds its particle's bin by a binary search over the bin starts.
+// ---------------------------------------------------------------------------
+template <typename T, int DIM>
+struct Segment {
+  int C, nb;         // cells and bins of the segment
+  int c0, i0, j, k;  // first cell and its coordinates
+  V4<T> *Bg;         // (C + 2) x 3 [x 3] cell centres from (i0 - 1, j - 1, k - 1), x fastest
+  V4<T> *Eg;         // (C + 1) x 2 [x 2] nodes from (i0, j, k)
+  T (*stab)[8];      // species charge and beta
+  int *binb;         // nb + 1 bin starts
+  int *keys;         // nb x NDIR counters (counting pass) or run bases (scatter)
+};
+
+// LDS bytes of a segment of C cells with S species.
+template <typename T, int DIM>
+__host__ __device__ constexpr size_t segment_lds_bytes(int C, int S) {
+  return sizeof(V4<T>) * ((size_t)(C + 2) * 3 * (DIM == 3 ? 3 : 1) + (size_t)(C + 1) * 2 * (DIM == 3 ? 2 : 1)) +
+         sizeof(T) * 16 + sizeof(int) * ((size_t)C * S + 1) + sizeof(int) * (size_t)C * S * (DIM == 3 ? 27 : 9);
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ Segment<T, DIM> stage_segment(const KParams &kp, int C, int wave, const PC<T> &pc,
+                                                         const int32_t *__restrict__ bin_start,
+                                                         const V4<T> *__restrict__ Es, const V4<T> *__restrict__ Bs,
+                                                         unsigned char *smem, int lane) {
+  Segment<T, DIM> sg;
+  const int S = kp.nspecies;
+  sg.C = C;
+  sg.nb = C * S;
+  // segments are visited tile by tile (tiles of max(tx, C) x ty x tz cells,
+  // segments row-major inside a tile), as the other particle kernels visit
+  // cells: the destinations of neighbouring sources are then written close
+  // together in time
+  const int TX = C > kp.tx ? C : kp.tx;
+  const int spr = TX / C, per_tile = spr * kp.ty * kp.tz;
+  const int tile = wave / per_tile, r = wave - tile * per_tile;
+  const int ntx = kp.nx / TX, nty = kp.ny / kp.ty;
+  const int t2 = tile / ntx;
+  sg.i0 = (tile - t2 * ntx) * TX + (r % spr) * C;
+  sg.j = (t2 % nty) * kp.ty + (r / spr) % kp.ty;
+  sg.k = DIM == 3 ? (t2 / nty) * kp.tz + r / (spr * kp.ty) : 0;
+  sg.c0 = sg.i0 + kp.nx * (sg.j + kp.ny * sg.k);
+  const int W = C + 2, nB = W * 3 * (DIM == 3 ? 3 : 1), nE = (C + 1) * 2 * (DIM == 3 ? 2 : 1);
+  sg.Bg = reinterpret_cast<V4<T> *>(smem);
+  sg.Eg = sg.Bg + nB;
+  sg.stab = reinterpret_cast<T(*)[8]>(sg.Eg + nE);
+  sg.binb = reinterpret_cast<int *>(sg.stab + 2);
+  sg.keys = sg.binb + sg.nb + 1;
+  // centre (i0 - 1 + a, j - 1 + b, k - 1 + c) sits at ghosted index
+  // (i0 + a) + gx (j + b) + gxy (k + c)
+  for (int t = lane; t < nB; t += 64) {
+    const int a = t % W, bc = t / W, b = bc % 3, c = bc / 3;
+    sg.Bg[t] = Bs[(sg.i0 + a) + kp.gx * (sg.j + b) + (DIM == 3 ? kp.gxy * (sg.k + c) : 0)];
+  }
+  for (int t = lane; t < nE; t += 64) {
+    const int a = t % (C + 1), bc = t / (C + 1), b = bc % 2, c = bc / 2;
+    sg.Eg[t] = Es[gidx<DIM>(kp, sg.i0 + a, sg.j + b, sg.k + c)];
+  }
+  for (int t = lane; t <= sg.nb; t += 64) sg.binb[t] = bin_start[sg.c0 * S + t];
+  fill_species_table<T>(pc, sg.stab, lane);
+  return sg;
+}
+
+// Bin (within the segment) of particle p, binb[0] <= p < binb[nb]: the last
+// b with binb[b] <= p, by binary search over the staged bin starts.
+__device__ __forceinline__ int segment_bin(const int *binb, int nb, int p) {
+  int lo = 0;
+  for (int step = nb > 1 ? 1 << (31 - __builtin_clz((unsigned)(nb - 1))) : 0; step > 0; step >>= 1) {
+    const int m = lo + step;
+    lo = (m < nb && binb[m] <= p) ? m : lo;
+  }
+  return lo;
+}
+
+// Charge and beta of species s: selected between values for two species
+// (the compiler may turn a select of two loads into one load from a
+// selected address), else from the LDS table.
+template <typename T>
+__device__ __forceinline__ void species_consts(int S, int s, T q0, T q1, T b0, T b1, const T (*tab)[8], T &q,
+                                               T &beta) {
+  if (S == 2) {
+    q = s ? q1 : q0;
+    beta = s ? b1 : b0;
+  } else {
+    q = tab[0][s];
+    beta = tab[1][s];
+  }
+}
+
+// Where the lane's particle finds its fields: cell lc of the segment.
+template <typename T, int DIM>
+__device__ __forceinline__ CellFields<T> segment_fields(const Segment<T, DIM> &sg, int lc) {
+  CellFields<T> cf;
+  cf.by = sg.C + 2;
+  cf.bz = 3 * (sg.C + 2);
+  cf.ey = sg.C + 1;
+  cf.ez = 2 * (sg.C + 1);
+  cf.bc = sg.Bg + (lc + 1) + cf.by + (DIM == 3 ? cf.bz : 0);
+  cf.e0 = sg.Eg + lc;
+  return cf;
+}
+
 // Push pass.  COUNT: the first pass of the re-sort; the particles are only
 // read: each one's move (dirc) and the per-(bin, move) counts are written,
 // and k_push_scatter later recomputes the push and writes the new state in
 // the new order.  !COUNT: push in place with no re-sort; offsets stay
 // relative to the old cell, in [-1, 2).
-template <typename T, int DIM, int G, bool COUNT>
-__global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restrict__ bin_start,
+template <typename T, int DIM, bool COUNT>
+__global__ __launch_bounds__(64) void k_push(KParams kp, int C, const int32_t *__restrict__ bin_start,
                                              V2<T> *__restrict__ xy, V4<T> *__restrict__ uw, T *__restrict__ zz,
-                                             const V4<T> *__restrict__ Es,
-                                             const V4<T> *__restrict__ Bs, uint8_t *__restrict__ dirc,
-                                             uint16_t *__restrict__ cnt, int32_t *__restrict__ err,
-                                             void *__restrict__ sink) {
+                                             const V4<T> *__restrict__ Es, const V4<T> *__restrict__ Bs,
+                                             uint8_t *__restrict__ dirc, uint16_t *__restrict__ cnt,
+                                             int32_t *__restrict__ err, void *__restrict__ sink) {
   constexpr int NDIR = DIM == 3 ? 27 : 9;
-  constexpr int NK = 8 * NDIR;  // (species, move) keys per group
-  constexpr int NGRP = 64 / G;
-  __shared__ uint32_t lcnt[COUNT ? NGRP * NK : 1];
-  __shared__ V4<T> bsh[DIM == 2 ? NGRP : 1][9];
-  __shared__ T stab[2][8];
-  const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
+  extern __shared__ __attribute__((aligned(32))) unsigned char smem[];
+  const int lane = threadIdx.x;
   const PC<T> pc(kp);
+  const Segment<T, DIM> sg =
+      stage_segment<T, DIM>(kp, C, xcd_remap(blockIdx.x, gridDim.x), pc, bin_start, Es, Bs, smem, lane);
+  if constexpr (COUNT)
+    for (int t = lane; t < sg.nb * NDIR; t += 64) sg.keys[t] = 0;
+  __syncthreads();
+  const int S = kp.nspecies;
+  const T sq0 = pc.q0, sq1 = pc.q1, sb0 = pc.b0, sb1 = pc.b1;
   T *const sinkT = sink_slot<T>(sink, lane);
   uint8_t *const sinkB = sink_slot<uint8_t>(sink, lane);
-  if constexpr (COUNT)
-    for (int t = lane; t < NGRP * NK; t += 64) lcnt[t] = 0u;
-  const V4<T> *const bblk = DIM == 2 ? bsh[grp] : nullptr;
-  if constexpr (DIM == 2) stage_B_block_2d<T, G>(kp, Bs, cs.gc, gl, bsh[grp]);
-  fill_species_table<T>(pc, stab, lane);
-  __syncthreads();
-  T Ec[3][DIM == 3 ? 8 : 4];
-  load_E_corners<T, DIM>(kp, Es, cs.gc, Ec);
-  const int pal = cs.pbeg & ~(round_align<T, G>() - 1);
-  const int rounds = wave_rounds<G>(cs.pend - pal);
+  const int p0 = __builtin_amdgcn_readfirstlane(sg.binb[0]);
+  const int p1 = __builtin_amdgcn_readfirstlane(sg.binb[sg.nb]);
+  // rounds start on 64-byte boundaries (lanes before p0 idle)
+  const int pal = p0 & ~(round_align<T, 64>() - 1);
+  const int rounds = __builtin_amdgcn_readfirstlane(p1 > p0 ? (p1 - pal + 63) >> 6 : 0);
   PRec<T> cur{}, nxt{};
-  int p = pal + gl;
+  int p = pal + lane;
   int bad = 0;
-  if (rounds > 0) load_rec<T, DIM>(p, cs.pend, xy, uw, zz, cur);
+  if (rounds > 0) load_rec<T, DIM>(p, p1, xy, uw, zz, cur);
   // enter the loop with nothing in flight, so the loop's waits only count
   // its own loads and stores
   __builtin_amdgcn_s_waitcnt(0);
-
 #pragma unroll 2
   for (int r = 0; r < rounds; ++r) {
-    const int pn = p + G;
-    load_rec<T, DIM>(pn, cs.pend, xy, uw, zz, nxt);
-    // lanes past the end compute on a copy of a valid particle (finite
-    // values) and store into the sink
-    const bool pv = p >= cs.pbeg && p < cs.pend;
+    const int pn = p + 64;
+    load_rec<T, DIM>(pn, p1, xy, uw, zz, nxt);
+    // lanes outside [p0, p1) compute on a valid particle's copy and store
+    // into the sink
+    const bool pv = p >= p0 && p < p1;
+    const int b = segment_bin(sg.binb, sg.nb, min(max(p, p0), p1 - 1));
+    const int lc = S == 2 ? b >> 1 : b / S, s = b - lc * S;
     T qs, bs;
-    const int s = species_of<T>(kp, pc, cs, p, stab, qs, bs);
+    species_consts<T>(S, s, sq0, sq1, sb0, sb1, sg.stab, qs, bs);
     T fx, fy, fz, nx, ny, nz;
-    push_one<T, DIM>(kp, pc, Bs, bblk, Ec, cs.gc, bs, cur, fx, fy, fz, nx, ny, nz);
+    push_one<T, DIM>(kp, pc, segment_fields(sg, lc), bs, cur, fx, fy, fz, nx, ny, nz);
     if constexpr (COUNT) {
       int flag = 0;
       const int mx = cross_cell<T>(fx, flag);
@@ -767,7 +870,7 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
       bad |= pv ? flag : 0;
       const int dir = (mx + 1) + 3 * (my + 1) + (DIM == 3 ? 9 * (mz + 1) : 0);
       *(pv ? dirc + p : sinkB) = (uint8_t)dir;
-      if (pv) atomicAdd(&lcnt[grp * NK + s * NDIR + dir], 1u);  // integer: order-independent
+      if (pv) atomicAdd(&sg.keys[b * NDIR + dir], 1);  // integer: order-independent
     } else {
       // no re-sort: offsets stay relative to the old cell, in [-1, 2)
       bool ok = fx >= T(-1) && fx < T(2) && fy >= T(-1) && fy < T(2);
@@ -791,14 +894,13 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, const int32_t *__restri
   if (__ballot(bad) && lane == 0) atomicOr(err, 1);
   if constexpr (COUNT) {
     __syncthreads();
-    if (cs.valid) {
-      const int S = kp.nspecies;
-      for (int t = gl; t < S * NDIR; t += G) {
-        const int s = t / NDIR, dir = t % NDIR;
-        const uint32_t v = lcnt[grp * NK + s * NDIR + dir];
-        if (v > 65535u) atomicOr(err, 2);  // a move class beyond the 16-bit counters
-        cnt[(size_t)dir * kp.nbins + (size_t)cs.cell * S + s] = (uint16_t)(v > 65535u ? 65535u : v);
-      }
+    // counts out in [move][bin] order, consecutive bins per move
+    const size_t nbins = (size_t)kp.nbins;
+    for (int t = lane; t < sg.nb * NDIR; t += 64) {
+      const int dir = t / sg.nb, bin = t - dir * sg.nb;
+      const int v = sg.keys[bin * NDIR + dir];
+      if (v > 65535) atomicOr(err, 2);  // a move class beyond the 16-bit counters
+      cnt[(size_t)dir * nbins + (size_t)sg.c0 * S + bin] = (uint16_t)(v > 65535 ? 65535 : v);
     }
   }
 }
@@ -845,29 +947,28 @@ __global__ __launch_bounds__(256) void k_sort_offsets(KParams kp, const uint16_t
   total[d] = run;
 }
 
-// One round of the pushing scatter for particle p of the lane's cell, on
+// One round of the pushing scatter for particle p of the segment, on
 // record buffer (cur, dc), which it then refills with the round three
 // ahead; see k_push_scatter.
-template <typename T, int DIM, int G, bool PERM>
-__device__ __forceinline__ void scatter_round(const KParams &kp, const PC<T> &pc, const CellSpan &cs,
-                                              const V4<T> *__restrict__ Bs, const V4<T> *bblk,
-                                              const T (&Ec)[3][DIM == 3 ? 8 : 4], int lane, int grp, int nkey,
-                                              int kbits, unsigned long long lt, int *lbase, int ntot,
+template <typename T, int DIM, bool PERM>
+__device__ __forceinline__ void scatter_round(const KParams &kp, const PC<T> &pc, const Segment<T, DIM> &sg,
+                                              int p1, int lane, unsigned long long lt, int ntot,
                                               const V2<T> *__restrict__ xy, const V4<T> *__restrict__ uw,
                                               const T *__restrict__ zz, const uint8_t *__restrict__ dirc,
                                               V2<T> *__restrict__ xo, V4<T> *__restrict__ uo, T *__restrict__ zo,
                                               int32_t *__restrict__ perm, void *__restrict__ sink, T q0, T q1,
-                                              T b0, T b1, const T *qt, const T *bt, int &p, int &bad,
-                                              PRec<T> &cur, uint8_t &dc) {
+                                              T b0, T b1, int &p, int &bad, PRec<T> &cur, uint8_t &dc) {
   constexpr int NDIR = DIM == 3 ? 27 : 9;
-  T *const sinkT = sink_slot<T>(sink, lane);
-  int32_t *const sinkI = sink_slot<int32_t>(sink, lane);
+  constexpr int DBITS = DIM == 3 ? 5 : 4;  // bits of a move code
+  const int S = kp.nspecies;
   const int dcur = dc;
-  const bool pv = p < cs.pend;
+  const bool pv = p < p1;
+  const int b = segment_bin(sg.binb, sg.nb, min(p, p1 - 1));
+  const int lc = S == 2 ? b >> 1 : b / S, s = b - lc * S;
   T qs, bs;
-  const int s = species_sel<T>(kp, cs, p, q0, q1, b0, b1, qt, bt, qs, bs);
+  species_consts<T>(S, s, q0, q1, b0, b1, sg.stab, qs, bs);
   T fx, fy, fz, nx, ny, nz;
-  push_one<T, DIM>(kp, pc, Bs, bblk, Ec, cs.gc, bs, cur, fx, fy, fz, nx, ny, nz);
+  push_one<T, DIM>(kp, pc, segment_fields(sg, lc), bs, cur, fx, fy, fz, nx, ny, nz);
   // the new state goes where the counting pass counted it (move dcur),
   // with its offsets taken relative to that cell
   int off = 0;
@@ -875,24 +976,26 @@ __device__ __forceinline__ void scatter_round(const KParams &kp, const PC<T> &pc
   fy = place_offset<T>(fy, (dcur / 3) % 3 - 1, off);
   if constexpr (DIM == 3) fz = place_offset<T>(fz, dcur / 9 - 1, off);
   bad |= (pv && off) ? 4 : 0;
-  const int key = pv ? grp * nkey + s * NDIR + dcur : 0;
-  // lanes of this round holding the same key
-  const unsigned long long act = __ballot(pv);
-  uint32_t same_lo = (uint32_t)act, same_hi = (uint32_t)(act >> 32);
-#pragma unroll 1
-  for (int b = 0; b < kbits; ++b) {
-    const bool bit = (key >> b) & 1;
-    const unsigned long long ones = __ballot(bit);
-    const uint32_t lo = (uint32_t)ones, hi = (uint32_t)(ones >> 32);
-    same_lo &= bit ? lo : ~lo;
-    same_hi &= bit ? hi : ~hi;
+  // lanes of this round with the same (bin, move) key: the bin's particles
+  // occupy the contiguous lanes [f, l) of the round, so only the move code
+  // needs matching, one ballot per bit
+  const int rb = p - lane;
+  const int f = sg.binb[b] - rb, l = sg.binb[b + 1] - rb;
+  const unsigned long long fmask = f <= 0 ? ~0ull : (~0ull << f);
+  const unsigned long long lmask = l <= 0 ? 0ull : (l >= 64 ? ~0ull : ((1ull << l) - 1ull));
+  unsigned long long same = __ballot(pv) & fmask & lmask;
+#pragma unroll
+  for (int bit = 0; bit < DBITS; ++bit) {
+    const bool on = (dcur >> bit) & 1;
+    const unsigned long long ones = __ballot(on);
+    same &= on ? ones : ~ones;
   }
-  const unsigned long long same = ((unsigned long long)same_hi << 32) | same_lo;
+  const int key = pv ? b * NDIR + dcur : 0;
   int pos = 0;
-  if (pv) pos = lbase[key] + __popcll(same & lt);
+  if (pv) pos = sg.keys[key] + __popcll(same & lt);
   __builtin_amdgcn_wave_barrier();
   // the highest lane of each key advances that key's base
-  if (pv && (same >> lane) == 1ull) lbase[key] += __popcll(same);
+  if (pv && (same >> lane) == 1ull) sg.keys[key] += __popcll(same);
   // only reachable out of range when a bin overflowed the 16-bit
   // counters (flagged); lanes past the end store into the sink
   const bool ok = pv && pos >= 0 && pos < ntot;
@@ -907,28 +1010,28 @@ __device__ __forceinline__ void scatter_round(const KParams &kp, const PC<T> &pc
   uv.w = cur.w;
   *(ok ? xo + pos : sink_slot<V2<T>>(sink, lane)) = xv;
   *(ok ? uo + pos : sink_slot<V4<T>>(sink, lane)) = uv;
-  if constexpr (DIM == 3) *(ok ? zo + pos : sinkT) = fz;
-  if constexpr (PERM) *(ok ? perm + p : sinkI) = pos;
+  if constexpr (DIM == 3) *(ok ? zo + pos : sink_slot<T>(sink, lane)) = fz;
+  if constexpr (PERM) *(ok ? perm + p : sink_slot<int32_t>(sink, lane)) = pos;
   __builtin_amdgcn_wave_barrier();
-  load_rec<T, DIM>(p + 3 * G, cs.pend, xy, uw, zz, cur);
-  dc = dirc[load_index(p + 3 * G, cs.pend)];
-  p += G;
+  load_rec<T, DIM>(p + 3 * 64, p1, xy, uw, zz, cur);
+  dc = dirc[load_index(p + 3 * 64, p1)];
+  p += 64;
 }
 
 // ---------------------------------------------------------------------------
 // re-sort, step 3: push again and scatter, stably, into the back buffers.
-// Each lane group first resolves, for each (species, move) key of its cell,
-// where that class's run starts in the new order (new bin start + offset of
-// this source cell among the bin's sources).  In the loop every particle is
+// The wave walks its row segment as the counting pass did.  It first
+// resolves, for every (bin, move) key of the segment, where that class's run
+// starts in the new order (new bin start of the destination + offset of this
+// source among the destination's sources).  In the loop every particle is
 // pushed once more (push_one, as in the counting pass; its offsets are
 // taken relative to the cell of the recorded move, see place_offset), and
 // its new state is written at that base plus its rank among the same-key
-// lanes of earlier rounds and lower lanes of this round, found from one
-// ballot per key bit.  The particle state is thus read twice and written
-// once per step.
+// lanes of earlier rounds and lower lanes of this round.  The particle state
+// is thus read twice and written once per step.
 // ---------------------------------------------------------------------------
-template <typename T, int DIM, int G, bool PERM>
-__global__ __launch_bounds__(64) void k_push_scatter(KParams kp, const int32_t *__restrict__ bin_start,
+template <typename T, int DIM, bool PERM>
+__global__ __launch_bounds__(64) void k_push_scatter(KParams kp, int C, const int32_t *__restrict__ bin_start,
                                                      const V2<T> *__restrict__ xy,
                                                      const V4<T> *__restrict__ uw, const T *__restrict__ zz,
                                                      const V4<T> *__restrict__ Es, const V4<T> *__restrict__ Bs,
@@ -939,36 +1042,27 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, const int32_t *
                                                      int32_t *__restrict__ err,
                                                      int32_t *__restrict__ perm, void *__restrict__ sink) {
   constexpr int NDIR = DIM == 3 ? 27 : 9;
-  constexpr int NGRP = 64 / G;
-  __shared__ int lbase[NGRP * 8 * NDIR];  // next destination of each (group, species, move) key
-  __shared__ V4<T> bsh[DIM == 2 ? NGRP : 1][9];
-  __shared__ T stab[2][8];
-  const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
+  extern __shared__ __attribute__((aligned(32))) unsigned char smem[];
+  const int lane = threadIdx.x;
   const PC<T> pc(kp);
-  const int S = kp.nspecies, nkey = S * NDIR;
-  fill_species_table<T>(pc, stab, lane);
-  const size_t nb = (size_t)kp.nbins;
-  if (cs.valid) {
-    for (int t = gl; t < nkey; t += G) {
-      const int s = t / NDIR, dir = t - s * NDIR;
-      const int mx = dir % 3 - 1, my = (dir / 3) % 3 - 1, mz = dir / 9 - 1;
-      const int dc = wrapi(cs.ci + mx, kp.nx) +
-                     kp.nx * (wrapi(cs.cj + my, kp.ny) + kp.ny * (DIM == 3 ? wrapi(cs.ck + mz, kp.nz) : 0));
-      const int d = dc * S + s;
-      lbase[grp * nkey + t] = bsn[d] + (int)pre[(size_t)dir * nb + d];
-    }
+  const Segment<T, DIM> sg =
+      stage_segment<T, DIM>(kp, C, xcd_remap(blockIdx.x, gridDim.x), pc, bin_start, Es, Bs, smem, lane);
+  const int S = kp.nspecies;
+  const size_t nbins = (size_t)kp.nbins;
+  for (int t = lane; t < sg.nb * NDIR; t += 64) {
+    const int bin = t / NDIR, dir = t - bin * NDIR;
+    const int lc = bin / S, s = bin - lc * S;
+    const int mx = dir % 3 - 1, my = (dir / 3) % 3 - 1, mz = dir / 9 - 1;
+    const int dc = wrapi(sg.i0 + lc + mx, kp.nx) +
+                   kp.nx * (wrapi(sg.j + my, kp.ny) + kp.ny * (DIM == 3 ? wrapi(sg.k + mz, kp.nz) : 0));
+    const int d = dc * S + s;
+    sg.keys[t] = bsn[d] + (int)pre[(size_t)dir * nbins + d];
   }
-  const V4<T> *const bblk = DIM == 2 ? bsh[grp] : nullptr;
-  if constexpr (DIM == 2) stage_B_block_2d<T, G>(kp, Bs, cs.gc, gl, bsh[grp]);
-  T Ec[3][DIM == 3 ? 8 : 4];
-  load_E_corners<T, DIM>(kp, Es, cs.gc, Ec);
   __syncthreads();
-  // key bits: keys are grp * nkey + species * NDIR + move < NGRP * nkey
-  const int kbits = 32 - __builtin_clz((unsigned)(NGRP * nkey - 1) | 1u);
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int rounds = wave_rounds<G>(cs.pend - cs.pbeg);
+  const int p0 = __builtin_amdgcn_readfirstlane(sg.binb[0]);
+  const int p1 = __builtin_amdgcn_readfirstlane(sg.binb[sg.nb]);
+  const int rounds = __builtin_amdgcn_readfirstlane(p1 > p0 ? (p1 - p0 + 63) >> 6 : 0);
   // Three record buffers in rotation: while one round is pushed and
   // stored, the loads of the next two are in flight.  Each round refills
   // its own buffer with the round three ahead once it has been used, so no
@@ -978,22 +1072,22 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, const int32_t *
   // last one or two rounds follow it.
   PRec<T> rb0{}, rb1{}, rb2{};
   uint8_t db0 = 0, db1 = 0, db2 = 0;
-  int p = cs.pbeg + gl, bad = 0;
+  int p = p0 + lane, bad = 0;
   if (rounds > 0) {
-    load_rec<T, DIM>(p, cs.pend, xy, uw, zz, rb0);
-    db0 = dirc[load_index(p, cs.pend)];
-    load_rec<T, DIM>(p + G, cs.pend, xy, uw, zz, rb1);
-    db1 = dirc[load_index(p + G, cs.pend)];
-    load_rec<T, DIM>(p + 2 * G, cs.pend, xy, uw, zz, rb2);
-    db2 = dirc[load_index(p + 2 * G, cs.pend)];
+    load_rec<T, DIM>(p, p1, xy, uw, zz, rb0);
+    db0 = dirc[load_index(p, p1)];
+    load_rec<T, DIM>(p + 64, p1, xy, uw, zz, rb1);
+    db1 = dirc[load_index(p + 64, p1)];
+    load_rec<T, DIM>(p + 128, p1, xy, uw, zz, rb2);
+    db2 = dirc[load_index(p + 128, p1)];
   }
   // enter the loop with nothing in flight, so that the waits in the loop
   // count only the loop's own loads and stores
   __builtin_amdgcn_s_waitcnt(0);
-#define RELSIM_SCATTER_ROUND(rb, db)                                                                          \
-  scatter_round<T, DIM, G, PERM>(kp, pc, cs, Bs, bblk, Ec, lane, grp, nkey, kbits, lt, lbase, ntot, xy, uw, zz, \
-                                 dirc, xo, uo, zo, perm, sink, sq0, sq1, sb0, sb1, stab[0], stab[1], p, bad, rb, db)
   const T sq0 = pc.q0, sq1 = pc.q1, sb0 = pc.b0, sb1 = pc.b1;
+#define RELSIM_SCATTER_ROUND(rb, db)                                                                            \
+  scatter_round<T, DIM, PERM>(kp, pc, sg, p1, lane, lt, ntot, xy, uw, zz, dirc, xo, uo, zo, perm, sink, sq0, sq1, \
+                              sb0, sb1, p, bad, rb, db)
   int r = 0;
 #pragma unroll 1
   for (; r + 3 <= rounds; r += 3) {
@@ -1149,29 +1243,32 @@ void deposit3_impl(const KParams &kp, const PartPtrs &pp, const void *Bst, void 
                      cp<V4<T>>(pp.uw), cp<T>(pp.z), cp<V4<T>>(Bst), mp<T>(S));
 }
 
-template <typename T, int DIM, int G>
-void push_impl(const KParams &kp, const PartPtrs &pp, const void *Est, const void *Bst, uint8_t *dirc,
+template <typename T, int DIM>
+void push_impl(const KParams &kp, int C, const PartPtrs &pp, const void *Est, const void *Bst, uint8_t *dirc,
                uint16_t *cnt, int32_t *err, int count_moves, void *sink, hipStream_t st) {
-  const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
+  const int nblk = kp.ncells / C;
+  const size_t lds = segment_lds_bytes<T, DIM>(C, kp.nspecies);
   if (count_moves)
-    hipLaunchKernelGGL((k_push<T, DIM, G, true>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, mp<V2<T>>(pp.xy),
+    hipLaunchKernelGGL((k_push<T, DIM, true>), dim3(nblk), dim3(64), lds, st, kp, C, pp.bin_start, mp<V2<T>>(pp.xy),
                        mp<V4<T>>(pp.uw), mp<T>(pp.z), cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, cnt, err, sink);
   else
-    hipLaunchKernelGGL((k_push<T, DIM, G, false>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, mp<V2<T>>(pp.xy),
-                       mp<V4<T>>(pp.uw), mp<T>(pp.z), cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, cnt, err, sink);
+    hipLaunchKernelGGL((k_push<T, DIM, false>), dim3(nblk), dim3(64), lds, st, kp, C, pp.bin_start,
+                       mp<V2<T>>(pp.xy), mp<V4<T>>(pp.uw), mp<T>(pp.z), cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, cnt,
+                       err, sink);
 }
 
-template <typename T, int DIM, int G>
-void scatter_impl(const KParams &kp, const PartPtrs &src, const void *Est, const void *Bst, const uint8_t *dirc,
-                  const uint16_t *pre, const int32_t *bsn, const PartPtrs &out, int ntot, int32_t *err, int32_t *perm,
-                  void *sink, hipStream_t st) {
-  const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
+template <typename T, int DIM>
+void scatter_impl(const KParams &kp, int C, const PartPtrs &src, const void *Est, const void *Bst,
+                  const uint8_t *dirc, const uint16_t *pre, const int32_t *bsn, const PartPtrs &out, int ntot,
+                  int32_t *err, int32_t *perm, void *sink, hipStream_t st) {
+  const int nblk = kp.ncells / C;
+  const size_t lds = segment_lds_bytes<T, DIM>(C, kp.nspecies);
   if (perm)
-    hipLaunchKernelGGL((k_push_scatter<T, DIM, G, true>), dim3(nblk), dim3(64), 0, st, kp, src.bin_start,
+    hipLaunchKernelGGL((k_push_scatter<T, DIM, true>), dim3(nblk), dim3(64), lds, st, kp, C, src.bin_start,
                        cp<V2<T>>(src.xy), cp<V4<T>>(src.uw), cp<T>(src.z), cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, pre,
                        bsn, mp<V2<T>>(out.xy), mp<V4<T>>(out.uw), mp<T>(out.z), ntot, err, perm, sink);
   else
-    hipLaunchKernelGGL((k_push_scatter<T, DIM, G, false>), dim3(nblk), dim3(64), 0, st, kp, src.bin_start,
+    hipLaunchKernelGGL((k_push_scatter<T, DIM, false>), dim3(nblk), dim3(64), lds, st, kp, C, src.bin_start,
                        cp<V2<T>>(src.xy), cp<V4<T>>(src.uw), cp<T>(src.z), cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, pre,
                        bsn, mp<V2<T>>(out.xy), mp<V4<T>>(out.uw), mp<T>(out.z), ntot, err, perm, sink);
 }
@@ -1198,16 +1295,6 @@ void dispatch(int prec, int dim, int group, A &&...args) {
 #undef RELSIM_CASE
 }
 
-template <typename T, int D, int G>
-struct PushF {
-  template <typename... A>
-  static void run(A &&...a) { push_impl<T, D, G>(a...); }
-};
-template <typename T, int D, int G>
-struct ScatterF {
-  template <typename... A>
-  static void run(A &&...a) { scatter_impl<T, D, G>(a...); }
-};
 template <typename T, int D, int G>
 struct KineticF {
   template <typename... A>
@@ -1259,9 +1346,21 @@ void launch_assemble(const KParams &kp, int prec, const void *S, double *J, doub
   }
 }
 
-void launch_push(const KParams &kp, int prec, int group, const PartPtrs &pp, const void *Est, const void *Bst,
+size_t push_lds_bytes(const KParams &kp, int prec, int cells) {
+  const bool f = prec == RELSIM_MIXED;
+  if (kp.dim == 3)
+    return f ? segment_lds_bytes<float, 3>(cells, kp.nspecies) : segment_lds_bytes<double, 3>(cells, kp.nspecies);
+  return f ? segment_lds_bytes<float, 2>(cells, kp.nspecies) : segment_lds_bytes<double, 2>(cells, kp.nspecies);
+}
+
+void launch_push(const KParams &kp, int prec, int cells, const PartPtrs &pp, const void *Est, const void *Bst,
                  uint8_t *dirc, uint16_t *cnt, int32_t *err, int count_moves, void *sink, hipStream_t st) {
-  dispatch<PushF>(prec, kp.dim, group, kp, pp, Est, Bst, dirc, cnt, err, count_moves, sink, st);
+  const bool f = prec == RELSIM_MIXED;
+  if (kp.dim == 3)
+    return f ? push_impl<float, 3>(kp, cells, pp, Est, Bst, dirc, cnt, err, count_moves, sink, st)
+             : push_impl<double, 3>(kp, cells, pp, Est, Bst, dirc, cnt, err, count_moves, sink, st);
+  return f ? push_impl<float, 2>(kp, cells, pp, Est, Bst, dirc, cnt, err, count_moves, sink, st)
+           : push_impl<double, 2>(kp, cells, pp, Est, Bst, dirc, cnt, err, count_moves, sink, st);
 }
 
 void launch_sort_offsets(const KParams &kp, const uint16_t *cnt, uint16_t *pre, int32_t *total, int32_t *err,
@@ -1282,11 +1381,18 @@ void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream
   if (nb > 1) hipLaunchKernelGGL(k_scan_add, dim3((n + 255) / 256), dim3(256), 0, st, out, n, tmp);
 }
 
-void launch_push_scatter(const KParams &kp, int prec, int group, const PartPtrs &src, const void *Est,
+void launch_push_scatter(const KParams &kp, int prec, int cells, const PartPtrs &src, const void *Est,
                          const void *Bst, const uint8_t *dirc, const uint16_t *pre, const int32_t *bin_start_new,
                          const PartPtrs &out, int ntot, int32_t *err, int32_t *perm, void *sink, hipStream_t st) {
-  dispatch<ScatterF>(prec, kp.dim, group, kp, src, Est, Bst, dirc, pre, bin_start_new, out, ntot, err, perm, sink,
-                     st);
+  const bool f = prec == RELSIM_MIXED;
+  if (kp.dim == 3)
+    return f ? scatter_impl<float, 3>(kp, cells, src, Est, Bst, dirc, pre, bin_start_new, out, ntot, err, perm, sink,
+                                      st)
+             : scatter_impl<double, 3>(kp, cells, src, Est, Bst, dirc, pre, bin_start_new, out, ntot, err, perm,
+                                       sink, st);
+  return f ? scatter_impl<float, 2>(kp, cells, src, Est, Bst, dirc, pre, bin_start_new, out, ntot, err, perm, sink, st)
+           : scatter_impl<double, 2>(kp, cells, src, Est, Bst, dirc, pre, bin_start_new, out, ntot, err, perm, sink,
+                                     st);
 }
 
 void launch_fill_cells(const KParams &kp, const int32_t *bin_start, int32_t *cell, hipStream_t st) {

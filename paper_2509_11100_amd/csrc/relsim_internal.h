@@ -73,9 +73,12 @@ void launch_deposit_cells(const KParams &kp, int prec, int group, const PartPtrs
 void launch_assemble(const KParams &kp, int prec, const void *S, double *J, double *M, hipStream_t st);
 // `sink`: kSinkSlots * 64 * 32 bytes of workspace that lanes without a
 // particle store into (contents meaningless)
+// The push passes give each wave `cells` consecutive cells of one grid row
+// (a power of two dividing nx); push_lds_bytes is the LDS one wave stages.
 // count_moves: only read the particles and write each one's move (dirc) and
 // the per-(move, bin) counts (first pass of the re-sort); else push in place
-void launch_push(const KParams &kp, int prec, int group, const PartPtrs &pp, const void *Est, const void *Bst,
+size_t push_lds_bytes(const KParams &kp, int prec, int cells);
+void launch_push(const KParams &kp, int prec, int cells, const PartPtrs &pp, const void *Est, const void *Bst,
                  uint8_t *dirc, uint16_t *cnt, int32_t *err, int count_moves, void *sink, hipStream_t st);
 void launch_sort_offsets(const KParams &kp, const uint16_t *cnt, uint16_t *pre, int32_t *total, int32_t *err,
                          hipStream_t st);
@@ -84,7 +87,7 @@ size_t scan_tmp_elems(int n);
 // second pass of the re-sort: push src again and write the new state into
 // out in the new bin order, each in the cell of its recorded move (err bit
 // 8: a recomputed position further than rounding outside that cell)
-void launch_push_scatter(const KParams &kp, int prec, int group, const PartPtrs &src, const void *Est,
+void launch_push_scatter(const KParams &kp, int prec, int cells, const PartPtrs &src, const void *Est,
                          const void *Bst, const uint8_t *dirc, const uint16_t *pre, const int32_t *bin_start_new,
                          const PartPtrs &out, int ntot, int32_t *err, int32_t *perm, void *sink, hipStream_t st);
 // cell[p] for every particle from the bin ranges
