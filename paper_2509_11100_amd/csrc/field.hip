@@ -157,18 +157,44 @@ __device__ __forceinline__ double block_sum_256(double v, double *lds) {
   return r;
 }
 
+// Multi-dot partial sums: block b owns one contiguous chunk of the vectors
+// and writes, for each vector v_k, the sum of v_k[i] w[i] over its chunk
+// (each thread in index order, then a fixed-order block sum).  The vectors
+// are taken kMdotBatch at a time with one accumulator each per thread, so w
+// is read once per batch and a thread has a batch of independent loads in
+// flight (one vector per pass left the kernel latency-bound).
+constexpr int kMdotBatch = 8;
 __global__ __launch_bounds__(256) void k_mdot(const double *__restrict__ V, size_t ld, int nvec,
                                               const double *__restrict__ w, size_t n, double *__restrict__ partials) {
-  __shared__ double lds[4];
+  __shared__ double lds[4][kMdotBatch];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const size_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const size_t beg = (size_t)blockIdx.x * chunk;
   const size_t end = beg + chunk < n ? beg + chunk : n;
-  for (int kv = 0; kv < nvec; ++kv) {
-    const double *v = V + (size_t)kv * ld;
-    double acc = 0.0;
-    for (size_t i = beg + threadIdx.x; i < end; i += 256) acc += v[i] * w[i];
-    const double s = block_sum_256(acc, lds);
-    if (threadIdx.x == 0) partials[(size_t)blockIdx.x * nvec + kv] = s;
+  for (int k0 = 0; k0 < nvec; k0 += kMdotBatch) {
+    const int kn = nvec - k0 < kMdotBatch ? nvec - k0 : kMdotBatch;
+    double acc[kMdotBatch];
+#pragma unroll
+    for (int q = 0; q < kMdotBatch; ++q) acc[q] = 0.0;
+    for (size_t i = beg + threadIdx.x; i < end; i += 256) {
+      const double wi = w[i];
+#pragma unroll
+      for (int q = 0; q < kMdotBatch; ++q)
+        if (q < kn) acc[q] += V[(size_t)(k0 + q) * ld + i] * wi;
+    }
+#pragma unroll
+    for (int q = 0; q < kMdotBatch; ++q) {
+      double v = acc[q];
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+      if (lane == 0) lds[wid][q] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < kn) {
+      const int q = threadIdx.x;
+      partials[(size_t)blockIdx.x * nvec + k0 + q] = (lds[0][q] + lds[1][q]) + (lds[2][q] + lds[3][q]);
+    }
+    __syncthreads();
   }
 }
 

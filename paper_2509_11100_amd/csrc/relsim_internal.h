@@ -34,7 +34,7 @@ struct Layout {
 };
 
 constexpr int kMaxRestart = 64;
-constexpr int kDotBlocks = 512;     // blocks of the multi-dot reduction
+constexpr int kDotBlocks = 1024;    // blocks of the multi-dot reduction
 constexpr int kRedBlocks = 1024;    // blocks of the energy reductions
 constexpr int kSinkSlots = 512;     // per-lane store sinks of the particle kernels (power of two), 32 B each
 
