@@ -319,6 +319,64 @@ def test_species_counts_other_than_two(gname, ns, precision):
         assert np.all(np.diff(new[src]) > 0)
 
 
+SEGMENT_GRIDS = {
+    "2d_256x64": oracle.Grid(dim=2, nx=256, ny=64, dx=1.0, dy=0.9, dt=0.4),
+    "3d_32x32x16": oracle.Grid(dim=3, nx=32, ny=32, nz=16, dx=1.0, dy=0.9, dz=1.1, dt=0.4),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("ns", [2, 3])
+@pytest.mark.parametrize("gname", ["2d_256x64", "3d_32x32x16"])
+def test_push_passes_over_multi_cell_segments(gname, ns, precision):
+    """Grids large enough (16384 cells, about 16 particles per cell, a fifth
+    of the cells empty) that the push passes give each wave a segment of
+    several cells, so the lanes of one round push particles of different
+    cells and bins.  The pushed state must be the oracle's, bit for bit the
+    in-place push's, and stably sorted by bin."""
+    need_gpu()
+    import dataclasses
+
+    import torch
+
+    from paper_2509_11100_amd import relsim
+
+    g = SEGMENT_GRIDS[gname]
+    if ns != 2:
+        q, m = SPECIES[ns]
+        g = dataclasses.replace(g, q=q, m=m)
+    rng = np.random.default_rng(90 + ns)
+    n = 16 * g.N * 4 // 5
+    cell, sp, off, u, w = random_cells(g, n, rng, umax=2.5, empty_frac=0.2)
+    B = (2 * rng.random((3, g.N)) - 1) * 2.0
+    E = (2 * rng.random((3, g.N)) - 1) * 0.5
+    ctx = make_ctx(g, precision, n)
+    parts = load(ctx, cell, sp, off, u, w)
+    st = host_state(g, parts)
+    ctx2 = make_ctx(g, precision, n)
+    p2 = load(ctx2, *parts.to_host())
+    relsim.push(ctx2, p2, torch_grid(E), torch_grid(B), resort=False)
+    s2 = host_state(g, p2)
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    relsim.push(ctx, parts, torch_grid(E), torch_grid(B), resort=True, new_index=perm)
+    s1 = host_state(g, parts)
+    new = perm.cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(new), np.arange(n))
+    np.testing.assert_array_equal(s1["u"][:, new], s2["u"])
+    np.testing.assert_array_equal(s1["w"][new], st["w"])
+    np.testing.assert_array_equal(s1["species"][new], st["species"])
+    xr, ur = oracle.push(g, st["x"], st["u"], st["species"], E, B)
+    assert normwise(s1["u"][:, new], ur) < TOL[precision]
+    disp = periodic_diff(g, xr, st["x"])
+    assert np.linalg.norm(periodic_diff(g, s1["x"][:, new], xr)) / np.linalg.norm(disp) < TOL[precision]
+    key = s1["cell"].astype(np.int64) * len(g.q) + s1["species"]
+    assert np.all(np.diff(key) >= 0)
+    np.testing.assert_array_equal(s1["bin_start"], np.searchsorted(key, np.arange(g.N * len(g.q) + 1)))
+    # stability: the particles of a bin keep their old relative order
+    order = np.argsort(key[new], kind="stable")
+    np.testing.assert_array_equal(new[order], np.arange(n))
+
+
 def test_push_flags_a_move_of_more_than_one_cell():
     need_gpu()
     # |v| < c, so a move of more than one cell needs c dt > dx: here c dt = 2.7 dx
