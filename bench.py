@@ -273,7 +273,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="harris2d_1024x512")
     ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"])
-    ap.add_argument("--group", type=int, default=0, help="lanes per cell in the particle kernels (0 = automatic)")
+    ap.add_argument("--group", type=int, default=0, help="lanes per cell in the deposit and energy kernels (0 = automatic)")
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--cpu-sample", type=int, default=10_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
