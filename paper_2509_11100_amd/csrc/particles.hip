@@ -740,18 +740,18 @@ __device__ __forceinline__ Segment<T, DIM> stage_segment(const KParams &kp, int 
   const int S = kp.nspecies;
   sg.C = C;
   sg.nb = C * S;
-  // segments are visited tile by tile (tiles of max(tx, C) x ty x tz cells,
+  // segments are visited tile by tile (tiles of max(tx, C) x sty x stz cells,
   // segments row-major inside a tile), as the other particle kernels visit
   // cells: the destinations of neighbouring sources are then written close
   // together in time
   const int TX = C > kp.tx ? C : kp.tx;
-  const int spr = TX / C, per_tile = spr * kp.ty * kp.tz;
+  const int spr = TX / C, per_tile = spr * kp.sty * kp.stz;
   const int tile = wave / per_tile, r = wave - tile * per_tile;
-  const int ntx = kp.nx / TX, nty = kp.ny / kp.ty;
+  const int ntx = kp.nx / TX, nty = kp.ny / kp.sty;
   const int t2 = tile / ntx;
   sg.i0 = (tile - t2 * ntx) * TX + (r % spr) * C;
-  sg.j = (t2 % nty) * kp.ty + (r / spr) % kp.ty;
-  sg.k = DIM == 3 ? (t2 / nty) * kp.tz + r / (spr * kp.ty) : 0;
+  sg.j = (t2 % nty) * kp.sty + (r / spr) % kp.sty;
+  sg.k = DIM == 3 ? (t2 / nty) * kp.stz + r / (spr * kp.sty) : 0;
   sg.c0 = sg.i0 + kp.nx * (sg.j + kp.ny * sg.k);
   const int W = C + 2, nB = W * 3 * (DIM == 3 ? 3 : 1), nE = (C + 1) * 2 * (DIM == 3 ? 2 : 1);
   sg.Bg = reinterpret_cast<V4<T> *>(smem);

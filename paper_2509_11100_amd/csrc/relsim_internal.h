@@ -15,6 +15,7 @@ namespace relsim {
 struct KParams {
   int dim, nx, ny, nz, ncells, nspecies, nbins, nonrel;
   int tx, ty, tz;     // tile extents of the particle kernels' cell order (powers of two dividing nx, ny, nz)
+  int sty, stz;       // y and z extents of the push passes' segment tiles (powers of two dividing ny, nz)
   int ltx, lty, ltz;  // their base-2 logarithms
   int ntx, nty;       // tiles along x and y
   int gx, gxy;        // strides of the ghosted field copies: nx + 2, (nx + 2)(ny + 2)
