@@ -195,14 +195,18 @@ KParams make_kparams(const relsim_params *p) {
   k.nspecies = p->nspecies;
   k.nbins = k.ncells * k.nspecies;
   k.nonrel = p->nonrelativistic ? 1 : 0;
-  // largest power-of-two tile extents (up to 16 x 8 in 2D, 8 x 4 x 4 in 3D)
-  // that divide the grid
+  // largest power-of-two tile extents (up to 16 x 8 in 2D, 16 x 4 x 4 in 3D)
+  // that divide the grid.  A wave of the 3D deposit then takes 16 cells of
+  // one row, so each of its 267 moment stores writes 64 contiguous bytes
+  // (with 8 x 2 cells, two 32-byte pieces whose neighbours another tile
+  // writes much later: the counters showed 1.47x the moment bytes written,
+  // and the deposit was 8-16 % slower)
   auto tile = [](int n, int cap) {
     int t = cap;
     while (t > 1 && n % t != 0) t >>= 1;
     return t;
   };
-  k.tx = tile(k.nx, p->dim == 3 ? 8 : 16);
+  k.tx = tile(k.nx, 16);
   k.ty = tile(k.ny, p->dim == 3 ? 4 : 8);
   k.tz = p->dim == 3 ? tile(k.nz, 4) : 1;
   // the push passes visit their row segments in taller tiles (2D 32 rows,

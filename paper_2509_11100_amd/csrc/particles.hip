@@ -13,7 +13,7 @@
 // across cell boundaries, with the segment's fields staged in LDS (no lane
 // idles because one cell holds more particles than its neighbours).  Cells
 // and segments are visited tile by tile (2D tiles of up to 16 x 8 cells, 3D
-// of up to 8 x 4 x 4), so that neighbouring cells, whose particles exchange
+// of up to 16 x 4 x 4), so that neighbouring cells, whose particles exchange
 // places in the re-sort, are processed close together in time; workgroups
 // are remapped so that each XCD (and its L2) works on one contiguous band.
 // The next rounds' particle loads are issued before the current round is
