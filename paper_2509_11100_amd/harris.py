@@ -61,15 +61,16 @@ class Workload:
     dx_over_a: float          # cell size in units of the sheet half thickness a
     ppc: int                  # macro-particles per cell per species
     cfl: float = 0.5          # dt = cfl * dx / c
-    theta_s: float = 1.0      # sheet temperature T / (m c^2)
+    theta_s: float = 1.0      # sheet temperature T / (m_e c^2); species s samples T / (m_s c^2)
     beta_d: float = 0.3       # sheet drift speed
     nb_over_n0: float = 0.1   # background density ratio
-    theta_b: float = 0.1      # background temperature
+    theta_b: float = 0.1      # background temperature T_b / (m_e c^2)
     eps: float = 0.01         # delta B_y seed amplitude / B0
     seed: int = 0
     steps: int = 10
     q: tuple = (1.0, -1.0)
     m: tuple = (1.0, 1.0)
+    dt_wpe: Optional[float] = None  # if set, dt = dt_wpe / omega_pe0 (overrides cfl)
 
     @property
     def nspecies(self) -> int:
@@ -93,7 +94,8 @@ class Workload:
 
     @property
     def dt(self) -> float:
-        return self.cfl * self.dx
+        # omega_pe0 = 1 in these units (n0 = N0, m_e = e = c = 1)
+        return self.dt_wpe if self.dt_wpe is not None else self.cfl * self.dx
 
     @property
     def sigma_c(self) -> float:
@@ -112,6 +114,18 @@ WORKLOADS: Dict[str, Workload] = {
     "harris3d_128x64x64": Workload("harris3d_128x64x64", 3, 128, 64, 64, 0.5, 16, seed=4, steps=50),
     "harris3d_256x128x128": Workload("harris3d_256x128x128", 3, 256, 128, 128, 0.5, 8, seed=5, steps=20),
     "harris3d_512x256x256": Workload("harris3d_512x256x256", 3, 512, 256, 256, 0.5, 8, seed=6, steps=20),
+    # The relativistic tearing run (Sec. 3.1, fiducial RelSIM case): ions and
+    # electrons, m_i/m_e = 100, T = 10 m_e c^2 for both, u_d/c = 0.05, no
+    # background, a / rho_Le,R = 20 (rho_Le,R = u_d a / c), dx = 5 rho_Le,R =
+    # a / 4, dt omega_pe0 = 0.758, 256 particles per cell per species, no seed
+    # (the instability grows from the particle noise).  Species 0: ions.
+    # The box is 1000 x 510 rho_Le,R = 200 x 102 cells: 510 = twice the sheet
+    # distance; along x the period is the one the mode numbering of Sec. 4.1
+    # and the k_max a column of Table 1 imply (m = 4 at ka ~ 0.5, modes down
+    # to ka ~ 0.1, so ka = 0.1257 m), twice the stated 2 L_x.
+    "tearing2d_200x102": Workload("tearing2d_200x102", 2, 200, 102, 1, 0.25, 256, theta_s=10.0,
+                                  beta_d=0.05 / math.sqrt(1.0 + 0.05 ** 2), nb_over_n0=0.0, eps=0.0, seed=7,
+                                  steps=45000, q=(1.0, -1.0), m=(100.0, 1.0), dt_wpe=0.758),
 }
 
 
@@ -171,7 +185,9 @@ def _generate(wl: Workload, rng: np.random.Generator, c0: int, c1: int) -> Dict[
     S, ppc = wl.nspecies, wl.ppc
     nc = c1 - c0
     n = nc * S * ppc
-    n_sheet = ppc // 2
+    # half the particles of a cell belong to the sheet and half to the
+    # background; without a background all of them belong to the sheet
+    n_sheet = ppc // 2 if wl.nb_over_n0 > 0 else ppc
     n_bg = ppc - n_sheet
     dx = wl.dx
     Y = wl.ny * dx
@@ -192,16 +208,32 @@ def _generate(wl: Workload, rng: np.random.Generator, c0: int, c1: int) -> Dict[
     y = (j + off[1]) * dx - 0.5 * Y           # physical y in [-Y/2, Y/2)
 
     dens_sheet = N0 * (_sech2((y - 0.5 * Ly) / hp.a) + _sech2((y + 0.5 * Ly) / hp.a))
-    w = np.where(is_sheet, dens_sheet * V / n_sheet, wl.nb_over_n0 * N0 * V / n_bg)
+    w = np.where(is_sheet, dens_sheet * V / n_sheet, wl.nb_over_n0 * N0 * V / max(n_bg, 1))
 
     u = np.empty((3, n))
     ns = int(is_sheet.sum())
-    us = sample_mj(rng, wl.theta_s, ns)
+    masses = sorted(set(wl.m))
+    if len(masses) == 1:
+        # one mass (the pair plasma): one draw for all sheet particles
+        us = sample_mj(rng, wl.theta_s / masses[0], ns)
+    else:
+        # the same temperature T for every species: theta = T / (m_s c^2)
+        us = np.empty((3, ns))
+        msh = np.asarray(wl.m)[species[is_sheet]]
+        for mv in masses:
+            sel = msh == mv
+            us[:, sel] = sample_mj(rng, wl.theta_s / mv, int(sel.sum()))
     qv = np.asarray(wl.q)[species[is_sheet]]
     beta = wl.beta_d * np.sign(y[is_sheet]) * np.sign(qv)
     beta[beta == 0] = wl.beta_d
     u[:, is_sheet] = boost_z(rng, us, beta)
-    u[:, ~is_sheet] = sample_mj(rng, wl.theta_b, n - ns)
+    if n - ns > 0:
+        mbg = np.asarray(wl.m)[species[~is_sheet]]
+        ub = np.empty((3, n - ns))
+        for mv in sorted(set(wl.m)):
+            sel = mbg == mv
+            ub[:, sel] = sample_mj(rng, wl.theta_b / mv, int(sel.sum()))
+        u[:, ~is_sheet] = ub
     return {"cell": cell, "species": species, "off": off, "u": u, "w": w}
 
 

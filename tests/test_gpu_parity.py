@@ -517,3 +517,19 @@ def test_harris_mixed_energy_drift_matches_oracle():
     assert normwise(Bg, Br) < 1e-5
     print("mixed 5-step drift vs oracle: E %.2e B %.2e W %.2e" % (normwise(Eg, Er), normwise(Bg, Br),
                                                                    np.abs(dg - dr).max()))
+
+
+def test_tearing_electron_ion_end_to_end_fp64():
+    """The electron-ion tearing sheet (m_i/m_e = 100, T = 10 m_e c^2, no
+    background) cut to 8 x 102 cells and 4 particles per cell per species:
+    five whole FP64 steps against the oracle."""
+    need_gpu()
+    wl, p, E, B = harris_inputs("tearing2d_200x102", nx=8, ppc=4)
+    g = grid_of(wl)
+    steps = 5
+    ctx, parts, Eg, Bg, Wg = run_gpu_steps(wl, p, E, B, "fp64", steps)
+    x0 = positions(g, p["cell"], p["off"])
+    xr, ur, Er, Br, Wr = run_oracle_steps(g, x0, p["u"], p["w"], p["species"].astype(np.int32), E, B, steps)
+    assert normwise(Eg, Er) < 1e-9
+    assert normwise(Bg, Br) < 1e-9
+    np.testing.assert_allclose(Wg, Wr, rtol=1e-10)
