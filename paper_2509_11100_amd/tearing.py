@@ -86,16 +86,46 @@ def fit_growth(t: np.ndarray, e: np.ndarray, t0: float, t1: float) -> float:
     return 0.5 * float(slope)
 
 
-def run(steps: int, every: int, precision: str = "fp64", rtol: float = 1e-10, seed=None, log=sys.stdout):
+def summarize(wl: harris.Workload, rec: dict, window=(0.5, 1.5)) -> dict:
+    """Growth rates (gamma a / c) and energy errors from the records of run():
+    the low-pass fit, one fit per box mode, k_max a (the mode with the
+    largest fitted rate), the dominant mode at t gamma_th = 1.5, the largest
+    relative energy error up to t gamma_th = 1 and the error at the end."""
+    hp = wl.harris
+    modes = box_modes(wl)
+    gth = gamma_max(wl)
+    t = np.asarray(rec["t_gamma_th"])
+    low = np.asarray(rec["lowpass"])
+    em = np.asarray(rec["modes"])
+    Wt = np.asarray(rec["W"])[:, 3]
+    # the fits give the rate in units of gamma_th
+    gm = fit_growth(t, low, *window) * gth
+    per_mode = [fit_growth(t, em[:, i], *window) * gth for i in range(len(modes))]
+    fastest = int(np.nanargmax(per_mode)) if np.isfinite(per_mode).any() else 0
+    dominant = int(np.argmax(em[int(np.argmin(np.abs(t - 1.5)))]))
+    err1 = float(np.max(np.abs(Wt[t <= 1.0] - Wt[0])) / Wt[0])
+    return {
+        "workload": wl.name, "ppc": wl.ppc, "dt_wpe": wl.dt, "a": hp.a, "rho_Le_R": hp.u_d * hp.a,
+        "box_modes": [{"m": m, "ka": ka, "gamma_th_a_over_c": g} for m, ka, g in modes],
+        "gamma_th_a_over_c": gth, "fit_window_t_gamma_th": list(window),
+        "gamma_m_a_over_c_lowpass": gm, "gamma_m_a_over_c_per_mode": per_mode,
+        "k_max_a": modes[fastest][1], "dominant_ka_at_t_gamma_th_1.5": modes[dominant][1],
+        "energy_error_max_to_t_gamma_th_1": err1,
+        "energy_error_end": float(abs(Wt[-1] - Wt[0]) / Wt[0]),
+        "t_gamma_th_end": float(t[-1]),
+    }
+
+
+def run(steps: int, every: int, precision: str = "fp64", rtol: float = 1e-10, seed=None, log=sys.stdout,
+        **overrides):
     import torch
 
     from . import relsim
 
-    wl = harris.workload("tearing2d_200x102")
+    wl = harris.workload("tearing2d_200x102", **overrides)
     hp = wl.harris
     modes = box_modes(wl)
-    gth = gamma_max(wl)
-    t_unit = hp.a / gth  # 1 / gamma_th in time units (c = 1)
+    t_unit = hp.a / gamma_max(wl)  # 1 / gamma_th in time units (c = 1)
     p = harris.make_particles(wl, seed=seed)
     E, B = harris.make_fields(wl)
     n = p["w"].shape[0]
@@ -130,27 +160,9 @@ def run(steps: int, every: int, precision: str = "fp64", rtol: float = 1e-10, se
                      abs(rec["W"][-1][3] - rec["W"][0][3]) / rec["W"][0][3], time.time() - t0), file=log, flush=True)
     torch.cuda.synchronize()
     wall = time.time() - t0
-    t = np.asarray(rec["t_gamma_th"])
-    low = np.asarray(rec["lowpass"])
-    Wt = np.asarray(rec["W"])[:, 3]
-    gm = fit_growth(t, low, 0.5, 1.5) * t_unit  # gamma_m in units of c / a
-    em = np.asarray(rec["modes"])
-    per_mode = [fit_growth(t, em[:, i], 0.5, 1.5) * t_unit for i in range(mmax)]
-    fastest = int(np.nanargmax(per_mode)) if np.isfinite(per_mode).any() else 0
-    at15 = int(np.argmin(np.abs(t - 1.5)))
-    dominant = int(np.argmax(em[at15]))
-    err1 = float(np.max(np.abs(Wt[t <= 1.0] - Wt[0])) / Wt[0]) if (t <= 1.0).any() else float("nan")
-    summary = {
-        "workload": wl.name, "precision": precision, "particles": int(n), "steps": steps, "dt": wl.dt,
-        "a": hp.a, "rho_Le_R": hp.u_d * hp.a, "box_modes": [{"m": m, "ka": ka, "gamma_th_a_over_c": g}
-                                                             for m, ka, g in modes],
-        "gamma_th_a_over_c": gth,
-        "gamma_m_a_over_c_lowpass": gm, "gamma_m_a_over_c_per_mode": per_mode,
-        "k_max_a": modes[fastest][1], "dominant_ka_at_t_gamma_th_1.5": modes[dominant][1],
-        "energy_error_max_to_t_gamma_th_1": err1,
-        "energy_error_end": float(abs(Wt[-1] - Wt[0]) / Wt[0]),
-        "wall_s": wall, "ms_per_step": 1e3 * wall / max(steps, 1),
-    }
+    summary = summarize(wl, rec)
+    summary.update({"precision": precision, "particles": int(n), "steps": steps,
+                    "wall_s": wall, "ms_per_step": 1e3 * wall / max(steps, 1)})
     return summary, rec
 
 
@@ -161,9 +173,12 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--seed", type=int, default=None)
+    ap.add_argument("--ppc", type=int, default=None, help="particles per cell per species (default 256)")
+    ap.add_argument("--dt-wpe", type=float, default=None, help="time step in 1 / omega_pe0 (default 0.758)")
     ap.add_argument("--out", default=None, help="write the summary and the records as JSON")
     args = ap.parse_args(argv)
-    summary, rec = run(args.steps, args.every, args.precision, args.rtol, args.seed)
+    over = {k: v for k, v in (("ppc", args.ppc), ("dt_wpe", args.dt_wpe)) if v is not None}
+    summary, rec = run(args.steps, args.every, args.precision, args.rtol, args.seed, **over)
     print(json.dumps(summary))
     if args.out:
         with open(args.out, "w") as f:
