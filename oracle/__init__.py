@@ -63,7 +63,7 @@ def _load():
                 "oracle_gather_B": [cp, L, dp, dp, dp],
                 "oracle_gather_E": [cp, L, dp, dp, dp],
                 "oracle_alphas": [cp, L, dp, dp, ip, dp, dp],
-                "oracle_deposit": [cp, L, dp, dp, dp, ip, dp, dp, dp],
+                "oracle_deposit": [cp, L, dp, dp, dp, ip, dp, dp, dp, dp],
                 "oracle_deposit_nodes": [cp, L, dp, dp, dp, ip, dp, L, lp, dp, dp],
                 "oracle_curl_nc": [cp, dp, dp],
                 "oracle_curl_cn": [cp, dp, dp],
@@ -71,7 +71,7 @@ def _load():
                 "oracle_apply_A": [cp, dp, dp, dp],
                 "oracle_rhs": [cp, dp, dp, dp, dp],
                 "oracle_field_update": [cp, dp, dp, dp, dp, dp],
-                "oracle_push": [cp, L, dp, dp, ip, dp, dp],
+                "oracle_push": [cp, L, dp, dp, ip, dp, dp, dp],
                 "oracle_energy": [cp, L, dp, dp, ip, dp, dp, dp],
             }
             for name, args in sig.items():
@@ -183,8 +183,16 @@ def alphas(g: Grid, x, u, species, B) -> np.ndarray:
     return out
 
 
-def deposit(g: Grid, x, u, w, species, B):
-    """S1-S3: returns (Jhat [3][N], M [noff][9][N])."""
+def _gbar(gbar, n):
+    if gbar is None:
+        return None, None
+    gb = np.ascontiguousarray(gbar, dtype=np.float64).reshape(n)
+    return gb, gb.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def deposit(g: Grid, x, u, w, species, B, gbar=None):
+    """S1-S3: returns (Jhat [3][N], M [noff][9][N]).  ``gbar`` (n,), if
+    given, replaces gamma(u^n) in S2-S3 (the energy-conserving variant)."""
     lib = _load()
     x, px = _d(x)
     u, pu = _d(u)
@@ -195,7 +203,8 @@ def deposit(g: Grid, x, u, w, species, B):
     J, pJ = _d(np.zeros((3, g.N)))
     M, pM = _d(np.zeros((g.noff, 9, g.N)))
     cfg = g.cfg()
-    lib.oracle_deposit(C.byref(cfg), n, px, pu, pw, ps, pB, pJ, pM)
+    gb, pg = _gbar(gbar, n)
+    lib.oracle_deposit(C.byref(cfg), n, px, pu, pw, ps, pB, pg, pJ, pM)
     return J, M
 
 
@@ -278,8 +287,9 @@ def field_update(g: Grid, En, Bn, Eth):
     return E1, B1
 
 
-def push(g: Grid, x, u, species, Eth, Bn):
-    """S6: returns new (x, u); inputs are not modified."""
+def push(g: Grid, x, u, species, Eth, Bn, gbar=None):
+    """S6: returns new (x, u); inputs are not modified.  ``gbar`` as in
+    deposit()."""
     lib = _load()
     x = np.array(x, dtype=np.float64, order="C", copy=True)
     u = np.array(u, dtype=np.float64, order="C", copy=True)
@@ -289,7 +299,8 @@ def push(g: Grid, x, u, species, Eth, Bn):
     Eth, pE = _d(Eth)
     Bn, pB = _d(Bn)
     cfg = g.cfg()
-    lib.oracle_push(C.byref(cfg), x.shape[1], px, pu, ps, pE, pB)
+    gb, pg = _gbar(gbar, x.shape[1])
+    lib.oracle_push(C.byref(cfg), x.shape[1], px, pu, ps, pE, pB, pg)
     return x, u
 
 
@@ -411,3 +422,37 @@ def step(g: Grid, x, u, w, species, E, B, direct_limit: int = 200_000, rtol: flo
     x1, u1 = push(g, x, u, species, Eth, B)
     W = energy(g, u1, w, species, E1, B1)
     return {"J": J, "M": M, "rhs": r, "E_theta": Eth, "E": E1, "B": B1, "x": x1, "u": u1, "W": W}
+
+
+def gamma(g: Grid, u) -> np.ndarray:
+    """Lorentz factor sqrt(1 + |u|^2/c^2) per particle (1 when non-relativistic)."""
+    u = np.asarray(u, dtype=np.float64)
+    if g.nonrel:
+        return np.ones(u.shape[1])
+    return np.sqrt(1.0 + (u * u).sum(0) / (g.c * g.c))
+
+
+def step_ec(g: Grid, x, u, w, species, E, B, tol: float = 1e-13, maxit: int = 50,
+            direct_limit: int = 200_000, rtol: float = 1e-13):
+    """One energy-conserving step: S1-S6 with gbar = (gamma(u^n) + gamma(u^{n+1}))/2,
+    found by fixed-point (Picard) iteration from gbar = gamma(u^n).  Each pass
+    deposits with the current gbar, solves, pushes, and forms the next gbar
+    from the pushed momenta; it stops once max |gbar_next - gbar| / gbar <=
+    tol and keeps that pass's fields and particles.  Returns step()'s dict plus
+    ``gbar`` (the value the kept pass used), ``iters`` and ``change``."""
+    g0 = gamma(g, u)
+    gbar = g0.copy()
+    for it in range(1, maxit + 1):
+        J, M = deposit(g, x, u, w, species, B, gbar)
+        r = rhs(g, E, B, J)
+        Eth = solve(g, M, r, direct_limit=direct_limit, rtol=rtol, x0=E)
+        x1, u1 = push(g, x, u, species, Eth, B, gbar)
+        nxt = 0.5 * (g0 + gamma(g, u1))
+        change = float(np.max(np.abs(nxt - gbar) / gbar)) if gbar.size else 0.0
+        if change <= tol or it == maxit:
+            break
+        gbar = nxt
+    E1, B1 = field_update(g, E, B, Eth)
+    W = energy(g, u1, w, species, E1, B1)
+    return {"J": J, "M": M, "rhs": r, "E_theta": Eth, "E": E1, "B": B1, "x": x1, "u": u1, "W": W,
+            "gbar": gbar, "iters": it, "change": change}

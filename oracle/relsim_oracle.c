@@ -24,6 +24,13 @@
  *             u' = 2 ubar - u;  x' = x + dt u'/gamma(u')  (periodic wrap)
  *   S7        W = sum_p w m c^2 (gamma - 1) + V/(8 pi) (sum |E|^2 + sum |B|^2)
  *
+ * Energy-conserving variant (the exact relativistic case the paper's methods
+ * paragraph says the standard scheme lacks): gbar = (gamma(u^n) +
+ * gamma(u^{n+1}))/2 in S2, S3 and S6.  Then m c^2 (gamma^{n+1} - gamma^n) =
+ * q dt E_p . ubar / gbar exactly, the work of the current S3 deposits, and the
+ * step conserves W; gbar depends on u^{n+1}, so the step is a fixed point,
+ * found by iterating S1-S6 (oracle.step_ec).  gbar then comes in per particle.
+ *
  * The discrete curls are centred differences averaged over the transverse
  * corners, so that C_CN is the transpose of C_NC.  In 2D the z direction is
  * ignorable (d/dz = 0) and V = dx dy.
@@ -119,14 +126,17 @@ static void gather_nodes(const ocfg *g, const double *x, long n, long p, const d
     for (int k = 0; k < 3; ++k) out[k] += wt[a] * E[k * N + idx[a]];
 }
 
-/* S1 + S2 for one particle: alpha, gbar and beta. */
+/* S1 + S2 for one particle: alpha, gbar and beta.  gb_in, if not NULL, gives
+ * gbar per particle (the energy-conserving variant: the mean of the old and
+ * new Lorentz factors, from the fixed-point iteration); it is ignored in the
+ * non-relativistic limit. */
 static void particle_alpha(const ocfg *g, const double *x, const double *u, const int32_t *sp, long n, long p,
-                           const double *B, double al[9], double *gbar, double *beta) {
+                           const double *B, const double *gb_in, double al[9], double *gbar, double *beta) {
   double up[3] = {u[p], u[n + p], u[2 * n + p]};
   int s = sp[p];
   double Bp[3];
   gather_centres(g, x, n, p, B, Bp);
-  *gbar = gamma_of(g, up);
+  *gbar = (gb_in && !g->nonrel) ? gb_in[p] : gamma_of(g, up);
   *beta = g->q[s] * g->dt / (2.0 * g->m[s]);
   double b[3];
   for (int k = 0; k < 3; ++k) b[k] = *beta * Bp[k] / (*gbar * g->c);
@@ -156,14 +166,14 @@ void oracle_alphas(const ocfg *g, long n, const double *x, const double *u, cons
                    double *alpha) {
   for (long p = 0; p < n; ++p) {
     double al[9], gb, be;
-    particle_alpha(g, x, u, sp, n, p, B, al, &gb, &be);
+    particle_alpha(g, x, u, sp, n, p, B, NULL, al, &gb, &be);
     for (int k = 0; k < 9; ++k) alpha[k * n + p] = al[k];
   }
 }
 
 /* S1-S3: Jhat [3][N] and M [noff][9][N], both overwritten. */
 void oracle_deposit(const ocfg *g, long n, const double *x, const double *u, const double *w, const int32_t *sp,
-                    const double *B, double *J, double *M) {
+                    const double *B, const double *gb_in, double *J, double *M) {
   long N = nnodes(g);
   int no = noff(g);
   double V = cellvol(g);
@@ -171,7 +181,7 @@ void oracle_deposit(const ocfg *g, long n, const double *x, const double *u, con
   memset(M, 0, sizeof(double) * (size_t)no * 9 * N);
   for (long p = 0; p < n; ++p) {
     double al[9], gb, be;
-    particle_alpha(g, x, u, sp, n, p, B, al, &gb, &be);
+    particle_alpha(g, x, u, sp, n, p, B, gb_in, al, &gb, &be);
     int s = sp[p];
     double cJ = w[p] * g->q[s] / V;
     double cM = w[p] * g->q[s] * be / (V * gb);
@@ -218,7 +228,7 @@ void oracle_deposit_nodes(const ocfg *g, long n, const double *x, const double *
     for (int a = 0; a < nc; ++a) hit |= slot[idx[a]] >= 0;
     if (!hit) continue;
     double al[9], gb, be;
-    particle_alpha(g, x, u, sp, n, p, B, al, &gb, &be);
+    particle_alpha(g, x, u, sp, n, p, B, NULL, al, &gb, &be);
     int s = sp[p];
     double cJ = w[p] * g->q[s] / V;
     double cM = w[p] * g->q[s] * be / (V * gb);
@@ -363,10 +373,10 @@ void oracle_field_update(const ocfg *g, const double *En, const double *Bn, cons
 
 /* S6 for all particles; x and u updated in place (x wrapped into [0, L)). */
 void oracle_push(const ocfg *g, long n, double *x, double *u, const int32_t *sp, const double *Eth,
-                 const double *Bn) {
+                 const double *Bn, const double *gb_in) {
   for (long p = 0; p < n; ++p) {
     double al[9], gb, be;
-    particle_alpha(g, x, u, sp, n, p, Bn, al, &gb, &be);
+    particle_alpha(g, x, u, sp, n, p, Bn, gb_in, al, &gb, &be);
     double Ep[3];
     gather_nodes(g, x, n, p, Eth, Ep);
     double up[3] = {u[p], u[n + p], u[2 * n + p]};

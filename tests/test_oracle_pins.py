@@ -409,3 +409,44 @@ def test_nonrelativistic_energy_conserved_to_solver_tolerance():
         out = oracle.step(g, x, u, w, sp, E, B)
         x, u, E, B = out["x"], out["u"], out["E"], out["B"]
         assert abs(out["W"][3] - W0) < 1e-13 * W0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_energy_conserving_variant_conserves_energy_when_relativistic(dim):
+    """gbar = (gamma^n + gamma^{n+1})/2 zeroes the budget term of the identity
+    above: the fixed point conserves W to solver tolerance where the standard
+    step does not."""
+    g = small_grid(dim, nx=5, ny=4, nz=3, dt=0.5)
+    rng = np.random.default_rng(60 + dim)
+    x, u, w, sp, E, B = random_state(g, 400, rng, umax=3.0, bmax=1.5, emax=0.4)
+    W0 = oracle.energy(g, u, w, sp, E, B)[3]
+    std = oracle.step(g, x, u, w, sp, E, B)
+    assert abs(std["W"][3] - W0) > 1e-6 * W0
+    for _ in range(3):
+        out = oracle.step_ec(g, x, u, w, sp, E, B, tol=1e-15)
+        assert out["iters"] < 50 and out["change"] <= 1e-15
+        # the kept pass is self-consistent and conserves energy
+        g0 = np.sqrt(1 + (u * u).sum(0))
+        g1 = np.sqrt(1 + (out["u"] ** 2).sum(0))
+        np.testing.assert_allclose(out["gbar"], 0.5 * (g0 + g1), rtol=2e-15)
+        assert abs(out["W"][3] - W0) < 1e-12 * W0, (out["W"][3] - W0) / W0
+        x, u, E, B = out["x"], out["u"], out["E"], out["B"]
+
+
+def test_energy_conserving_variant_reduces_to_the_standard_step():
+    """With gbar = gamma(u^n) given explicitly, deposit and push are the
+    standard ones; without relativity gbar plays no part and step_ec is step."""
+    g = small_grid(2, nx=5, ny=4, dt=0.5)
+    rng = np.random.default_rng(70)
+    x, u, w, sp, E, B = random_state(g, 300, rng, umax=3.0, bmax=1.5, emax=0.4)
+    g0 = oracle.gamma(g, u)
+    J0, M0 = oracle.deposit(g, x, u, w, sp, B)
+    J1, M1 = oracle.deposit(g, x, u, w, sp, B, g0)
+    assert np.array_equal(J0, J1) and np.array_equal(M0, M1)
+    assert all(np.array_equal(a, b) for a, b in zip(oracle.push(g, x, u, sp, E, B), oracle.push(g, x, u, sp, E, B, g0)))
+    gn = small_grid(2, nx=5, ny=4, dt=0.5, nonrel=True)
+    a = oracle.step(gn, x, 0.1 * u, w, sp, E, B)
+    b = oracle.step_ec(gn, x, 0.1 * u, w, sp, E, B)
+    assert b["iters"] == 1
+    for k in ("E", "B", "x", "u", "W"):
+        assert np.array_equal(a[k], b[k])
