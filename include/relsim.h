@@ -157,6 +157,39 @@ int relsim_field_solve(relsim_ctx *ctx, const double *M, const double *Jhat, con
 int relsim_push(relsim_ctx *ctx, relsim_particles *part, const double *E_theta, const double *B_n, int32_t resort,
                 int32_t *new_index);
 
+/* Energy-conserving relativistic variant.  The methods paragraph of Sec. 2
+ * says the scheme conserves energy exactly only without relativity; with the
+ * Lorentz factor of S2-S3 and S6 taken as gbar = (gamma(u^n) +
+ * gamma(u^{n+1}))/2 the work done on each particle equals its kinetic energy
+ * change, and the step conserves energy exactly, but gbar then depends on the
+ * step's own result.  A caller finds it by fixed-point iteration:
+ *   gbar = NULL (gamma(u^n));
+ *   repeat: relsim_deposit_moments_ec(gbar) -> relsim_field_solve ->
+ *           relsim_gamma_mean(gbar -> gbar_next, change); swap gbar, gbar_next
+ *   until change is small; then relsim_push_ec with the gbar the last
+ *   relsim_gamma_mean was given (the one the field solve used).
+ * gbar / gbar_next: device arrays of part->n elements of the particle type T
+ * (double for RELSIM_FP64, float for RELSIM_MIXED, aligned to it), one per
+ * particle in the current (front) order, owned by the caller.  A NULL gbar
+ * means gamma(u^n), which makes the first two calls the standard ones.  In the
+ * non-relativistic limit gbar is ignored (gamma = 1). */
+
+/* relsim_deposit_moments with gbar in place of gamma(u^n). */
+int relsim_deposit_moments_ec(relsim_ctx *ctx, const relsim_particles *part, const double *B_n, const void *gbar,
+                              double *Jhat, double *M);
+
+/* One fixed-point pass: pushes every particle as relsim_push would with
+ * gbar (state untouched), writes gbar_next[p] = (gamma(u^n_p) +
+ * gamma(u^{n+1}_p))/2, and stores in *max_rel_change (host) the largest
+ * |gbar_next - gbar| / gbar over the particles (infinity if any is not
+ * finite).  gbar_next must not alias gbar.  Synchronous (one 8-byte copy). */
+int relsim_gamma_mean(relsim_ctx *ctx, const relsim_particles *part, const double *E_theta, const double *B_n,
+                      const void *gbar, void *gbar_next, double *max_rel_change);
+
+/* relsim_push with gbar in place of gamma(u^n). */
+int relsim_push_ec(relsim_ctx *ctx, relsim_particles *part, const double *E_theta, const double *B_n,
+                   const void *gbar, int32_t resort, int32_t *new_index);
+
 /* Write part->cell (front set) from bin_start: particle p of bin b gets cell
  * b / nspecies.  Needed after relsim_push before anything reads the cell
  * ids (the adjoint entry points read state_n->cell). */

@@ -76,6 +76,9 @@ def load() -> C.CDLL:
         "relsim_deposit_moments": (C.c_int, [vp, pt, vp, vp, vp]),
         "relsim_field_solve": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i32), dp]),
         "relsim_push": (C.c_int, [vp, pt, vp, vp, i32, vp]),
+        "relsim_deposit_moments_ec": (C.c_int, [vp, pt, vp, vp, vp, vp]),
+        "relsim_gamma_mean": (C.c_int, [vp, pt, vp, vp, vp, vp, dp]),
+        "relsim_push_ec": (C.c_int, [vp, pt, vp, vp, vp, i32, vp]),
         "relsim_apply_AT": (C.c_int, [vp, vp, vp, vp]),
         "relsim_push_adjoint": (C.c_int, [vp, pt, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "relsim_field_solve_adjoint": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i32), dp]),
@@ -106,5 +109,5 @@ def exported_symbols():
         "relsim_field_solve", "relsim_push", "relsim_fill_cells", "relsim_energy", "relsim_curl_nc", "relsim_curl_cn",
         "relsim_apply_A", "relsim_apply_AT", "relsim_push_adjoint", "relsim_field_solve_adjoint",
         "relsim_deposit_adjoint", "relsim_timing_enable", "relsim_timing_reset", "relsim_timing_read",
-        "relsim_strerror", "relsim_last_error",
+        "relsim_strerror", "relsim_last_error", "relsim_deposit_moments_ec", "relsim_gamma_mean", "relsim_push_ec",
     ]

@@ -481,25 +481,43 @@ int relsim_sort(relsim_ctx *c, relsim_particles *pt) {
 }
 
 int relsim_deposit_moments(relsim_ctx *c, const relsim_particles *pt, const double *B_n, double *Jhat, double *M) {
+  return relsim_deposit_moments_ec(c, pt, B_n, nullptr, Jhat, M);
+}
+
+int relsim_deposit_moments_ec(relsim_ctx *c, const relsim_particles *pt, const double *B_n, const void *gbar,
+                              double *Jhat, double *M) {
   if (!c) return RELSIM_EINVAL;
   int rc = check_particles(c, pt, false);
   if (rc) return rc;
   if (!B_n || !Jhat || !M) return fail(c, RELSIM_EINVAL, "null grid array");
+  if (gbar && !aligned(gbar, c->p.precision == RELSIM_MIXED ? 4 : 8))
+    return fail(c, RELSIM_EINVAL, "gbar not aligned to its element size");
   const int G = choose_group(c, pt->n, K_DEPOSIT);
   void *S = c->at<char>(c->L.S);
   void *stB = c->at<char>(c->L.stB);
+  PartPtrs pp = front(pt);
+  pp.gbar = gbar;
   timed(c, "stage_fields", [&] { launch_stage_field(c->kp, c->p.precision, B_n, stB, c->st); });
-  timed(c, "deposit_cells", [&] { launch_deposit_cells(c->kp, c->p.precision, G, front(pt), stB, S, c->st); });
+  timed(c, "deposit_cells", [&] { launch_deposit_cells(c->kp, c->p.precision, G, pp, stB, S, c->st); });
   timed(c, "assemble_nodes", [&] { launch_assemble(c->kp, c->p.precision, S, Jhat, M, c->st); });
   return launch_status(c, "relsim_deposit_moments");
 }
 
 int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, const double *B_n, int32_t resort,
                 int32_t *new_index) {
+  return relsim_push_ec(c, pt, E_theta, B_n, nullptr, resort, new_index);
+}
+
+int relsim_push_ec(relsim_ctx *c, relsim_particles *pt, const double *E_theta, const double *B_n, const void *gbar,
+                   int32_t resort, int32_t *new_index) {
   if (!c) return RELSIM_EINVAL;
   int rc = check_particles(c, pt, resort != 0);
   if (rc) return rc;
   if (!E_theta || !B_n) return fail(c, RELSIM_EINVAL, "null grid array");
+  if (gbar && !aligned(gbar, c->p.precision == RELSIM_MIXED ? 4 : 8))
+    return fail(c, RELSIM_EINVAL, "gbar not aligned to its element size");
+  PartPtrs pp = front(pt);
+  pp.gbar = gbar;
   const int cells = choose_cells(c, pt->n, K_PUSH);
   const int cells_s = choose_cells(c, pt->n, K_SCATTER);
   uint8_t *dirc = c->at<uint8_t>(c->L.dirc);
@@ -516,7 +534,7 @@ int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, cons
   // with resort the first pass only counts the moves, and the second pushes
   // again, writing the new state straight into its new place
   timed(c, resort ? "push_count" : "push", [&] {
-    launch_push(c->kp, c->p.precision, cells, front(pt), stE, stB, dirc, cnt, err, resort ? 1 : 0,
+    launch_push(c->kp, c->p.precision, cells, pp, stE, stB, dirc, cnt, err, resort ? 1 : 0,
                 c->at<char>(c->L.sink), c->st);
   });
   if (resort) {
@@ -525,7 +543,7 @@ int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, cons
       launch_scan(total, pt->bin_start_back, c->kp.nbins, c->at<int32_t>(c->L.scan_tmp), c->st);
     });
     timed(c, "push_scatter", [&] {
-      launch_push_scatter(c->kp, c->p.precision, cells_s, front(pt), stE, stB, dirc, pre, pt->bin_start_back, back(pt),
+      launch_push_scatter(c->kp, c->p.precision, cells_s, pp, stE, stB, dirc, pre, pt->bin_start_back, back(pt),
                           (int)pt->n, err, new_index, c->at<char>(c->L.sink), c->st);
     });
     rc = launch_status(c, "relsim_push");
@@ -534,6 +552,42 @@ int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, cons
     return RELSIM_OK;
   }
   return launch_status(c, "relsim_push");
+}
+
+int relsim_gamma_mean(relsim_ctx *c, const relsim_particles *pt, const double *E_theta, const double *B_n,
+                      const void *gbar, void *gbar_next, double *max_rel_change) {
+  if (!c) return RELSIM_EINVAL;
+  int rc = check_particles(c, pt, false);
+  if (rc) return rc;
+  if (!E_theta || !B_n) return fail(c, RELSIM_EINVAL, "null grid array");
+  if (!gbar_next || !max_rel_change) return fail(c, RELSIM_EINVAL, "null gbar_next or max_rel_change");
+  const size_t es = c->p.precision == RELSIM_MIXED ? 4 : 8;
+  if ((gbar && !aligned(gbar, es)) || !aligned(gbar_next, es))
+    return fail(c, RELSIM_EINVAL, "gbar not aligned to its element size");
+  if (gbar && gbar == gbar_next) return fail(c, RELSIM_EINVAL, "gbar and gbar_next must not alias");
+  const int cells = choose_cells(c, pt->n, K_PUSH);
+  int32_t *err = c->at<int32_t>(c->L.err);
+  // the 8 bytes after the error flags (both in the 64-byte flag slot)
+  unsigned long long *chg = reinterpret_cast<unsigned long long *>(c->at<char>(c->L.err) + 8);
+  void *stB = c->at<char>(c->L.stB);
+  void *stE = c->at<char>(c->L.stE);
+  PartPtrs pp = front(pt);
+  pp.gbar = gbar;
+  HIP_CHECK(c, hipMemsetAsync(chg, 0, sizeof(unsigned long long), c->st));
+  timed(c, "stage_fields", [&] {
+    launch_stage_field(c->kp, c->p.precision, B_n, stB, c->st);
+    launch_stage_field(c->kp, c->p.precision, E_theta, stE, c->st);
+  });
+  timed(c, "gamma_mean", [&] {
+    launch_gamma_mean(c->kp, c->p.precision, cells, pp, stE, stB, err, c->at<char>(c->L.sink), gbar_next, chg,
+                      c->st);
+  });
+  rc = launch_status(c, "relsim_gamma_mean");
+  if (rc) return rc;
+  HIP_CHECK(c, hipMemcpyAsync(c->host, chg, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->st));
+  HIP_CHECK(c, hipStreamSynchronize(c->st));
+  std::memcpy(max_rel_change, c->host, sizeof(double));
+  return RELSIM_OK;
 }
 
 int relsim_fill_cells(relsim_ctx *c, relsim_particles *pt) {

@@ -260,6 +260,7 @@ __device__ __forceinline__ void fill_species_table(const PC<T> &pc, T (*tab)[8],
 template <typename T>
 struct PRec {
   T fx, fy, fz, ux, uy, uz, w;
+  T g;  // gbar of the energy-conserving variant (loaded only there)
 };
 
 // Index a lane loads for particle p of a cell ending at pend: lanes past
@@ -292,17 +293,34 @@ __device__ __forceinline__ void load_rec(int p, int pend, const V2<T> *__restric
   r.w = b.w;
 }
 
+// The energy-conserving variant gives gbar per particle (in the particle
+// arithmetic type, in the particles' order); its kernels load it beside the
+// record (GB).  1 / gbar of S2: that value, or 1 / gamma(u^n).
+template <bool GB, typename T>
+__device__ __forceinline__ void load_gbar(int p, int pend, const T *__restrict__ gb, PRec<T> &r) {
+  if constexpr (GB) r.g = gb[load_index(p, pend)];
+}
+
+template <bool GB, typename T>
+__device__ __forceinline__ T inv_gbar(const KParams &kp, const PC<T> &pc, const PRec<T> &r, T ux, T uy, T uz) {
+  if constexpr (GB)
+    return kp.nonrel ? T(1) : T(1) / r.g;
+  else
+    return kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
+}
+
 // ---------------------------------------------------------------------------
 // S1-S3: per-cell moments
 // ---------------------------------------------------------------------------
 // 2D: the G lanes of a group split the cell's particles; each lane sums all
 // 93 moments (81 mass, 12 current) of its particles, and the group's G
 // partial sums are then added in fixed lane order.
-template <typename T, int G>
+template <typename T, int G, bool GB>
 __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t *__restrict__ bin_start,
                                                       const V2<T> *__restrict__ xy,
                                                       const V4<T> *__restrict__ uw,
-                                                      const V4<T> *__restrict__ Bs, T *__restrict__ S) {
+                                                      const V4<T> *__restrict__ Bs, T *__restrict__ S,
+                                                      const T *__restrict__ gb) {
   constexpr int NACC = 93;  // 81 mass moments + 12 current moments
   constexpr int CH = 32;    // moments per LDS transpose chunk (keeps LDS off the occupancy limit)
   __shared__ T red[64 * (CH + 1)];
@@ -325,12 +343,16 @@ __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t 
   for (int k = 0; k < NACC; ++k) acc[k] = T(0);
   PRec<T> cur{}, nxt{};
   int p = pal + gl;
-  if (rounds > 0) load_rec<T, 2>(p, cs.pend, xy, uw, nullptr, cur);
+  if (rounds > 0) {
+    load_rec<T, 2>(p, cs.pend, xy, uw, nullptr, cur);
+    load_gbar<GB>(p, cs.pend, gb, cur);
+  }
   __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll 2
   for (int r = 0; r < rounds; ++r) {
     const int pn = p + G;
     load_rec<T, 2>(pn, cs.pend, xy, uw, nullptr, nxt);
+    load_gbar<GB>(pn, cs.pend, gb, nxt);
     if (p >= cs.pbeg && p < cs.pend) {
       const T fx = cur.fx, fy = cur.fy;
       const T ux = cur.ux, uy = cur.uy, uz = cur.uz, wp = cur.w;
@@ -338,7 +360,7 @@ __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t 
       species_of<T>(kp, pc, cs, p, stab, qs, bs);
       T Bx, By, Bz;
       gather_B<T, 2>(bsh[grp] + 4, 3, 9, fx, fy, T(0), Bx, By, Bz);
-      const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
+      const T igb = inv_gbar<GB>(kp, pc, cur, ux, uy, uz);
       const T kb = bs * igb * pc.invc;
       T a[9];
       const T inv = alpha_num<T>(kb * Bx, kb * By, kb * Bz, a);
@@ -404,11 +426,12 @@ __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t 
 //   lane 3:    X = (1-f_x, f_x, 0), Y = (1-f_y, f_y, 0), Z = 1,
 //              P = (current x (1-f_z), current x f_z, 0, 0, 0),
 // so lane 3 uses 24 of its 81 accumulators.
-template <typename T>
+template <typename T, bool GB>
 __global__ __launch_bounds__(64) void k_deposit_split3(KParams kp, const int32_t *__restrict__ bin_start,
                                                        const V2<T> *__restrict__ xy,
                                                        const V4<T> *__restrict__ uw, const T *__restrict__ zz,
-                                                       const V4<T> *__restrict__ Bs, T *__restrict__ S) {
+                                                       const V4<T> *__restrict__ Bs, T *__restrict__ S,
+                                                       const T *__restrict__ gb) {
   constexpr int G = 4;
   // per producing lane: operand blocks (X0 X1 X2 Y0) (Y1 Y2 P0 P1) (P2..P5)
   // (P6 P7 P8 -) for the mass lanes [0] and the current lane [1], and Z
@@ -437,11 +460,13 @@ __global__ __launch_bounds__(64) void k_deposit_split3(KParams kp, const int32_t
   PRec<T> cur{}, nxt{};
   int p = pal + gl;
   if (rounds > 0) load_rec<T, 3>(p, cs.pend, xy, uw, zz, cur);
+  if (GB && rounds > 0) load_gbar<GB>(p, cs.pend, gb, cur);
   __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll 1
   for (int r = 0; r < rounds; ++r) {
     const int pn = p + G;
     load_rec<T, 3>(pn, cs.pend, xy, uw, zz, nxt);
+    load_gbar<GB>(pn, cs.pend, gb, nxt);
     {
       // this lane's particle (lanes outside the cell's range contribute 0)
       const bool pv = p >= cs.pbeg && p < cs.pend;
@@ -451,7 +476,11 @@ __global__ __launch_bounds__(64) void k_deposit_split3(KParams kp, const int32_t
       species_of<T>(kp, pc, cs, p, stab, qs, bs);
       T Bx, By, Bz;
       gather_B<T, 3>(bsh[grp] + 13, 3, 9, fx, fy, fz, Bx, By, Bz);
-      const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
+      T igb;
+      if constexpr (GB)
+        igb = inv_gbar<GB>(kp, pc, cur, ux, uy, uz);
+      else
+        igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
       const T kb = bs * igb * pc.invc;
       T a[9];
       const T inv = alpha_num<T>(kb * Bx, kb * By, kb * Bz, a);
@@ -662,7 +691,7 @@ struct CellFields {
 // offsets advanced by dt u^{n+1} / gamma^{n+1} in cell units, not yet brought
 // back into [0, 1).  Every kernel that pushes calls this one function, so
 // that they all round identically.
-template <typename T, int DIM>
+template <typename T, int DIM, bool GB = false>
 __device__ __forceinline__ void push_one(const KParams &kp, const PC<T> &pc, const CellFields<T> &cf, T bs,
                                          const PRec<T> &cur, T &fx, T &fy, T &fz, T &nx, T &ny, T &nz) {
   constexpr int NCORN = DIM == 3 ? 8 : 4;
@@ -672,7 +701,7 @@ __device__ __forceinline__ void push_one(const KParams &kp, const PC<T> &pc, con
   const T ux = cur.ux, uy = cur.uy, uz = cur.uz;
   T Bx, By, Bz;
   gather_B<T, DIM>(cf.bc, cf.by, cf.bz, fx, fy, fz, Bx, By, Bz);
-  const T igb = kp.nonrel ? T(1) : rsqrt_t(T(1) + (ux * ux + uy * uy + uz * uz) * pc.invc2);
+  const T igb = inv_gbar<GB>(kp, pc, cur, ux, uy, uz);
   const T kb = bs * igb * pc.invc;
   T a[9];
   const T inv2 = T(2) * alpha_num<T>(kb * Bx, kb * By, kb * Bz, a);
@@ -818,13 +847,27 @@ __device__ __forceinline__ CellFields<T> segment_fields(const Segment<T, DIM> &s
 // and k_push_scatter later recomputes the push and writes the new state in
 // the new order.  !COUNT: push in place with no re-sort; offsets stay
 // relative to the old cell, in [-1, 2).
-template <typename T, int DIM, bool COUNT>
+// GB selects the Lorentz factor of S2 and what the pass does:
+//   0  gamma(u^n); count the moves (COUNT) or push in place
+//   1  gbar from gb; as 0
+//   2  gbar from gb; leave the state alone and write, per particle, the next
+//      fixed-point value gnx = (gamma(u^n) + gamma(u^{n+1}))/2 of the
+//      energy-conserving variant, and into *chg the largest
+//      |gnx - gbar| / gbar (as the bits of a non-negative double, so that
+//      an integer atomic max orders them; infinite if not finite)
+//   3  as 2 with gbar = gamma(u^n) (the iteration's start; gb unused)
+template <typename T, int DIM, bool COUNT, int GB>
 __global__ __launch_bounds__(64) void k_push(KParams kp, int C, const int32_t *__restrict__ bin_start,
                                              V2<T> *__restrict__ xy, V4<T> *__restrict__ uw, T *__restrict__ zz,
                                              const V4<T> *__restrict__ Es, const V4<T> *__restrict__ Bs,
                                              uint8_t *__restrict__ dirc, uint16_t *__restrict__ cnt,
-                                             int32_t *__restrict__ err, void *__restrict__ sink) {
+                                             int32_t *__restrict__ err, void *__restrict__ sink,
+                                             const T *__restrict__ gb, T *__restrict__ gnx,
+                                             unsigned long long *__restrict__ chg) {
   constexpr int NDIR = DIM == 3 ? 27 : 9;
+  constexpr bool LOADG = GB == 1 || GB == 2;
+  constexpr bool TRIAL = GB >= 2;
+  static_assert(!(TRIAL && COUNT), "a fixed-point pass counts nothing");
   extern __shared__ __attribute__((aligned(32))) unsigned char smem[];
   const int lane = threadIdx.x;
   const PC<T> pc(kp);
@@ -845,7 +888,11 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, int C, const int32_t *_
   PRec<T> cur{}, nxt{};
   int p = pal + lane;
   int bad = 0;
-  if (rounds > 0) load_rec<T, DIM>(p, p1, xy, uw, zz, cur);
+  double dmax = 0.0;
+  if (rounds > 0) {
+    load_rec<T, DIM>(p, p1, xy, uw, zz, cur);
+    load_gbar<LOADG>(p, p1, gb, cur);
+  }
   // enter the loop with nothing in flight, so the loop's waits only count
   // its own loads and stores
   __builtin_amdgcn_s_waitcnt(0);
@@ -853,6 +900,7 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, int C, const int32_t *_
   for (int r = 0; r < rounds; ++r) {
     const int pn = p + 64;
     load_rec<T, DIM>(pn, p1, xy, uw, zz, nxt);
+    load_gbar<LOADG>(pn, p1, gb, nxt);
     // lanes outside [p0, p1) compute on a valid particle's copy and store
     // into the sink
     const bool pv = p >= p0 && p < p1;
@@ -861,8 +909,16 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, int C, const int32_t *_
     T qs, bs;
     species_consts<T>(S, s, sq0, sq1, sb0, sb1, sg.stab, qs, bs);
     T fx, fy, fz, nx, ny, nz;
-    push_one<T, DIM>(kp, pc, segment_fields(sg, lc), bs, cur, fx, fy, fz, nx, ny, nz);
-    if constexpr (COUNT) {
+    push_one<T, DIM, LOADG>(kp, pc, segment_fields(sg, lc), bs, cur, fx, fy, fz, nx, ny, nz);
+    if constexpr (TRIAL) {
+      const T g0 = kp.nonrel ? T(1) : sqrt(T(1) + (cur.ux * cur.ux + cur.uy * cur.uy + cur.uz * cur.uz) * pc.invc2);
+      const T g1 = kp.nonrel ? T(1) : sqrt(T(1) + (nx * nx + ny * ny + nz * nz) * pc.invc2);
+      const T gm = T(0.5) * (g0 + g1);
+      const T gin = GB == 2 ? cur.g : g0;
+      *(pv ? gnx + p : sinkT) = gm;
+      const double d = fabs((double)gm - (double)gin) / (double)gin;
+      dmax = pv ? (d <= dmax ? dmax : (d == d ? d : __builtin_inf())) : dmax;
+    } else if constexpr (COUNT) {
       int flag = 0;
       const int mx = cross_cell<T>(fx, flag);
       const int my = cross_cell<T>(fy, flag);
@@ -892,6 +948,11 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, int C, const int32_t *_
     p = pn;
   }
   if (__ballot(bad) && lane == 0) atomicOr(err, 1);
+  if constexpr (TRIAL) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o));
+    if (lane == 0) atomicMax(chg, (unsigned long long)__double_as_longlong(dmax));
+  }
   if constexpr (COUNT) {
     __syncthreads();
     // counts out in [move][bin] order, consecutive bins per move
@@ -950,11 +1011,12 @@ __global__ __launch_bounds__(256) void k_sort_offsets(KParams kp, const uint16_t
 // One round of the pushing scatter for particle p of the segment, on
 // record buffer (cur, dc), which it then refills with the round three
 // ahead; see k_push_scatter.
-template <typename T, int DIM, bool PERM>
+template <typename T, int DIM, bool PERM, bool GB>
 __device__ __forceinline__ void scatter_round(const KParams &kp, const PC<T> &pc, const Segment<T, DIM> &sg,
                                               int p1, int lane, unsigned long long lt, int ntot,
                                               const V2<T> *__restrict__ xy, const V4<T> *__restrict__ uw,
-                                              const T *__restrict__ zz, const uint8_t *__restrict__ dirc,
+                                              const T *__restrict__ zz, const T *__restrict__ gb,
+                                              const uint8_t *__restrict__ dirc,
                                               V2<T> *__restrict__ xo, V4<T> *__restrict__ uo, T *__restrict__ zo,
                                               int32_t *__restrict__ perm, void *__restrict__ sink, T q0, T q1,
                                               T b0, T b1, int &p, int &bad, PRec<T> &cur, uint8_t &dc) {
@@ -968,7 +1030,7 @@ __device__ __forceinline__ void scatter_round(const KParams &kp, const PC<T> &pc
   T qs, bs;
   species_consts<T>(S, s, q0, q1, b0, b1, sg.stab, qs, bs);
   T fx, fy, fz, nx, ny, nz;
-  push_one<T, DIM>(kp, pc, segment_fields(sg, lc), bs, cur, fx, fy, fz, nx, ny, nz);
+  push_one<T, DIM, GB>(kp, pc, segment_fields(sg, lc), bs, cur, fx, fy, fz, nx, ny, nz);
   // the new state goes where the counting pass counted it (move dcur),
   // with its offsets taken relative to that cell
   int off = 0;
@@ -1014,6 +1076,7 @@ __device__ __forceinline__ void scatter_round(const KParams &kp, const PC<T> &pc
   if constexpr (PERM) *(ok ? perm + p : sink_slot<int32_t>(sink, lane)) = pos;
   __builtin_amdgcn_wave_barrier();
   load_rec<T, DIM>(p + 3 * 64, p1, xy, uw, zz, cur);
+  load_gbar<GB>(p + 3 * 64, p1, gb, cur);
   dc = dirc[load_index(p + 3 * 64, p1)];
   p += 64;
 }
@@ -1030,7 +1093,7 @@ __device__ __forceinline__ void scatter_round(const KParams &kp, const PC<T> &pc
 // lanes of earlier rounds and lower lanes of this round.  The particle state
 // is thus read twice and written once per step.
 // ---------------------------------------------------------------------------
-template <typename T, int DIM, bool PERM>
+template <typename T, int DIM, bool PERM, bool GB>
 __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, int C, const int32_t *__restrict__ bin_start,
                                                      const V2<T> *__restrict__ xy,
                                                      const V4<T> *__restrict__ uw, const T *__restrict__ zz,
@@ -1040,7 +1103,8 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, int C, const in
                                                      const int32_t *__restrict__ bsn, V2<T> *__restrict__ xo,
                                                      V4<T> *__restrict__ uo, T *__restrict__ zo, int ntot,
                                                      int32_t *__restrict__ err,
-                                                     int32_t *__restrict__ perm, void *__restrict__ sink) {
+                                                     int32_t *__restrict__ perm, void *__restrict__ sink,
+                                                     const T *__restrict__ gb) {
   constexpr int NDIR = DIM == 3 ? 27 : 9;
   extern __shared__ __attribute__((aligned(32))) unsigned char smem[];
   const int lane = threadIdx.x;
@@ -1075,10 +1139,13 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, int C, const in
   int p = p0 + lane, bad = 0;
   if (rounds > 0) {
     load_rec<T, DIM>(p, p1, xy, uw, zz, rb0);
+    load_gbar<GB>(p, p1, gb, rb0);
     db0 = dirc[load_index(p, p1)];
     load_rec<T, DIM>(p + 64, p1, xy, uw, zz, rb1);
+    load_gbar<GB>(p + 64, p1, gb, rb1);
     db1 = dirc[load_index(p + 64, p1)];
     load_rec<T, DIM>(p + 128, p1, xy, uw, zz, rb2);
+    load_gbar<GB>(p + 128, p1, gb, rb2);
     db2 = dirc[load_index(p + 128, p1)];
   }
   // enter the loop with nothing in flight, so that the waits in the loop
@@ -1086,8 +1153,8 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, int C, const in
   __builtin_amdgcn_s_waitcnt(0);
   const T sq0 = pc.q0, sq1 = pc.q1, sb0 = pc.b0, sb1 = pc.b1;
 #define RELSIM_SCATTER_ROUND(rb, db)                                                                            \
-  scatter_round<T, DIM, PERM>(kp, pc, sg, p1, lane, lt, ntot, xy, uw, zz, dirc, xo, uo, zo, perm, sink, sq0, sq1, \
-                              sb0, sb1, p, bad, rb, db)
+  scatter_round<T, DIM, PERM, GB>(kp, pc, sg, p1, lane, lt, ntot, xy, uw, zz, gb, dirc, xo, uo, zo, perm, sink, \
+                                  sq0, sq1, sb0, sb1, p, bad, rb, db)
   int r = 0;
 #pragma unroll 1
   for (; r + 3 <= rounds; r += 3) {
@@ -1232,45 +1299,87 @@ T *mp(void *p) {
 template <typename T, int G>
 void deposit_impl(const KParams &kp, const PartPtrs &pp, const void *Bst, void *S, hipStream_t st) {
   const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
-  hipLaunchKernelGGL((k_deposit_cells<T, G>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, cp<V2<T>>(pp.xy),
-                     cp<V4<T>>(pp.uw), cp<V4<T>>(Bst), mp<T>(S));
+  if (pp.gbar)
+    hipLaunchKernelGGL((k_deposit_cells<T, G, true>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start,
+                       cp<V2<T>>(pp.xy), cp<V4<T>>(pp.uw), cp<V4<T>>(Bst), mp<T>(S), cp<T>(pp.gbar));
+  else
+    hipLaunchKernelGGL((k_deposit_cells<T, G, false>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start,
+                       cp<V2<T>>(pp.xy), cp<V4<T>>(pp.uw), cp<V4<T>>(Bst), mp<T>(S), nullptr);
 }
 
 template <typename T>
 void deposit3_impl(const KParams &kp, const PartPtrs &pp, const void *Bst, void *S, hipStream_t st) {
   const int nblk = (kp.ncells + 15) / 16;
-  hipLaunchKernelGGL((k_deposit_split3<T>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, cp<V2<T>>(pp.xy),
-                     cp<V4<T>>(pp.uw), cp<T>(pp.z), cp<V4<T>>(Bst), mp<T>(S));
+  if (pp.gbar)
+    hipLaunchKernelGGL((k_deposit_split3<T, true>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start,
+                       cp<V2<T>>(pp.xy), cp<V4<T>>(pp.uw), cp<T>(pp.z), cp<V4<T>>(Bst), mp<T>(S), cp<T>(pp.gbar));
+  else
+    hipLaunchKernelGGL((k_deposit_split3<T, false>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start,
+                       cp<V2<T>>(pp.xy), cp<V4<T>>(pp.uw), cp<T>(pp.z), cp<V4<T>>(Bst), mp<T>(S), nullptr);
+}
+
+template <typename T, int DIM, bool COUNT, int GB>
+void push_launch(const KParams &kp, int C, const PartPtrs &pp, const void *Est, const void *Bst, uint8_t *dirc,
+                 uint16_t *cnt, int32_t *err, void *sink, void *gnx, unsigned long long *chg, hipStream_t st) {
+  const int nblk = kp.ncells / C;
+  const size_t lds = segment_lds_bytes<T, DIM>(C, kp.nspecies);
+  hipLaunchKernelGGL((k_push<T, DIM, COUNT, GB>), dim3(nblk), dim3(64), lds, st, kp, C, pp.bin_start,
+                     mp<V2<T>>(pp.xy), mp<V4<T>>(pp.uw), mp<T>(pp.z), cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, cnt, err,
+                     sink, cp<T>(pp.gbar), mp<T>(gnx), chg);
 }
 
 template <typename T, int DIM>
 void push_impl(const KParams &kp, int C, const PartPtrs &pp, const void *Est, const void *Bst, uint8_t *dirc,
                uint16_t *cnt, int32_t *err, int count_moves, void *sink, hipStream_t st) {
+  if (pp.gbar) {
+    if (count_moves)
+      push_launch<T, DIM, true, 1>(kp, C, pp, Est, Bst, dirc, cnt, err, sink, nullptr, nullptr, st);
+    else
+      push_launch<T, DIM, false, 1>(kp, C, pp, Est, Bst, dirc, cnt, err, sink, nullptr, nullptr, st);
+  } else {
+    if (count_moves)
+      push_launch<T, DIM, true, 0>(kp, C, pp, Est, Bst, dirc, cnt, err, sink, nullptr, nullptr, st);
+    else
+      push_launch<T, DIM, false, 0>(kp, C, pp, Est, Bst, dirc, cnt, err, sink, nullptr, nullptr, st);
+  }
+}
+
+template <typename T, int DIM>
+void gamma_mean_impl(const KParams &kp, int C, const PartPtrs &pp, const void *Est, const void *Bst, int32_t *err,
+                     void *sink, void *gnx, unsigned long long *chg, hipStream_t st) {
+  if (pp.gbar)
+    push_launch<T, DIM, false, 2>(kp, C, pp, Est, Bst, nullptr, nullptr, err, sink, gnx, chg, st);
+  else
+    push_launch<T, DIM, false, 3>(kp, C, pp, Est, Bst, nullptr, nullptr, err, sink, gnx, chg, st);
+}
+
+template <typename T, int DIM, bool PERM, bool GB>
+void scatter_launch(const KParams &kp, int C, const PartPtrs &src, const void *Est, const void *Bst,
+                    const uint8_t *dirc, const uint16_t *pre, const int32_t *bsn, const PartPtrs &out, int ntot,
+                    int32_t *err, int32_t *perm, void *sink, hipStream_t st) {
   const int nblk = kp.ncells / C;
   const size_t lds = segment_lds_bytes<T, DIM>(C, kp.nspecies);
-  if (count_moves)
-    hipLaunchKernelGGL((k_push<T, DIM, true>), dim3(nblk), dim3(64), lds, st, kp, C, pp.bin_start, mp<V2<T>>(pp.xy),
-                       mp<V4<T>>(pp.uw), mp<T>(pp.z), cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, cnt, err, sink);
-  else
-    hipLaunchKernelGGL((k_push<T, DIM, false>), dim3(nblk), dim3(64), lds, st, kp, C, pp.bin_start,
-                       mp<V2<T>>(pp.xy), mp<V4<T>>(pp.uw), mp<T>(pp.z), cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, cnt,
-                       err, sink);
+  hipLaunchKernelGGL((k_push_scatter<T, DIM, PERM, GB>), dim3(nblk), dim3(64), lds, st, kp, C, src.bin_start,
+                     cp<V2<T>>(src.xy), cp<V4<T>>(src.uw), cp<T>(src.z), cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, pre,
+                     bsn, mp<V2<T>>(out.xy), mp<V4<T>>(out.uw), mp<T>(out.z), ntot, err, perm, sink,
+                     cp<T>(src.gbar));
 }
 
 template <typename T, int DIM>
 void scatter_impl(const KParams &kp, int C, const PartPtrs &src, const void *Est, const void *Bst,
                   const uint8_t *dirc, const uint16_t *pre, const int32_t *bsn, const PartPtrs &out, int ntot,
                   int32_t *err, int32_t *perm, void *sink, hipStream_t st) {
-  const int nblk = kp.ncells / C;
-  const size_t lds = segment_lds_bytes<T, DIM>(C, kp.nspecies);
-  if (perm)
-    hipLaunchKernelGGL((k_push_scatter<T, DIM, true>), dim3(nblk), dim3(64), lds, st, kp, C, src.bin_start,
-                       cp<V2<T>>(src.xy), cp<V4<T>>(src.uw), cp<T>(src.z), cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, pre,
-                       bsn, mp<V2<T>>(out.xy), mp<V4<T>>(out.uw), mp<T>(out.z), ntot, err, perm, sink);
-  else
-    hipLaunchKernelGGL((k_push_scatter<T, DIM, false>), dim3(nblk), dim3(64), lds, st, kp, C, src.bin_start,
-                       cp<V2<T>>(src.xy), cp<V4<T>>(src.uw), cp<T>(src.z), cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, pre,
-                       bsn, mp<V2<T>>(out.xy), mp<V4<T>>(out.uw), mp<T>(out.z), ntot, err, perm, sink);
+  if (src.gbar) {
+    if (perm)
+      scatter_launch<T, DIM, true, true>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, perm, sink, st);
+    else
+      scatter_launch<T, DIM, false, true>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, perm, sink, st);
+  } else {
+    if (perm)
+      scatter_launch<T, DIM, true, false>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, perm, sink, st);
+    else
+      scatter_launch<T, DIM, false, false>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, perm, sink, st);
+  }
 }
 
 template <typename T, int DIM, int G>
@@ -1361,6 +1470,17 @@ void launch_push(const KParams &kp, int prec, int cells, const PartPtrs &pp, con
              : push_impl<double, 3>(kp, cells, pp, Est, Bst, dirc, cnt, err, count_moves, sink, st);
   return f ? push_impl<float, 2>(kp, cells, pp, Est, Bst, dirc, cnt, err, count_moves, sink, st)
            : push_impl<double, 2>(kp, cells, pp, Est, Bst, dirc, cnt, err, count_moves, sink, st);
+}
+
+void launch_gamma_mean(const KParams &kp, int prec, int cells, const PartPtrs &pp, const void *Est,
+                       const void *Bst, int32_t *err, void *sink, void *gbar_next, unsigned long long *chg,
+                       hipStream_t st) {
+  const bool f = prec == RELSIM_MIXED;
+  if (kp.dim == 3)
+    return f ? gamma_mean_impl<float, 3>(kp, cells, pp, Est, Bst, err, sink, gbar_next, chg, st)
+             : gamma_mean_impl<double, 3>(kp, cells, pp, Est, Bst, err, sink, gbar_next, chg, st);
+  return f ? gamma_mean_impl<float, 2>(kp, cells, pp, Est, Bst, err, sink, gbar_next, chg, st)
+           : gamma_mean_impl<double, 2>(kp, cells, pp, Est, Bst, err, sink, gbar_next, chg, st);
 }
 
 void launch_sort_offsets(const KParams &kp, const uint16_t *cnt, uint16_t *pre, int32_t *total, int32_t *err,

@@ -63,6 +63,7 @@ struct PartPtrs {
   void *xy;
   void *uw;
   void *z;
+  const void *gbar = nullptr;  // per-particle gbar of the energy-conserving variant, or null
 };
 
 // Ghosted, component-interleaved copy of a grid vector field (SoA FP64 on
@@ -81,6 +82,13 @@ void launch_assemble(const KParams &kp, int prec, const void *S, double *J, doub
 size_t push_lds_bytes(const KParams &kp, int prec, int cells);
 void launch_push(const KParams &kp, int prec, int cells, const PartPtrs &pp, const void *Est, const void *Bst,
                  uint8_t *dirc, uint16_t *cnt, int32_t *err, int count_moves, void *sink, hipStream_t st);
+// The energy-conserving variant's fixed-point pass: pushes each particle
+// with pp.gbar (gamma(u^n) if null) without touching the state, writes
+// gbar_next = (gamma(u^n) + gamma(u^{n+1}))/2 and raises *chg to the bits of
+// max |gbar_next - gbar| / gbar.
+void launch_gamma_mean(const KParams &kp, int prec, int cells, const PartPtrs &pp, const void *Est,
+                       const void *Bst, int32_t *err, void *sink, void *gbar_next, unsigned long long *chg,
+                       hipStream_t st);
 void launch_sort_offsets(const KParams &kp, const uint16_t *cnt, uint16_t *pre, int32_t *total, int32_t *err,
                          hipStream_t st);
 void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream_t st);

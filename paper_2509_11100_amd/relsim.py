@@ -244,15 +244,42 @@ def sort(ctx: Context, parts: Particles) -> None:
     parts._sync_front()
 
 
+def _gbar_ok(ctx: Context, parts: "Particles", *ts):
+    for t in ts:
+        if t is not None and (t.device != ctx.device or t.dtype != ctx.dtype or not t.is_contiguous()
+                              or t.numel() < parts.n):
+            raise ValueError("gbar arrays must be contiguous tensors of the particle type with at least n elements")
+
+
 def deposit_moments(ctx: Context, parts: Particles, B: torch.Tensor, J: Optional[torch.Tensor] = None,
-                    M: Optional[torch.Tensor] = None):
-    """relsim_deposit_moments -> (Jhat [3][N], M [noff][9][N])"""
+                    M: Optional[torch.Tensor] = None, gbar: Optional[torch.Tensor] = None):
+    """relsim_deposit_moments -> (Jhat [3][N], M [noff][9][N]); with gbar
+    (per particle, particle type), relsim_deposit_moments_ec"""
     J = ctx.grid() if J is None else J
     M = ctx.mass_matrix() if M is None else M
     _grid_ok(ctx, B, J, M)
     parts.s.n = parts.n
-    ctx.check(ctx.lib.relsim_deposit_moments(ctx.handle, C.byref(parts.s), _ptr(B), _ptr(J), _ptr(M)))
+    if gbar is None:
+        ctx.check(ctx.lib.relsim_deposit_moments(ctx.handle, C.byref(parts.s), _ptr(B), _ptr(J), _ptr(M)))
+    else:
+        _gbar_ok(ctx, parts, gbar)
+        ctx.check(ctx.lib.relsim_deposit_moments_ec(ctx.handle, C.byref(parts.s), _ptr(B), _ptr(gbar), _ptr(J),
+                                                    _ptr(M)))
     return J, M
+
+
+def gamma_mean(ctx: Context, parts: Particles, E_theta: torch.Tensor, B: torch.Tensor,
+               gbar: Optional[torch.Tensor], gbar_next: torch.Tensor) -> float:
+    """relsim_gamma_mean: gbar_next = (gamma(u^n) + gamma(u^{n+1}))/2 with
+    u^{n+1} pushed using gbar (None: gamma(u^n)); returns max |gbar_next -
+    gbar| / gbar"""
+    _grid_ok(ctx, E_theta, B)
+    _gbar_ok(ctx, parts, gbar, gbar_next)
+    parts.s.n = parts.n
+    out = C.c_double(0.0)
+    ctx.check(ctx.lib.relsim_gamma_mean(ctx.handle, C.byref(parts.s), _ptr(E_theta), _ptr(B), _ptr(gbar),
+                                        _ptr(gbar_next), C.byref(out)))
+    return out.value
 
 
 def field_solve(ctx: Context, M, J, E, B, E_theta=None, E1=None, B1=None, allow_unconverged: bool = False):
@@ -271,16 +298,22 @@ def field_solve(ctx: Context, M, J, E, B, E_theta=None, E1=None, B1=None, allow_
 
 
 def push(ctx: Context, parts: Particles, E_theta: torch.Tensor, B: torch.Tensor, resort: bool = True,
-         new_index: Optional[torch.Tensor] = None) -> None:
+         new_index: Optional[torch.Tensor] = None, gbar: Optional[torch.Tensor] = None) -> None:
     """relsim_push (with resort: the pushed state goes into the back buffers
     in the new order and the sets swap, leaving the old state in the back
-    set; new_index, int32 [n], receives each old particle's new position)"""
+    set; new_index, int32 [n], receives each old particle's new position);
+    with gbar, relsim_push_ec"""
     _grid_ok(ctx, E_theta, B)
     if new_index is not None and (new_index.dtype != torch.int32 or new_index.numel() < parts.n):
         raise ValueError("new_index must be an int32 tensor of at least n elements")
     parts.s.n = parts.n
-    ctx.check(ctx.lib.relsim_push(ctx.handle, C.byref(parts.s), _ptr(E_theta), _ptr(B), 1 if resort else 0,
-                                  _ptr(new_index)))
+    if gbar is None:
+        ctx.check(ctx.lib.relsim_push(ctx.handle, C.byref(parts.s), _ptr(E_theta), _ptr(B), 1 if resort else 0,
+                                      _ptr(new_index)))
+    else:
+        _gbar_ok(ctx, parts, gbar)
+        ctx.check(ctx.lib.relsim_push_ec(ctx.handle, C.byref(parts.s), _ptr(E_theta), _ptr(B), _ptr(gbar),
+                                         1 if resort else 0, _ptr(new_index)))
     parts._sync_front()
 
 
@@ -340,9 +373,17 @@ class Step:
     relsim_deposit_moments (S1-S3), relsim_field_solve (S4-S5) and
     relsim_push with re-sort (S6 + a1), in that order, on the context's
     stream.  Holds E^n and B^n (copies of the tensors given) and the per-step
-    grid arrays (J-hat, M, E_theta and the next fields), allocated once."""
+    grid arrays (J-hat, M, E_theta and the next fields), allocated once.
 
-    def __init__(self, ctx: Context, parts: Particles, E: torch.Tensor, B: torch.Tensor):
+    energy_conserving=True takes gbar = (gamma^n + gamma^{n+1})/2 in place
+    of gamma(u^n) (exact energy conservation when relativistic): each step
+    iterates deposit -> solve -> relsim_gamma_mean from gbar = gamma(u^n)
+    until the largest relative change of gbar is at most picard_tol (or
+    picard_maxit passes), then pushes with the gbar of the last pass.
+    picard_iters / picard_change hold the last step's passes and change."""
+
+    def __init__(self, ctx: Context, parts: Particles, E: torch.Tensor, B: torch.Tensor,
+                 energy_conserving: bool = False, picard_tol: float = 1e-12, picard_maxit: int = 30):
         _grid_ok(ctx, E, B)
         self.ctx, self.parts = ctx, parts
         self.E, self.B = E.clone(), B.clone()
@@ -350,13 +391,33 @@ class Step:
         self.E_theta = ctx.grid()
         self._E1, self._B1 = ctx.grid(), ctx.grid()
         self.iters, self.rel_resid = 0, 0.0
+        self.energy_conserving = energy_conserving
+        self.picard_tol, self.picard_maxit = picard_tol, picard_maxit
+        self.picard_iters, self.picard_change = 0, 0.0
+        if energy_conserving:
+            cap = max(parts.n, 1)
+            self._gb = [torch.empty(cap, dtype=ctx.dtype, device=ctx.device) for _ in range(2)]
+
+    def _solve(self, gbar):
+        deposit_moments(self.ctx, self.parts, self.B, self.J, self.M, gbar=gbar)
+        _, _, _, self.iters, self.rel_resid = field_solve(self.ctx, self.M, self.J, self.E, self.B, self.E_theta,
+                                                          self._E1, self._B1)
 
     def __call__(self, steps: int = 1) -> "Step":
         for _ in range(steps):
-            deposit_moments(self.ctx, self.parts, self.B, self.J, self.M)
-            _, _, _, self.iters, self.rel_resid = field_solve(self.ctx, self.M, self.J, self.E, self.B, self.E_theta,
-                                                              self._E1, self._B1)
-            push(self.ctx, self.parts, self.E_theta, self.B, resort=True)
+            gbar = None
+            if self.energy_conserving:
+                nxt = 0
+                for it in range(1, self.picard_maxit + 1):
+                    self._solve(gbar)
+                    self.picard_change = gamma_mean(self.ctx, self.parts, self.E_theta, self.B, gbar, self._gb[nxt])
+                    self.picard_iters = it
+                    if self.picard_change <= self.picard_tol or it == self.picard_maxit:
+                        break
+                    gbar, nxt = self._gb[nxt], 1 - nxt
+            else:
+                self._solve(None)
+            push(self.ctx, self.parts, self.E_theta, self.B, resort=True, gbar=gbar)
             self.E, self._E1 = self._E1, self.E
             self.B, self._B1 = self._B1, self.B
         return self

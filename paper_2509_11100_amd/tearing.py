@@ -117,7 +117,7 @@ def summarize(wl: harris.Workload, rec: dict, window=(0.5, 1.5)) -> dict:
 
 
 def run(steps: int, every: int, precision: str = "fp64", rtol: float = 1e-10, seed=None, log=sys.stdout,
-        **overrides):
+        energy_conserving: bool = False, picard_tol: float = 1e-12, **overrides):
     import torch
 
     from . import relsim
@@ -132,9 +132,10 @@ def run(steps: int, every: int, precision: str = "fp64", rtol: float = 1e-10, se
     ctx = relsim.Context(dim=2, nx=wl.nx, ny=wl.ny, dx=wl.dx, dt=wl.dt, precision=precision, q=wl.q, m=wl.m,
                          max_particles=n, gmres_rtol=rtol, gmres_restart=30, gmres_maxit=5000)
     parts = relsim.Particles(ctx).load(p["cell"], p["species"], p["off"], p["u"], p["w"], p["bin_start"])
-    step = relsim.Step(ctx, parts, torch.as_tensor(E).cuda(), torch.as_tensor(B).cuda())
+    step = relsim.Step(ctx, parts, torch.as_tensor(E).cuda(), torch.as_tensor(B).cuda(),
+                       energy_conserving=energy_conserving, picard_tol=picard_tol)
     mmax = len(modes)
-    rec = {"step": [], "t_gamma_th": [], "lowpass": [], "modes": [], "W": [], "gmres_iters": []}
+    rec = {"step": [], "t_gamma_th": [], "lowpass": [], "modes": [], "W": [], "gmres_iters": [], "picard_iters": []}
 
     def record(k):
         em = mode_energies(step.B, wl, mmax)
@@ -145,6 +146,7 @@ def run(steps: int, every: int, precision: str = "fp64", rtol: float = 1e-10, se
         rec["lowpass"].append(float(em.sum()))
         rec["W"].append([float(x) for x in W])
         rec["gmres_iters"].append(int(step.iters))
+        rec["picard_iters"].append(int(step.picard_iters))
 
     t0 = time.time()
     record(0)
@@ -161,7 +163,7 @@ def run(steps: int, every: int, precision: str = "fp64", rtol: float = 1e-10, se
     torch.cuda.synchronize()
     wall = time.time() - t0
     summary = summarize(wl, rec)
-    summary.update({"precision": precision, "particles": int(n), "steps": steps,
+    summary.update({"precision": precision, "energy_conserving": energy_conserving, "particles": int(n), "steps": steps,
                     "wall_s": wall, "ms_per_step": 1e3 * wall / max(steps, 1)})
     return summary, rec
 
@@ -173,12 +175,16 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--seed", type=int, default=None)
+    ap.add_argument("--energy-conserving", action="store_true",
+                    help="gbar = (gamma^n + gamma^{n+1})/2 by fixed-point iteration (exact energy)")
+    ap.add_argument("--picard-tol", type=float, default=1e-12)
     ap.add_argument("--ppc", type=int, default=None, help="particles per cell per species (default 256)")
     ap.add_argument("--dt-wpe", type=float, default=None, help="time step in 1 / omega_pe0 (default 0.758)")
     ap.add_argument("--out", default=None, help="write the summary and the records as JSON")
     args = ap.parse_args(argv)
     over = {k: v for k, v in (("ppc", args.ppc), ("dt_wpe", args.dt_wpe)) if v is not None}
-    summary, rec = run(args.steps, args.every, args.precision, args.rtol, args.seed, **over)
+    summary, rec = run(args.steps, args.every, args.precision, args.rtol, args.seed,
+                       energy_conserving=args.energy_conserving, picard_tol=args.picard_tol, **over)
     print(json.dumps(summary))
     if args.out:
         with open(args.out, "w") as f:

@@ -533,3 +533,94 @@ def test_tearing_electron_ion_end_to_end_fp64():
     assert normwise(Eg, Er) < 1e-9
     assert normwise(Bg, Br) < 1e-9
     np.testing.assert_allclose(Wg, Wr, rtol=1e-10)
+
+
+# ----------------------------------------------------------------------------
+# energy-conserving variant: gbar per particle
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("gname", ["2d_7x5", "3d_5x4x3"])
+def test_energy_conserving_passes(gname, precision):
+    """relsim_deposit_moments_ec, relsim_gamma_mean and relsim_push_ec with a
+    given gbar against the oracle's deposit and push with that gbar."""
+    need_gpu()
+    import torch
+
+    from paper_2509_11100_amd import relsim
+
+    g = grids()[gname]
+    rng = np.random.default_rng(90)
+    n = 3000
+    cell, sp, off, u, w = random_cells(g, n, rng, umax=2.5, empty_frac=0.2)
+    B = (2 * rng.random((3, g.N)) - 1) * 2.0
+    E = (2 * rng.random((3, g.N)) - 1) * 0.5
+    ctx = make_ctx(g, precision, n)
+    parts = load(ctx, cell, sp, off, u, w)
+    st = host_state(g, parts)
+    g0 = np.sqrt(1 + (st["u"] ** 2).sum(0))
+    gb = rounded(precision, g0 * (1 + 0.05 * rng.random(n)))
+    gbar = torch.as_tensor(gb, dtype=ctx.dtype, device="cuda")
+    J, M = relsim.deposit_moments(ctx, parts, torch_grid(B), gbar=gbar)
+    Jr, Mr = oracle.deposit(g, st["x"], st["u"], st["w"], st["species"], B, gb)
+    assert normwise(J.cpu().numpy(), Jr) < TOL[precision]
+    assert normwise(M.cpu().numpy(), Mr) < TOL[precision]
+    # the fixed-point pass, with the given gbar and from gamma(u^n)
+    xr, ur = oracle.push(g, st["x"], st["u"], st["species"], E, B, gb)
+    nxt = 0.5 * (g0 + np.sqrt(1 + (ur ** 2).sum(0)))
+    for given in (True, False):
+        gn = torch.empty(n, dtype=ctx.dtype, device="cuda")
+        ch = relsim.gamma_mean(ctx, parts, torch_grid(E), torch_grid(B), gbar if given else None, gn)
+        if given:
+            ref_next, ref_in = nxt, gb
+        else:
+            _, u0 = oracle.push(g, st["x"], st["u"], st["species"], E, B)
+            ref_next, ref_in = 0.5 * (g0 + np.sqrt(1 + (u0 ** 2).sum(0))), g0
+        np.testing.assert_allclose(gn.cpu().numpy(), ref_next, rtol=TOL[precision])
+        ref_ch = np.max(np.abs(ref_next - ref_in) / ref_in)
+        assert abs(ch - ref_ch) <= 1e-3 * ref_ch + TOL[precision]
+    # the state is untouched by the fixed-point pass
+    st2 = host_state(g, parts)
+    assert np.array_equal(st2["u"], st["u"]) and np.array_equal(st2["x"], st["x"])
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    relsim.push(ctx, parts, torch_grid(E), torch_grid(B), resort=True, new_index=perm, gbar=gbar)
+    s1 = host_state(g, parts)
+    new = perm.cpu().numpy().astype(np.int64)
+    assert normwise(s1["u"][:, new], ur) < TOL[precision]
+    disp = periodic_diff(g, xr, st["x"])
+    assert np.linalg.norm(periodic_diff(g, s1["x"][:, new], xr)) / np.linalg.norm(disp) < TOL[precision]
+
+
+def test_energy_conserving_steps_match_oracle_and_conserve_energy():
+    """Three energy-conserving FP64 steps of the 64 x 32 pair sheet (theta =
+    1, relativistic) against the oracle's fixed point; the energy stays
+    constant to the iteration's tolerance where the standard step drifts."""
+    need_gpu()
+    from paper_2509_11100_amd import relsim
+
+    wl, p, E, B = harris_inputs()
+    g = grid_of(wl)
+    steps = 3
+    ctx = make_ctx(g, "fp64", p["w"].shape[0], rtol=1e-13)
+    parts = load(ctx, p["cell"], p["species"], p["off"], p["u"], p["w"], p["bin_start"])
+    step = relsim.Step(ctx, parts, torch_grid(E), torch_grid(B), energy_conserving=True, picard_tol=1e-14)
+    W = [step.energy()]
+    for _ in range(steps):
+        step()
+        assert step.picard_change <= 1e-14 and step.picard_iters < 30
+        W.append(step.energy())
+    W = np.array(W)
+    x = positions(g, p["cell"], p["off"])
+    u, Er, Br = p["u"], E, B
+    sp = p["species"].astype(np.int32)
+    Wr = [oracle.energy(g, u, p["w"], sp, Er, Br)]
+    for _ in range(steps):
+        out = oracle.step_ec(g, x, u, p["w"], sp, Er, Br, tol=1e-14)
+        x, u, Er, Br = out["x"], out["u"], out["E"], out["B"]
+        Wr.append(out["W"])
+    Wr = np.array(Wr)
+    assert normwise(step.E.cpu().numpy(), Er) < 1e-9
+    assert normwise(step.B.cpu().numpy(), Br) < 1e-9
+    np.testing.assert_allclose(W, Wr, rtol=1e-10)
+    assert np.abs(W[:, 3] - W[0, 3]).max() < 1e-12 * W[0, 3]
+    print("energy-conserving steps: |dW|/W %.2e, passes %d" % (np.abs(W[:, 3] - W[0, 3]).max() / W[0, 3],
+                                                              step.picard_iters))
