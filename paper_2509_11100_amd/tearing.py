@@ -170,7 +170,8 @@ def run(steps: int, every: int, precision: str = "fp64", rtol: float = 1e-10, se
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--steps", type=int, default=45000)
+    ap.add_argument("--steps", type=int, default=None, help="default: to t gamma_th = --t-end")
+    ap.add_argument("--t-end", type=float, default=2.0, help="run length in units of 1 / gamma_th")
     ap.add_argument("--every", type=int, default=100)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--rtol", type=float, default=1e-10)
@@ -180,9 +181,17 @@ def main(argv=None):
     ap.add_argument("--picard-tol", type=float, default=1e-12)
     ap.add_argument("--ppc", type=int, default=None, help="particles per cell per species (default 256)")
     ap.add_argument("--dt-wpe", type=float, default=None, help="time step in 1 / omega_pe0 (default 0.758)")
+    ap.add_argument("--dx-rho", type=float, default=None,
+                    help="cell size in rho_Le,R (default 5); the box stays 1000 x 510 rho_Le,R, rounded to cells")
     ap.add_argument("--out", default=None, help="write the summary and the records as JSON")
     args = ap.parse_args(argv)
     over = {k: v for k, v in (("ppc", args.ppc), ("dt_wpe", args.dt_wpe)) if v is not None}
+    if args.dx_rho is not None:
+        over.update(dx_over_a=args.dx_rho / 20.0, nx=int(round(1000.0 / args.dx_rho)),
+                    ny=int(round(510.0 / args.dx_rho)))
+    if args.steps is None:
+        wl = harris.workload("tearing2d_200x102", **over)
+        args.steps = int(math.ceil(args.t_end * wl.harris.a / gamma_max(wl) / wl.dt))
     summary, rec = run(args.steps, args.every, args.precision, args.rtol, args.seed,
                        energy_conserving=args.energy_conserving, picard_tol=args.picard_tol, **over)
     print(json.dumps(summary))
