@@ -379,11 +379,13 @@ class Step:
     of gamma(u^n) (exact energy conservation when relativistic): each step
     iterates deposit -> solve -> relsim_gamma_mean from gbar = gamma(u^n)
     until the largest relative change of gbar is at most picard_tol (or
-    picard_maxit passes), then pushes with the gbar of the last pass.
+    picard_maxit passes), then pushes with the gbar of the last pass.  The
+    default tolerance is 1e-12 in FP64 and 1e-6 in mixed precision (FP32
+    particles round gbar at about 6e-8).
     picard_iters / picard_change hold the last step's passes and change."""
 
     def __init__(self, ctx: Context, parts: Particles, E: torch.Tensor, B: torch.Tensor,
-                 energy_conserving: bool = False, picard_tol: float = 1e-12, picard_maxit: int = 30):
+                 energy_conserving: bool = False, picard_tol: Optional[float] = None, picard_maxit: int = 30):
         _grid_ok(ctx, E, B)
         self.ctx, self.parts = ctx, parts
         self.E, self.B = E.clone(), B.clone()
@@ -392,6 +394,8 @@ class Step:
         self._E1, self._B1 = ctx.grid(), ctx.grid()
         self.iters, self.rel_resid = 0, 0.0
         self.energy_conserving = energy_conserving
+        if picard_tol is None:
+            picard_tol = 1e-12 if ctx.precision == "fp64" else 1e-6
         self.picard_tol, self.picard_maxit = picard_tol, picard_maxit
         self.picard_iters, self.picard_change = 0, 0.0
         if energy_conserving:

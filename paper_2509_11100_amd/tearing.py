@@ -30,6 +30,7 @@ import sys
 import time
 
 import numpy as np
+from typing import Optional
 
 from . import harris
 
@@ -117,7 +118,7 @@ def summarize(wl: harris.Workload, rec: dict, window=(0.5, 1.5)) -> dict:
 
 
 def run(steps: int, every: int, precision: str = "fp64", rtol: float = 1e-10, seed=None, log=sys.stdout,
-        energy_conserving: bool = False, picard_tol: float = 1e-12, **overrides):
+        energy_conserving: bool = False, picard_tol: Optional[float] = None, **overrides):
     import torch
 
     from . import relsim
@@ -178,7 +179,7 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=None)
     ap.add_argument("--energy-conserving", action="store_true",
                     help="gbar = (gamma^n + gamma^{n+1})/2 by fixed-point iteration (exact energy)")
-    ap.add_argument("--picard-tol", type=float, default=1e-12)
+    ap.add_argument("--picard-tol", type=float, default=None, help="default 1e-12 (FP64), 1e-6 (mixed)")
     ap.add_argument("--ppc", type=int, default=None, help="particles per cell per species (default 256)")
     ap.add_argument("--dt-wpe", type=float, default=None, help="time step in 1 / omega_pe0 (default 0.758)")
     ap.add_argument("--dx-rho", type=float, default=None,
