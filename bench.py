@@ -109,6 +109,42 @@ def measured_traffic(tag, kernel):
     return None if k is None else k["hbm_bytes"]
 
 
+def run_energy_conserving(prec, wl, host, steps, warmup, rtol, group=0):
+    """Whole energy-conserving steps (relsim.Step(energy_conserving=True):
+    fixed-point passes of deposit, solve and relsim_gamma_mean, then the
+    push) on the same workload: wall time per step, passes per step and the
+    relative energy change over the timed steps.  Not the headline metric."""
+    import numpy as np
+    import torch
+
+    from paper_2509_11100_amd import relsim
+
+    n = host["w"].shape[0]
+    ctx = relsim.Context(dim=wl.dim, nx=wl.nx, ny=wl.ny, nz=wl.nz if wl.dim == 3 else 1, dx=wl.dx, dt=wl.dt,
+                         precision=prec, q=wl.q, m=wl.m, max_particles=n, gmres_rtol=rtol, gmres_restart=30,
+                         gmres_maxit=5000, group=group)
+    parts = relsim.Particles(ctx).load(host["cell"], host["species"], host["off"], host["u"], host["w"],
+                                       host["bin_start"])
+    step = relsim.Step(ctx, parts, torch.as_tensor(host["E"]).cuda(), torch.as_tensor(host["B"]).cuda(),
+                       energy_conserving=True)
+    step(warmup)
+    W0 = step.energy()
+    passes = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+        passes.append(step.picard_iters)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    W1 = step.energy()
+    del step, parts, ctx
+    torch.cuda.empty_cache()
+    return {"precision": prec, "particle_steps_per_s": n * steps / wall, "ms_per_step": 1e3 * wall / steps,
+            "picard_tol": 1e-12 if prec == "fp64" else 1e-6, "passes_per_step": float(np.mean(passes)),
+            "rel_energy_change": float(abs(W1[3] - W0[3]) / W0[3])}
+
+
 def run_precision(prec, wl, host, steps, warmup, rtol, want_kernels=True, group=0):
     import numpy as np
     import torch
@@ -277,6 +313,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--cpu-sample", type=int, default=10_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--energy-conserving", action="store_true",
+                    help="also time the energy-conserving step (reported beside the headline, not in it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -344,6 +382,15 @@ def main():
             "frac_single_pass_min": round(head["value"] * fused / 1e9 / PEAK_HBM_GBS, 4),
         }
 
+    ec = None
+    if args.energy_conserving:
+        ec = {}
+        for p in precs:
+            log("running the energy-conserving step, %s" % p)
+            ec[p] = run_energy_conserving(p, wl, host, args.steps, args.warmup, args.rtol, group=args.group)
+            log("%s energy-conserving: %.3f ms/step, %.1f passes/step, |dW|/W %.2e" % (
+                p, ec[p]["ms_per_step"], ec[p]["passes_per_step"], ec[p]["rel_energy_change"]))
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on %d particles" % args.cpu_sample)
@@ -372,6 +419,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if ec is not None:
+        out["energy_conserving"] = ec
     if "mixed" in results and "fp64" in results:
         out["mixed_over_fp64"] = results["mixed"]["value"] / results["fp64"]["value"]
     print(json.dumps(out), flush=True)
