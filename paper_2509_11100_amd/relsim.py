@@ -381,7 +381,10 @@ class Step:
     until the largest relative change of gbar is at most picard_tol (or
     picard_maxit passes), then pushes with the gbar of the last pass.  The
     default tolerance is 1e-12 in FP64 and 1e-6 in mixed precision (FP32
-    particles round gbar at about 6e-8).
+    particles round gbar at about 6e-8).  The iteration starts from one
+    relsim_gamma_mean pass with the known E^n in place of E_theta (no
+    deposit or solve), which lands nearer the fixed point than gamma(u^n);
+    the fixed point itself does not depend on the start.
     picard_iters / picard_change hold the last step's passes and change."""
 
     def __init__(self, ctx: Context, parts: Particles, E: torch.Tensor, B: torch.Tensor,
@@ -411,7 +414,8 @@ class Step:
         for _ in range(steps):
             gbar = None
             if self.energy_conserving:
-                nxt = 0
+                gamma_mean(self.ctx, self.parts, self.E, self.B, None, self._gb[0])
+                gbar, nxt = self._gb[0], 1
                 for it in range(1, self.picard_maxit + 1):
                     self._solve(gbar)
                     self.picard_change = gamma_mean(self.ctx, self.parts, self.E_theta, self.B, gbar, self._gb[nxt])
