@@ -624,3 +624,36 @@ def test_energy_conserving_steps_match_oracle_and_conserve_energy():
     assert np.abs(W[:, 3] - W[0, 3]).max() < 1e-12 * W[0, 3]
     print("energy-conserving steps: |dW|/W %.2e, passes %d" % (np.abs(W[:, 3] - W[0, 3]).max() / W[0, 3],
                                                               step.picard_iters))
+
+
+def test_energy_conserving_argument_checks():
+    """relsim_gamma_mean refuses an output that aliases its input and a
+    misaligned gbar; the binding refuses gbar of the wrong type or length.
+    All are caught on the host before any kernel runs."""
+    need_gpu()
+    import ctypes as C
+
+    import torch
+
+    from paper_2509_11100_amd import relsim
+    from paper_2509_11100_amd._lib import RELSIM_EINVAL, RelsimError
+
+    g = grids()["2d_7x5"]
+    rng = np.random.default_rng(91)
+    n = 500
+    cell, sp, off, u, w = random_cells(g, n, rng, umax=2.0, empty_frac=0.0)
+    ctx = make_ctx(g, "fp64", n)
+    parts = load(ctx, cell, sp, off, u, w)
+    E, B = torch_grid(np.zeros((3, g.N))), torch_grid(np.ones((3, g.N)))
+    gb = torch.ones(n + 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(RelsimError) as ei:
+        relsim.gamma_mean(ctx, parts, E, B, gb, gb)
+    assert ei.value.code == RELSIM_EINVAL
+    parts.s.n = parts.n
+    rc = ctx.lib.relsim_gamma_mean(ctx.handle, C.byref(parts.s), E.data_ptr(), B.data_ptr(), gb.data_ptr() + 4,
+                                   gb.data_ptr(), C.byref(C.c_double()))
+    assert rc == RELSIM_EINVAL
+    with pytest.raises(ValueError):
+        relsim.deposit_moments(ctx, parts, B, gbar=torch.ones(n, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        relsim.push(ctx, parts, E, B, gbar=torch.ones(n - 1, dtype=torch.float64, device="cuda"))
