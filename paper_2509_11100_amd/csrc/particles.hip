@@ -951,7 +951,11 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, int C, const int32_t *_
   if constexpr (TRIAL) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, o));
-    if (lane == 0) atomicMax(chg, (unsigned long long)__double_as_longlong(dmax));
+    // one atomic per wave on a single address serialises (tens of thousands
+    // of waves); a wave whose value is not above the one already stored has
+    // nothing to add, so it reads first and skips the atomic
+    const unsigned long long v = (unsigned long long)__double_as_longlong(dmax);
+    if (lane == 0 && v > __hip_atomic_load(chg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(chg, v);
   }
   if constexpr (COUNT) {
     __syncthreads();
