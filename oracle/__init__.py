@@ -77,7 +77,7 @@ def _load():
             for name, args in sig.items():
                 fn = getattr(lib, name)
                 fn.argtypes = args
-                fn.restype = None
+                fn.restype = C.c_int if name == "oracle_deposit_nodes" else None
             _lib = lib
     return _lib
 
@@ -209,7 +209,9 @@ def deposit(g: Grid, x, u, w, species, B, gbar=None):
 
 
 def deposit_nodes(g: Grid, x, u, w, species, B, nodes):
-    """S1-S3 for a sample of nodes: (Jhat [3][ns], M [noff][9][ns])."""
+    """S1-S3 for a sample of nodes: (Jhat [3][ns], M [noff][9][ns]), the
+    columns ``nodes`` of deposit()'s result, bit for bit.  Node ids must be
+    distinct and in [0, N)."""
     lib = _load()
     x, px = _d(x)
     u, pu = _d(u)
@@ -222,7 +224,12 @@ def deposit_nodes(g: Grid, x, u, w, species, B, nodes):
     J, pJ = _d(np.zeros((3, ns)))
     M, pM = _d(np.zeros((g.noff, 9, ns)))
     cfg = g.cfg()
-    lib.oracle_deposit_nodes(C.byref(cfg), n, px, pu, pw, ps, pB, ns, nodes.ctypes.data_as(C.POINTER(C.c_long)), pJ, pM)
+    rc = lib.oracle_deposit_nodes(C.byref(cfg), n, px, pu, pw, ps, pB, ns,
+                                  nodes.ctypes.data_as(C.POINTER(C.c_long)), pJ, pM)
+    if rc == -2:
+        raise ValueError("deposit_nodes: node ids must be distinct and in [0, N)")
+    if rc != 0:
+        raise MemoryError("deposit_nodes: slot table allocation failed")
     return J, M
 
 
@@ -305,7 +312,8 @@ def push(g: Grid, x, u, species, Eth, Bn, gbar=None):
 
 
 def energy(g: Grid, u, w, species, E, B) -> np.ndarray:
-    """S7: (kinetic, electric, magnetic, total)."""
+    """S7: (kinetic, electric, magnetic, total), each sum compensated
+    (correct to a few ulps whatever the number of terms)."""
     lib = _load()
     u, pu = _d(u)
     w, pw = _d(w)

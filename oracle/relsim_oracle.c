@@ -208,16 +208,27 @@ void oracle_deposit(const ocfg *g, long n, const double *x, const double *u, con
 }
 
 /* S1-S3 restricted to a list of nodes (for sampled checks at large sizes):
- * Jout [3][ns], Mout [noff][9][ns] for nodes node_ids[ns]. */
-void oracle_deposit_nodes(const ocfg *g, long n, const double *x, const double *u, const double *w,
-                          const int32_t *sp, const double *B, long ns, const long *node_ids, double *Jout,
-                          double *Mout) {
+ * Jout [3][ns], Mout [noff][9][ns] for nodes node_ids[ns].  Each sampled
+ * node receives exactly the terms oracle_deposit adds into it, in the same
+ * particle order.  Returns 0, -1 if the slot table cannot be allocated, or
+ * -2 if a node id is out of range or listed twice (outputs then untouched). */
+int oracle_deposit_nodes(const ocfg *g, long n, const double *x, const double *u, const double *w,
+                         const int32_t *sp, const double *B, long ns, const long *node_ids, double *Jout,
+                         double *Mout) {
   long N = nnodes(g);
   int no = noff(g);
   double V = cellvol(g);
-  long *slot = (long *)malloc(sizeof(long) * N);
+  long *slot = (long *)malloc(sizeof(long) * (size_t)(N > 0 ? N : 1));
+  if (!slot) return -1;
   for (long i = 0; i < N; ++i) slot[i] = -1;
-  for (long s = 0; s < ns; ++s) slot[node_ids[s]] = s;
+  for (long s = 0; s < ns; ++s) {
+    long id = node_ids[s];
+    if (id < 0 || id >= N || slot[id] >= 0) {
+      free(slot);
+      return -2;
+    }
+    slot[id] = s;
+  }
   memset(Jout, 0, sizeof(double) * 3 * ns);
   memset(Mout, 0, sizeof(double) * (size_t)no * 9 * ns);
   for (long p = 0; p < n; ++p) {
@@ -252,6 +263,7 @@ void oracle_deposit_nodes(const ocfg *g, long n, const double *x, const double *
     }
   }
   free(slot);
+  return 0;
 }
 
 /* Difference along dim d, averaged over the transverse corners.
@@ -397,27 +409,48 @@ void oracle_push(const ocfg *g, long n, double *x, double *u, const int32_t *sp,
   }
 }
 
-/* S7: out = {kinetic, electric, magnetic, total} */
+/* Compensated running sum (Neumaier's variant of Kahan summation): the sum
+ * of n terms is then correct to a few ulps plus the terms' own rounding,
+ * whatever n, where a plain running sum loses up to about n ulps. */
+typedef struct {
+  double s, c;
+} csum;
+
+static void csum_add(csum *a, double v) {
+  double t = a->s + v;
+  if (fabs(a->s) >= fabs(v))
+    a->c += (a->s - t) + v;
+  else
+    a->c += (v - t) + a->s;
+  a->s = t;
+}
+
+static double csum_value(const csum *a) { return a->s + a->c; }
+
+/* S7: out = {kinetic, electric, magnetic, total}.  The kinetic energy per
+ * particle is w m c^2 (gamma - 1) = w m |u|^2 / (gamma + 1) (no cancellation
+ * at small |u|), or w m |u|^2 / 2 without relativity; each of the three sums
+ * is compensated. */
 void oracle_energy(const ocfg *g, long n, const double *u, const double *w, const int32_t *sp, const double *E,
                    const double *B, double out[4]) {
   long N = nnodes(g);
-  double ke = 0.0, we = 0.0, wb = 0.0;
+  csum ke = {0.0, 0.0}, we = {0.0, 0.0}, wb = {0.0, 0.0};
   for (long p = 0; p < n; ++p) {
     double up[3] = {u[p], u[n + p], u[2 * n + p]};
     double uu = up[0] * up[0] + up[1] * up[1] + up[2] * up[2];
     double m = g->m[sp[p]];
     if (g->nonrel)
-      ke += 0.5 * w[p] * m * uu;
+      csum_add(&ke, 0.5 * w[p] * m * uu);
     else
-      ke += w[p] * m * uu / (sqrt(1.0 + uu / (g->c * g->c)) + 1.0);
+      csum_add(&ke, w[p] * m * uu / (sqrt(1.0 + uu / (g->c * g->c)) + 1.0));
   }
   for (long i = 0; i < 3 * N; ++i) {
-    we += E[i] * E[i];
-    wb += B[i] * B[i];
+    csum_add(&we, E[i] * E[i]);
+    csum_add(&wb, B[i] * B[i]);
   }
   double V = cellvol(g);
-  out[0] = ke;
-  out[1] = V / (8.0 * M_PI) * we;
-  out[2] = V / (8.0 * M_PI) * wb;
+  out[0] = csum_value(&ke);
+  out[1] = V / (8.0 * M_PI) * csum_value(&we);
+  out[2] = V / (8.0 * M_PI) * csum_value(&wb);
   out[3] = out[0] + out[1] + out[2];
 }

@@ -70,3 +70,32 @@ def normwise(a, b) -> float:
     b = np.asarray(b, dtype=np.float64)
     den = np.linalg.norm(b.ravel())
     return float(np.linalg.norm((a - b).ravel()) / (den if den > 0 else 1.0))
+
+
+def maxrel(a, b) -> float:
+    """max |a - b| / max |b| (the elementwise measure beside the normwise one)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    den = np.abs(b).max() if b.size else 0.0
+    return float(np.abs(a - b).max() / (den if den > 0 else 1.0)) if a.size else 0.0
+
+
+def check_rel(a, b, tol: float, what: str = ""):
+    """Gate both ||a - b|| / ||b|| and max |a - b| / max |b| at tol; returns
+    the two errors."""
+    nw, mx = normwise(a, b), maxrel(a, b)
+    assert nw < tol, "%s normwise %.3e >= %.1e" % (what, nw, tol)
+    assert mx < tol, "%s max-abs/max-ref %.3e >= %.1e" % (what, mx, tol)
+    return nw, mx
+
+
+def check_disp(dx, disp, tol: float, what: str = "positions"):
+    """Position error relative to the displacement of the step, normwise and
+    as max |dx| / max |displacement|."""
+    dx = np.asarray(dx, dtype=np.float64)
+    disp = np.asarray(disp, dtype=np.float64)
+    nw = float(np.linalg.norm(dx) / np.linalg.norm(disp))
+    mx = float(np.abs(dx).max() / np.abs(disp).max()) if dx.size else 0.0
+    assert nw < tol, "%s normwise %.3e >= %.1e" % (what, nw, tol)
+    assert mx < tol, "%s max-abs/max-displacement %.3e >= %.1e" % (what, mx, tol)
+    return nw, mx

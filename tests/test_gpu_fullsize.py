@@ -16,9 +16,12 @@ cell per species (67,108,864 particles) and the 3D sheets 128 x 64 x 64 x 16
 both precisions.  (The 536,870,912-particle 3D sheet is in
 test_gpu_zlarge.py.)  Inputs are the seeded generator's; the mixed path
 is teacher-forced (the oracle receives the FP32-rounded particle state).
-Tolerances as in test_gpu_parity: 1e-12 (FP64) and 1e-5 (mixed), normwise;
-for the energy sums, the rounding bound of the oracle's sequential sums
-(4 x terms x eps relative, about 1e-9 here).
+Tolerances as in test_gpu_parity: 1e-12 (FP64) and 1e-5 (mixed), both
+normwise and as max |error| / max |reference|.  The energy sums are gated at
+1e-12 relative in both precisions: the oracle sums with compensation (exact
+to a few ulps whatever the number of terms) and the GPU in fixed-order blocks
+(error about 50 ulps at 5e8 terms); in mixed precision both sum the same
+FP32-held state in FP64.
 """
 import os
 
@@ -28,7 +31,7 @@ import pytest
 import oracle
 from paper_2509_11100_amd import harris
 from tests.gpu_helpers import load, make_ctx, need_gpu, rounded
-from tests.helpers import grid_of, normwise, periodic_diff, positions
+from tests.helpers import check_disp, check_rel, grid_of, normwise, periodic_diff, positions
 
 pytestmark = pytest.mark.gpu
 
@@ -92,8 +95,8 @@ def check_deposit(wl, p, B, ctx, parts, precision):
     nt = torch.as_tensor(nodes, device=J.device)
     Jg = J[:, nt].cpu().numpy()
     Mg = M[:, :, nt].cpu().numpy()
-    assert normwise(Jg, Jr) < TOL[precision]
-    assert normwise(Mg, Mr) < TOL[precision]
+    check_rel(Jg, Jr, TOL[precision])
+    check_rel(Mg, Mr, TOL[precision])
     return J, M
 
 
@@ -127,10 +130,10 @@ def check_push(wl, p, E, B, ctx, parts, J, M, precision):
     x0 = positions(g, p["cell"][old], off0)
     u0 = rounded(precision, p["u"][:, old])
     xr, ur = oracle.push(g, x0, u0, p["species"][old].astype(np.int32), Eth.cpu().numpy(), B)
-    assert normwise(u1, ur) < TOL[precision]
+    check_rel(u1, ur, TOL[precision])
     dx = periodic_diff(g, positions(g, cell1, off1), xr)
     disp = periodic_diff(g, xr, x0)
-    assert np.linalg.norm(dx) / np.linalg.norm(disp) < TOL[precision]
+    check_disp(dx, disp, TOL[precision])
     np.testing.assert_array_equal(w1, rounded(precision, p["w"][old]))
     assert np.all((off1 >= 0) & (off1 < 1))
     # the whole re-sorted state is in bin order and bin_start matches it
@@ -148,12 +151,14 @@ def check_energy(wl, p, E, B, ctx, parts, precision):
     W = relsim.energy(ctx, parts, cuda_grid(E), cuda_grid(B))
     Wr = oracle.energy(g, rounded(precision, p["u"]), rounded(precision, p["w"]), p["species"].astype(np.int32), E,
                        B)
-    # the oracle sums sequentially, so its rounding error grows with the
-    # number of terms (bound: terms x eps); the GPU sums in blocks
+    # the oracle's sums are compensated (a few ulps whatever the number of
+    # terms); the GPU's blocked fixed-order sums stay within about 50 ulps
     eps = np.finfo(np.float64).eps
-    tol = [4 * n * eps, 4 * 3 * g.N * eps, 4 * 3 * g.N * eps]
+    rel = [abs(W[k] - Wr[k]) / abs(Wr[k]) for k in range(3)]
+    print("%s %s energy rel. errors: kinetic %.2e electric %.2e magnetic %.2e (%d particles)"
+          % (wl.name, precision, rel[0], rel[1], rel[2], n))
     for k in range(3):
-        assert abs(W[k] - Wr[k]) <= tol[k] * abs(Wr[k])
+        assert rel[k] <= 1e-12, (k, rel[k])
     np.testing.assert_allclose(W[3], W[0] + W[1] + W[2], rtol=4 * eps)
 
 

@@ -7,7 +7,10 @@ oracle fails at least one of them:
   rotation operator   alpha solves (I + [b]x) ubar = v; 2 alpha - I is a rotation
   gather/push         exact gyration angle 2 atan(Omega dt/2); exact E x B drift
   deposit             partition of unity; cold-plasma closed form; dense
-                      brute-force assembly; node-pair symmetry and PSD
+                      brute-force assembly; node-pair symmetry and PSD; the
+                      sampled-node deposit equals the full deposit's columns
+  energy              one particle's closed form (relativistic and not); the
+                      compensated sums exact for many equal terms
   curls               transpose pair; curl of a gradient vanishes; second-order
                       convergence to the analytic curl
   field solve         vacuum wave phase 2 atan(c dt sin(k dx/2)/dx) with exact
@@ -450,3 +453,79 @@ def test_energy_conserving_variant_reduces_to_the_standard_step():
     assert b["iters"] == 1
     for k in ("E", "B", "x", "u", "W"):
         assert np.array_equal(a[k], b[k])
+
+
+# ----------------------------------------------------------------------------
+# sampled-node deposit (the reference of the full-size parity checks)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(2, 3, 3, 1), (2, 7, 5, 1), (3, 3, 3, 3), (3, 5, 4, 3)])
+def test_deposit_nodes_equals_the_full_deposit_columns(shape):
+    """deposit_nodes adds, into each sampled node, the same terms in the same
+    particle order as deposit (itself pinned by the dense brute force above),
+    so its result is those columns bit for bit, for any sample of nodes."""
+    dim, nx, ny, nz = shape
+    g = small_grid(dim, nx=nx, ny=ny, nz=nz)
+    rng = np.random.default_rng(300 + nx * ny * nz)
+    x, u, w, sp, E, B = random_state(g, 700, rng, umax=3.0, bmax=2.0)
+    J, M = oracle.deposit(g, x, u, w, sp, B)
+    for nodes in (np.arange(g.N), rng.permutation(g.N)[: max(1, g.N // 3)], np.array([g.N - 1, 0])):
+        Jn, Mn = oracle.deposit_nodes(g, x, u, w, sp, B, nodes)
+        np.testing.assert_array_equal(Jn, J[:, nodes])
+        np.testing.assert_array_equal(Mn, M[:, :, nodes])
+    # no particles: exact zeros
+    Jn, Mn = oracle.deposit_nodes(g, x[:, :0], u[:, :0], w[:0], sp[:0], B, np.arange(g.N))
+    assert not Jn.any() and not Mn.any()
+
+
+def test_deposit_nodes_rejects_repeated_or_out_of_range_nodes():
+    g = small_grid(2, nx=4, ny=3)
+    rng = np.random.default_rng(5)
+    x, u, w, sp, E, B = random_state(g, 50, rng)
+    for bad in ([0, 3, 3], [g.N], [-1]):
+        with pytest.raises(ValueError):
+            oracle.deposit_nodes(g, x, u, w, sp, B, np.array(bad))
+
+
+# ----------------------------------------------------------------------------
+# S7 energy sums
+# ----------------------------------------------------------------------------
+def test_kinetic_energy_of_one_particle_closed_form():
+    """w m c^2 (gamma - 1) with |u| = 5 c (gamma = sqrt 26), and w m |u|^2 / 2
+    without relativity; fields enter as V/(8 pi) sum |F|^2."""
+    g = small_grid(2, nx=3, ny=3, c=2.0, q=(1.0, -1.0), m=(3.0, 0.5))
+    u = np.array([[3.0 * 2.0], [0.0], [4.0 * 2.0]])
+    w = np.array([0.7])
+    E = np.zeros((3, g.N))
+    B = np.zeros((3, g.N))
+    E[1, 4] = 2.0
+    B[2, 0] = 3.0
+    W = oracle.energy(g, u, w, np.array([1], np.int32), E, B)
+    assert abs(W[0] - 0.7 * 0.5 * 4.0 * (math.sqrt(26.0) - 1.0)) <= 4e-16 * W[0]
+    assert abs(W[1] - g.V / (8 * math.pi) * 4.0) <= 4e-16 * W[1]
+    assert abs(W[2] - g.V / (8 * math.pi) * 9.0) <= 4e-16 * W[2]
+    gn = small_grid(2, nx=3, ny=3, c=2.0, q=(1.0, -1.0), m=(3.0, 0.5), nonrel=True)
+    Wn = oracle.energy(gn, u, w, np.array([1], np.int32), E, B)
+    assert abs(Wn[0] - 0.5 * 0.7 * 0.5 * 100.0) <= 4e-16 * Wn[0]
+
+
+def test_energy_sums_are_exact_for_many_equal_terms():
+    """Many equal terms: the sum is n times one term (computed once, in
+    exact integer multiples) to a few ulps, whatever n.  A plain running sum
+    drifts by about n/2 ulps here (shown beside it), so this pins the
+    compensated summation the full-size energy checks rely on."""
+    n = 1 << 21
+    g = small_grid(2, nx=1024, ny=1024)
+    u = np.tile(np.array([[0.1], [0.3], [0.7]]), (1, n))
+    w = np.full(n, 0.1)
+    sp = np.zeros(n, np.int32)
+    E = np.full((3, g.N), 0.1)
+    B = np.full((3, g.N), 0.3)
+    W = oracle.energy(g, u, w, sp, E, B)
+    uu = 0.1 * 0.1 + 0.3 * 0.3 + 0.7 * 0.7
+    term = 0.1 * 1.0 * uu / (math.sqrt(1.0 + uu) + 1.0)
+    eps = np.finfo(np.float64).eps
+    assert abs(W[0] - n * term) <= 4 * eps * n * term
+    assert abs(W[1] - g.V / (8 * math.pi) * (3 * g.N) * (0.1 * 0.1)) <= 8 * eps * W[1]
+    assert abs(W[2] - g.V / (8 * math.pi) * (3 * g.N) * (0.3 * 0.3)) <= 8 * eps * W[2]
+    naive = np.cumsum(np.full(n, term))[-1]
+    assert abs(naive - n * term) > 100 * eps * n * term
