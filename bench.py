@@ -11,6 +11,17 @@ the stream the library launches on); the field solve and the energy
 diagnostic are timed and reported separately.  Inputs are generated on the host, copied to HBM,
 and are resident before the timed region starts.
 
+A second workload, the 3D double Harris sheet 128 x 64 x 64 cells x 16
+particles per cell per species (16,777,216 particles, 27-offset mass matrix),
+is timed the same way after the headline and reported under "secondary".
+
+The CPU-baseline leg runs the oracle (plain C, FP64) on the host: once on one
+thread over a bounded sample, once on every host core over the whole
+workload (one thread per chunk of particles, private J-hat/M copies summed in
+a fixed order), and it reports the error of every GPU result against the
+oracle on the same inputs: J-hat and M at sampled nodes, the pushed
+particles at a sample followed through the re-sort, and the FP64 energy.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 One JSON line is printed on stdout.
 """
@@ -261,45 +272,262 @@ def device_copy_bandwidth(nbytes=1 << 30, reps=10):
 
 def path_bytes_per_particle(wl, prec, n, nbins, ncells):
     """Algorithmic bytes per particle-step of this design (deposit + push +
-    re-sort, as separate kernels) and the single-pass minimum (one read and
-    one write of the particle state plus the per-step grid traffic: M and
-    J-hat written once, E_theta and B^n read once)."""
+    re-sort, as separate kernels) and the fused minimum of a step: one read
+    and one write of each particle's offsets, momentum and weight (the mixed
+    state counted with a 4-byte cell index beside its FP32 values), plus the
+    grid traffic of a step with push and the next deposit in one pass: M and
+    J-hat written once, E_theta, B^n and B^{n+1} read once per node."""
     T = 4 if prec == "mixed" else 8
     d = wl.dim
     noff = 27 if d == 3 else 9
     this = sum(kernel_bytes(k, wl, prec, n, nbins, ncells) for k in
                ("deposit_cells", "assemble_nodes", "push_count", "push_scatter")) / n
     state = (d + 4) * T
-    grid = ncells * (8 * 9 * noff + 3 * 24) / n
-    return this, 2 * state + grid
+    grid = ncells * (8 * 9 * noff + 24 + 3 * 24) / n
+    return this, 2 * state + (4 if prec == "mixed" else 0) + grid
 
 
-def cpu_baseline(wl, host, nsample):
-    """The CPU oracle (serial C, FP64) on the first nsample particles of the
-    same workload: deposit (S1-S3) + push (S6), one step."""
+def sample_nodes_and_particles(wl, host, seed=7):
+    """The sampled outputs compared with the oracle: about 150 random nodes
+    plus the box corners and the sheet centres (their J-hat and M depend only
+    on the particles of the cells around them), and about 20,000 random
+    particles followed through the re-sort."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    N = wl.ncells
+    nodes = np.unique(np.concatenate([rng.integers(0, N, 150), [0, wl.nx - 1, N - 1],
+                                      [wl.nx * (wl.ny // 4), wl.nx * (3 * wl.ny // 4)]]))
+    i, j, k = nodes % wl.nx, (nodes // wl.nx) % wl.ny, nodes // (wl.nx * wl.ny)
+    cells = []
+    for a in range(1 << wl.dim):
+        ii = (i - (a & 1)) % wl.nx
+        jj = (j - ((a >> 1) & 1)) % wl.ny
+        kk = (k - ((a >> 2) & 1)) % wl.nz if wl.dim == 3 else 0
+        cells.append(ii + wl.nx * (jj + wl.ny * kk))
+    cells = np.unique(np.concatenate(cells))
+    S = wl.nspecies
+    b = host["bin_start"]
+    around = np.concatenate([np.arange(b[c * S], b[c * S + S]) for c in cells])
+    n = host["w"].shape[0]
+    parts = np.unique(np.concatenate([np.random.default_rng(seed + 4).integers(0, n, 20000), [0, n - 1]]))
+    return nodes, around, parts
+
+
+def gpu_sampled_results(prec, wl, host, rtol):
+    """One deposit, solve and push + re-sort of the initial state on a fresh
+    context (outside any timed region), read back at the sampled nodes and
+    particles, plus the energy of the initial state."""
+    import numpy as np
+    import torch
+
+    from paper_2509_11100_amd import relsim
+
+    n = host["w"].shape[0]
+    nodes, _, sel = sample_nodes_and_particles(wl, host)
+    ctx = relsim.Context(dim=wl.dim, nx=wl.nx, ny=wl.ny, nz=wl.nz if wl.dim == 3 else 1, dx=wl.dx, dt=wl.dt,
+                         precision=prec, q=wl.q, m=wl.m, max_particles=n, gmres_rtol=rtol, gmres_restart=30,
+                         gmres_maxit=5000)
+    parts = relsim.Particles(ctx).load(host["cell"], host["species"], host["off"], host["u"], host["w"],
+                                       host["bin_start"])
+    E = torch.as_tensor(host["E"]).cuda()
+    B = torch.as_tensor(host["B"]).cuda()
+    W = relsim.energy(ctx, parts, E, B)
+    J, M = relsim.deposit_moments(ctx, parts, B)
+    nt = torch.as_tensor(nodes, device=J.device)
+    out = {"W": W, "J": J[:, nt].cpu().numpy(), "M": M[:, :, nt].cpu().numpy()}
+    Eth, _, _, _, _ = relsim.field_solve(ctx, M, J, E, B)
+    del J, M
+    perm = torch.empty(n, dtype=torch.int32, device=E.device)
+    relsim.push(ctx, parts, Eth, B, resort=True, new_index=perm)
+    out["clamps"] = relsim.placement_clamps(ctx)
+    new = perm[torch.as_tensor(sel, device=E.device)].long()
+    del perm
+    out["cell"] = parts.cell[new].cpu().numpy()
+    out["off"] = np.stack([o[new].cpu().numpy().astype(np.float64) for o in parts.off])
+    out["u"] = np.stack([c[new].cpu().numpy().astype(np.float64) for c in parts.u])
+    out["E_theta"] = Eth.cpu().numpy()
+    del parts, ctx, E, B, Eth
+    torch.cuda.empty_cache()
+    return out
+
+
+def _oracle_grid(wl):
+    import oracle
+
+    return oracle.Grid(dim=wl.dim, nx=wl.nx, ny=wl.ny, nz=wl.nz if wl.dim == 3 else 1, dx=wl.dx, dy=wl.dx, dz=wl.dx,
+                       dt=wl.dt, q=wl.q, m=wl.m)
+
+
+def _positions(wl, cell, off):
+    import numpy as np
+
+    c = np.asarray(cell, dtype=np.int64)
+    xs = [((c % wl.nx) + off[0]) * wl.dx, (((c // wl.nx) % wl.ny) + off[1]) * wl.dx]
+    if wl.dim == 3:
+        xs.append(((c // (wl.nx * wl.ny)) + off[2]) * wl.dx)
+    return np.stack(xs)
+
+
+def _errors(a, b):
+    import numpy as np
+
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return {"normwise": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+            "max_abs_over_max_ref": float(np.abs(a - b).max() / np.abs(b).max())}
+
+
+def oracle_errors(prec, wl, host, gpu):
+    """Error of the GPU results against the oracle on the same inputs (the
+    mixed run's inputs rounded to FP32 and promoted for the oracle)."""
     import numpy as np
 
     import oracle
 
-    g = oracle.Grid(dim=wl.dim, nx=wl.nx, ny=wl.ny, nz=wl.nz if wl.dim == 3 else 1, dx=wl.dx, dy=wl.dx, dz=wl.dx,
-                    dt=wl.dt, q=wl.q, m=wl.m)
-    c = host["cell"][:nsample].astype(np.int64)
-    off = host["off"][:, :nsample]
-    xs = [((c % wl.nx) + off[0]) * wl.dx, (((c // wl.nx) % wl.ny) + off[1]) * wl.dx]
-    if wl.dim == 3:
-        xs.append(((c // (wl.nx * wl.ny)) + off[2]) * wl.dx)
-    x = np.stack(xs)
-    u = np.ascontiguousarray(host["u"][:, :nsample])
-    w = np.ascontiguousarray(host["w"][:nsample])
-    sp = host["species"][:nsample].astype(np.int32)
+    def r(a):
+        a = np.asarray(a, dtype=np.float64)
+        return a.astype(np.float32).astype(np.float64) if prec == "mixed" else a
+
+    g = _oracle_grid(wl)
+    nodes, around, sel = sample_nodes_and_particles(wl, host)
+    sp = host["species"].astype(np.int32)
+    Jr, Mr = oracle.deposit_nodes(g, _positions(wl, host["cell"][around], r(host["off"][:, around])),
+                                  r(host["u"][:, around]), r(host["w"][around]), sp[around], host["B"], nodes)
+    x0 = _positions(wl, host["cell"][sel], r(host["off"][:, sel]))
+    xr, ur = oracle.push(g, x0, r(host["u"][:, sel]), sp[sel], gpu["E_theta"], host["B"])
+    L = np.array(g.L)[:, None]
+    dx = _positions(wl, gpu["cell"], gpu["off"]) - xr
+    dx -= L * np.round(dx / L)
+    disp = xr - x0
+    disp -= L * np.round(disp / L)
+    Wr = oracle.energy(g, r(host["u"]), r(host["w"]), sp, host["E"], host["B"])
+    W = gpu["W"]
+    return {
+        "J_sampled_nodes": _errors(gpu["J"], Jr),
+        "M_sampled_nodes": _errors(gpu["M"], Mr),
+        "u_pushed_sampled": _errors(gpu["u"], ur),
+        "x_pushed_sampled_over_displacement": {
+            "normwise": float(np.linalg.norm(dx) / np.linalg.norm(disp)),
+            "max_abs_over_max_ref": float(np.abs(dx).max() / np.abs(disp).max())},
+        # relative to each part, or to the total where the part is zero (E^0 = 0)
+        "energy_rel": {k: float(abs(W[i] - Wr[i]) / (abs(Wr[i]) if Wr[i] != 0 else abs(Wr[3]))) for i, k in
+                       enumerate(("kinetic", "electric", "magnetic", "total"))},
+        "placement_clamps": int(gpu["clamps"]),
+        "samples": {"nodes": int(nodes.size), "particles": int(sel.size)},
+    }
+
+
+def host_cores():
+    """Host cores this process may use, capped at the 16 a one-GPU machine gives."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(wl, host, nsample, all_cores=True):
+    """The CPU oracle (plain C, FP64) on the same work as the metric, deposit
+    (S1-S3) + push (S6), one step: on one thread over the first nsample
+    particles, and on every host core over all particles (one thread per
+    contiguous chunk; the C calls release the interpreter lock; each chunk
+    deposits into its own J-hat/M, summed in chunk order)."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    import oracle
+
+    g = _oracle_grid(wl)
     oracle.build(force=False)
+    n_all = host["w"].shape[0]
+    sp_all = host["species"].astype(np.int32)
+
+    def work(lo, hi):
+        x = _positions(wl, host["cell"][lo:hi], host["off"][:, lo:hi])
+        u = np.ascontiguousarray(host["u"][:, lo:hi])
+        J, M = oracle.deposit(g, x, u, np.ascontiguousarray(host["w"][lo:hi]), sp_all[lo:hi], host["B"])
+        oracle.push(g, x, u, sp_all[lo:hi], host["E"], host["B"])
+        return J, M
+
+    nsample = min(nsample, n_all)
     t = time.perf_counter()
-    oracle.deposit(g, x, u, w, sp, host["B"])
-    oracle.push(g, x, u, sp, host["E"], host["B"])
-    dt = time.perf_counter() - t
-    return {"value": nsample / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d particles (bin order) of the same workload, one step of deposit (S1-S3) + push (S6), "
-                      "serial C FP64, %.1f s" % (nsample, dt)}
+    work(0, nsample)
+    dt1 = time.perf_counter() - t
+    out = {"value": nsample / dt1, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+           "sample": "first %d particles (bin order) of the same workload, one step of deposit (S1-S3) + push (S6), "
+                     "plain C FP64 on one thread, %.1f s" % (nsample, dt1)}
+    if all_cores:
+        cores = host_cores()
+        bounds = np.linspace(0, n_all, cores + 1).astype(np.int64)
+        t = time.perf_counter()
+        with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+            res = list(ex.map(lambda k: work(int(bounds[k]), int(bounds[k + 1])), range(cores)))
+        J, M = res[0]
+        for Jk, Mk in res[1:]:
+            J += Jk
+            M += Mk
+        dtn = time.perf_counter() - t
+        del res, J, M
+        out["all_cores"] = {"value": n_all / dtn, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+                            "sample": "all %d particles of the workload, one step of deposit + push, %d threads "
+                                      "(one chunk each, private J-hat/M summed in chunk order), %.1f s"
+                                      % (n_all, cores, dtn)}
+    return out
+
+
+def roofline_of(res, wl, copy_gbs):
+    """HBM roofline of the dominant particle kernel of a timed run, and of the
+    whole path."""
+    prec = res["precision"]
+    n = res["particles"]
+    nbins = wl.ncells * wl.nspecies
+    cand = {k: v for k, v in res["kernels"].items() if kernel_bytes(k, wl, prec, n, nbins, wl.ncells)}
+    if not cand:
+        return None
+    dom = max(cand, key=lambda k: cand[k]["ms_per_launch"] * cand[k]["launches"])
+    byt = kernel_bytes(dom, wl, prec, n, nbins, wl.ncells)
+    ach = byt / (cand[dom]["ms_per_launch"] * 1e-3) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(ach / PEAK_HBM_GBS, 4),
+            "traffic": measured_traffic("%s_%s" % (wl.name, prec), dom),
+            "bytes_per_launch": byt, "ms_per_launch": round(cand[dom]["ms_per_launch"], 4)}
+    per_kernel = {}
+    for k, v in cand.items():
+        b = kernel_bytes(k, wl, prec, n, nbins, wl.ncells)
+        per_kernel[k] = round(b / (v["ms_per_launch"] * 1e-3) / 1e9, 1)
+    roof["achieved_by_kernel_GBs"] = per_kernel
+    roof["measured_copy_GBs"] = round(copy_gbs, 1)
+    roof["frac_of_measured_copy"] = round(ach / copy_gbs, 4)
+    this, fused = path_bytes_per_particle(wl, prec, n, nbins, wl.ncells)
+    roof["path"] = {
+        "bytes_per_particle_step": round(this, 2),
+        "achieved_GBs": round(res["value"] * this / 1e9, 1),
+        "frac": round(res["value"] * this / 1e9 / PEAK_HBM_GBS, 4),
+        "fused_min_bytes_per_particle_step": round(fused, 2),
+        "frac_fused_min": round(res["value"] * fused / 1e9 / PEAK_HBM_GBS, 4),
+        "particle_steps_per_s_at_half_of_peak_fused": round(0.5 * PEAK_HBM_GBS * 1e9 / fused, -7),
+    }
+    return roof
+
+
+def make_inputs(name):
+    from paper_2509_11100_amd import harris
+
+    wl = harris.workload(name)
+    log("generating %s: %d particles" % (wl.name, wl.nparticles))
+    t = time.perf_counter()
+    host = harris.make_particles(wl, workers=host_cores())
+    host["E"], host["B"] = harris.make_fields(wl)
+    log("inputs ready in %.1f s" % (time.perf_counter() - t))
+    return wl, host
+
+
+def workload_label(wl, n, rtol):
+    return "%s: %dD double Harris sheet %s cells, %d particles/cell/species, %d particles, dt = 0.5 dx/c, " \
+           "GMRES rtol %g" % (wl.name, wl.dim, "x".join(str(v) for v in (wl.nx, wl.ny, wl.nz)[:wl.dim]), wl.ppc, n,
+                              rtol)
 
 
 def main():
@@ -308,11 +536,15 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="harris2d_1024x512")
+    ap.add_argument("--secondary", default="harris3d_128x64x64",
+                    help="second workload timed after the headline ('none' to skip)")
+    ap.add_argument("--secondary-steps", type=int, default=10)
     ap.add_argument("--precision", default="both", choices=["both", "mixed", "fp64"])
     ap.add_argument("--group", type=int, default=0, help="lanes per cell in the deposit and energy kernels (0 = automatic)")
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--cpu-sample", type=int, default=10_000_000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (its timings and the errors against it)")
     ap.add_argument("--energy-conserving", action="store_true",
                     help="also time the energy-conserving step (reported beside the headline, not in it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -322,18 +554,12 @@ def main():
         print("bench.py measures one GPU; the multi-GPU path is not built. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
-    from paper_2509_11100_amd import _lib, harris
+    from paper_2509_11100_amd import _lib
 
     _lib.load()  # fail loudly before the long input generation
-    wl = harris.workload(args.workload)
-    log("generating %s: %d particles" % (wl.name, wl.nparticles))
-    t = time.perf_counter()
-    host = harris.make_particles(wl, workers=min(16, os.cpu_count() or 1))
-    host["E"], host["B"] = harris.make_fields(wl)
-    log("inputs ready in %.1f s" % (time.perf_counter() - t))
+    wl, host = make_inputs(args.workload)
     torch.cuda.set_device(0)
 
     if args.copy_probe_mib:
@@ -351,36 +577,11 @@ def main():
         results[p] = run_precision(p, wl, host, args.steps, args.warmup, args.rtol, group=args.group)
         log("%s: %.4g particle-steps/s, hot %.3f ms/step, solve %.3f ms/step" % (
             p, results[p]["value"], results[p]["hot_ms_per_step"], results[p]["solve_ms_per_step"]))
-
     head = results[precs[0]]
     n = head["particles"]
-    nbins = wl.ncells * wl.nspecies
-    # dominant particle kernel of the headline run, and its HBM roofline
-    cand = {k: v for k, v in head["kernels"].items() if kernel_bytes(k, wl, head["precision"], n, nbins, wl.ncells)}
-    roof = None
-    if cand:
-        dom = max(cand, key=lambda k: cand[k]["ms_per_launch"] * cand[k]["launches"])
-        byt = kernel_bytes(dom, wl, head["precision"], n, nbins, wl.ncells)
-        ach = byt / (cand[dom]["ms_per_launch"] * 1e-3) / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(ach / PEAK_HBM_GBS, 4),
-                "traffic": measured_traffic("%s_%s" % (wl.name, head["precision"]), dom),
-                "bytes_per_launch": byt, "ms_per_launch": round(cand[dom]["ms_per_launch"], 4)}
-        per_kernel = {}
-        for k, v in cand.items():
-            b = kernel_bytes(k, wl, head["precision"], n, nbins, wl.ncells)
-            per_kernel[k] = round(b / (v["ms_per_launch"] * 1e-3) / 1e9, 1)
-        roof["achieved_by_kernel_GBs"] = per_kernel
-        roof["measured_copy_GBs"] = round(copy_gbs, 1)
-        roof["frac_of_measured_copy"] = round(ach / copy_gbs, 4)
-        this, fused = path_bytes_per_particle(wl, head["precision"], n, nbins, wl.ncells)
-        roof["path"] = {
-            "bytes_per_particle_step": round(this, 2),
-            "achieved_GBs": round(head["value"] * this / 1e9, 1),
-            "frac": round(head["value"] * this / 1e9 / PEAK_HBM_GBS, 4),
-            "single_pass_min_bytes_per_particle_step": round(fused, 2),
-            "frac_single_pass_min": round(head["value"] * fused / 1e9 / PEAK_HBM_GBS, 4),
-        }
+    roof = roofline_of(head, wl, copy_gbs)
+    # the GPU results the oracle leg checks (fresh context, untimed)
+    samples = {p: gpu_sampled_results(p, wl, host, args.rtol) for p in precs} if not args.no_cpu_baseline else {}
 
     ec = None
     if args.energy_conserving:
@@ -391,9 +592,36 @@ def main():
             log("%s energy-conserving: %.3f ms/step, %.1f passes/step, |dW|/W %.2e" % (
                 p, ec[p]["ms_per_step"], ec[p]["passes_per_step"], ec[p]["rel_energy_change"]))
 
+    secondary = None
+    if args.secondary != "none":
+        wl2, host2 = make_inputs(args.secondary)
+        secondary = {"config": {"workload": workload_label(wl2, host2["w"].shape[0], args.rtol)}, "results": {}}
+        samples2 = {}
+        for p in precs:
+            log("running %s on %s: %d warmup + %d timed steps" % (p, wl2.name, min(args.warmup, 2),
+                                                                  args.secondary_steps))
+            r2 = run_precision(p, wl2, host2, args.secondary_steps, min(args.warmup, 2), args.rtol, group=args.group)
+            r2["roofline"] = roofline_of(r2, wl2, copy_gbs)
+            secondary["results"][p] = r2
+            log("%s %s: %.4g particle-steps/s, hot %.3f ms/step" % (wl2.name, p, r2["value"], r2["hot_ms_per_step"]))
+            if not args.no_cpu_baseline:
+                samples2[p] = gpu_sampled_results(p, wl2, host2, args.rtol)
+        if "mixed" in secondary["results"] and "fp64" in secondary["results"]:
+            secondary["mixed_over_fp64"] = secondary["results"]["mixed"]["value"] / secondary["results"]["fp64"]["value"]
+
     cpu = None
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on %d particles" % args.cpu_sample)
+        # the oracle leg: its errors against every GPU result, then its timings
+        log("oracle: errors of the GPU results")
+        for p in precs:
+            results[p]["oracle_error"] = oracle_errors(p, wl, host, samples[p])
+            log("%s vs oracle: %s" % (p, json.dumps(results[p]["oracle_error"])))
+        if secondary is not None:
+            for p in precs:
+                secondary["results"][p]["oracle_error"] = oracle_errors(p, wl2, host2, samples2[p])
+            del host2
+        log("timing the CPU oracle: %d particles on one thread, all particles on %d threads"
+            % (args.cpu_sample, host_cores()))
         cpu = cpu_baseline(wl, host, min(args.cpu_sample, n))
 
     out = {
@@ -410,19 +638,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if head["precision"] == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": "%s: %dD double Harris sheet %s cells, %d particles/cell/species, %d particles, "
-                               "dt = 0.5 dx/c, GMRES rtol %g" % (
-                                   wl.name, wl.dim, "x".join(str(v) for v in (wl.nx, wl.ny, wl.nz)[:wl.dim]), wl.ppc,
-                                   n, args.rtol),
-                   "precision": head["precision"], "parallelism": "single GPU"},
+        "config": {"workload": workload_label(wl, n, args.rtol), "precision": head["precision"],
+                   "parallelism": "single GPU"},
         "results": results,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if "oracle_error" in head:
+        out["oracle_error"] = head["oracle_error"]
     if ec is not None:
         out["energy_conserving"] = ec
     if "mixed" in results and "fp64" in results:
         out["mixed_over_fp64"] = results["mixed"]["value"] / results["fp64"]["value"]
+    if secondary is not None:
+        out["secondary"] = secondary
     print(json.dumps(out), flush=True)
 
 

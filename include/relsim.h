@@ -73,10 +73,12 @@ typedef struct {
   int32_t gmres_restart;       /* Krylov dimension (1..64)                        */
   int32_t gmres_maxit;         /* total Arnoldi steps allowed                     */
   int32_t nonrelativistic;     /* 1: gamma == 1, kinetic energy m|u|^2/2          */
-  int32_t group;               /* lanes per cell in the deposit and kinetic-
-                                  energy kernels: 0 = choose from the mean
-                                  occupancy, else 8, 16, 32 or 64 (the push
-                                  passes size their row segments themselves)     */
+  int32_t group;               /* lanes per cell in the 2D deposit and the
+                                  kinetic-energy kernel: 0 = choose from the
+                                  mean occupancy, else 4, 8, 16, 32 or 64 (the
+                                  3D deposit always splits a cell's moments
+                                  over 4 lanes; the push passes size their
+                                  row segments themselves)                      */
 } relsim_params;
 
 /* Particle state, sorted by bin = cell * nspecies + s, so that the
@@ -189,6 +191,16 @@ int relsim_gamma_mean(relsim_ctx *ctx, const relsim_particles *part, const doubl
 /* relsim_push with gbar in place of gamma(u^n). */
 int relsim_push_ec(relsim_ctx *ctx, relsim_particles *part, const double *E_theta, const double *B_n,
                    const void *gbar, int32_t resort, int32_t *new_index);
+
+/* Particles that the re-sort's second pass placed on a face of the cell the
+ * first pass counted them in, because the recomputed offset came out within
+ * rounding (1e-4 cell) outside that cell, summed over every relsim_push and
+ * relsim_push_ec with resort since the last call; *count receives the sum
+ * and the counter restarts at zero.  Both passes evaluate one function with
+ * the same operands, so the count is expected to stay 0 (a difference
+ * larger than rounding is reported as RELSIM_EINTERNAL instead).
+ * Synchronous. */
+int relsim_placement_clamps(relsim_ctx *ctx, int64_t *count);
 
 /* Write part->cell (front set) from bin_start: particle p of bin b gets cell
  * b / nspecies.  Needed after relsim_push before anything reads the cell

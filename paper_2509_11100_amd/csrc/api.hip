@@ -138,8 +138,8 @@ int validate(const relsim_params *p, std::string &msg) {
   if (p->gmres_restart < 1 || p->gmres_restart > kMaxRestart) return msg = "gmres_restart must be 1..64", RELSIM_EINVAL;
   if (p->gmres_maxit < 1) return msg = "gmres_maxit must be >= 1", RELSIM_EINVAL;
   if (!(p->gmres_rtol > 0)) return msg = "gmres_rtol must be > 0", RELSIM_EINVAL;
-  if (p->group != 0 && p->group != 8 && p->group != 16 && p->group != 32 && p->group != 64)
-    return msg = "group must be 0, 8, 16, 32 or 64", RELSIM_EINVAL;
+  if (p->group != 0 && p->group != 4 && p->group != 8 && p->group != 16 && p->group != 32 && p->group != 64)
+    return msg = "group must be 0, 4, 8, 16, 32 or 64", RELSIM_EINVAL;
   return RELSIM_OK;
 }
 
@@ -287,17 +287,19 @@ int choose_cells(const relsim_ctx *c, int64_t n, KernelKind k) {
 // (16 in FP32; 32 in FP64, whose register-bound occupancy favours narrower
 // groups) and may go down to 4 lanes.  (The 3D deposit always splits a
 // cell's moments over 4 lanes and takes no group.)
-int choose_group(const relsim_ctx *c, int64_t n, KernelKind k = K_OTHER) {
-  if (c->p.group) return c->p.group;
-  const bool fp64 = c->p.precision == RELSIM_FP64;
+int choose_group(const relsim_params &p, const KParams &kp, int64_t n, KernelKind k = K_OTHER) {
+  if (p.group) return p.group;
+  const bool fp64 = p.precision == RELSIM_FP64;
   double rounds = 4.0;
   if (k == K_DEPOSIT) rounds = fp64 ? 32.0 : 16.0;
-  const double mean = (double)n / (double)c->kp.ncells;
+  const double mean = (double)n / (double)kp.ncells;
   int g = k == K_DEPOSIT ? 4 : 8;
   while (g < 64 && 2.0 * g <= mean / rounds) g *= 2;
-  while (g < 64 && (double)c->kp.ncells * g < 512.0 * 64.0) g *= 2;
+  while (g < 64 && (double)kp.ncells * g < 512.0 * 64.0) g *= 2;
   return g;
 }
+
+int choose_group(const relsim_ctx *c, int64_t n, KernelKind k = K_OTHER) { return choose_group(c->p, c->kp, n, k); }
 
 PartPtrs front(const relsim_particles *pt) {
   PartPtrs pp;
@@ -362,6 +364,42 @@ int launch_status(relsim_ctx *c, const char *where) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(c, e, where);
   return RELSIM_OK;
+}
+
+// S7 on the device: the kinetic energy into res[0] (per-block partials in
+// kpart, one per 64/G cells, then a fixed-order reduction through
+// part[0..kRedBlocks)), the sums of |E|^2 and |B|^2 into res[1], res[2]
+// (partials in part[kRedBlocks..3 kRedBlocks)).
+int kinetic_partials(const KParams &kp, int G) { return (kp.ncells + (64 / G) - 1) / (64 / G); }
+
+void enqueue_kinetic(const KParams &kp, int prec, int G, const PartPtrs &pp, double *kpart, double *part, double *res,
+                     hipStream_t st) {
+  launch_kinetic(kp, prec, G, pp, kpart, st);
+  launch_reduce_long(kpart, kinetic_partials(kp, G), part, res, st);
+}
+
+void enqueue_field_energy(const KParams &kp, const double *E, const double *B, double *part, double *res,
+                          hipStream_t st) {
+  const size_t n3 = 3 * (size_t)kp.ncells;
+  launch_sumsq_partials(E, n3, part + kRedBlocks, st);
+  launch_reduce_partials(part + kRedBlocks, kRedBlocks, 1, res + 1, st);
+  launch_sumsq_partials(B, n3, part + 2 * kRedBlocks, st);
+  launch_reduce_partials(part + 2 * kRedBlocks, kRedBlocks, 1, res + 2, st);
+}
+
+// kinetic, electric, magnetic and total energy from the three device sums
+void finish_energy(const KParams &kp, const double sums[3], double out[4]) {
+  const double f = kp.V / (8.0 * M_PI);
+  out[0] = sums[0];
+  out[1] = f * sums[1];
+  out[2] = f * sums[2];
+  out[3] = out[0] + out[1] + out[2];
+}
+
+// Count of particles the pushing scatter put on a face of their counted cell
+// (8 bytes in the flag slot, after the fixed-point pass's change).
+unsigned long long *clamp_counter(relsim_ctx *c) {
+  return reinterpret_cast<unsigned long long *>(c->at<char>(c->L.err) + 16);
 }
 
 // device -> host copy of k doubles into c->host, synchronising
@@ -544,7 +582,7 @@ int relsim_push_ec(relsim_ctx *c, relsim_particles *pt, const double *E_theta, c
     });
     timed(c, "push_scatter", [&] {
       launch_push_scatter(c->kp, c->p.precision, cells_s, pp, stE, stB, dirc, pre, pt->bin_start_back, back(pt),
-                          (int)pt->n, err, new_index, c->at<char>(c->L.sink), c->st);
+                          (int)pt->n, err, clamp_counter(c), new_index, c->at<char>(c->L.sink), c->st);
     });
     rc = launch_status(c, "relsim_push");
     if (rc) return rc;
@@ -590,6 +628,18 @@ int relsim_gamma_mean(relsim_ctx *c, const relsim_particles *pt, const double *E
   return RELSIM_OK;
 }
 
+int relsim_placement_clamps(relsim_ctx *c, int64_t *count) {
+  if (!c || !count) return RELSIM_EINVAL;
+  unsigned long long *d = reinterpret_cast<unsigned long long *>(c->at<char>(c->L.err) + 16);
+  HIP_CHECK(c, hipMemcpyAsync(c->host, d, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->st));
+  HIP_CHECK(c, hipStreamSynchronize(c->st));
+  unsigned long long v;
+  std::memcpy(&v, c->host, sizeof(v));
+  HIP_CHECK(c, hipMemsetAsync(d, 0, sizeof(unsigned long long), c->st));
+  *count = (int64_t)v;
+  return RELSIM_OK;
+}
+
 int relsim_fill_cells(relsim_ctx *c, relsim_particles *pt) {
   if (!c) return RELSIM_EINVAL;
   int rc = check_particles(c, pt, false);
@@ -609,27 +659,15 @@ int relsim_energy(relsim_ctx *c, const relsim_particles *pt, const double *E, co
   const int G = choose_group(c, pt->n);
   double *part = c->at<double>(c->L.red_part);
   double *res = c->at<double>(c->L.gm_small);
-  const size_t n3 = 3 * (size_t)c->kp.ncells;
   timed(c, "kinetic", [&] {
-    double *kpart = c->at<double>(c->L.kin_part);
-    launch_kinetic(c->kp, c->p.precision, G, front(pt), kpart, c->st);
-    launch_reduce_long(kpart, (c->kp.ncells + (64 / G) - 1) / (64 / G), part, res, c->st);
+    enqueue_kinetic(c->kp, c->p.precision, G, front(pt), c->at<double>(c->L.kin_part), part, res, c->st);
   });
-  timed(c, "field_energy", [&] {
-    launch_sumsq_partials(E, n3, part + kRedBlocks, c->st);
-    launch_reduce_partials(part + kRedBlocks, kRedBlocks, 1, res + 1, c->st);
-    launch_sumsq_partials(B, n3, part + 2 * kRedBlocks, c->st);
-    launch_reduce_partials(part + 2 * kRedBlocks, kRedBlocks, 1, res + 2, c->st);
-  });
+  timed(c, "field_energy", [&] { enqueue_field_energy(c->kp, E, B, part, res, c->st); });
   rc = launch_status(c, "relsim_energy");
   if (rc) return rc;
   rc = fetch(c, res, 3);
   if (rc) return rc;
-  const double f = c->kp.V / (8.0 * M_PI);
-  out[0] = c->host[0];
-  out[1] = f * c->host[1];
-  out[2] = f * c->host[2];
-  out[3] = out[0] + out[1] + out[2];
+  finish_energy(c->kp, c->host, out);
   for (int i = 0; i < 4; ++i)
     if (!std::isfinite(out[i])) return fail(c, RELSIM_ENONFINITE, "energy is not finite");
   return RELSIM_OK;

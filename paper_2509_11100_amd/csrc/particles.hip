@@ -657,13 +657,20 @@ __device__ __forceinline__ int cross_cell(T &f, int &bad) {
 // within rounding of a face is put on that face inside the counted cell;
 // anything further off (a disagreement a rounding difference cannot
 // explain) sets off.
+// The counting pass's own rule for an offset just below 0 whose correction
+// rounds to exactly 1 (no move, offset 0; see cross_cell) gives move 0 and a
+// negative f here: that particle is placed at 0 as the first pass placed it.
+// Any other placement onto the face (within rounding outside the cell) sets
+// clamp; the scatter counts those particles.
 template <typename T>
-__device__ __forceinline__ T place_offset(T f, int m, int &off) {
+__device__ __forceinline__ T place_offset(T f, int m, int &off, int &clamp) {
   constexpr T below1 = sizeof(T) == 4 ? T(0x1.fffffep-1) : T(0x1.fffffffffffffp-1);
   constexpr T tol = T(1e-4);
   T g = m > 0 ? f - T(1) : (m < 0 ? f + T(1) : f);
+  const bool edge = m == 0 && f < T(0) && f + T(1) == T(1);
   const bool lo = !(g >= T(0)), hi = g >= T(1);  // lo includes NaN
   off = ((lo && !(g > -tol)) || (hi && !(g < T(1) + tol))) ? 1 : off;
+  clamp = ((lo && !edge) || hi) ? 1 : clamp;
   return lo ? T(0) : (hi ? below1 : g);
 }
 
@@ -749,15 +756,27 @@ struct Segment {
   V4<T> *Bg;         // (C + 2) x 3 [x 3] cell centres from (i0 - 1, j - 1, k - 1), x fastest
   V4<T> *Eg;         // (C + 1) x 2 [x 2] nodes from (i0, j, k)
   T (*stab)[8];      // species charge and beta
-  int *binb;         // nb + 1 bin starts
+  int *binb;         // nb + 1 bin starts, then INT_MAX up to a power of two
   int *keys;         // nb x NDIR counters (counting pass) or run bases (scatter)
 };
+
+// Smallest power of two >= nb (nb >= 1).
+__host__ __device__ constexpr int pow2_at_least(int nb) {
+  int q = 1;
+  while (q < nb) q <<= 1;
+  return q;
+}
+
+// Slots of the staged bin starts: nb + 1 starts, padded to a power of two so
+// that the bin search needs no bounds check.
+__host__ __device__ constexpr int binb_slots(int nb) { return nb + 1 > pow2_at_least(nb) ? nb + 1 : pow2_at_least(nb); }
 
 // LDS bytes of a segment of C cells with S species.
 template <typename T, int DIM>
 __host__ __device__ constexpr size_t segment_lds_bytes(int C, int S) {
   return sizeof(V4<T>) * ((size_t)(C + 2) * 3 * (DIM == 3 ? 3 : 1) + (size_t)(C + 1) * 2 * (DIM == 3 ? 2 : 1)) +
-         sizeof(T) * 16 + sizeof(int) * ((size_t)C * S + 1) + sizeof(int) * (size_t)C * S * (DIM == 3 ? 27 : 9);
+         sizeof(T) * 16 + sizeof(int) * (size_t)binb_slots(C * S) +
+         sizeof(int) * (size_t)C * S * (DIM == 3 ? 27 : 9);
 }
 
 template <typename T, int DIM>
@@ -787,7 +806,7 @@ __device__ __forceinline__ Segment<T, DIM> stage_segment(const KParams &kp, int 
   sg.Eg = sg.Bg + nB;
   sg.stab = reinterpret_cast<T(*)[8]>(sg.Eg + nE);
   sg.binb = reinterpret_cast<int *>(sg.stab + 2);
-  sg.keys = sg.binb + sg.nb + 1;
+  sg.keys = sg.binb + binb_slots(sg.nb);
   // centre (i0 - 1 + a, j - 1 + b, k - 1 + c) sits at ghosted index
   // (i0 + a) + gx (j + b) + gxy (k + c)
   for (int t = lane; t < nB; t += 64) {
@@ -798,18 +817,21 @@ __device__ __forceinline__ Segment<T, DIM> stage_segment(const KParams &kp, int 
     const int a = t % (C + 1), bc = t / (C + 1), b = bc % 2, c = bc / 2;
     sg.Eg[t] = Es[gidx<DIM>(kp, sg.i0 + a, sg.j + b, sg.k + c)];
   }
-  for (int t = lane; t <= sg.nb; t += 64) sg.binb[t] = bin_start[sg.c0 * S + t];
+  for (int t = lane; t < binb_slots(sg.nb); t += 64) sg.binb[t] = t <= sg.nb ? bin_start[sg.c0 * S + t] : INT_MAX;
   fill_species_table<T>(pc, sg.stab, lane);
   return sg;
 }
 
 // Bin (within the segment) of particle p, binb[0] <= p < binb[nb]: the last
-// b with binb[b] <= p, by binary search over the staged bin starts.
+// b with binb[b] <= p, by binary search over the staged bin starts.  The
+// starts are padded with INT_MAX up to a power of two, so every probe reads
+// a valid slot and the search is straight-line code (a wave-uniform number
+// of steps, no lane-dependent branch).
 __device__ __forceinline__ int segment_bin(const int *binb, int nb, int p) {
   int lo = 0;
-  for (int step = nb > 1 ? 1 << (31 - __builtin_clz((unsigned)(nb - 1))) : 0; step > 0; step >>= 1) {
+  for (int step = pow2_at_least(nb) >> 1; step > 0; step >>= 1) {
     const int m = lo + step;
-    lo = (m < nb && binb[m] <= p) ? m : lo;
+    lo = binb[m] <= p ? m : lo;
   }
   return lo;
 }
@@ -1023,7 +1045,8 @@ __device__ __forceinline__ void scatter_round(const KParams &kp, const PC<T> &pc
                                               const uint8_t *__restrict__ dirc,
                                               V2<T> *__restrict__ xo, V4<T> *__restrict__ uo, T *__restrict__ zo,
                                               int32_t *__restrict__ perm, void *__restrict__ sink, T q0, T q1,
-                                              T b0, T b1, int &p, int &bad, PRec<T> &cur, uint8_t &dc) {
+                                              T b0, T b1, int &p, int &bad, int &nclamp, PRec<T> &cur,
+                                              uint8_t &dc) {
   constexpr int NDIR = DIM == 3 ? 27 : 9;
   constexpr int DBITS = DIM == 3 ? 5 : 4;  // bits of a move code
   const int S = kp.nspecies;
@@ -1037,11 +1060,12 @@ __device__ __forceinline__ void scatter_round(const KParams &kp, const PC<T> &pc
   push_one<T, DIM, GB>(kp, pc, segment_fields(sg, lc), bs, cur, fx, fy, fz, nx, ny, nz);
   // the new state goes where the counting pass counted it (move dcur),
   // with its offsets taken relative to that cell
-  int off = 0;
-  fx = place_offset<T>(fx, dcur % 3 - 1, off);
-  fy = place_offset<T>(fy, (dcur / 3) % 3 - 1, off);
-  if constexpr (DIM == 3) fz = place_offset<T>(fz, dcur / 9 - 1, off);
+  int off = 0, clamp = 0;
+  fx = place_offset<T>(fx, dcur % 3 - 1, off, clamp);
+  fy = place_offset<T>(fy, (dcur / 3) % 3 - 1, off, clamp);
+  if constexpr (DIM == 3) fz = place_offset<T>(fz, dcur / 9 - 1, off, clamp);
   bad |= (pv && off) ? 4 : 0;
+  nclamp += __popcll(__ballot(pv && clamp));  // wave-uniform
   // lanes of this round with the same (bin, move) key: the bin's particles
   // occupy the contiguous lanes [f, l) of the round, so only the move code
   // needs matching, one ballot per bit
@@ -1107,6 +1131,7 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, int C, const in
                                                      const int32_t *__restrict__ bsn, V2<T> *__restrict__ xo,
                                                      V4<T> *__restrict__ uo, T *__restrict__ zo, int ntot,
                                                      int32_t *__restrict__ err,
+                                                     unsigned long long *__restrict__ clamps,
                                                      int32_t *__restrict__ perm, void *__restrict__ sink,
                                                      const T *__restrict__ gb) {
   constexpr int NDIR = DIM == 3 ? 27 : 9;
@@ -1140,7 +1165,7 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, int C, const in
   // last one or two rounds follow it.
   PRec<T> rb0{}, rb1{}, rb2{};
   uint8_t db0 = 0, db1 = 0, db2 = 0;
-  int p = p0 + lane, bad = 0;
+  int p = p0 + lane, bad = 0, nclamp = 0;
   if (rounds > 0) {
     load_rec<T, DIM>(p, p1, xy, uw, zz, rb0);
     load_gbar<GB>(p, p1, gb, rb0);
@@ -1158,7 +1183,7 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, int C, const in
   const T sq0 = pc.q0, sq1 = pc.q1, sb0 = pc.b0, sb1 = pc.b1;
 #define RELSIM_SCATTER_ROUND(rb, db)                                                                            \
   scatter_round<T, DIM, PERM, GB>(kp, pc, sg, p1, lane, lt, ntot, xy, uw, zz, gb, dirc, xo, uo, zo, perm, sink, \
-                                  sq0, sq1, sb0, sb1, p, bad, rb, db)
+                                  sq0, sq1, sb0, sb1, p, bad, nclamp, rb, db)
   int r = 0;
 #pragma unroll 1
   for (; r + 3 <= rounds; r += 3) {
@@ -1172,6 +1197,7 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, int C, const in
   const int ball = __ballot(bad & 2) ? 2 : 0;
   const int balm = __ballot(bad & 4) ? 8 : 0;
   if ((ball | balm) && lane == 0) atomicOr(err, ball | balm);
+  if (nclamp && lane == 0) atomicAdd(clamps, (unsigned long long)nclamp);
 }
 
 // ---------------------------------------------------------------------------
@@ -1360,29 +1386,30 @@ void gamma_mean_impl(const KParams &kp, int C, const PartPtrs &pp, const void *E
 template <typename T, int DIM, bool PERM, bool GB>
 void scatter_launch(const KParams &kp, int C, const PartPtrs &src, const void *Est, const void *Bst,
                     const uint8_t *dirc, const uint16_t *pre, const int32_t *bsn, const PartPtrs &out, int ntot,
-                    int32_t *err, int32_t *perm, void *sink, hipStream_t st) {
+                    int32_t *err, unsigned long long *clamps, int32_t *perm, void *sink, hipStream_t st) {
   const int nblk = kp.ncells / C;
   const size_t lds = segment_lds_bytes<T, DIM>(C, kp.nspecies);
   hipLaunchKernelGGL((k_push_scatter<T, DIM, PERM, GB>), dim3(nblk), dim3(64), lds, st, kp, C, src.bin_start,
                      cp<V2<T>>(src.xy), cp<V4<T>>(src.uw), cp<T>(src.z), cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, pre,
-                     bsn, mp<V2<T>>(out.xy), mp<V4<T>>(out.uw), mp<T>(out.z), ntot, err, perm, sink,
+                     bsn, mp<V2<T>>(out.xy), mp<V4<T>>(out.uw), mp<T>(out.z), ntot, err, clamps, perm, sink,
                      cp<T>(src.gbar));
 }
 
 template <typename T, int DIM>
 void scatter_impl(const KParams &kp, int C, const PartPtrs &src, const void *Est, const void *Bst,
                   const uint8_t *dirc, const uint16_t *pre, const int32_t *bsn, const PartPtrs &out, int ntot,
-                  int32_t *err, int32_t *perm, void *sink, hipStream_t st) {
+                  int32_t *err, unsigned long long *cl, int32_t *perm, void *sink, hipStream_t st) {
   if (src.gbar) {
     if (perm)
-      scatter_launch<T, DIM, true, true>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, perm, sink, st);
+      scatter_launch<T, DIM, true, true>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, cl, perm, sink, st);
     else
-      scatter_launch<T, DIM, false, true>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, perm, sink, st);
+      scatter_launch<T, DIM, false, true>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, cl, perm, sink, st);
   } else {
     if (perm)
-      scatter_launch<T, DIM, true, false>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, perm, sink, st);
+      scatter_launch<T, DIM, true, false>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, cl, perm, sink, st);
     else
-      scatter_launch<T, DIM, false, false>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, perm, sink, st);
+      scatter_launch<T, DIM, false, false>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, cl, perm, sink,
+                                           st);
   }
 }
 
@@ -1399,11 +1426,13 @@ void dispatch(int prec, int dim, int group, A &&...args) {
 #define RELSIM_CASE(TT, DD, GG) \
   if (dim == DD && group == GG) return F<TT, DD, GG>::run(args...);
   if (prec == RELSIM_MIXED) {
-    RELSIM_CASE(float, 2, 8) RELSIM_CASE(float, 2, 16) RELSIM_CASE(float, 2, 32) RELSIM_CASE(float, 2, 64)
-    RELSIM_CASE(float, 3, 8) RELSIM_CASE(float, 3, 16) RELSIM_CASE(float, 3, 32) RELSIM_CASE(float, 3, 64)
+    RELSIM_CASE(float, 2, 4) RELSIM_CASE(float, 2, 8) RELSIM_CASE(float, 2, 16) RELSIM_CASE(float, 2, 32)
+    RELSIM_CASE(float, 2, 64) RELSIM_CASE(float, 3, 4) RELSIM_CASE(float, 3, 8) RELSIM_CASE(float, 3, 16)
+    RELSIM_CASE(float, 3, 32) RELSIM_CASE(float, 3, 64)
   } else {
-    RELSIM_CASE(double, 2, 8) RELSIM_CASE(double, 2, 16) RELSIM_CASE(double, 2, 32) RELSIM_CASE(double, 2, 64)
-    RELSIM_CASE(double, 3, 8) RELSIM_CASE(double, 3, 16) RELSIM_CASE(double, 3, 32) RELSIM_CASE(double, 3, 64)
+    RELSIM_CASE(double, 2, 4) RELSIM_CASE(double, 2, 8) RELSIM_CASE(double, 2, 16) RELSIM_CASE(double, 2, 32)
+    RELSIM_CASE(double, 2, 64) RELSIM_CASE(double, 3, 4) RELSIM_CASE(double, 3, 8) RELSIM_CASE(double, 3, 16)
+    RELSIM_CASE(double, 3, 32) RELSIM_CASE(double, 3, 64)
   }
 #undef RELSIM_CASE
 }
@@ -1507,16 +1536,18 @@ void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream
 
 void launch_push_scatter(const KParams &kp, int prec, int cells, const PartPtrs &src, const void *Est,
                          const void *Bst, const uint8_t *dirc, const uint16_t *pre, const int32_t *bin_start_new,
-                         const PartPtrs &out, int ntot, int32_t *err, int32_t *perm, void *sink, hipStream_t st) {
+                         const PartPtrs &out, int ntot, int32_t *err, unsigned long long *clamps, int32_t *perm,
+                         void *sink, hipStream_t st) {
   const bool f = prec == RELSIM_MIXED;
   if (kp.dim == 3)
-    return f ? scatter_impl<float, 3>(kp, cells, src, Est, Bst, dirc, pre, bin_start_new, out, ntot, err, perm, sink,
-                                      st)
-             : scatter_impl<double, 3>(kp, cells, src, Est, Bst, dirc, pre, bin_start_new, out, ntot, err, perm,
-                                       sink, st);
-  return f ? scatter_impl<float, 2>(kp, cells, src, Est, Bst, dirc, pre, bin_start_new, out, ntot, err, perm, sink, st)
-           : scatter_impl<double, 2>(kp, cells, src, Est, Bst, dirc, pre, bin_start_new, out, ntot, err, perm, sink,
-                                     st);
+    return f ? scatter_impl<float, 3>(kp, cells, src, Est, Bst, dirc, pre, bin_start_new, out, ntot, err, clamps,
+                                      perm, sink, st)
+             : scatter_impl<double, 3>(kp, cells, src, Est, Bst, dirc, pre, bin_start_new, out, ntot, err, clamps,
+                                       perm, sink, st);
+  return f ? scatter_impl<float, 2>(kp, cells, src, Est, Bst, dirc, pre, bin_start_new, out, ntot, err, clamps,
+                                    perm, sink, st)
+           : scatter_impl<double, 2>(kp, cells, src, Est, Bst, dirc, pre, bin_start_new, out, ntot, err, clamps,
+                                     perm, sink, st);
 }
 
 void launch_fill_cells(const KParams &kp, const int32_t *bin_start, int32_t *cell, hipStream_t st) {

@@ -95,10 +95,12 @@ void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream
 size_t scan_tmp_elems(int n);
 // second pass of the re-sort: push src again and write the new state into
 // out in the new bin order, each in the cell of its recorded move (err bit
-// 8: a recomputed position further than rounding outside that cell)
+// 8: a recomputed position further than rounding outside that cell; *clamps
+// += particles within rounding outside it, put on its face)
 void launch_push_scatter(const KParams &kp, int prec, int cells, const PartPtrs &src, const void *Est,
                          const void *Bst, const uint8_t *dirc, const uint16_t *pre, const int32_t *bin_start_new,
-                         const PartPtrs &out, int ntot, int32_t *err, int32_t *perm, void *sink, hipStream_t st);
+                         const PartPtrs &out, int ntot, int32_t *err, unsigned long long *clamps, int32_t *perm,
+                         void *sink, hipStream_t st);
 // cell[p] for every particle from the bin ranges
 void launch_fill_cells(const KParams &kp, const int32_t *bin_start, int32_t *cell, hipStream_t st);
 // partials: one double per block of 64/group cells (at most ncells)

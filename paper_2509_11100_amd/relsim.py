@@ -282,6 +282,14 @@ def gamma_mean(ctx: Context, parts: Particles, E_theta: torch.Tensor, B: torch.T
     return out.value
 
 
+def placement_clamps(ctx: Context) -> int:
+    """relsim_placement_clamps: particles the re-sort placed on a face of
+    their counted cell since the last call (expected 0)"""
+    out = C.c_int64(0)
+    ctx.check(ctx.lib.relsim_placement_clamps(ctx.handle, C.byref(out)))
+    return out.value
+
+
 def field_solve(ctx: Context, M, J, E, B, E_theta=None, E1=None, B1=None, allow_unconverged: bool = False):
     """relsim_field_solve -> (E_theta, E^{n+1}, B^{n+1}, iterations, relative residual)"""
     E_theta = ctx.grid() if E_theta is None else E_theta
@@ -368,6 +376,15 @@ def energy(ctx: Context, parts: Particles, E: torch.Tensor, B: torch.Tensor) -> 
     return np.array(list(out))
 
 
+class PicardNotConverged(RuntimeError):
+    """The energy-conserving step's fixed point did not reach its tolerance."""
+
+    def __init__(self, iters: int, change: float, tol: float):
+        super().__init__("energy-conserving step: gbar change %.3e after %d passes (tolerance %.1e)"
+                         % (change, iters, tol))
+        self.iters, self.change, self.tol = iters, change, tol
+
+
 class Step:
     """Advances a particle state and its fields by whole steps n -> n+1:
     relsim_deposit_moments (S1-S3), relsim_field_solve (S4-S5) and
@@ -385,10 +402,17 @@ class Step:
     relsim_gamma_mean pass with the known E^n in place of E_theta (no
     deposit or solve), which lands nearer the fixed point than gamma(u^n);
     the fixed point itself does not depend on the start.
-    picard_iters / picard_change hold the last step's passes and change."""
+    picard_iters / picard_change hold the last step's passes and change.
+
+    If the change is still above picard_tol after picard_maxit passes, or
+    is not finite, the step raises PicardNotConverged before pushing (the
+    state and fields stay at step n), since energy would then not be
+    conserved to the stated tolerance; with allow_unconverged=True a finite
+    change only clears picard_converged and the step goes on."""
 
     def __init__(self, ctx: Context, parts: Particles, E: torch.Tensor, B: torch.Tensor,
-                 energy_conserving: bool = False, picard_tol: Optional[float] = None, picard_maxit: int = 30):
+                 energy_conserving: bool = False, picard_tol: Optional[float] = None, picard_maxit: int = 30,
+                 allow_unconverged: bool = False):
         _grid_ok(ctx, E, B)
         self.ctx, self.parts = ctx, parts
         self.E, self.B = E.clone(), B.clone()
@@ -400,7 +424,8 @@ class Step:
         if picard_tol is None:
             picard_tol = 1e-12 if ctx.precision == "fp64" else 1e-6
         self.picard_tol, self.picard_maxit = picard_tol, picard_maxit
-        self.picard_iters, self.picard_change = 0, 0.0
+        self.allow_unconverged = allow_unconverged
+        self.picard_iters, self.picard_change, self.picard_converged = 0, 0.0, True
         if energy_conserving:
             cap = max(parts.n, 1)
             self._gb = [torch.empty(cap, dtype=ctx.dtype, device=ctx.device) for _ in range(2)]
@@ -423,6 +448,9 @@ class Step:
                     if self.picard_change <= self.picard_tol or it == self.picard_maxit:
                         break
                     gbar, nxt = self._gb[nxt], 1 - nxt
+                self.picard_converged = self.picard_change <= self.picard_tol
+                if not self.picard_converged and (not self.allow_unconverged or not np.isfinite(self.picard_change)):
+                    raise PicardNotConverged(self.picard_iters, self.picard_change, self.picard_tol)
             else:
                 self._solve(None)
             push(self.ctx, self.parts, self.E_theta, self.B, resort=True, gbar=gbar)

@@ -1,0 +1,404 @@
+"""GPU parity of the modes and inputs the random-state tests do not reach.
+
+* the non-relativistic mode (gamma = 1, kinetic energy m|u|^2/2; the case in
+  which the scheme conserves energy exactly, Sec. 2 methods paragraph):
+  deposit, push + re-sort and energy against the oracle, and whole FP64 steps
+  that keep the total energy to the solver's tolerance;
+* a time centring theta other than 1/2 in the solve and the field update;
+* whole steps of a small 3D double Harris sheet against the oracle's steps;
+* deterministic edge-case particles: offsets exactly 0, 1/2 (the kink of the
+  cell-centre gather) and the largest value below 1 of the particle type;
+  B = 0, |b| >> 1 and gamma >> 1; moves across a periodic corner;
+* the re-sort's placement counter (expected 0) and the report of an
+  energy-conserving step whose fixed point does not converge.
+
+Tolerances as in test_gpu_parity (1e-12 FP64, 1e-5 mixed; normwise and
+max-abs over max-reference), with the mixed path teacher-forced.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2509_11100_amd import harris
+from tests.gpu_helpers import host_state, load, make_ctx, need_gpu, random_cells, rounded
+from tests.helpers import check_disp, check_rel, grid_of, normwise, periodic_diff, positions
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "mixed": 1e-5}
+
+
+def torch_grid(a):
+    import torch
+
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def nonrel_grid(dim):
+    if dim == 2:
+        return oracle.Grid(dim=2, nx=7, ny=5, dx=1.1, dy=0.9, dt=0.45, nonrel=True)
+    return oracle.Grid(dim=3, nx=5, ny=4, nz=3, dx=1.1, dy=0.9, dz=1.2, dt=0.4, nonrel=True)
+
+
+def push_and_compare(g, ctx, parts, E, B, precision, gbar=None):
+    """Push with re-sort; every particle's new state (through the new index)
+    against the oracle push; the re-sort's placement counter stays 0."""
+    import torch
+
+    from paper_2509_11100_amd import relsim
+
+    st = host_state(g, parts)
+    n = parts.n
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    relsim.push(ctx, parts, torch_grid(E), torch_grid(B), resort=True, new_index=perm)
+    s1 = host_state(g, parts)
+    new = perm[:n].cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(new), np.arange(n))
+    xr, ur = oracle.push(g, st["x"], st["u"], st["species"], E, B)
+    check_rel(s1["u"][:, new], ur, TOL[precision], "u")
+    disp = periodic_diff(g, xr, st["x"])
+    check_disp(periodic_diff(g, s1["x"][:, new], xr), disp, TOL[precision])
+    assert np.all((s1["off"] >= 0) & (s1["off"] < 1))
+    key = s1["cell"].astype(np.int64) * len(g.q) + s1["species"]
+    assert np.all(np.diff(key) >= 0)
+    assert relsim.placement_clamps(ctx) == 0
+    return st, s1, new
+
+
+# ----------------------------------------------------------------------------
+# non-relativistic mode
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_nonrelativistic_deposit_push_energy(dim, precision):
+    need_gpu()
+    from paper_2509_11100_amd import relsim
+
+    g = nonrel_grid(dim)
+    rng = np.random.default_rng(400 + dim)
+    n = 2500
+    # |u| dt / dx stays below one cell per step (gamma = 1: v = u)
+    cell, sp, off, u, w = random_cells(g, n, rng, umax=1.0, empty_frac=0.2)
+    B = (2 * rng.random((3, g.N)) - 1) * 2.0
+    E = (2 * rng.random((3, g.N)) - 1) * 0.5
+    ctx = make_ctx(g, precision, n)
+    parts = load(ctx, cell, sp, off, u, w)
+    st = host_state(g, parts)
+    J, M = relsim.deposit_moments(ctx, parts, torch_grid(B))
+    Jr, Mr = oracle.deposit(g, st["x"], st["u"], st["w"], st["species"], B)
+    check_rel(J.cpu().numpy(), Jr, TOL[precision], "J")
+    check_rel(M.cpu().numpy(), Mr, TOL[precision], "M")
+    W = relsim.energy(ctx, parts, torch_grid(E), torch_grid(B))
+    Wr = oracle.energy(g, st["u"], st["w"], st["species"], E, B)
+    np.testing.assert_allclose(W, Wr, rtol=1e-12)
+    # the kinetic part is the non-relativistic one
+    ke = 0.5 * (st["w"] * np.asarray(g.m)[st["species"]] * (st["u"] ** 2).sum(0)).sum()
+    assert abs(W[0] - ke) <= 1e-12 * ke
+    push_and_compare(g, ctx, parts, E, B, precision)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_nonrelativistic_steps_conserve_energy(dim):
+    """Whole FP64 steps without relativity: |W^n - W^0| / W^0 <= 1e-12 on
+    the GPU (GMRES to 1e-13), and the fields match the oracle's steps."""
+    need_gpu()
+    from paper_2509_11100_amd import relsim
+
+    if dim == 2:
+        g = oracle.Grid(dim=2, nx=16, ny=12, dx=1.0, dy=1.0, dt=0.4, nonrel=True)
+    else:
+        g = oracle.Grid(dim=3, nx=8, ny=6, nz=4, dx=1.0, dy=1.0, dz=1.0, dt=0.4, nonrel=True)
+    rng = np.random.default_rng(410 + dim)
+    n = 20 * g.N
+    cell, sp, off, u, w = random_cells(g, n, rng, umax=0.6)
+    B = (2 * rng.random((3, g.N)) - 1) * 1.0
+    E = (2 * rng.random((3, g.N)) - 1) * 0.3
+    ctx = make_ctx(g, "fp64", n, rtol=1e-13)
+    parts = load(ctx, cell, sp, off, u, w)
+    st = host_state(g, parts)
+    step = relsim.Step(ctx, parts, torch_grid(E), torch_grid(B))
+    steps = 6
+    W = [step.energy()]
+    for _ in range(steps):
+        step()
+        W.append(step.energy())
+    W = np.array(W)
+    dW = np.abs(W[:, 3] - W[0, 3]).max() / W[0, 3]
+    print("non-relativistic %dD, %d steps: max |W - W0| / W0 = %.2e" % (dim, steps, dW))
+    assert dW <= 1e-12
+    x, uu, Er, Br = st["x"], st["u"], E, B
+    for _ in range(steps):
+        out = oracle.step(g, x, uu, st["w"], st["species"], Er, Br)
+        x, uu, Er, Br = out["x"], out["u"], out["E"], out["B"]
+    assert normwise(step.E.cpu().numpy(), Er) < 1e-9
+    assert normwise(step.B.cpu().numpy(), Br) < 1e-9
+
+
+# ----------------------------------------------------------------------------
+# time centring theta != 1/2
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("theta", [0.6, 1.0])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_field_solve_and_update_at_theta(dim, theta):
+    need_gpu()
+    import dataclasses
+
+    from paper_2509_11100_amd import relsim
+
+    g = nonrel_grid(dim)
+    g = dataclasses.replace(g, nonrel=False, theta=theta)
+    rng = np.random.default_rng(int(420 + 10 * theta + dim))
+    n = 1500
+    cell, sp, off, u, w = random_cells(g, n, rng, umax=2.0)
+    B = (2 * rng.random((3, g.N)) - 1) * 2.0
+    E = (2 * rng.random((3, g.N)) - 1) * 0.5
+    ctx = make_ctx(g, "fp64", n)
+    parts = load(ctx, cell, sp, off, u, w)
+    J, M = relsim.deposit_moments(ctx, parts, torch_grid(B))
+    Eth, E1, B1, it, rr = relsim.field_solve(ctx, M, J, torch_grid(E), torch_grid(B))
+    assert rr <= 1e-13 and it > 0
+    Jh, Mh = J.cpu().numpy(), M.cpu().numpy()
+    check_rel(relsim.apply_A(ctx, M, torch_grid(E)).cpu().numpy(), oracle.apply_A(g, Mh, E), 1e-13, "A E")
+    ref = oracle.solve(g, Mh, oracle.rhs(g, E, B, Jh))
+    E1r, B1r = oracle.field_update(g, E, B, ref)
+    check_rel(Eth.cpu().numpy(), ref, 1e-12, "E_theta")
+    check_rel(E1.cpu().numpy(), E1r, 1e-12, "E^{n+1}")
+    check_rel(B1.cpu().numpy(), B1r, 1e-12, "B^{n+1}")
+    # the update inverts the theta-average: E_theta = theta E^{n+1} + (1 - theta) E^n
+    check_rel(theta * E1.cpu().numpy() + (1 - theta) * E, Eth.cpu().numpy(), 1e-13, "theta average")
+
+
+# ----------------------------------------------------------------------------
+# 3D whole steps
+# ----------------------------------------------------------------------------
+def test_harris3d_end_to_end_fp64_five_steps():
+    """A 16 x 8 x 8 double Harris sheet (4 particles per cell per species,
+    dx = a/2, dt = dx/2c): five whole FP64 steps against the oracle."""
+    need_gpu()
+    from paper_2509_11100_amd import relsim
+
+    wl = harris.workload("harris3d_128x64x64", nx=16, ny=8, nz=8, ppc=4)
+    p = harris.make_particles(wl)
+    E, B = harris.make_fields(wl)
+    g = grid_of(wl)
+    ctx = make_ctx(g, "fp64", p["w"].shape[0], rtol=1e-13)
+    parts = load(ctx, p["cell"], p["species"], p["off"], p["u"], p["w"], p["bin_start"])
+    step = relsim.Step(ctx, parts, torch_grid(E), torch_grid(B))
+    steps = 5
+    Wg = [step.energy()]
+    for _ in range(steps):
+        step()
+        Wg.append(step.energy())
+    x = positions(g, p["cell"], p["off"])
+    u, Er, Br = p["u"], E, B
+    sp = p["species"].astype(np.int32)
+    Wr = [oracle.energy(g, u, p["w"], sp, Er, Br)]
+    for _ in range(steps):
+        out = oracle.step(g, x, u, p["w"], sp, Er, Br)
+        x, u, Er, Br = out["x"], out["u"], out["E"], out["B"]
+        Wr.append(out["W"])
+    assert normwise(step.E.cpu().numpy(), Er) < 1e-9
+    assert normwise(step.B.cpu().numpy(), Br) < 1e-9
+    np.testing.assert_allclose(np.array(Wg), np.array(Wr), rtol=1e-10)
+    assert relsim.placement_clamps(ctx) == 0
+
+
+def test_harris3d_mixed_energy_drift_matches_oracle():
+    """Mixed precision on the same 3D sheet: the per-step energy change
+    relative to W0 within 1e-4 of the oracle's (teacher-forced start)."""
+    need_gpu()
+    from paper_2509_11100_amd import relsim
+
+    wl = harris.workload("harris3d_128x64x64", nx=16, ny=8, nz=8, ppc=4)
+    p = harris.make_particles(wl)
+    E, B = harris.make_fields(wl)
+    g = grid_of(wl)
+    for k in ("off", "u", "w"):
+        p[k] = rounded("mixed", p[k])
+    ctx = make_ctx(g, "mixed", p["w"].shape[0], rtol=1e-13)
+    parts = load(ctx, p["cell"], p["species"], p["off"], p["u"], p["w"], p["bin_start"])
+    step = relsim.Step(ctx, parts, torch_grid(E), torch_grid(B))
+    steps = 4
+    Wg = [step.energy()]
+    for _ in range(steps):
+        step()
+        Wg.append(step.energy())
+    x = positions(g, p["cell"], p["off"])
+    u, Er, Br = p["u"], E, B
+    sp = p["species"].astype(np.int32)
+    Wr = [oracle.energy(g, u, p["w"], sp, Er, Br)]
+    for _ in range(steps):
+        out = oracle.step(g, x, u, p["w"], sp, Er, Br)
+        x, u, Er, Br = out["x"], out["u"], out["E"], out["B"]
+        Wr.append(out["W"])
+    Wg, Wr = np.array(Wg), np.array(Wr)
+    dg = np.diff(Wg[:, 3]) / Wg[0, 3]
+    dr = np.diff(Wr[:, 3]) / Wr[0, 3]
+    print("3D mixed drift vs oracle: %.2e, B %.2e" % (np.abs(dg - dr).max(), normwise(step.B.cpu().numpy(), Br)))
+    assert np.abs(dg - dr).max() <= 1e-4
+    assert normwise(step.B.cpu().numpy(), Br) < 1e-5
+
+
+# ----------------------------------------------------------------------------
+# deterministic edge cases
+# ----------------------------------------------------------------------------
+def edge_case_particles(g, precision):
+    """Particles at the offsets where the arithmetic changes branch, in the
+    fields where alpha and gamma are extreme, and at the box corners."""
+    below1 = np.nextafter(np.float32(1), np.float32(0)) if precision == "mixed" else np.nextafter(1.0, 0.0)
+    below1 = float(below1)
+    offs = [0.0, 0.5, below1]
+    cells, off, u, sp = [], [], [], []
+    last = g.N - 1
+    mid = g.N // 2
+    # offset grid x momentum directions in a middle cell and both corner cells
+    dirs = [np.zeros(3), np.array([0.3, -0.2, 0.1]), np.array([-0.9, -0.9, 0.2]), np.array([0.9, 0.9, -0.2])]
+    for c in (0, mid, last):
+        for fx in offs:
+            for fy in offs:
+                for fz in (offs if g.dim == 3 else [0.0]):
+                    for d in dirs:
+                        cells.append(c)
+                        off.append([fx, fy, fz][: g.dim])
+                        u.append(d)
+                        sp.append(len(cells) % 2)
+    # ultra-relativistic particles (gamma ~ 1e3) moving at ~ c along a
+    # diagonal out of the last cell (across the periodic corner) and into the
+    # first one from below
+    for c, sgn in ((last, 1.0), (0, -1.0)):
+        for f in (0.5, below1 if sgn > 0 else 0.0):
+            cells.append(c)
+            off.append([f] * g.dim)
+            u.append(sgn * np.array([700.0, 700.0, 100.0]))
+            sp.append(0)
+    cells = np.array(cells, np.int32)
+    off = np.array(off, np.float64).T
+    u = np.array(u, np.float64).T
+    sp = np.array(sp, np.uint8)
+    w = 0.5 + 0.01 * np.arange(cells.size)
+    return cells, sp, off, u, w
+
+
+def edge_case_fields(g, rng):
+    """B = 0 over the lower third of the cells, a strong B (|b| of order 50
+    for gamma ~ 1) over the upper third, moderate elsewhere; E moderate."""
+    B = (2 * rng.random((3, g.N)) - 1) * 1.0
+    third = g.N // 3
+    B[:, :third] = 0.0
+    B[:, 2 * third:] *= 250.0
+    E = (2 * rng.random((3, g.N)) - 1) * 0.3
+    return E, B
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_edge_case_particles(dim, precision):
+    need_gpu()
+    from paper_2509_11100_amd import relsim
+
+    g = nonrel_grid(dim)
+    import dataclasses
+
+    g = dataclasses.replace(g, nonrel=False)
+    rng = np.random.default_rng(430 + dim)
+    cell, sp, off, u, w = edge_case_particles(g, precision)
+    E, B = edge_case_fields(g, rng)
+    n = cell.size
+    ctx = make_ctx(g, precision, n)
+    parts = load(ctx, cell, sp, off, u, w)
+    st = host_state(g, parts)
+    # the loaded offsets are the exact edge values
+    assert (st["off"] == 0.0).any() and (st["off"] == 0.5).any() and (st["off"] > 0.9999999).any()
+    J, M = relsim.deposit_moments(ctx, parts, torch_grid(B))
+    Jr, Mr = oracle.deposit(g, st["x"], st["u"], st["w"], st["species"], B)
+    check_rel(J.cpu().numpy(), Jr, TOL[precision], "J")
+    check_rel(M.cpu().numpy(), Mr, TOL[precision], "M")
+    W = relsim.energy(ctx, parts, torch_grid(E), torch_grid(B))
+    np.testing.assert_allclose(W, oracle.energy(g, st["u"], st["w"], st["species"], E, B), rtol=1e-12)
+    st0, s1, new = push_and_compare(g, ctx, parts, E, B, precision)
+    # the ultra-relativistic particles that start on the far face of the last
+    # cell (moving up) or on the near face of the first (moving down) cross
+    # a face in every dimension, wrapping around the box corner
+    fast = np.abs(st0["u"][0]) > 500
+    onface = np.all(st0["off"] > 0.99, axis=0) | np.all(st0["off"] == 0.0, axis=0)
+    sel = np.nonzero(fast & onface)[0]
+    assert sel.size == 2
+    ext = [g.nx, g.ny, g.nz][: g.dim]
+
+    def coords(c):
+        c = np.asarray(c, np.int64)
+        return [c % g.nx, (c // g.nx) % g.ny, c // (g.nx * g.ny)][: g.dim]
+
+    c0, c1 = coords(st0["cell"][sel]), coords(s1["cell"][new[sel]])
+    sgn = np.sign(st0["u"][0][sel]).astype(np.int64)
+    for d in range(g.dim):
+        np.testing.assert_array_equal(c1[d], (c0[d] + sgn) % ext[d])
+
+
+# ----------------------------------------------------------------------------
+# fixed point of the energy-conserving step: non-convergence is reported
+# ----------------------------------------------------------------------------
+def test_energy_conserving_step_reports_an_unconverged_fixed_point():
+    need_gpu()
+    import torch
+
+    from paper_2509_11100_amd import relsim
+
+    wl = harris.workload("harris2d_64x32")
+    p = harris.make_particles(wl)
+    E, B = harris.make_fields(wl)
+    g = grid_of(wl)
+    ctx = make_ctx(g, "fp64", p["w"].shape[0], rtol=1e-12)
+    parts = load(ctx, p["cell"], p["species"], p["off"], p["u"], p["w"], p["bin_start"])
+    step = relsim.Step(ctx, parts, torch_grid(E), torch_grid(B), energy_conserving=True, picard_tol=1e-15,
+                       picard_maxit=1)
+    xy0 = parts.sets[parts.front]["xy"][: parts.n].clone()
+    with pytest.raises(relsim.PicardNotConverged) as ei:
+        step()
+    assert ei.value.iters == 1 and ei.value.change > 1e-15
+    assert not step.picard_converged
+    # nothing was pushed
+    assert torch.equal(parts.sets[parts.front]["xy"][: parts.n], xy0)
+    # allowed explicitly, the step goes on and says so
+    step.allow_unconverged = True
+    step()
+    assert not step.picard_converged and step.picard_iters == 1
+    step.picard_maxit, step.picard_tol = 30, 1e-12
+    step()
+    assert step.picard_converged
+
+
+def test_offset_rounding_to_the_face_is_not_a_clamp():
+    """FP32: an offset of 2^-26 moved by -2^-25 of a cell lands at -2^-26,
+    and -2^-26 + 1 rounds to exactly 1: both re-sort passes keep such a
+    particle in its cell at offset 0 (the crossing rule for that rounding),
+    which is not a disagreement between the passes, so the placement
+    counter stays 0.  (Non-relativistic, no fields: v = u.)"""
+    need_gpu()
+    import torch
+
+    from paper_2509_11100_amd import relsim
+
+    g = oracle.Grid(dim=2, nx=7, ny=5, dx=1.0, dy=1.0, dt=0.5, nonrel=True)
+    n = 64
+    cell = np.full(n, 17, np.int32)
+    off = np.full((2, n), 0.5)
+    off[0, :32] = 2.0 ** -26
+    u = np.zeros((3, n))
+    u[0, :32] = -(2.0 ** -24)           # dt u / dx = -2^-25 exactly
+    w = np.ones(n)
+    sp = (np.arange(n) % 2).astype(np.uint8)
+    ctx = make_ctx(g, "mixed", n)
+    parts = load(ctx, cell, sp, off, u, w)
+    Z = torch_grid(np.zeros((3, g.N)))
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    st0 = host_state(g, parts)
+    relsim.push(ctx, parts, Z, Z, resort=True, new_index=perm)
+    assert relsim.placement_clamps(ctx) == 0
+    s1 = host_state(g, parts)
+    new = perm.cpu().numpy().astype(np.int64)
+    edge = st0["off"][0] < 1e-6
+    assert edge.sum() == 32
+    np.testing.assert_array_equal(s1["cell"][new], st0["cell"])
+    np.testing.assert_array_equal(s1["off"][0][new][edge], 0.0)
+    np.testing.assert_array_equal(s1["off"][0][new][~edge], 0.5)

@@ -100,9 +100,12 @@ def test_deposit_parity(gname, precision):
         np.testing.assert_array_equal(M[off], M[opp][:, gj])
 
 
-@pytest.mark.parametrize("group", [8, 16, 32, 64])
-def test_deposit_every_lane_group_width(group):
-    """Cells with far more particles than lanes (many rounds) and empty cells."""
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("group", [4, 8, 16, 32, 64])
+def test_deposit_every_lane_group_width(group, precision):
+    """Cells with far more particles than lanes (many rounds) and empty cells,
+    at every lane-group width of the 2D deposit (the automatic choice takes
+    4 lanes on the FP64 bench sheet) and of the kinetic-energy kernel."""
     need_gpu()
     g = grids()["2d_7x5"]
     rng = np.random.default_rng(5)
@@ -110,15 +113,18 @@ def test_deposit_every_lane_group_width(group):
     cell, sp, off, u, w = random_cells(g, n, rng, empty_frac=0.5)
     cell[: n // 2] = 3       # one crowded cell
     B = (2 * rng.random((3, g.N)) - 1) * 2.0
-    ctx = make_ctx(g, "fp64", n, group=group)
+    E = (2 * rng.random((3, g.N)) - 1) * 0.5
+    ctx = make_ctx(g, precision, n, group=group)
     parts = load(ctx, cell, sp, off, u, w)
     from paper_2509_11100_amd import relsim
 
     J, M = relsim.deposit_moments(ctx, parts, torch_grid(B))
     st = host_state(g, parts)
     Jr, Mr = oracle.deposit(g, st["x"], st["u"], st["w"], st["species"], B)
-    check_rel(J.cpu().numpy(), Jr, 1e-12)
-    check_rel(M.cpu().numpy(), Mr, 1e-12)
+    check_rel(J.cpu().numpy(), Jr, TOL[precision])
+    check_rel(M.cpu().numpy(), Mr, TOL[precision])
+    W = relsim.energy(ctx, parts, torch_grid(E), torch_grid(B))
+    np.testing.assert_allclose(W, oracle.energy(g, st["u"], st["w"], st["species"], E, B), rtol=1e-12)
 
 
 def test_deposit_with_no_particles():
@@ -591,9 +597,10 @@ def test_energy_conserving_passes(gname, precision):
 
 
 def test_energy_conserving_steps_match_oracle_and_conserve_energy():
-    """Three energy-conserving FP64 steps of the 64 x 32 pair sheet (theta =
-    1, relativistic) against the oracle's fixed point; the energy stays
-    constant to the iteration's tolerance where the standard step drifts."""
+    """Three energy-conserving FP64 steps of the 64 x 32 pair sheet (sheet
+    temperature kT = m c^2, relativistic; time centring theta = 1/2) against
+    the oracle's fixed point; the energy stays constant to the iteration's
+    tolerance where the standard step drifts."""
     need_gpu()
     from paper_2509_11100_amd import relsim
 
