@@ -211,6 +211,26 @@ int relsim_fill_cells(relsim_ctx *ctx, relsim_particles *part);
  * array), accumulated in FP64 in both precisions.  Synchronous. */
 int relsim_energy(relsim_ctx *ctx, const relsim_particles *part, const double *E, const double *B, double out[4]);
 
+/* relsim_energy for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * No context and no workspace: the reduction partials live in a file-scope
+ * device array of this library (4 MiB, one copy per device, held until the
+ * process ends; its device address is looked up once per device on the first
+ * call there).  p: the parameters a context would be created with (validated
+ * as relsim_init does); hip_stream: the stream to enqueue on (NULL = default
+ * stream); part: bin-sorted particles (front set); E, B: FP64 [3][N] device
+ * arrays; out: device array of 4 doubles that receives kinetic, electric,
+ * magnetic and total energy, the same values relsim_energy returns for the
+ * same inputs, bit for bit.  Asynchronous (no host copy, no synchronisation,
+ * no allocation): non-finite values are not reported, and the deferred
+ * range flags of a context's push are not checked.  Returns RELSIM_EINVAL
+ * for bad parameters or pointers and RELSIM_ERANGE when the grid needs more
+ * kinetic partials (one per 64/group cells) than the scratch holds (about
+ * 520,000: 4.2M cells at 8 lanes per cell).  Calls that overlap on one
+ * device (other streams, other threads) share the array and race. */
+int relsim_energy_noalloc(const relsim_params *p, void *hip_stream, const relsim_particles *part, const double *E,
+                          const double *B, double *out);
+
 /* Field operators, exposed for tests and for the adjoint (all FP64 [3][N]).
  * out = C_NC in (nodes -> centres), C_CN in (centres -> nodes), or the S4
  * operator A applied to x. */

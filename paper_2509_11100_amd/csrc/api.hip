@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -388,7 +389,7 @@ void enqueue_field_energy(const KParams &kp, const double *E, const double *B, d
 }
 
 // kinetic, electric, magnetic and total energy from the three device sums
-void finish_energy(const KParams &kp, const double sums[3], double out[4]) {
+__host__ __device__ void finish_energy(const KParams &kp, const double sums[3], double out[4]) {
   const double f = kp.V / (8.0 * M_PI);
   out[0] = sums[0];
   out[1] = f * sums[1];
@@ -954,3 +955,86 @@ const char *relsim_strerror(int code) {
 const char *relsim_last_error(const relsim_ctx *c) { return c ? c->err.c_str() : "no context"; }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free energy diagnostic: relsim_energy without a context, its
+// reduction partials in a file-scope device array instead of the caller's
+// workspace.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchDoubles = size_t(1) << 19;  // 4 MiB per device
+constexpr size_t kScratchFixed = 3 * (size_t)kRedBlocks + 8;  // reduction partials and the three sums
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+// One copy per device, held by the device until the process ends; every
+// relsim_energy_noalloc call on that device uses it.
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (the array's host-side name is not a device address).
+int scratch_on_device(double **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return RELSIM_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return RELSIM_EHIP;
+    g_scratch_ptr[dev] = static_cast<double *>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return RELSIM_OK;
+}
+
+// out[0..3] = kinetic, electric, magnetic, total from the three sums.
+__global__ void k_finish_energy(KParams kp, const double *__restrict__ sums, double *__restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double v[4];
+    finish_energy(kp, sums, v);
+    for (int i = 0; i < 4; ++i) out[i] = v[i];
+  }
+}
+
+}  // namespace
+
+extern "C" int relsim_energy_noalloc(const relsim_params *params, void *hip_stream, const relsim_particles *pt,
+                                     const double *E, const double *B, double *out) {
+  std::string msg;
+  if (validate(params, msg) != RELSIM_OK) return RELSIM_EINVAL;
+  if (!pt || !E || !B || !out) return RELSIM_EINVAL;
+  relsim_params p = *params;
+  if (p.dim == 2) p.nz = 1;
+  if (pt->n < 0 || pt->n > p.max_particles) return RELSIM_EINVAL;
+  if (!pt->bin_start || !pt->uw || !aligned(pt->uw, 4 * (p.precision == RELSIM_MIXED ? 4 : 8)) ||
+      !aligned(out, sizeof(double)))
+    return RELSIM_EINVAL;
+  const KParams kp = make_kparams(&p);
+  const int G = choose_group(p, kp, pt->n);
+  const size_t need = kScratchFixed + (size_t)kinetic_partials(kp, G);
+  if (need > kScratchDoubles) return RELSIM_ERANGE;  // grid too large for the fixed scratch
+  double *sc = nullptr;
+  const int rc = scratch_on_device(&sc);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  // [0, 3 kRedBlocks): reduction partials; then the three sums; then the
+  // per-block kinetic partials.  Every kernel writes all it reads.
+  double *part = sc;
+  double *res = sc + 3 * (size_t)kRedBlocks;
+  double *kpart = sc + kScratchFixed;
+  PartPtrs pp;
+  pp.bin_start = pt->bin_start;
+  pp.xy = pt->xy;
+  pp.uw = pt->uw;
+  pp.z = pt->z;
+  enqueue_kinetic(kp, p.precision, G, pp, kpart, part, res, st);
+  enqueue_field_energy(kp, E, B, part, res, st);
+  hipLaunchKernelGGL(k_finish_energy, dim3(1), dim3(64), 0, st, kp, res, out);
+  return hipGetLastError() == hipSuccess ? RELSIM_OK : RELSIM_EHIP;
+}

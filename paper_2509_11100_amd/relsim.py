@@ -376,6 +376,29 @@ def energy(ctx: Context, parts: Particles, E: torch.Tensor, B: torch.Tensor) -> 
     return np.array(list(out))
 
 
+def energy_noalloc(params, parts: Particles, E: torch.Tensor, B: torch.Tensor,
+                   out: Optional[torch.Tensor] = None, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """relsim_energy_noalloc: the S7 energy without a context or workspace,
+    written asynchronously into out (4 float64 on the device: kinetic,
+    electric, magnetic, total).  params: a Context or its relsim_params."""
+    p = params.params if isinstance(params, Context) else params
+    dev = E.device
+    out = torch.empty(4, dtype=torch.float64, device=dev) if out is None else out
+    for t in (E, B, out):
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.device != dev:
+            raise ValueError("E, B and out must be contiguous float64 tensors on one device")
+    st = torch.cuda.current_stream(dev) if stream is None else stream
+    parts.s.n = parts.n
+    rc = _lib.load().relsim_energy_noalloc(C.byref(p), C.c_void_p(st.cuda_stream), C.byref(parts.s), _ptr(E),
+                                           _ptr(B), _ptr(out))
+    if rc == _lib.RELSIM_ERANGE:
+        raise RelsimError(rc, "relsim_energy_noalloc: the grid needs more than the 4 MiB of per-device scratch "
+                              "(about 520,000 kinetic partials, one per 64/group cells)")
+    if rc != _lib.RELSIM_OK:
+        raise RelsimError(rc, "relsim_energy_noalloc: %s" % _lib.load().relsim_strerror(rc).decode())
+    return out
+
+
 class PicardNotConverged(RuntimeError):
     """The energy-conserving step's fixed point did not reach its tolerance."""
 
