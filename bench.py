@@ -193,7 +193,8 @@ def run_precision(prec, wl, host, steps, warmup, rtol, want_kernels=True, group=
         relsim.timing_enable(ctx, False)
         if ev is not None:
             ev[3].record(st)
-        W = relsim.energy(ctx, parts, E1, B1)
+        # S7 with the kinetic part the push summed (no pass over the particles)
+        W = relsim.energy_pushed(ctx, E1, B1)
         if ev is not None:
             ev[4].record(st)
         return it, rr, W

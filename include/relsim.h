@@ -211,6 +211,17 @@ int relsim_fill_cells(relsim_ctx *ctx, relsim_particles *part);
  * array), accumulated in FP64 in both precisions.  Synchronous. */
 int relsim_energy(relsim_ctx *ctx, const relsim_particles *part, const double *E, const double *B, double out[4]);
 
+/* a7 fused into a6: the S7 energy of the particle state written by the
+ * last relsim_push or relsim_push_ec with resort on this context, whose
+ * second pass summed each pushed particle's FP64 kinetic term per wave (in
+ * a fixed order, so the result is deterministic; it equals relsim_energy's
+ * to rounding order), plus the field energies of E and B as in
+ * relsim_energy.  No pass over the particles.  The caller must not have
+ * changed the particle arrays since that push.  RELSIM_EINVAL if no push
+ * with resort happened since the context was made or since relsim_sort or
+ * a relsim_push without resort.  Synchronous. */
+int relsim_energy_pushed(relsim_ctx *ctx, const double *E, const double *B, double out[4]);
+
 /* relsim_energy for callers that cannot allocate device memory: code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation.
  * No context and no workspace: the reduction partials live in a file-scope

@@ -87,6 +87,7 @@ def load() -> C.CDLL:
         "relsim_fill_cells": (C.c_int, [vp, pt]),
         "relsim_placement_clamps": (C.c_int, [vp, C.POINTER(C.c_int64)]),
         "relsim_energy_noalloc": (C.c_int, [pp, vp, pt, vp, vp, vp]),
+        "relsim_energy_pushed": (C.c_int, [vp, vp, vp, dp]),
         "relsim_curl_nc": (C.c_int, [vp, vp, vp]),
         "relsim_curl_cn": (C.c_int, [vp, vp, vp]),
         "relsim_apply_A": (C.c_int, [vp, vp, vp, vp]),
@@ -112,5 +113,5 @@ def exported_symbols():
         "relsim_apply_A", "relsim_apply_AT", "relsim_push_adjoint", "relsim_field_solve_adjoint",
         "relsim_deposit_adjoint", "relsim_timing_enable", "relsim_timing_reset", "relsim_timing_read",
         "relsim_strerror", "relsim_last_error", "relsim_deposit_moments_ec", "relsim_gamma_mean", "relsim_push_ec",
-        "relsim_placement_clamps", "relsim_energy_noalloc",
+        "relsim_placement_clamps", "relsim_energy_noalloc", "relsim_energy_pushed",
     ]

@@ -39,6 +39,10 @@ struct relsim_ctx {
   int device;
   std::string err;
   double *host;  // pinned scratch for small device-to-host copies
+  // kinetic-energy partials of the last push with re-sort (one per wave of
+  // its second pass), or 0 when no such push has happened since the last
+  // call that could change the particle state
+  int push_ke_parts = 0;
   // timing
   bool timing = false;
   std::vector<hipEvent_t> pool;
@@ -182,6 +186,7 @@ Layout make_layout(const relsim_params *p) {
   L.stE = take(ng * 4 * es);
   L.sink = take((size_t)kSinkSlots * 64 * 32);
   L.kin_part = take(nc * 8);
+  L.push_ke = take(nc * 8);
   L.end = o;
   return L;
 }
@@ -511,6 +516,7 @@ int relsim_sort(relsim_ctx *c, relsim_particles *pt) {
                  c->at<int32_t>(c->L.gs_hist), c->at<int32_t>(c->L.scan_tmp), c->at<int32_t>(c->L.err),
                  pt->bin_start_back, pt->cell_back, back(pt), c->st);
   });
+  c->push_ke_parts = 0;
   rc = launch_status(c, "relsim_sort");
   if (rc) return rc;
   rc = check_flags(c);
@@ -583,13 +589,16 @@ int relsim_push_ec(relsim_ctx *c, relsim_particles *pt, const double *E_theta, c
     });
     timed(c, "push_scatter", [&] {
       launch_push_scatter(c->kp, c->p.precision, cells_s, pp, stE, stB, dirc, pre, pt->bin_start_back, back(pt),
-                          (int)pt->n, err, clamp_counter(c), new_index, c->at<char>(c->L.sink), c->st);
+                          (int)pt->n, err, clamp_counter(c), new_index, c->at<char>(c->L.sink),
+                          c->at<double>(c->L.push_ke), c->st);
     });
     rc = launch_status(c, "relsim_push");
     if (rc) return rc;
     swap_sets(pt);
+    c->push_ke_parts = c->kp.ncells / cells_s;
     return RELSIM_OK;
   }
+  c->push_ke_parts = 0;
   return launch_status(c, "relsim_push");
 }
 
@@ -665,6 +674,29 @@ int relsim_energy(relsim_ctx *c, const relsim_particles *pt, const double *E, co
   });
   timed(c, "field_energy", [&] { enqueue_field_energy(c->kp, E, B, part, res, c->st); });
   rc = launch_status(c, "relsim_energy");
+  if (rc) return rc;
+  rc = fetch(c, res, 3);
+  if (rc) return rc;
+  finish_energy(c->kp, c->host, out);
+  for (int i = 0; i < 4; ++i)
+    if (!std::isfinite(out[i])) return fail(c, RELSIM_ENONFINITE, "energy is not finite");
+  return RELSIM_OK;
+}
+
+int relsim_energy_pushed(relsim_ctx *c, const double *E, const double *B, double out[4]) {
+  if (!c) return RELSIM_EINVAL;
+  if (!E || !B || !out) return fail(c, RELSIM_EINVAL, "null argument");
+  if (c->push_ke_parts <= 0)
+    return fail(c, RELSIM_EINVAL, "relsim_energy_pushed needs a relsim_push with resort since the last sort");
+  int rc = check_flags(c);
+  if (rc) return rc;
+  double *part = c->at<double>(c->L.red_part);
+  double *res = c->at<double>(c->L.gm_small);
+  timed(c, "kinetic_reduce", [&] {
+    launch_reduce_long(c->at<double>(c->L.push_ke), c->push_ke_parts, part, res, c->st);
+  });
+  timed(c, "field_energy", [&] { enqueue_field_energy(c->kp, E, B, part, res, c->st); });
+  rc = launch_status(c, "relsim_energy_pushed");
   if (rc) return rc;
   rc = fetch(c, res, 3);
   if (rc) return rc;

@@ -756,6 +756,7 @@ struct Segment {
   V4<T> *Bg;         // (C + 2) x 3 [x 3] cell centres from (i0 - 1, j - 1, k - 1), x fastest
   V4<T> *Eg;         // (C + 1) x 2 [x 2] nodes from (i0, j, k)
   T (*stab)[8];      // species charge and beta
+  double *mtab;      // species mass (FP64)
   int *binb;         // nb + 1 bin starts, then INT_MAX up to a power of two
   int *keys;         // nb x NDIR counters (counting pass) or run bases (scatter)
 };
@@ -775,7 +776,7 @@ __host__ __device__ constexpr int binb_slots(int nb) { return nb + 1 > pow2_at_l
 template <typename T, int DIM>
 __host__ __device__ constexpr size_t segment_lds_bytes(int C, int S) {
   return sizeof(V4<T>) * ((size_t)(C + 2) * 3 * (DIM == 3 ? 3 : 1) + (size_t)(C + 1) * 2 * (DIM == 3 ? 2 : 1)) +
-         sizeof(T) * 16 + sizeof(int) * (size_t)binb_slots(C * S) +
+         sizeof(T) * 16 + sizeof(double) * 8 + sizeof(int) * (size_t)binb_slots(C * S) +
          sizeof(int) * (size_t)C * S * (DIM == 3 ? 27 : 9);
 }
 
@@ -805,7 +806,8 @@ __device__ __forceinline__ Segment<T, DIM> stage_segment(const KParams &kp, int 
   sg.Bg = reinterpret_cast<V4<T> *>(smem);
   sg.Eg = sg.Bg + nB;
   sg.stab = reinterpret_cast<T(*)[8]>(sg.Eg + nE);
-  sg.binb = reinterpret_cast<int *>(sg.stab + 2);
+  sg.mtab = reinterpret_cast<double *>(sg.stab + 2);
+  sg.binb = reinterpret_cast<int *>(sg.mtab + 8);
   sg.keys = sg.binb + binb_slots(sg.nb);
   // centre (i0 - 1 + a, j - 1 + b, k - 1 + c) sits at ghosted index
   // (i0 + a) + gx (j + b) + gxy (k + c)
@@ -819,6 +821,7 @@ __device__ __forceinline__ Segment<T, DIM> stage_segment(const KParams &kp, int 
   }
   for (int t = lane; t < binb_slots(sg.nb); t += 64) sg.binb[t] = t <= sg.nb ? bin_start[sg.c0 * S + t] : INT_MAX;
   fill_species_table<T>(pc, sg.stab, lane);
+  if (lane < 8) sg.mtab[lane] = kp.m[lane];
   return sg;
 }
 
@@ -1045,8 +1048,8 @@ __device__ __forceinline__ void scatter_round(const KParams &kp, const PC<T> &pc
                                               const uint8_t *__restrict__ dirc,
                                               V2<T> *__restrict__ xo, V4<T> *__restrict__ uo, T *__restrict__ zo,
                                               int32_t *__restrict__ perm, void *__restrict__ sink, T q0, T q1,
-                                              T b0, T b1, int &p, int &bad, int &nclamp, PRec<T> &cur,
-                                              uint8_t &dc) {
+                                              T b0, T b1, double m0, double m1, int &p, int &bad, int &nclamp,
+                                              double &ke, PRec<T> &cur, uint8_t &dc) {
   constexpr int NDIR = DIM == 3 ? 27 : 9;
   constexpr int DBITS = DIM == 3 ? 5 : 4;  // bits of a move code
   const int S = kp.nspecies;
@@ -1058,6 +1061,16 @@ __device__ __forceinline__ void scatter_round(const KParams &kp, const PC<T> &pc
   species_consts<T>(S, s, q0, q1, b0, b1, sg.stab, qs, bs);
   T fx, fy, fz, nx, ny, nz;
   push_one<T, DIM, GB>(kp, pc, segment_fields(sg, lc), bs, cur, fx, fy, fz, nx, ny, nz);
+  // S7's kinetic term of the pushed particle, in FP64 whatever T:
+  // w m c^2 (gamma - 1) = w m |u|^2 / (gamma + 1), or w m |u|^2 / 2 without
+  // relativity
+  {
+    const double ux = nx, uy = ny, uz = nz;
+    const double uu = ux * ux + uy * uy + uz * uz;
+    const double wm = (double)cur.w * (S == 2 ? (s ? m1 : m0) : sg.mtab[s]);
+    const double term = kp.nonrel ? 0.5 * wm * uu : wm * uu / (sqrt(1.0 + uu * kp.inv_c2) + 1.0);
+    ke += pv ? term : 0.0;
+  }
   // the new state goes where the counting pass counted it (move dcur),
   // with its offsets taken relative to that cell
   int off = 0, clamp = 0;
@@ -1133,7 +1146,7 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, int C, const in
                                                      int32_t *__restrict__ err,
                                                      unsigned long long *__restrict__ clamps,
                                                      int32_t *__restrict__ perm, void *__restrict__ sink,
-                                                     const T *__restrict__ gb) {
+                                                     const T *__restrict__ gb, double *__restrict__ kep) {
   constexpr int NDIR = DIM == 3 ? 27 : 9;
   extern __shared__ __attribute__((aligned(32))) unsigned char smem[];
   const int lane = threadIdx.x;
@@ -1166,6 +1179,7 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, int C, const in
   PRec<T> rb0{}, rb1{}, rb2{};
   uint8_t db0 = 0, db1 = 0, db2 = 0;
   int p = p0 + lane, bad = 0, nclamp = 0;
+  double ke = 0.0;  // this lane's kinetic energy of the pushed particles
   if (rounds > 0) {
     load_rec<T, DIM>(p, p1, xy, uw, zz, rb0);
     load_gbar<GB>(p, p1, gb, rb0);
@@ -1181,9 +1195,10 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, int C, const in
   // count only the loop's own loads and stores
   __builtin_amdgcn_s_waitcnt(0);
   const T sq0 = pc.q0, sq1 = pc.q1, sb0 = pc.b0, sb1 = pc.b1;
+  const double sm0 = kp.m[0], sm1 = kp.m[1];
 #define RELSIM_SCATTER_ROUND(rb, db)                                                                            \
   scatter_round<T, DIM, PERM, GB>(kp, pc, sg, p1, lane, lt, ntot, xy, uw, zz, gb, dirc, xo, uo, zo, perm, sink, \
-                                  sq0, sq1, sb0, sb1, p, bad, nclamp, rb, db)
+                                  sq0, sq1, sb0, sb1, sm0, sm1, p, bad, nclamp, ke, rb, db)
   int r = 0;
 #pragma unroll 1
   for (; r + 3 <= rounds; r += 3) {
@@ -1198,6 +1213,11 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, int C, const in
   const int balm = __ballot(bad & 4) ? 8 : 0;
   if ((ball | balm) && lane == 0) atomicOr(err, ball | balm);
   if (nclamp && lane == 0) atomicAdd(clamps, (unsigned long long)nclamp);
+  // the wave's kinetic energy, summed in a fixed butterfly (every lane ends
+  // with the same value), one partial per segment
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) ke += __shfl_xor(ke, o);
+  if (lane == 0) kep[xcd_remap(blockIdx.x, gridDim.x)] = ke;
 }
 
 // ---------------------------------------------------------------------------
@@ -1386,30 +1406,34 @@ void gamma_mean_impl(const KParams &kp, int C, const PartPtrs &pp, const void *E
 template <typename T, int DIM, bool PERM, bool GB>
 void scatter_launch(const KParams &kp, int C, const PartPtrs &src, const void *Est, const void *Bst,
                     const uint8_t *dirc, const uint16_t *pre, const int32_t *bsn, const PartPtrs &out, int ntot,
-                    int32_t *err, unsigned long long *clamps, int32_t *perm, void *sink, hipStream_t st) {
+                    int32_t *err, unsigned long long *clamps, int32_t *perm, void *sink, double *kep,
+                    hipStream_t st) {
   const int nblk = kp.ncells / C;
   const size_t lds = segment_lds_bytes<T, DIM>(C, kp.nspecies);
   hipLaunchKernelGGL((k_push_scatter<T, DIM, PERM, GB>), dim3(nblk), dim3(64), lds, st, kp, C, src.bin_start,
                      cp<V2<T>>(src.xy), cp<V4<T>>(src.uw), cp<T>(src.z), cp<V4<T>>(Est), cp<V4<T>>(Bst), dirc, pre,
                      bsn, mp<V2<T>>(out.xy), mp<V4<T>>(out.uw), mp<T>(out.z), ntot, err, clamps, perm, sink,
-                     cp<T>(src.gbar));
+                     cp<T>(src.gbar), kep);
 }
 
 template <typename T, int DIM>
 void scatter_impl(const KParams &kp, int C, const PartPtrs &src, const void *Est, const void *Bst,
                   const uint8_t *dirc, const uint16_t *pre, const int32_t *bsn, const PartPtrs &out, int ntot,
-                  int32_t *err, unsigned long long *cl, int32_t *perm, void *sink, hipStream_t st) {
+                  int32_t *err, unsigned long long *cl, int32_t *perm, void *sink, double *kep, hipStream_t st) {
   if (src.gbar) {
     if (perm)
-      scatter_launch<T, DIM, true, true>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, cl, perm, sink, st);
+      scatter_launch<T, DIM, true, true>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, cl, perm, sink, kep,
+                                         st);
     else
-      scatter_launch<T, DIM, false, true>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, cl, perm, sink, st);
+      scatter_launch<T, DIM, false, true>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, cl, perm, sink,
+                                          kep, st);
   } else {
     if (perm)
-      scatter_launch<T, DIM, true, false>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, cl, perm, sink, st);
+      scatter_launch<T, DIM, true, false>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, cl, perm, sink,
+                                          kep, st);
     else
       scatter_launch<T, DIM, false, false>(kp, C, src, Est, Bst, dirc, pre, bsn, out, ntot, err, cl, perm, sink,
-                                           st);
+                                           kep, st);
   }
 }
 
@@ -1537,17 +1561,17 @@ void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream
 void launch_push_scatter(const KParams &kp, int prec, int cells, const PartPtrs &src, const void *Est,
                          const void *Bst, const uint8_t *dirc, const uint16_t *pre, const int32_t *bin_start_new,
                          const PartPtrs &out, int ntot, int32_t *err, unsigned long long *clamps, int32_t *perm,
-                         void *sink, hipStream_t st) {
+                         void *sink, double *kep, hipStream_t st) {
   const bool f = prec == RELSIM_MIXED;
   if (kp.dim == 3)
     return f ? scatter_impl<float, 3>(kp, cells, src, Est, Bst, dirc, pre, bin_start_new, out, ntot, err, clamps,
-                                      perm, sink, st)
+                                      perm, sink, kep, st)
              : scatter_impl<double, 3>(kp, cells, src, Est, Bst, dirc, pre, bin_start_new, out, ntot, err, clamps,
-                                       perm, sink, st);
+                                       perm, sink, kep, st);
   return f ? scatter_impl<float, 2>(kp, cells, src, Est, Bst, dirc, pre, bin_start_new, out, ntot, err, clamps,
-                                    perm, sink, st)
+                                    perm, sink, kep, st)
            : scatter_impl<double, 2>(kp, cells, src, Est, Bst, dirc, pre, bin_start_new, out, ntot, err, clamps,
-                                     perm, sink, st);
+                                     perm, sink, kep, st);
 }
 
 void launch_fill_cells(const KParams &kp, const int32_t *bin_start, int32_t *cell, hipStream_t st) {

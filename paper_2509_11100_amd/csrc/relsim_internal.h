@@ -31,7 +31,7 @@ struct KParams {
 // Offsets (in bytes) of the regions carved out of the caller's workspace.
 struct Layout {
   size_t S, cnt, pre, total, scan_tmp, dirc, err, gm_V, gm_t, gm_b, gm_r, gm_part, gm_small, red_part;
-  size_t gs_k0, gs_k1, gs_v0, gs_v1, gs_hist, stB, stE, sink, kin_part, end;
+  size_t gs_k0, gs_k1, gs_v0, gs_v1, gs_hist, stB, stE, sink, kin_part, push_ke, end;
 };
 
 constexpr int kMaxRestart = 64;
@@ -96,11 +96,13 @@ size_t scan_tmp_elems(int n);
 // second pass of the re-sort: push src again and write the new state into
 // out in the new bin order, each in the cell of its recorded move (err bit
 // 8: a recomputed position further than rounding outside that cell; *clamps
-// += particles within rounding outside it, put on its face)
+// += particles within rounding outside it, put on its face).  kep[w] gets
+// the FP64 kinetic energy of the particles wave w pushed (ncells / cells
+// waves; w in the segment order).
 void launch_push_scatter(const KParams &kp, int prec, int cells, const PartPtrs &src, const void *Est,
                          const void *Bst, const uint8_t *dirc, const uint16_t *pre, const int32_t *bin_start_new,
                          const PartPtrs &out, int ntot, int32_t *err, unsigned long long *clamps, int32_t *perm,
-                         void *sink, hipStream_t st);
+                         void *sink, double *kep, hipStream_t st);
 // cell[p] for every particle from the bin ranges
 void launch_fill_cells(const KParams &kp, const int32_t *bin_start, int32_t *cell, hipStream_t st);
 // partials: one double per block of 64/group cells (at most ncells)

@@ -376,6 +376,16 @@ def energy(ctx: Context, parts: Particles, E: torch.Tensor, B: torch.Tensor) -> 
     return np.array(list(out))
 
 
+def energy_pushed(ctx: Context, E: torch.Tensor, B: torch.Tensor) -> np.ndarray:
+    """relsim_energy_pushed -> (kinetic, electric, magnetic, total) of the
+    state the last push with re-sort wrote (its kinetic part summed by that
+    push)"""
+    _grid_ok(ctx, E, B)
+    out = (C.c_double * 4)()
+    ctx.check(ctx.lib.relsim_energy_pushed(ctx.handle, _ptr(E), _ptr(B), out))
+    return np.array(list(out))
+
+
 def energy_noalloc(params, parts: Particles, E: torch.Tensor, B: torch.Tensor,
                    out: Optional[torch.Tensor] = None, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
     """relsim_energy_noalloc: the S7 energy without a context or workspace,
@@ -449,6 +459,7 @@ class Step:
         self.picard_tol, self.picard_maxit = picard_tol, picard_maxit
         self.allow_unconverged = allow_unconverged
         self.picard_iters, self.picard_change, self.picard_converged = 0, 0.0, True
+        self._pushed = False
         if energy_conserving:
             cap = max(parts.n, 1)
             self._gb = [torch.empty(cap, dtype=ctx.dtype, device=ctx.device) for _ in range(2)]
@@ -477,12 +488,17 @@ class Step:
             else:
                 self._solve(None)
             push(self.ctx, self.parts, self.E_theta, self.B, resort=True, gbar=gbar)
+            self._pushed = True
             self.E, self._E1 = self._E1, self.E
             self.B, self._B1 = self._B1, self.B
         return self
 
     def energy(self) -> np.ndarray:
-        """relsim_energy of the current state: (kinetic, electric, magnetic, total)"""
+        """S7 of the current state: (kinetic, electric, magnetic, total); after
+        a step, relsim_energy_pushed (the kinetic sum formed by the push),
+        before the first, relsim_energy"""
+        if self._pushed:
+            return energy_pushed(self.ctx, self.E, self.B)
         return energy(self.ctx, self.parts, self.E, self.B)
 
 

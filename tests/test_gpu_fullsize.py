@@ -117,6 +117,10 @@ def check_push(wl, p, E, B, ctx, parts, J, M, precision):
     relsim.push(ctx, parts, Eth, Bt, resort=True, new_index=perm)
     # the re-sort placed no particle on a face by a rounding difference
     assert relsim.placement_clamps(ctx) == 0
+    # the kinetic energy the push summed equals a separate pass over the
+    # pushed state (itself checked against the oracle by test_fullsize_energy)
+    Wp = relsim.energy_pushed(ctx, Eth, Bt)
+    np.testing.assert_allclose(Wp, relsim.energy(ctx, parts, Eth, Bt), rtol=1e-12)
     rng = np.random.default_rng(11)
     old = np.unique(np.concatenate([rng.integers(0, n, 20000), [0, n - 1]]))
     new = perm[torch.as_tensor(old, device=perm.device)].cpu().numpy().astype(np.int64)

@@ -402,3 +402,46 @@ def test_offset_rounding_to_the_face_is_not_a_clamp():
     np.testing.assert_array_equal(s1["cell"][new], st0["cell"])
     np.testing.assert_array_equal(s1["off"][0][new][edge], 0.0)
     np.testing.assert_array_equal(s1["off"][0][new][~edge], 0.5)
+
+
+# ----------------------------------------------------------------------------
+# kinetic energy summed by the push (S7 fused into S6)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("nonrel", [False, True])
+@pytest.mark.parametrize("ns", [2, 3])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_energy_pushed_is_the_energy_of_the_pushed_state(dim, precision, ns, nonrel):
+    need_gpu()
+    import dataclasses
+
+    from paper_2509_11100_amd import _lib, relsim
+
+    g = dataclasses.replace(nonrel_grid(dim), nonrel=nonrel)
+    if ns == 3:
+        g = dataclasses.replace(g, q=(1.0, -1.0, 2.0), m=(1.0, 1.0, 25.0))
+    rng = np.random.default_rng(440 + dim + 3 * ns + (7 if nonrel else 0))
+    n = 3000
+    cell, sp, off, u, w = random_cells(g, n, rng, umax=1.0 if nonrel else 3.0, empty_frac=0.2)
+    B = (2 * rng.random((3, g.N)) - 1) * 2.0
+    E = (2 * rng.random((3, g.N)) - 1) * 0.5
+    ctx = make_ctx(g, precision, n)
+    parts = load(ctx, cell, sp, off, u, w)
+    Et, Bt = torch_grid(E), torch_grid(B)
+    with pytest.raises(_lib.RelsimError) as ei:
+        relsim.energy_pushed(ctx, Et, Bt)  # nothing pushed yet
+    assert ei.value.code == _lib.RELSIM_EINVAL
+    st0 = host_state(g, parts)
+    relsim.push(ctx, parts, Et, Bt, resort=True)
+    W = relsim.energy_pushed(ctx, Et, Bt)
+    np.testing.assert_allclose(W, relsim.energy(ctx, parts, Et, Bt), rtol=1e-12)
+    s1 = host_state(g, parts)
+    np.testing.assert_allclose(W, oracle.energy(g, s1["u"], s1["w"], s1["species"], E, B), rtol=1e-12)
+    # against the oracle's own push of the starting state (teacher-forced)
+    xr, ur = oracle.push(g, st0["x"], st0["u"], st0["species"], E, B)
+    Wr = oracle.energy(g, ur, st0["w"], st0["species"], E, B)
+    assert abs(W[0] - Wr[0]) <= TOL[precision] * abs(Wr[0])
+    # a push without re-sort leaves no fused sum behind
+    relsim.push(ctx, parts, Et, Bt, resort=False)
+    with pytest.raises(_lib.RelsimError):
+        relsim.energy_pushed(ctx, Et, Bt)
