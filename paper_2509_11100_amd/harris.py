@@ -71,6 +71,17 @@ class Workload:
     q: tuple = (1.0, -1.0)
     m: tuple = (1.0, 1.0)
     dt_wpe: Optional[float] = None  # if set, dt = dt_wpe / omega_pe0 (overrides cfl)
+    # Separate populations (the nonlinear runs of Sec. 3.2): if ppc_sheet is
+    # set, the sheet and the background are loaded as separate species, the
+    # sheet ones first (q and m list both, e.g. ion sheet, electron sheet,
+    # ion background, electron background), with ppc_sheet particles per
+    # cell for each sheet species and ppc for each background species.
+    ppc_sheet: Optional[int] = None
+    # ... loaded only in the cells where the sheet density reaches sheet_cut
+    # n0 somewhere in the cell (0: in every cell)
+    sheet_cut: float = 0.0
+    dx_over_de: Optional[float] = None  # if set, dx in units of d_e,C (background density; overrides dx_over_a)
+    dt_wpb: Optional[float] = None      # if set, dt times the background omega_pe (overrides cfl and dt_wpe)
 
     @property
     def nspecies(self) -> int:
@@ -81,8 +92,58 @@ class Workload:
         return self.nx * self.ny * (self.nz if self.dim == 3 else 1)
 
     @property
+    def split(self) -> bool:
+        """Sheet and background loaded as separate species."""
+        return self.ppc_sheet is not None
+
+    @property
+    def ppc_of_species(self) -> tuple:
+        """Particles per cell of every species."""
+        if not self.split:
+            return (self.ppc,) * self.nspecies
+        h = self.nspecies // 2
+        return (self.ppc_sheet,) * h + (self.ppc,) * h
+
+    @property
+    def ppc_total(self) -> int:
+        return int(sum(self.ppc_of_species))
+
+    def sheet_rows(self) -> np.ndarray:
+        """Separate populations: True for the cell rows (y index) that hold
+        sheet particles (where n0 sech^2 of either sheet reaches sheet_cut
+        n0 somewhere in the row)."""
+        ny, dx = self.ny, self.dx
+        Y = ny * dx
+        lo = np.arange(ny) * dx - 0.5 * Y
+        hi = lo + dx
+        a = self.harris.a
+        keep = np.zeros(ny, bool)
+        for ys in (-0.25 * Y, 0.25 * Y):  # the two sheets, at +-L_y/2
+            d = np.maximum(0.0, np.maximum(lo - ys, ys - hi))  # distance of the row from the sheet centre
+            keep |= _sech2(d / a) >= self.sheet_cut
+        return keep
+
+    def counts(self) -> np.ndarray:
+        """Particles per (cell, species), shape (ncells, nspecies)."""
+        c = np.tile(np.asarray(self.ppc_of_species, dtype=np.int64), (self.ncells, 1))
+        if self.split and self.sheet_cut > 0:
+            assert self.dim == 2, "separate populations are a 2D loading"
+            rows = self.sheet_rows()
+            j = (np.arange(self.ncells) // self.nx) % self.ny
+            c[~rows[j], : self.nspecies // 2] = 0
+        return c
+
+    @property
     def nparticles(self) -> int:
-        return self.ncells * self.nspecies * self.ppc
+        if self.split and self.sheet_cut > 0:
+            return int(self.counts().sum())
+        return self.ncells * self.ppc_total
+
+    @property
+    def de_C(self) -> float:
+        """Classical electron inertial length with the background density
+        (the paper's d_e,C; electron mass 1)."""
+        return math.sqrt(1.0 / (4.0 * math.pi * self.nb_over_n0 * N0))
 
     @property
     def harris(self) -> _params.HarrisParams:
@@ -90,11 +151,16 @@ class Workload:
 
     @property
     def dx(self) -> float:
+        if self.dx_over_de is not None:
+            return self.dx_over_de * self.de_C
         return self.dx_over_a * self.harris.a
 
     @property
     def dt(self) -> float:
-        # omega_pe0 = 1 in these units (n0 = N0, m_e = e = c = 1)
+        # omega_pe0 = 1 in these units (n0 = N0, m_e = e = c = 1); the
+        # background omega_pe is sqrt(n_b / n0) of it
+        if self.dt_wpb is not None:
+            return self.dt_wpb / math.sqrt(self.nb_over_n0)
         return self.dt_wpe if self.dt_wpe is not None else self.cfl * self.dx
 
     @property
@@ -127,6 +193,25 @@ WORKLOADS: Dict[str, Workload] = {
                                   beta_d=0.05 / math.sqrt(1.0 + 0.05 ** 2), nb_over_n0=0.0, eps=0.0, seed=7,
                                   steps=45000, q=(1.0, -1.0), m=(100.0, 1.0), dt_wpe=0.758),
 }
+
+
+# The fiducial nonlinear run of Table 2 (Sec. 3.2): ions and electrons,
+# m_i/m_e = 100, T = 10 m_e c^2 for both species and both populations, proper
+# drift u_d/c = 0.4, sigma_ci = 100 (n0/n_b = 269.26 from pressure balance;
+# Ampere's law then gives a = 0.50 d_e,C), L_x = L_y = 50 d_i,C = 500 d_e,C
+# (a box of 2 L_x x 2 L_y = 625 x 625 cells at dx = 1.6 d_e,C), dt omega_pe
+# = 0.96, 256 sheet and 16 background particles per cell per species, no
+# seed, to t c / L_y = 7.77 (4,047 steps).  Species: ion sheet, electron
+# sheet, ion background, electron background.  The sheet particles fill the
+# rows where the sheet density reaches 1e-6 n0 (6 rows per sheet at a = dx /
+# 3.2; the density left out is below 3e-4 of the background): 16,340,000
+# particles (sheet_cut = 0 puts 256 in every cell: 212,500,000).
+_B_D_F3 = 0.4 / math.sqrt(1.0 + 0.4 ** 2)
+_NB_F3 = 1.0 / _params.n0_over_nb_for_sigma(100.0, 10.0, 100.0, 0.4)
+WORKLOADS["reconnection2d_625x625"] = Workload(
+    "reconnection2d_625x625", 2, 625, 625, 1, 0.0, 16, theta_s=10.0, beta_d=_B_D_F3, nb_over_n0=_NB_F3,
+    theta_b=10.0, eps=0.0, seed=8, steps=4047, q=(1.0, -1.0, 1.0, -1.0), m=(100.0, 1.0, 100.0, 1.0),
+    ppc_sheet=256, sheet_cut=1e-6, dx_over_de=1.6, dt_wpb=0.96)
 
 
 def workload(name: str, **overrides) -> Workload:
@@ -179,8 +264,82 @@ def _sech2(x: np.ndarray) -> np.ndarray:
     return 4.0 * e / (1.0 + e) ** 2
 
 
+def _sheet_momenta(wl: Workload, rng: np.random.Generator, species: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Drifting MJ momenta of sheet particles: temperature T / (m_s c^2),
+    boosted along z by the drift speed with the sign of the nearer sheet and
+    of the charge."""
+    n = species.size
+    us = np.empty((3, n))
+    ms = np.asarray(wl.m)[species]
+    for mv in sorted(set(wl.m)):
+        sel = ms == mv
+        if sel.any():
+            us[:, sel] = sample_mj(rng, wl.theta_s / mv, int(sel.sum()))
+    qv = np.asarray(wl.q)[species]
+    beta = wl.beta_d * np.sign(y) * np.sign(qv)
+    beta[beta == 0] = wl.beta_d
+    return boost_z(rng, us, beta)
+
+
+def _background_momenta(wl: Workload, rng: np.random.Generator, species: np.ndarray) -> np.ndarray:
+    """MJ momenta at rest, temperature T_b / (m_s c^2)."""
+    ub = np.empty((3, species.size))
+    ms = np.asarray(wl.m)[species]
+    for mv in sorted(set(wl.m)):
+        sel = ms == mv
+        if sel.any():
+            ub[:, sel] = sample_mj(rng, wl.theta_b / mv, int(sel.sum()))
+    return ub
+
+
+def _generate_split(wl: Workload, rng: np.random.Generator, c0: int, c1: int) -> Dict[str, np.ndarray]:
+    """Cells [c0, c1) of a workload with separate populations: per cell, the
+    sheet species (ppc_sheet each) and then the background species (ppc
+    each).  Within a population every species shares the positions (pair
+    loading: each population is exactly neutral)."""
+    hp = wl.harris
+    S = wl.nspecies
+    h = S // 2
+    dx = wl.dx
+    Y = wl.ny * dx
+    Ly = 0.5 * Y
+    V = dx * dx * (dx if wl.dim == 3 else 1.0)
+    cnt = wl.counts()[c0:c1]                      # (cells, species)
+    per = cnt.sum(1)
+    cbeg = np.concatenate([[0], np.cumsum(per)])  # first particle of each cell
+    n = int(cbeg[-1])
+    cell = np.repeat(np.arange(c0, c1, dtype=np.int32), per)
+    species = np.repeat(np.tile(np.arange(S, dtype=np.uint8), c1 - c0), cnt.reshape(-1))
+    off = np.empty((wl.dim, n))
+    w = np.empty(n)
+    u = np.empty((3, n))
+    # a population's positions are drawn once per cell and shared by its
+    # species; the species of a cell sit one after the other
+    start = np.zeros(c1 - c0, dtype=np.int64)     # first slot of the current species in each cell
+    for pop in (0, 1):
+        npp = cnt[:, pop * h]
+        tot = int(npp.sum())
+        pos = rng.random((wl.dim, tot))
+        k = np.arange(tot) - np.repeat(np.concatenate([[0], np.cumsum(npp)[:-1]]), npp)  # index in the cell
+        cidx = np.repeat(np.arange(c1 - c0), npp)
+        for _ in range(h):
+            off[:, cbeg[cidx] + start[cidx] + k] = pos
+            start += npp
+    j = (cell.astype(np.int64) // wl.nx) % wl.ny
+    y = (j + off[1]) * dx - 0.5 * Y
+    sheet = species < h
+    dens = N0 * (_sech2((y[sheet] - 0.5 * Ly) / hp.a) + _sech2((y[sheet] + 0.5 * Ly) / hp.a))
+    w[sheet] = dens * V / wl.ppc_sheet
+    w[~sheet] = wl.nb_over_n0 * N0 * V / wl.ppc
+    u[:, sheet] = _sheet_momenta(wl, rng, species[sheet], y[sheet])
+    u[:, ~sheet] = _background_momenta(wl, rng, species[~sheet])
+    return {"cell": cell, "species": species, "off": off, "u": u, "w": w}
+
+
 def _generate(wl: Workload, rng: np.random.Generator, c0: int, c1: int) -> Dict[str, np.ndarray]:
     """Particles of cells [c0, c1) drawn from rng (bin order, no bin_start)."""
+    if wl.split:
+        return _generate_split(wl, rng, c0, c1)
     hp = wl.harris
     S, ppc = wl.nspecies, wl.ppc
     nc = c1 - c0
@@ -252,12 +411,17 @@ def make_layers(wl: Workload, k0: int, k1: int, seed: Optional[int] = None) -> D
     nxy = wl.nx * wl.ny
     parts = [_generate(wl, layer_rng(seed, k), k * nxy, (k + 1) * nxy) for k in range(k0, k1)]
     out = {key: np.concatenate([q[key] for q in parts], axis=-1) for key in ("cell", "species", "off", "u", "w")}
-    out["bin_start"] = _uniform_bins((k1 - k0) * nxy * wl.nspecies, wl.ppc)
+    out["bin_start"] = _uniform_bins((k1 - k0) * nxy * wl.nspecies, wl.ppc_of_species)
     return out
 
 
-def _uniform_bins(nbins: int, ppc: int) -> np.ndarray:
-    counts = np.full(nbins, ppc, dtype=np.int64)
+def _uniform_bins(nbins: int, ppc) -> np.ndarray:
+    """bin_start of nbins bins holding ppc particles each (ppc an int, or the
+    per-species counts repeated cell after cell)."""
+    if np.ndim(ppc) == 0:
+        counts = np.full(nbins, ppc, dtype=np.int64)
+    else:
+        counts = np.tile(np.asarray(ppc, dtype=np.int64), nbins // len(ppc))
     bin_start = np.zeros(nbins + 1, dtype=np.int64)
     np.cumsum(counts, out=bin_start[1:])
     return bin_start.astype(np.int32)
@@ -273,14 +437,44 @@ def make_particles(wl: Workload, seed: Optional[int] = None, workers: int = 1) -
     interpreter lock in the array work).
     """
     seed = wl.seed if seed is None else seed
+    if wl.dim == 2 and wl.split:
+        # separate populations: blocks of rows, each from its own stream,
+        # generated independently (in `workers` threads) into one array
+        rows = max(1, min(wl.ny, (1 << 21) // max(1, wl.nx * wl.ppc_total)))
+        nblk = (wl.ny + rows - 1) // rows
+        cnt = wl.counts()
+        n = int(cnt.sum())
+        out = {"cell": np.empty(n, np.int32), "species": np.empty(n, np.uint8), "off": np.empty((2, n)),
+               "u": np.empty((3, n)), "w": np.empty(n)}
+        row_start = np.concatenate([[0], np.cumsum(cnt.reshape(wl.ny, -1).sum(1))])
+
+        def put_rows(b):
+            j0, j1 = b * rows, min(wl.ny, (b + 1) * rows)
+            q = _generate_split(wl, layer_rng(seed, b), j0 * wl.nx, j1 * wl.nx)
+            sl = slice(int(row_start[j0]), int(row_start[j1]))
+            for key in ("cell", "species", "w"):
+                out[key][sl] = q[key]
+            out["off"][:, sl] = q["off"]
+            out["u"][:, sl] = q["u"]
+
+        if workers > 1:
+            from concurrent.futures import ThreadPoolExecutor
+
+            with ThreadPoolExecutor(workers) as ex:
+                list(ex.map(put_rows, range(nblk)))
+        else:
+            for b in range(nblk):
+                put_rows(b)
+        out["bin_start"] = np.concatenate([[0], np.cumsum(cnt.reshape(-1))]).astype(np.int32)
+        return out
     if wl.dim == 2:
         out = _generate(wl, np.random.Generator(np.random.PCG64(seed)), 0, wl.ncells)
-        out["bin_start"] = _uniform_bins(wl.ncells * wl.nspecies, wl.ppc)
+        out["bin_start"] = _uniform_bins(wl.ncells * wl.nspecies, wl.ppc_of_species)
         return out
     n = wl.nparticles
     out = {"cell": np.empty(n, np.int32), "species": np.empty(n, np.uint8), "off": np.empty((3, n)),
            "u": np.empty((3, n)), "w": np.empty(n)}
-    per = wl.nx * wl.ny * wl.nspecies * wl.ppc
+    per = wl.nx * wl.ny * wl.ppc_total
 
     def put(k):
         q = make_layers(wl, k, k + 1, seed)
@@ -298,7 +492,7 @@ def make_particles(wl: Workload, seed: Optional[int] = None, workers: int = 1) -
     else:
         for k in range(wl.nz):
             put(k)
-    out["bin_start"] = _uniform_bins(wl.ncells * wl.nspecies, wl.ppc)
+    out["bin_start"] = _uniform_bins(wl.ncells * wl.nspecies, wl.ppc_of_species)
     return out
 
 

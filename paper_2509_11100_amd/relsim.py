@@ -409,6 +409,50 @@ def energy_noalloc(params, parts: Particles, E: torch.Tensor, B: torch.Tensor,
     return out
 
 
+class _AndersonMix:
+    """Anderson mixing of the fixed point g = F(g) (type II, depth m); the
+    history is kept on the device in the particle arithmetic type."""
+
+    def __init__(self, m: int):
+        self.m = m
+        self.dG, self.dF = [], []
+        self.g_prev = self.f_prev = None
+
+    def __call__(self, g: torch.Tensor, Fg: torch.Tensor) -> None:
+        """g: the pass's input, Fg: its output; Fg is overwritten with the
+        next input."""
+        f = Fg - g
+        if self.g_prev is not None:
+            self.dG.append(g - self.g_prev)
+            self.dF.append(f - self.f_prev)
+            if len(self.dG) > self.m:
+                self.dG.pop(0)
+                self.dF.pop(0)
+        self.g_prev, self.f_prev = g.clone(), f
+        if not self.dF:
+            return  # first pass: plain fixed-point update (Fg as it is)
+        wt = 1.0 / g.double()
+        F = torch.stack([d.double() * wt for d in self.dF], 1)
+        r = f.double() * wt
+        A = F.T @ F
+        b = F.T @ r
+        # a small ridge keeps the normal equations solvable when two
+        # differences are nearly parallel
+        A = A + 1e-12 * torch.trace(A) * torch.eye(A.shape[0], dtype=A.dtype, device=A.device)
+        try:
+            theta = torch.linalg.solve(A, b)
+        except RuntimeError:
+            return
+        if not torch.isfinite(theta).all():
+            return
+        nxt = g.double() + f.double()
+        for k in range(theta.numel()):
+            nxt -= theta[k] * (self.dG[k].double() + self.dF[k].double())
+        if not torch.isfinite(nxt).all():
+            return
+        Fg.copy_(torch.clamp(nxt, min=1.0).to(Fg.dtype))
+
+
 class PicardNotConverged(RuntimeError):
     """The energy-conserving step's fixed point did not reach its tolerance."""
 
@@ -441,11 +485,22 @@ class Step:
     is not finite, the step raises PicardNotConverged before pushing (the
     state and fields stay at step n), since energy would then not be
     conserved to the stated tolerance; with allow_unconverged=True a finite
-    change only clears picard_converged and the step goes on."""
+    change only clears picard_converged and the step goes on.
+
+    anderson=m > 0 accelerates the fixed point gbar = F(gbar) by Anderson
+    mixing of the last m passes (Walker and Ni 2011, type II): with the
+    residuals f_k = F(g_k) - g_k, the next input is g_k + f_k - (dG + dF)
+    theta, theta minimising |(f_k - dF theta) / g_k| over the differences dF,
+    dG of the last m residuals and inputs (least squares on their FP64 dot
+    products, weighted by 1 / g_k so that every particle counts relatively);
+    gbar is kept >= 1, and a non-finite mix falls back to the plain pass.
+    The stopping test (the largest relative change of one pass) and the
+    final push (with the last pass's input) are those of the plain
+    iteration, so the fixed point reached is the same."""
 
     def __init__(self, ctx: Context, parts: Particles, E: torch.Tensor, B: torch.Tensor,
                  energy_conserving: bool = False, picard_tol: Optional[float] = None, picard_maxit: int = 30,
-                 allow_unconverged: bool = False):
+                 allow_unconverged: bool = False, anderson: int = 0):
         _grid_ok(ctx, E, B)
         self.ctx, self.parts = ctx, parts
         self.E, self.B = E.clone(), B.clone()
@@ -458,6 +513,7 @@ class Step:
             picard_tol = 1e-12 if ctx.precision == "fp64" else 1e-6
         self.picard_tol, self.picard_maxit = picard_tol, picard_maxit
         self.allow_unconverged = allow_unconverged
+        self.anderson = int(anderson)
         self.picard_iters, self.picard_change, self.picard_converged = 0, 0.0, True
         self._pushed = False
         if energy_conserving:
@@ -475,12 +531,16 @@ class Step:
             if self.energy_conserving:
                 gamma_mean(self.ctx, self.parts, self.E, self.B, None, self._gb[0])
                 gbar, nxt = self._gb[0], 1
+                mix = _AndersonMix(self.anderson) if self.anderson > 0 else None
                 for it in range(1, self.picard_maxit + 1):
                     self._solve(gbar)
                     self.picard_change = gamma_mean(self.ctx, self.parts, self.E_theta, self.B, gbar, self._gb[nxt])
                     self.picard_iters = it
                     if self.picard_change <= self.picard_tol or it == self.picard_maxit:
                         break
+                    if mix is not None:
+                        # the mixed input overwrites F(g_k) in place
+                        mix(gbar[: self.parts.n], self._gb[nxt][: self.parts.n])
                     gbar, nxt = self._gb[nxt], 1 - nxt
                 self.picard_converged = self.picard_change <= self.picard_tol
                 if not self.picard_converged and (not self.allow_unconverged or not np.isfinite(self.picard_change)):
