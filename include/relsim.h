@@ -83,14 +83,16 @@ typedef struct {
 
 /* Particle state, sorted by bin = cell * nspecies + s, so that the
  * particles of (cell, species) occupy [bin_start[bin], bin_start[bin+1]).
- * Element type T is double for RELSIM_FP64 and float for RELSIM_MIXED.  The
- * record of particle p is split over three packed arrays (structure of small
- * arrays): xy[p] = (off_x, off_y) (2 T, aligned to 2 T), uw[p] = (u_x, u_y,
- * u_z, w) (4 T, aligned to 4 T) and, in 3D, z[p] = off_z.  off in [0,1) is the
- * position inside the cell in units of the cell size; u = gamma v; w = number
- * of physical particles represented.  Each array exists twice ("front" and
- * "back"); the re-sort writes into the back set and then swaps the two sets
- * (and the two bin_start arrays) inside this struct. */
+ * Element type T is double for RELSIM_FP64 and float for RELSIM_MIXED.  In
+ * 2D the record of particle p is split over two packed arrays: xy[p] =
+ * (off_x, off_y) (2 T, aligned to 2 T) and uw[p] = (u_x, u_y, u_z, w) (4 T,
+ * aligned to 4 T).  In 3D it is one block of 8 T at xy, (off_x, off_y, off_z,
+ * 0, u_x, u_y, u_z, w), aligned to 8 T (one 32-byte memory sector in FP32);
+ * uw and z are not used and may be NULL.  off in [0,1) is the position inside
+ * the cell in units of the cell size; u = gamma v; w = number of physical
+ * particles represented.  Each array exists twice ("front" and "back"); the
+ * re-sort writes into the back set and then swaps the two sets (and the two
+ * bin_start arrays) inside this struct. */
 typedef struct {
   int64_t n;                   /* particles in use                                */
   int32_t *bin_start;          /* [ncells*nspecies + 1]                           */
@@ -100,9 +102,9 @@ typedef struct {
                                   stale (the bins already say where each
                                   particle is, and the re-sort saves the
                                   4-byte write per particle)                    */
-  void *xy;                    /* [capacity][2] T                                 */
-  void *uw;                    /* [capacity][4] T                                 */
-  void *z;                     /* [capacity] T, 3D only (NULL in 2D)              */
+  void *xy;                    /* [capacity][2] T (2D), [capacity][8] T (3D)      */
+  void *uw;                    /* [capacity][4] T (2D; unused in 3D)              */
+  void *z;                     /* unused (NULL)                                   */
   int32_t *bin_start_back;
   int32_t *cell_back;
   void *xy_back;

@@ -41,10 +41,8 @@ class Stepper:
             raise ValueError("state larger than the context's max_particles")
         f = p.sets[p.front]
         p.n = n
-        for d in range(2):
+        for d in range(self.ctx.dim):
             f["xy"][:n, d].copy_(off[d])
-        if self.ctx.dim == 3:
-            f["z"][:n].copy_(off[2])
         for k in range(3):
             f["uw"][:n, k].copy_(u[k])
         f["uw"][:n, 3].copy_(w)

@@ -53,13 +53,25 @@ __device__ __forceinline__ PState load_particle(const KParams &kp, const int32_t
   st.ci = c % kp.nx;
   st.cj = (c / kp.nx) % kp.ny;
   st.ck = c / (kp.nx * kp.ny);
-  st.f[0] = xy[2 * (size_t)p];
-  st.f[1] = xy[2 * (size_t)p + 1];
-  st.f[2] = DIM == 3 ? zz[p] : 0.0;
-  st.u[0] = uw[4 * (size_t)p];
-  st.u[1] = uw[4 * (size_t)p + 1];
-  st.u[2] = uw[4 * (size_t)p + 2];
-  st.w = uw[4 * (size_t)p + 3];
+  if (DIM == 3) {
+    // one 8-value record per particle at xy: (off_x, off_y, off_z, 0, u_x, u_y, u_z, w)
+    const double *r = xy + 8 * (size_t)p;
+    st.f[0] = r[0];
+    st.f[1] = r[1];
+    st.f[2] = r[2];
+    st.u[0] = r[4];
+    st.u[1] = r[5];
+    st.u[2] = r[6];
+    st.w = r[7];
+  } else {
+    st.f[0] = xy[2 * (size_t)p];
+    st.f[1] = xy[2 * (size_t)p + 1];
+    st.f[2] = 0.0;
+    st.u[0] = uw[4 * (size_t)p];
+    st.u[1] = uw[4 * (size_t)p + 1];
+    st.u[2] = uw[4 * (size_t)p + 2];
+    st.w = uw[4 * (size_t)p + 3];
+  }
   return st;
 }
 

@@ -335,19 +335,21 @@ void swap_sets(relsim_particles *pt) {
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+// 2D: xy (2 T per particle) and uw (4 T); 3D: one 8-T record per particle
+// in xy (uw and z unused).  Records must be aligned to their size.
+bool records_ok(int dim, size_t es, const void *xy, const void *uw) {
+  if (dim == 3) return xy && aligned(xy, 8 * es);
+  return xy && uw && aligned(xy, 2 * es) && aligned(uw, 4 * es);
+}
+
 int check_particles(relsim_ctx *c, const relsim_particles *pt, bool need_back) {
   if (!pt) return fail(c, RELSIM_EINVAL, "null particles");
   if (pt->n < 0 || pt->n > c->p.max_particles) return fail(c, RELSIM_EINVAL, "particle count outside [0, max_particles]");
-  if (!pt->bin_start || !pt->xy || !pt->uw || (c->p.dim == 3 && !pt->z))
-    return fail(c, RELSIM_EINVAL, "null particle array");
   const size_t es = c->p.precision == RELSIM_MIXED ? 4 : 8;
-  if (!aligned(pt->xy, 2 * es) || !aligned(pt->uw, 4 * es))
-    return fail(c, RELSIM_EINVAL, "particle records not aligned to their size");
-  if (need_back && (!pt->bin_start_back || !pt->cell_back || !pt->xy_back || !pt->uw_back ||
-                    (c->p.dim == 3 && !pt->z_back)))
-    return fail(c, RELSIM_EINVAL, "null back-buffer particle array");
-  if (need_back && (!aligned(pt->xy_back, 2 * es) || !aligned(pt->uw_back, 4 * es)))
-    return fail(c, RELSIM_EINVAL, "particle records not aligned to their size");
+  if (!pt->bin_start || !records_ok(c->p.dim, es, pt->xy, pt->uw))
+    return fail(c, RELSIM_EINVAL, "null particle array, or records not aligned to their size");
+  if (need_back && (!pt->bin_start_back || !pt->cell_back || !records_ok(c->p.dim, es, pt->xy_back, pt->uw_back)))
+    return fail(c, RELSIM_EINVAL, "null back-buffer particle array, or records not aligned to their size");
   return RELSIM_OK;
 }
 
@@ -1044,7 +1046,7 @@ extern "C" int relsim_energy_noalloc(const relsim_params *params, void *hip_stre
   relsim_params p = *params;
   if (p.dim == 2) p.nz = 1;
   if (pt->n < 0 || pt->n > p.max_particles) return RELSIM_EINVAL;
-  if (!pt->bin_start || !pt->uw || !aligned(pt->uw, 4 * (p.precision == RELSIM_MIXED ? 4 : 8)) ||
+  if (!pt->bin_start || !records_ok(p.dim, p.precision == RELSIM_MIXED ? 4 : 8, pt->xy, pt->uw) ||
       !aligned(out, sizeof(double)))
     return RELSIM_EINVAL;
   const KParams kp = make_kparams(&p);

@@ -278,19 +278,72 @@ constexpr int round_align() {
   return (64 / (int)sizeof(T)) < G ? 64 / (int)sizeof(T) : G;
 }
 
+// 2D: (off_x, off_y) in xy[p] and (u_x, u_y, u_z, w) in uw[p].  3D: one
+// 8-value record per particle at xy (two V4: (off_x, off_y, off_z, 0) and
+// (u_x, u_y, u_z, w)), so that a particle is one aligned 32-byte block in
+// FP32 (a whole memory sector) and the re-sort writes whole sectors; uw and
+// zz are unused in 3D.
+template <typename T>
+__device__ __forceinline__ const V4<T> *rec3(const V2<T> *xy) {
+  return reinterpret_cast<const V4<T> *>(xy);
+}
+template <typename T>
+__device__ __forceinline__ V4<T> *rec3(V2<T> *xy) {
+  return reinterpret_cast<V4<T> *>(xy);
+}
+
 template <typename T, int DIM>
 __device__ __forceinline__ void load_rec(int p, int pend, const V2<T> *__restrict__ xy, const V4<T> *__restrict__ uw,
                                          const T *__restrict__ zz, PRec<T> &r) {
   const int q = load_index(p, pend);
-  const V2<T> a = xy[q];
-  const V4<T> b = uw[q];
-  r.fx = a.x;
-  r.fy = a.y;
-  if constexpr (DIM == 3) r.fz = zz[q];
+  V4<T> b;
+  if constexpr (DIM == 3) {
+    const V4<T> *R = rec3<T>(xy) + 2 * (size_t)q;
+    const V4<T> a = R[0];
+    b = R[1];
+    r.fx = a.x;
+    r.fy = a.y;
+    r.fz = a.z;
+  } else {
+    const V2<T> a = xy[q];
+    b = uw[q];
+    r.fx = a.x;
+    r.fy = a.y;
+  }
   r.ux = b.x;
   r.uy = b.y;
   r.uz = b.z;
   r.w = b.w;
+}
+
+// Store one particle's state at slot q of the record arrays (3D: one
+// 8-value record), or into the lane's sink slot when `to_sink`.
+template <typename T, int DIM>
+__device__ __forceinline__ void store_rec(bool to_sink, size_t q, V2<T> *__restrict__ xy, V4<T> *__restrict__ uw,
+                                          T *__restrict__ zz, void *sink, T fx, T fy, T fz, T ux, T uy, T uz, T w) {
+  V4<T> b;
+  b.x = ux;
+  b.y = uy;
+  b.z = uz;
+  b.w = w;
+  if constexpr (DIM == 3) {
+    V4<T> a;
+    a.x = fx;
+    a.y = fy;
+    a.z = fz;
+    a.w = T(0);
+    // both halves of a sink store go to the lane's one slot
+    V4<T> *R = to_sink ? reinterpret_cast<V4<T> *>(sink) : rec3<T>(xy) + 2 * q;
+    const int h = to_sink ? 0 : 1;
+    R[0] = a;
+    R[h] = b;
+  } else {
+    V2<T> a;
+    a.x = fx;
+    a.y = fy;
+    *(to_sink ? reinterpret_cast<V2<T> *>(sink) : xy + q) = a;
+    *(to_sink ? reinterpret_cast<V4<T> *>(sink) : uw + q) = b;
+  }
 }
 
 // The energy-conserving variant gives gbar per particle (in the particle
@@ -957,17 +1010,7 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, int C, const int32_t *_
       bool ok = fx >= T(-1) && fx < T(2) && fy >= T(-1) && fy < T(2);
       if constexpr (DIM == 3) ok = ok && fz >= T(-1) && fz < T(2);
       bad |= (pv && !ok) ? 1 : 0;
-      V2<T> xo;
-      xo.x = fx;
-      xo.y = fy;
-      V4<T> uo;
-      uo.x = nx;
-      uo.y = ny;
-      uo.z = nz;
-      uo.w = cur.w;
-      *(pv ? xy + p : sink_slot<V2<T>>(sink, lane)) = xo;
-      *(pv ? uw + p : sink_slot<V4<T>>(sink, lane)) = uo;
-      if constexpr (DIM == 3) *(pv ? zz + p : sinkT) = fz;
+      store_rec<T, DIM>(!pv, (size_t)p, xy, uw, zz, sink_slot<V4<T>>(sink, lane), fx, fy, fz, nx, ny, nz, cur.w);
     }
     cur = nxt;
     p = pn;
@@ -1103,17 +1146,8 @@ __device__ __forceinline__ void scatter_round(const KParams &kp, const PC<T> &pc
   // counters (flagged); lanes past the end store into the sink
   const bool ok = pv && pos >= 0 && pos < ntot;
   bad |= (pv && !ok) ? 2 : 0;
-  V2<T> xv;
-  xv.x = fx;
-  xv.y = fy;
-  V4<T> uv;
-  uv.x = nx;
-  uv.y = ny;
-  uv.z = nz;
-  uv.w = cur.w;
-  *(ok ? xo + pos : sink_slot<V2<T>>(sink, lane)) = xv;
-  *(ok ? uo + pos : sink_slot<V4<T>>(sink, lane)) = uv;
-  if constexpr (DIM == 3) *(ok ? zo + pos : sink_slot<T>(sink, lane)) = fz;
+  store_rec<T, DIM>(!ok, (size_t)(ok ? pos : 0), xo, uo, zo, sink_slot<V4<T>>(sink, lane), fx, fy, fz, nx, ny, nz,
+                    cur.w);
   if constexpr (PERM) *(ok ? perm + p : sink_slot<int32_t>(sink, lane)) = pos;
   __builtin_amdgcn_wave_barrier();
   load_rec<T, DIM>(p + 3 * 64, p1, xy, uw, zz, cur);
@@ -1253,7 +1287,8 @@ __global__ __launch_bounds__(64) void k_kinetic(KParams kp, const int32_t *__res
       for (int s2 = 1; s2 < 8; ++s2)
         if (p >= cs.bound[s2]) s = s2;
     }
-    const V4<T> r = uw[p];
+    // 3D: uw points at the records, whose second half is (u, w)
+    const V4<T> r = DIM == 3 ? uw[2 * (size_t)p + 1] : uw[p];
     const double ux = r.x, uy = r.y, uz = r.z;
     const double uu = ux * ux + uy * uy + uz * uz;
     const double wm = (double)r.w * kp.m[s];
@@ -1440,8 +1475,9 @@ void scatter_impl(const KParams &kp, int C, const PartPtrs &src, const void *Est
 template <typename T, int DIM, int G>
 void kinetic_impl(const KParams &kp, const PartPtrs &pp, double *partials, hipStream_t st) {
   const int nblk = (kp.ncells + (64 / G) - 1) / (64 / G);
-  hipLaunchKernelGGL((k_kinetic<T, DIM, G>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start, cp<V4<T>>(pp.uw),
-                     partials);
+  // 3D: the momenta are the second half of each record in xy
+  hipLaunchKernelGGL((k_kinetic<T, DIM, G>), dim3(nblk), dim3(64), 0, st, kp, pp.bin_start,
+                     cp<V4<T>>(DIM == 3 ? pp.xy : pp.uw), partials);
 }
 
 // Dispatch over (precision, dim, group) to the template instances.

@@ -57,7 +57,8 @@ struct alignas(2 * sizeof(T)) V2 {
 
 // ---- particle kernels (particles.hip) ----
 // Particle arrays of one buffer set (element type T = float or double):
-// xy [n] of (off_x, off_y), uw [n] of (u_x, u_y, u_z, w), z [n] of off_z (3D).
+// 2D: xy [n] of (off_x, off_y), uw [n] of (u_x, u_y, u_z, w); 3D: xy [n] of
+// 8-value records (off_x, off_y, off_z, 0, u_x, u_y, u_z, w), uw and z unused.
 struct PartPtrs {
   const int32_t *bin_start;
   void *xy;
@@ -118,9 +119,9 @@ void launch_gsort(const KParams &kp, int prec, int64_t n, const int32_t *cell, c
 struct AdjInPtrs {
   const int32_t *bin_start = nullptr;
   const int32_t *cell = nullptr;
-  const double *xy = nullptr;  // [n] (off_x, off_y)
-  const double *uw = nullptr;  // [n] (u_x, u_y, u_z, w)
-  const double *z = nullptr;   // [n] off_z (3D)
+  const double *xy = nullptr;  // 2D: [n] (off_x, off_y); 3D: [n] 8-value records
+  const double *uw = nullptr;  // 2D: [n] (u_x, u_y, u_z, w); unused in 3D
+  const double *z = nullptr;   // unused
 };
 void launch_push_adjoint(const KParams &kp, const AdjInPtrs &in, int n, const double *Eth, const double *B,
                          const int32_t *new_index, const double *lx_in, const double *lu_in, double *lx_out,

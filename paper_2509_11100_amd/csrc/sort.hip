@@ -93,9 +93,16 @@ __global__ __launch_bounds__(256) void k_gather(KParams kp, int n, const int32_t
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= n) return;
   const int i = idx[j];
-  xo[j] = xy[i];
-  uo[j] = uw[i];
-  if (kp.dim == 3) zo[j] = zz[i];
+  if (kp.dim == 3) {
+    // one 8-value record per particle, at xy (two V4)
+    const V4<T> *R = reinterpret_cast<const V4<T> *>(xy) + 2 * (size_t)i;
+    V4<T> *O = reinterpret_cast<V4<T> *>(xo) + 2 * (size_t)j;
+    O[0] = R[0];
+    O[1] = R[1];
+  } else {
+    xo[j] = xy[i];
+    uo[j] = uw[i];
+  }
   cell_out[j] = keys[j] / kp.nspecies;
 }
 

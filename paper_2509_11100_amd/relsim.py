@@ -111,9 +111,11 @@ class Context:
 
 
 class Particles:
-    """Double-buffered particle state on the device: per set, xy [cap][2]
-    (offsets x, y), uw [cap][4] (momentum, weight), z [cap] (offset z, 3D),
-    cell ids and bin starts.  `off`, `u` and `w` are strided views."""
+    """Double-buffered particle state on the device: per set, in 2D xy
+    [cap][2] (offsets x, y) and uw [cap][4] (momentum, weight); in 3D one
+    record tensor xy [cap][8] (offsets x, y, z, 0, momentum, weight), with
+    uw and z kept as strided views of it; cell ids and bin starts.  `off`,
+    `u` and `w` are strided views."""
 
     def __init__(self, ctx: Context, capacity: Optional[int] = None):
         self.ctx = ctx
@@ -125,13 +127,15 @@ class Particles:
         self.capacity = cap
         self.sets = []
         for _ in range(2):
-            self.sets.append({
-                "bin_start": torch.zeros(nb + 1, dtype=torch.int32, device=dev),
-                "cell": torch.zeros(max(cap, 1), dtype=torch.int32, device=dev),
-                "xy": torch.zeros((max(cap, 1), 2), dtype=dt, device=dev),
-                "uw": torch.zeros((max(cap, 1), 4), dtype=dt, device=dev),
-                "z": torch.zeros(max(cap, 1), dtype=dt, device=dev) if ctx.dim == 3 else None,
-            })
+            st = {"bin_start": torch.zeros(nb + 1, dtype=torch.int32, device=dev),
+                  "cell": torch.zeros(max(cap, 1), dtype=torch.int32, device=dev)}
+            if ctx.dim == 3:
+                rec = torch.zeros((max(cap, 1), 8), dtype=dt, device=dev)
+                st.update(xy=rec, uw=rec[:, 4:8], z=rec[:, 2])
+            else:
+                st.update(xy=torch.zeros((max(cap, 1), 2), dtype=dt, device=dev),
+                          uw=torch.zeros((max(cap, 1), 4), dtype=dt, device=dev), z=None)
+            self.sets.append(st)
         self.species_in = torch.zeros(max(cap, 1), dtype=torch.uint8, device=dev)
         self.s = _lib.relsim_particles()
         self.front = 0
@@ -144,10 +148,11 @@ class Particles:
         s.n = self.n
         s.bin_start, s.cell = f["bin_start"].data_ptr(), f["cell"].data_ptr()
         s.bin_start_back, s.cell_back = b["bin_start"].data_ptr(), b["cell"].data_ptr()
-        s.xy, s.uw = f["xy"].data_ptr(), f["uw"].data_ptr()
-        s.xy_back, s.uw_back = b["xy"].data_ptr(), b["uw"].data_ptr()
-        s.z = f["z"].data_ptr() if f["z"] is not None else None
-        s.z_back = b["z"].data_ptr() if b["z"] is not None else None
+        s.xy, s.xy_back = f["xy"].data_ptr(), b["xy"].data_ptr()
+        two = self.ctx.dim == 2  # in 3D the records are all in xy
+        s.uw = f["uw"].data_ptr() if two else None
+        s.uw_back = b["uw"].data_ptr() if two else None
+        s.z = s.z_back = None
         s.species = self.species_in.data_ptr()
 
     def _sync_front(self):
@@ -168,10 +173,8 @@ class Particles:
         self.species_in[:n].copy_(torch.as_tensor(np.asarray(species, dtype=np.uint8)).to(dev))
         offs = np.asarray(off)
         uu = np.asarray(u)
-        for d in range(2):
+        for d in range(self.ctx.dim):
             f["xy"][:n, d].copy_(torch.as_tensor(offs[d]).to(dev, dt))
-        if f["z"] is not None:
-            f["z"][:n].copy_(torch.as_tensor(offs[2]).to(dev, dt))
         for k in range(3):
             f["uw"][:n, k].copy_(torch.as_tensor(uu[k]).to(dev, dt))
         f["uw"][:n, 3].copy_(torch.as_tensor(np.asarray(w)).to(dev, dt))
@@ -198,10 +201,7 @@ class Particles:
     @property
     def off(self):
         f = self.sets[self.front]
-        views = [f["xy"][: self.n, 0], f["xy"][: self.n, 1]]
-        if f["z"] is not None:
-            views.append(f["z"][: self.n])
-        return views
+        return [f["xy"][: self.n, d] for d in range(self.ctx.dim)]
 
     @property
     def u(self):
@@ -410,46 +410,57 @@ def energy_noalloc(params, parts: Particles, E: torch.Tensor, B: torch.Tensor,
 
 
 class _AndersonMix:
-    """Anderson mixing of the fixed point g = F(g) (type II, depth m); the
-    history is kept on the device in the particle arithmetic type."""
+    """Anderson mixing of the fixed point g = F(g) (type II, depth m).  The
+    last m differences of inputs and residuals are kept on the device in
+    FP64 (preallocated rings); each pass forms the weighted m x m normal
+    equations with two small products on the device, solves them on the host
+    (one small copy), and writes the mixed input with device arithmetic."""
 
     def __init__(self, m: int):
         self.m = m
-        self.dG, self.dF = [], []
+        self.k = 0            # history entries in use
+        self.head = 0         # ring position of the next entry
+        self.dG = self.dF = None
         self.g_prev = self.f_prev = None
 
     def __call__(self, g: torch.Tensor, Fg: torch.Tensor) -> None:
         """g: the pass's input, Fg: its output; Fg is overwritten with the
         next input."""
-        f = Fg - g
+        # a copy: g's buffer receives the output of the pass after next
+        gd = g.to(torch.float64, copy=True)
+        f = Fg.double() - gd
+        if self.dG is None:
+            n = g.numel()
+            self.dG = torch.empty((self.m, n), dtype=torch.float64, device=g.device)
+            self.dF = torch.empty((self.m, n), dtype=torch.float64, device=g.device)
         if self.g_prev is not None:
-            self.dG.append(g - self.g_prev)
-            self.dF.append(f - self.f_prev)
-            if len(self.dG) > self.m:
-                self.dG.pop(0)
-                self.dF.pop(0)
-        self.g_prev, self.f_prev = g.clone(), f
-        if not self.dF:
-            return  # first pass: plain fixed-point update (Fg as it is)
-        wt = 1.0 / g.double()
-        F = torch.stack([d.double() * wt for d in self.dF], 1)
-        r = f.double() * wt
-        A = F.T @ F
-        b = F.T @ r
+            torch.sub(gd, self.g_prev, out=self.dG[self.head])
+            torch.sub(f, self.f_prev, out=self.dF[self.head])
+            self.head = (self.head + 1) % self.m
+            self.k = min(self.k + 1, self.m)
+        self.g_prev, self.f_prev = gd, f
+        if self.k == 0:
+            return  # first pass: the plain fixed-point update (Fg as it is)
+        dF, dG = self.dF[: self.k], self.dG[: self.k]
+        w2 = 1.0 / (gd * gd)  # least squares on the residual relative to g
+        wF = dF * w2
+        small = torch.cat([(wF @ dF.T).reshape(-1), wF @ f]).cpu().numpy()
+        k = self.k
+        A = small[: k * k].reshape(k, k)
+        b = small[k * k:]
+        if not np.all(np.isfinite(A)) or not np.all(np.isfinite(b)):
+            return
         # a small ridge keeps the normal equations solvable when two
         # differences are nearly parallel
-        A = A + 1e-12 * torch.trace(A) * torch.eye(A.shape[0], dtype=A.dtype, device=A.device)
+        A = A + 1e-12 * max(np.trace(A), 1e-300) * np.eye(k)
         try:
-            theta = torch.linalg.solve(A, b)
-        except RuntimeError:
+            theta = np.linalg.solve(A, b)
+        except np.linalg.LinAlgError:
             return
-        if not torch.isfinite(theta).all():
+        if not np.all(np.isfinite(theta)):
             return
-        nxt = g.double() + f.double()
-        for k in range(theta.numel()):
-            nxt -= theta[k] * (self.dG[k].double() + self.dF[k].double())
-        if not torch.isfinite(nxt).all():
-            return
+        th = torch.as_tensor(theta, dtype=torch.float64, device=g.device)
+        nxt = gd + f - th @ (dG + dF)
         Fg.copy_(torch.clamp(nxt, min=1.0).to(Fg.dtype))
 
 
