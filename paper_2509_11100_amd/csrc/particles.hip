@@ -863,18 +863,55 @@ __device__ __forceinline__ Segment<T, DIM> stage_segment(const KParams &kp, int 
   sg.binb = reinterpret_cast<int *>(sg.mtab + 8);
   sg.keys = sg.binb + binb_slots(sg.nb);
   // centre (i0 - 1 + a, j - 1 + b, k - 1 + c) sits at ghosted index
-  // (i0 + a) + gx (j + b) + gxy (k + c)
-  for (int t = lane; t < nB; t += 64) {
-    const int a = t % W, bc = t / W, b = bc % 3, c = bc / 3;
-    sg.Bg[t] = Bs[(sg.i0 + a) + kp.gx * (sg.j + b) + (DIM == 3 ? kp.gxy * (sg.k + c) : 0)];
+  // (i0 + a) + gx (j + b) + gxy (k + c); the staged rows are (b, c), x
+  // fastest
+  constexpr int RB = DIM == 3 ? 9 : 3, RE = DIM == 3 ? 4 : 2;
+  const int WE = C + 1;
+  auto b_at = [&](int r, int a) {
+    return Bs[(sg.i0 + a) + kp.gx * (sg.j + r % 3) + (DIM == 3 ? kp.gxy * (sg.k + r / 3) : 0)];
+  };
+  auto e_at = [&](int r, int a) { return Es[gidx<DIM>(kp, sg.i0 + a, sg.j + r % 2, sg.k + r / 2)]; };
+  const int nbb = binb_slots(sg.nb);
+  auto bin_at = [&](int t) { return t <= sg.nb ? bin_start[sg.c0 * S + t] : INT_MAX; };
+  // One lane per x position of every staged row: all of the first 64
+  // positions' loads are in registers before any of them is stored, so that
+  // the staging waits for one round trip to memory instead of one per row
+  // (a wave holds a few hundred particles: a round trip per row would be a
+  // sizeable part of its time), and no lane divides by the row length.
+  // Rows longer than 64 and bin starts past the first 64 finish in plain
+  // loops.
+  V4<T> vb[RB], ve[RE];
+  int vn = 0;
+  const T tq = pc.q[lane & 7], tbeta = pc.beta[lane & 7];
+  const double tm = kp.m[lane & 7];
+  if (lane < W) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r) vb[r] = b_at(r, lane);
   }
-  for (int t = lane; t < nE; t += 64) {
-    const int a = t % (C + 1), bc = t / (C + 1), b = bc % 2, c = bc / 2;
-    sg.Eg[t] = Es[gidx<DIM>(kp, sg.i0 + a, sg.j + b, sg.k + c)];
+  if (lane < WE) {
+#pragma unroll
+    for (int r = 0; r < RE; ++r) ve[r] = e_at(r, lane);
   }
-  for (int t = lane; t < binb_slots(sg.nb); t += 64) sg.binb[t] = t <= sg.nb ? bin_start[sg.c0 * S + t] : INT_MAX;
-  fill_species_table<T>(pc, sg.stab, lane);
-  if (lane < 8) sg.mtab[lane] = kp.m[lane];
+  if (lane < nbb) vn = bin_at(lane);
+  if (lane < W) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r) sg.Bg[r * W + lane] = vb[r];
+  }
+  if (lane < WE) {
+#pragma unroll
+    for (int r = 0; r < RE; ++r) sg.Eg[r * WE + lane] = ve[r];
+  }
+  if (lane < nbb) sg.binb[lane] = vn;
+  for (int a = lane + 64; a < W; a += 64)
+    for (int r = 0; r < RB; ++r) sg.Bg[r * W + a] = b_at(r, a);
+  for (int a = lane + 64; a < WE; a += 64)
+    for (int r = 0; r < RE; ++r) sg.Eg[r * WE + a] = e_at(r, a);
+  for (int t = lane + 64; t < nbb; t += 64) sg.binb[t] = bin_at(t);
+  if (lane < 8) {
+    sg.stab[0][lane] = tq;
+    sg.stab[1][lane] = tbeta;
+    sg.mtab[lane] = tm;
+  }
   return sg;
 }
 
@@ -1027,14 +1064,19 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, int C, const int32_t *_
   }
   if constexpr (COUNT) {
     __syncthreads();
-    // counts out in [move][bin] order, consecutive bins per move
+    // counts out in [move][bin] order: one lane per bin, consecutive bins
+    // per move
     const size_t nbins = (size_t)kp.nbins;
-    for (int t = lane; t < sg.nb * NDIR; t += 64) {
-      const int dir = t / sg.nb, bin = t - dir * sg.nb;
-      const int v = sg.keys[bin * NDIR + dir];
-      if (v > 65535) atomicOr(err, 2);  // a move class beyond the 16-bit counters
-      cnt[(size_t)dir * nbins + (size_t)sg.c0 * S + bin] = (uint16_t)(v > 65535 ? 65535 : v);
+    bool over = false;  // a move class beyond the 16-bit counters
+    for (int bin = lane; bin < sg.nb; bin += 64) {
+#pragma unroll
+      for (int dir = 0; dir < NDIR; ++dir) {
+        const int v = sg.keys[bin * NDIR + dir];
+        over = over || v > 65535;
+        cnt[(size_t)dir * nbins + (size_t)sg.c0 * S + bin] = (uint16_t)(v > 65535 ? 65535 : v);
+      }
     }
+    if (over) atomicOr(err, 2);
   }
 }
 
@@ -1189,14 +1231,28 @@ __global__ __launch_bounds__(64) void k_push_scatter(KParams kp, int C, const in
       stage_segment<T, DIM>(kp, C, xcd_remap(blockIdx.x, gridDim.x), pc, bin_start, Es, Bs, smem, lane);
   const int S = kp.nspecies;
   const size_t nbins = (size_t)kp.nbins;
-  for (int t = lane; t < sg.nb * NDIR; t += 64) {
-    const int bin = t / NDIR, dir = t - bin * NDIR;
-    const int lc = bin / S, s = bin - lc * S;
-    const int mx = dir % 3 - 1, my = (dir / 3) % 3 - 1, mz = dir / 9 - 1;
-    const int dc = wrapi(sg.i0 + lc + mx, kp.nx) +
-                   kp.nx * (wrapi(sg.j + my, kp.ny) + kp.ny * (DIM == 3 ? wrapi(sg.k + mz, kp.nz) : 0));
-    const int d = dc * S + s;
-    sg.keys[t] = bsn[d] + (int)pre[(size_t)dir * nbins + d];
+  // one lane per bin of the segment, all moves at once: the 2 NDIR loads
+  // of a lane are in flight together, and for each move the lanes read
+  // consecutive destination bins
+  for (int b0 = 0; b0 < sg.nb; b0 += 64) {
+    // lanes past the segment's bins compute (and do not store) its last
+    // bin's keys, so that every address is a valid one
+    const bool on = b0 + lane < sg.nb;
+    const int bin = on ? b0 + lane : sg.nb - 1;
+    const int lc = S == 2 ? bin >> 1 : bin / S, s = bin - lc * S;
+    int v[NDIR];
+#pragma unroll
+    for (int dir = 0; dir < NDIR; ++dir) {
+      const int mx = dir % 3 - 1, my = (dir / 3) % 3 - 1, mz = dir / 9 - 1;
+      const int dc = wrapi(sg.i0 + lc + mx, kp.nx) +
+                     kp.nx * (wrapi(sg.j + my, kp.ny) + kp.ny * (DIM == 3 ? wrapi(sg.k + mz, kp.nz) : 0));
+      const int d = dc * S + s;
+      v[dir] = bsn[d] + (int)pre[(size_t)dir * nbins + d];
+    }
+    if (on) {
+#pragma unroll
+      for (int dir = 0; dir < NDIR; ++dir) sg.keys[bin * NDIR + dir] = v[dir];
+    }
   }
   __syncthreads();
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
