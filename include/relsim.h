@@ -144,6 +144,17 @@ int relsim_deposit_moments(relsim_ctx *ctx, const relsim_particles *part, const 
 int relsim_field_solve(relsim_ctx *ctx, const double *M, const double *Jhat, const double *E_n, const double *B_n,
                        double *E_theta, double *E_np1, double *B_np1, int32_t *iters, double *rel_resid);
 
+/* a5 (S4-S5) from a caller's initial guess: as relsim_field_solve, with
+ * the GMRES started from the values E_theta holds on entry (device, [3][N],
+ * finite) instead of E^n.  For the passes of a fixed-point iteration whose
+ * systems change little from one pass to the next (the energy-conserving
+ * variant below): started from the previous pass's E_th, GMRES needs fewer
+ * Arnoldi steps to the same relative tolerance.  The stopping rule and
+ * everything else are relsim_field_solve's. */
+int relsim_field_solve_guess(relsim_ctx *ctx, const double *M, const double *Jhat, const double *E_n,
+                             const double *B_n, double *E_theta, double *E_np1, double *B_np1, int32_t *iters,
+                             double *rel_resid);
+
 /* a6 (S6, +a1 when resort != 0): push every particle with E_th and B^n and
  * move it across at most one cell face per dimension (periodic).  With
  * resort, the pushed state is written into the back set in the new bin
@@ -168,7 +179,8 @@ int relsim_push(relsim_ctx *ctx, relsim_particles *part, const double *E_theta, 
  * change, and the step conserves energy exactly, but gbar then depends on the
  * step's own result.  A caller finds it by fixed-point iteration:
  *   gbar = NULL (gamma(u^n));
- *   repeat: relsim_deposit_moments_ec(gbar) -> relsim_field_solve ->
+ *   repeat: relsim_deposit_moments_ec(gbar) -> relsim_field_solve (after
+ *           the first pass: relsim_field_solve_guess from the last E_th) ->
  *           relsim_gamma_mean(gbar -> gbar_next, change); swap gbar, gbar_next
  *   until change is small; then relsim_push_ec with the gbar the last
  *   relsim_gamma_mean was given (the one the field solve used).

@@ -75,6 +75,7 @@ def load() -> C.CDLL:
         "relsim_sort": (C.c_int, [vp, pt]),
         "relsim_deposit_moments": (C.c_int, [vp, pt, vp, vp, vp]),
         "relsim_field_solve": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i32), dp]),
+        "relsim_field_solve_guess": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(i32), dp]),
         "relsim_push": (C.c_int, [vp, pt, vp, vp, i32, vp]),
         "relsim_deposit_moments_ec": (C.c_int, [vp, pt, vp, vp, vp, vp]),
         "relsim_gamma_mean": (C.c_int, [vp, pt, vp, vp, vp, vp, dp]),
@@ -109,7 +110,7 @@ def exported_symbols():
     """Names of the C functions this binding expects the library to export."""
     return [
         "relsim_workspace_bytes", "relsim_init", "relsim_finalize", "relsim_sort", "relsim_deposit_moments",
-        "relsim_field_solve", "relsim_push", "relsim_fill_cells", "relsim_energy", "relsim_curl_nc", "relsim_curl_cn",
+        "relsim_field_solve", "relsim_field_solve_guess", "relsim_push", "relsim_fill_cells", "relsim_energy", "relsim_curl_nc", "relsim_curl_cn",
         "relsim_apply_A", "relsim_apply_AT", "relsim_push_adjoint", "relsim_field_solve_adjoint",
         "relsim_deposit_adjoint", "relsim_timing_enable", "relsim_timing_reset", "relsim_timing_read",
         "relsim_strerror", "relsim_last_error", "relsim_deposit_moments_ec", "relsim_gamma_mean", "relsim_push_ec",

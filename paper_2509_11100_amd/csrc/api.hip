@@ -782,27 +782,27 @@ static int gmres_solve(relsim_ctx *c, const double *M, bool transpose, double *x
       double *w = V + (size_t)(j + 1) * n3;
       op(vj, w);
       // classical Gram-Schmidt, twice, with the coefficients staying on the
-      // device (h1, then the correction h2, whose last entry is |w|^2 after
-      // the first pass); one copy to the host per Arnoldi step
+      // device: h1, then the correction h2, whose entry j + 1 is |w|^2 after
+      // the first pass.  The first pass's update and the second pass's dots
+      // share one read of the basis, and the second update normalises w by
+      // |w| = sqrt(|w|^2 - |h2|^2) (entry j + 2, 0 if that cancelled and w
+      // was left as it is); one copy to the host per Arnoldi step.
       timed(c, "mdot", [&] { launch_mdot(V, n3, j + 1, w, n3, part, h1dev, c->st); });
-      timed(c, "maxpy", [&] { launch_maxpy(V, n3, j + 1, h1dev, w, n3, c->st); });
-      timed(c, "mdot", [&] { launch_mdot(V, n3, j + 2, w, n3, part, h2dev, c->st); });
-      timed(c, "maxpy", [&] { launch_maxpy(V, n3, j + 1, h2dev, w, n3, c->st); });
-      rc = fetch(c, hdev, (int)(h2dev - hdev) + j + 2);
+      int fused = 0;
+      timed(c, "maxpy_dot", [&] { fused = launch_maxpy_dot(V, n3, j + 1, h1dev, w, n3, part, h2dev, c->st); });
+      if (!fused) {
+        timed(c, "maxpy", [&] { launch_maxpy(V, n3, j + 1, h1dev, w, n3, c->st); });
+        timed(c, "mdot", [&] { launch_mdot(V, n3, j + 2, w, n3, part, h2dev, c->st); });
+      }
+      timed(c, "maxpy", [&] { launch_maxpy_scale(V, n3, j + 1, h2dev, w, n3, c->st); });
+      rc = fetch(c, hdev, (int)(h2dev - hdev) + j + 3);
       if (rc) return rc;
       const double *h1 = c->host, *h2 = c->host + (h2dev - hdev);
       std::vector<double> h(h1, h1 + j + 1);
-      double s2 = 0.0;
-      for (int k = 0; k <= j; ++k) {
-        s2 += h2[k] * h2[k];
-        h[k] += h2[k];
-      }
-      double ww = h2[j + 1];
-      double hn2 = ww - s2;
-      double hn;
-      if (hn2 > 1e-4 * ww) {
-        hn = std::sqrt(hn2);
-      } else {
+      for (int k = 0; k <= j; ++k) h[k] += h2[k];
+      double hn = h2[j + 2];
+      const bool scaled = hn > 0.0;
+      if (!scaled) {
         rc = norm2(c, w, n3, &hn);
         if (rc) return rc;
       }
@@ -826,7 +826,7 @@ static int gmres_solve(relsim_ctx *c, const double *M, bool transpose, double *x
       jdone = j + 1;
       const bool last = std::fabs(g[j + 1]) <= tol || hn == 0.0 || j == m - 1 || total_it >= c->p.gmres_maxit;
       if (last) break;
-      timed(c, "axpby", [&] { launch_axpby(1.0 / hn, w, 0.0, w, n3, c->st); });
+      if (!scaled) timed(c, "axpby", [&] { launch_axpby(1.0 / hn, w, 0.0, w, n3, c->st); });
     }
     // y = H^-1 g (upper triangular), x += V y
     for (int k = jdone - 1; k >= 0; --k) {
@@ -848,8 +848,12 @@ static int gmres_solve(relsim_ctx *c, const double *M, bool transpose, double *x
 
 extern "C" {
 
-int relsim_field_solve(relsim_ctx *c, const double *M, const double *Jhat, const double *E_n, const double *B_n,
-                       double *E_theta, double *E_np1, double *B_np1, int32_t *iters, double *rel_resid) {
+}  // extern "C"
+
+// S4-S5 from E^n (guess == false) or from E_theta's contents (guess == true).
+static int field_solve(relsim_ctx *c, const double *M, const double *Jhat, const double *E_n, const double *B_n,
+                       double *E_theta, double *E_np1, double *B_np1, int32_t *iters, double *rel_resid,
+                       bool guess) {
   if (!c) return RELSIM_EINVAL;
   if (!M || !Jhat || !E_n || !B_n || !E_theta || !E_np1 || !B_np1) return fail(c, RELSIM_EINVAL, "null grid array");
   if (E_theta == E_n || E_theta == E_np1 || B_np1 == B_n) return fail(c, RELSIM_EINVAL, "aliased solve arguments");
@@ -858,13 +862,26 @@ int relsim_field_solve(relsim_ctx *c, const double *M, const double *Jhat, const
   const size_t n3 = 3 * (size_t)c->kp.ncells;
   double *b = c->at<double>(c->L.gm_b);
   timed(c, "rhs", [&] { launch_rhs(c->kp, E_n, B_n, Jhat, b, c->st); });
-  HIP_CHECK(c, hipMemcpyAsync(E_theta, E_n, n3 * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  if (!guess) HIP_CHECK(c, hipMemcpyAsync(E_theta, E_n, n3 * sizeof(double), hipMemcpyDeviceToDevice, c->st));
   const int solved = gmres_solve(c, M, false, E_theta, iters, rel_resid);
   if (solved != RELSIM_OK && solved != RELSIM_ENOTCONVERGED) return solved;
   timed(c, "field_update", [&] { launch_field_update(c->kp, E_n, B_n, E_theta, E_np1, B_np1, c->st); });
-  rc = launch_status(c, "relsim_field_solve");
+  rc = launch_status(c, guess ? "relsim_field_solve_guess" : "relsim_field_solve");
   if (rc) return rc;
   return solved;
+}
+
+extern "C" {
+
+int relsim_field_solve(relsim_ctx *c, const double *M, const double *Jhat, const double *E_n, const double *B_n,
+                       double *E_theta, double *E_np1, double *B_np1, int32_t *iters, double *rel_resid) {
+  return field_solve(c, M, Jhat, E_n, B_n, E_theta, E_np1, B_np1, iters, rel_resid, false);
+}
+
+int relsim_field_solve_guess(relsim_ctx *c, const double *M, const double *Jhat, const double *E_n,
+                             const double *B_n, double *E_theta, double *E_np1, double *B_np1, int32_t *iters,
+                             double *rel_resid) {
+  return field_solve(c, M, Jhat, E_n, B_n, E_theta, E_np1, B_np1, iters, rel_resid, true);
 }
 
 int relsim_apply_AT(relsim_ctx *c, const double *M, const double *x, double *out) {

@@ -230,6 +230,79 @@ __global__ __launch_bounds__(256) void k_maxpy(const double *__restrict__ V, siz
   w[i] = acc;
 }
 
+// The two halves of an Arnoldi step's second Gram-Schmidt pass, each fused
+// with its neighbour so that the basis is read once per half:
+//
+// k_maxpy_dot: w -= sum_k h[k] V[k], then the partial sums (per block, as in
+// k_mdot) of V[k] . w for k < nvec and of w . w, all from one read of the
+// nvec basis vectors (held in registers between the update and the dots).
+// The update rounds as k_maxpy's and the sums are taken in k_mdot's order.
+template <int NV>
+__global__ __launch_bounds__(256) void k_maxpy_dot(const double *__restrict__ V, size_t ld, int nvec,
+                                                   const double *__restrict__ h, double *__restrict__ w, size_t n,
+                                                   double *__restrict__ partials) {
+  __shared__ double lds[4][NV + 1];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const size_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const size_t beg = (size_t)blockIdx.x * chunk;
+  const size_t end = beg + chunk < n ? beg + chunk : n;
+  double hk[NV], acc[NV + 1];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) hk[q] = q < nvec ? h[q] : 0.0;
+#pragma unroll
+  for (int q = 0; q <= NV; ++q) acc[q] = 0.0;
+  for (size_t i = beg + threadIdx.x; i < end; i += 256) {
+    double v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = q < nvec ? V[(size_t)q * ld + i] : 0.0;
+    double wi = w[i];
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+      if (q < nvec) wi -= hk[q] * v[q];
+    w[i] = wi;
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+      if (q < nvec) acc[q] += v[q] * wi;
+    acc[NV] += wi * wi;
+  }
+#pragma unroll
+  for (int q = 0; q <= NV; ++q) {
+    if (q < nvec || q == NV) {
+      double v = acc[q];
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+      if (lane == 0) lds[wid][q] = v;
+    }
+  }
+  __syncthreads();
+  // partials[b][0..nvec]: the dots, then w . w
+  if ((int)threadIdx.x <= nvec) {
+    const int q = (int)threadIdx.x == nvec ? NV : threadIdx.x;
+    partials[(size_t)blockIdx.x * (nvec + 1) + threadIdx.x] = (lds[0][q] + lds[1][q]) + (lds[2][q] + lds[3][q]);
+  }
+}
+
+// k_maxpy_scale: w = (w - sum_k h[k] V[k]) / hn, with hn = sqrt(ww - sum_k
+// h[k]^2) and ww = h[nvec] (the norm of w after the update, from the
+// orthogonality of the basis).  When the difference has cancelled (at most
+// 1e-4 ww) w is left unscaled, for the host to normalise by an explicit
+// norm.  h[nvec + 1] receives hn, or 0 when w was left unscaled.
+__global__ __launch_bounds__(256) void k_maxpy_scale(const double *__restrict__ V, size_t ld, int nvec,
+                                                     double *__restrict__ h, double *__restrict__ w, size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s2 = 0.0;
+  for (int kv = 0; kv < nvec; ++kv) s2 += h[kv] * h[kv];
+  const double ww = h[nvec], hn2 = ww - s2;
+  const bool ok = hn2 > 1e-4 * ww;
+  const double hn = ok ? sqrt(hn2) : 0.0;
+  const double a = ok ? 1.0 / hn : 1.0;
+  double acc = w[i];
+  for (int kv = 0; kv < nvec; ++kv) acc -= h[kv] * V[(size_t)kv * ld + i];
+  w[i] = a * acc;
+  if (i == 0) h[nvec + 1] = hn;
+}
+
 __global__ __launch_bounds__(256) void k_axpby(double a, const double *__restrict__ x, double b, double *__restrict__ y,
                                                size_t n) {
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -291,6 +364,24 @@ void launch_mdot(const double *V, size_t ld, int nvec, const double *w, size_t n
 
 void launch_maxpy(const double *V, size_t ld, int nvec, const double *h, double *w, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_maxpy, dim3(grid_of(n)), dim3(256), 0, st, V, ld, nvec, h, w, n);
+}
+
+int launch_maxpy_dot(const double *V, size_t ld, int nvec, const double *h, double *w, size_t n, double *partials,
+                     double *res, hipStream_t st) {
+  if (nvec <= 8)
+    hipLaunchKernelGGL(k_maxpy_dot<8>, dim3(kDotBlocks), dim3(256), 0, st, V, ld, nvec, h, w, n, partials);
+  else if (nvec <= 16)
+    hipLaunchKernelGGL(k_maxpy_dot<16>, dim3(kDotBlocks), dim3(256), 0, st, V, ld, nvec, h, w, n, partials);
+  else if (nvec <= 32)
+    hipLaunchKernelGGL(k_maxpy_dot<32>, dim3(kDotBlocks), dim3(256), 0, st, V, ld, nvec, h, w, n, partials);
+  else
+    return 0;
+  hipLaunchKernelGGL(k_reduce_partials, dim3(nvec + 1), dim3(256), 0, st, partials, kDotBlocks, nvec + 1, res);
+  return 1;
+}
+
+void launch_maxpy_scale(const double *V, size_t ld, int nvec, double *h, double *w, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_maxpy_scale, dim3(grid_of(n)), dim3(256), 0, st, V, ld, nvec, h, w, n);
 }
 
 void launch_axpby(double a, const double *x, double b, double *y, size_t n, hipStream_t st) {

@@ -148,6 +148,15 @@ void launch_mdot(const double *V, size_t ld, int nvec, const double *w, size_t n
                  hipStream_t st);
 // w -= sum_k h[k] V[k]  (h on the device)
 void launch_maxpy(const double *V, size_t ld, int nvec, const double *h, double *w, size_t n, hipStream_t st);
+// w -= sum_k h[k] V[k] (k < nvec), then res[0..nvec] = (V[k] . w for k <
+// nvec, w . w), reading the basis once; returns 0 (and launches nothing)
+// for nvec > 32, where the caller takes launch_maxpy and launch_mdot.
+int launch_maxpy_dot(const double *V, size_t ld, int nvec, const double *h, double *w, size_t n, double *partials,
+                     double *res, hipStream_t st);
+// w = (w - sum_k h[k] V[k]) / hn, hn = sqrt(h[nvec] - sum_k h[k]^2), left
+// unscaled when that difference is at most 1e-4 h[nvec]; h[nvec + 1] = hn,
+// or 0 when unscaled
+void launch_maxpy_scale(const double *V, size_t ld, int nvec, double *h, double *w, size_t n, hipStream_t st);
 // y = a * x + b * y  (scalars from the host)
 void launch_axpby(double a, const double *x, double b, double *y, size_t n, hipStream_t st);
 void launch_sumsq_partials(const double *x, size_t n, double *partials, hipStream_t st);

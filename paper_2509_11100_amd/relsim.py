@@ -290,16 +290,22 @@ def placement_clamps(ctx: Context) -> int:
     return out.value
 
 
-def field_solve(ctx: Context, M, J, E, B, E_theta=None, E1=None, B1=None, allow_unconverged: bool = False):
-    """relsim_field_solve -> (E_theta, E^{n+1}, B^{n+1}, iterations, relative residual)"""
+def field_solve(ctx: Context, M, J, E, B, E_theta=None, E1=None, B1=None, allow_unconverged: bool = False,
+                guess: bool = False):
+    """relsim_field_solve -> (E_theta, E^{n+1}, B^{n+1}, iterations, relative
+    residual); with guess=True, relsim_field_solve_guess (GMRES starts from
+    the E_theta given)"""
+    if guess and E_theta is None:
+        raise ValueError("guess=True needs E_theta (the initial guess)")
     E_theta = ctx.grid() if E_theta is None else E_theta
     E1 = ctx.grid() if E1 is None else E1
     B1 = ctx.grid() if B1 is None else B1
     _grid_ok(ctx, M, J, E, B, E_theta, E1, B1)
     it = C.c_int32(0)
     rr = C.c_double(0.0)
-    rc = ctx.lib.relsim_field_solve(ctx.handle, _ptr(M), _ptr(J), _ptr(E), _ptr(B), _ptr(E_theta), _ptr(E1), _ptr(B1),
-                                    C.byref(it), C.byref(rr))
+    fn = ctx.lib.relsim_field_solve_guess if guess else ctx.lib.relsim_field_solve
+    rc = fn(ctx.handle, _ptr(M), _ptr(J), _ptr(E), _ptr(B), _ptr(E_theta), _ptr(E1), _ptr(B1), C.byref(it),
+            C.byref(rr))
     if not (allow_unconverged and rc == _lib.RELSIM_ENOTCONVERGED):
         ctx.check(rc)
     return E_theta, E1, B1, it.value, rr.value
@@ -444,10 +450,20 @@ class _AndersonMix:
         dF, dG = self.dF[: self.k], self.dG[: self.k]
         w2 = 1.0 / (gd * gd)  # least squares on the residual relative to g
         wF = dF * w2
-        small = torch.cat([(wF @ dF.T).reshape(-1), wF @ f]).cpu().numpy()
         k = self.k
-        A = small[: k * k].reshape(k, k)
-        b = small[k * k:]
+        # the k(k+1)/2 + k inner products as separate dot products: a
+        # (k x n)(n x k) matrix product with n in the millions runs as one
+        # long serial reduction per output in the BLAS
+        dots = [torch.dot(wF[i], dF[j]) for i in range(k) for j in range(i, k)]
+        dots += [torch.dot(wF[i], f) for i in range(k)]
+        small = torch.stack(dots).cpu().numpy()
+        A = np.empty((k, k))
+        t = 0
+        for i in range(k):
+            for j in range(i, k):
+                A[i, j] = A[j, i] = small[t]
+                t += 1
+        b = small[t:]
         if not np.all(np.isfinite(A)) or not np.all(np.isfinite(b)):
             return
         # a small ridge keeps the normal equations solvable when two
@@ -507,11 +523,15 @@ class Step:
     gbar is kept >= 1, and a non-finite mix falls back to the plain pass.
     The stopping test (the largest relative change of one pass) and the
     final push (with the last pass's input) are those of the plain
-    iteration, so the fixed point reached is the same."""
+    iteration, so the fixed point reached is the same.
+
+    warm_start=True (the default) starts each pass's GMRES after the first
+    from the previous pass's E_theta (relsim_field_solve_guess); the solve's
+    tolerance is unchanged."""
 
     def __init__(self, ctx: Context, parts: Particles, E: torch.Tensor, B: torch.Tensor,
                  energy_conserving: bool = False, picard_tol: Optional[float] = None, picard_maxit: int = 30,
-                 allow_unconverged: bool = False, anderson: int = 0):
+                 allow_unconverged: bool = False, anderson: int = 0, warm_start: bool = True):
         _grid_ok(ctx, E, B)
         self.ctx, self.parts = ctx, parts
         self.E, self.B = E.clone(), B.clone()
@@ -525,16 +545,17 @@ class Step:
         self.picard_tol, self.picard_maxit = picard_tol, picard_maxit
         self.allow_unconverged = allow_unconverged
         self.anderson = int(anderson)
+        self.warm_start = bool(warm_start)
         self.picard_iters, self.picard_change, self.picard_converged = 0, 0.0, True
         self._pushed = False
         if energy_conserving:
             cap = max(parts.n, 1)
             self._gb = [torch.empty(cap, dtype=ctx.dtype, device=ctx.device) for _ in range(2)]
 
-    def _solve(self, gbar):
+    def _solve(self, gbar, guess: bool = False):
         deposit_moments(self.ctx, self.parts, self.B, self.J, self.M, gbar=gbar)
         _, _, _, self.iters, self.rel_resid = field_solve(self.ctx, self.M, self.J, self.E, self.B, self.E_theta,
-                                                          self._E1, self._B1)
+                                                          self._E1, self._B1, guess=guess)
 
     def __call__(self, steps: int = 1) -> "Step":
         for _ in range(steps):
@@ -544,7 +565,8 @@ class Step:
                 gbar, nxt = self._gb[0], 1
                 mix = _AndersonMix(self.anderson) if self.anderson > 0 else None
                 for it in range(1, self.picard_maxit + 1):
-                    self._solve(gbar)
+                    # after the first pass GMRES starts from the last pass's E_theta
+                    self._solve(gbar, guess=self.warm_start and it > 1)
                     self.picard_change = gamma_mean(self.ctx, self.parts, self.E_theta, self.B, gbar, self._gb[nxt])
                     self.picard_iters = it
                     if self.picard_change <= self.picard_tol or it == self.picard_maxit:

@@ -178,6 +178,55 @@ def test_field_solve_parity(gname):
     check_rel(B1.cpu().numpy(), B1r, 1e-12)
 
 
+@pytest.mark.parametrize("restart", [5, 30])
+def test_field_solve_from_a_guess(restart):
+    """relsim_field_solve_guess: started from the converged E_theta it takes
+    no Arnoldi step and returns the same fields bit for bit; started from a
+    perturbed E^n it converges to the oracle's solution."""
+    need_gpu()
+    import torch
+
+    g, ctx0, parts, B, E = setup_random("3d_5x4x3", "fp64", 1500, 45)
+    from paper_2509_11100_amd import relsim
+
+    ctx = make_ctx(g, "fp64", 1500, rtol=1e-13, gmres_restart=restart)
+    parts = load(ctx, *parts.to_host()[:5])
+    J, M = relsim.deposit_moments(ctx, parts, torch_grid(B))
+    Eth, E1, B1, it, rr = relsim.field_solve(ctx, M, J, torch_grid(E), torch_grid(B))
+    assert it > 0 and rr <= 1e-13
+    Eg = Eth.clone()
+    Eth2, E12, B12, it2, rr2 = relsim.field_solve(ctx, M, J, torch_grid(E), torch_grid(B), E_theta=Eg, guess=True)
+    assert it2 == 0 and rr2 == rr
+    assert torch.equal(Eth2, Eth) and torch.equal(E12, E1) and torch.equal(B12, B1)
+    rng = np.random.default_rng(7)
+    Eg = torch_grid(E + 0.01 * rng.standard_normal(E.shape))
+    Eth3, E13, B13, it3, rr3 = relsim.field_solve(ctx, M, J, torch_grid(E), torch_grid(B), E_theta=Eg, guess=True)
+    assert rr3 <= 1e-13
+    Jh, Mh = J.cpu().numpy(), M.cpu().numpy()
+    ref = oracle.solve(g, Mh, oracle.rhs(g, E, B, Jh))
+    E1r, B1r = oracle.field_update(g, E, B, ref)
+    check_rel(Eth3.cpu().numpy(), ref, 1e-12)
+    check_rel(E13.cpu().numpy(), E1r, 1e-12)
+    check_rel(B13.cpu().numpy(), B1r, 1e-12)
+
+
+def test_field_solve_with_a_long_restart_cycle():
+    """GMRES(64) to 1e-15 on a 3D grid: Arnoldi steps past the 32nd of a
+    cycle take the unfused second Gram-Schmidt pass."""
+    need_gpu()
+    g, ctx0, parts, B, E = setup_random("3d_5x4x3", "fp64", 1500, 47)
+    from paper_2509_11100_amd import relsim
+
+    ctx = make_ctx(g, "fp64", 1500, rtol=1e-15, gmres_restart=64)
+    parts = load(ctx, *parts.to_host()[:5])
+    J, M = relsim.deposit_moments(ctx, parts, torch_grid(B))
+    Eth, E1, B1, it, rr = relsim.field_solve(ctx, M, J, torch_grid(E), torch_grid(B), allow_unconverged=True)
+    print("GMRES(64) to 1e-15: %d Arnoldi steps, relative residual %.3e" % (it, rr))
+    Jh, Mh = J.cpu().numpy(), M.cpu().numpy()
+    ref = oracle.solve(g, Mh, oracle.rhs(g, E, B, Jh))
+    check_rel(Eth.cpu().numpy(), ref, 1e-13)
+
+
 def test_field_solve_reports_non_convergence():
     need_gpu()
     g, ctx0, parts, B, E = setup_random("2d_7x5", "fp64", 500, 43)
