@@ -117,7 +117,7 @@ def device_spectra(parts, species: Sequence[int], edges: np.ndarray = EDGES) -> 
 
 def run(steps: Optional[int] = None, snapshots: Sequence[float] = (0, 1, 2, 3, 4, 5, 6, 7, 7.77),
         precision: str = "mixed", energy_conserving: bool = True, rtol: float = 1e-10,
-        workers: int = 16, log=sys.stdout, anderson: int = 3, out: Optional[str] = None, **overrides) -> Dict:
+        workers: int = 16, log=sys.stdout, anderson: int = 0, out: Optional[str] = None, **overrides) -> Dict:
     """The fiducial Table 2 run: spectra of the background electrons and
     ions at the given times (t c / L_y), the energy history, and the slope
     and cutoff of the last electron spectrum.  With `out`, the record is
@@ -155,16 +155,18 @@ def run(steps: Optional[int] = None, snapshots: Sequence[float] = (0, 1, 2, 3, 4
     W0 = step.energy()
     k = 0
     passes, unconverged = 0, 0
-    tstart = time.time()
+    tstart = tlast = time.time()
     for mark in marks:
         while k < mark:
             step()
             k += 1
             passes += step.picard_iters
             unconverged += 0 if step.picard_converged else 1
-            if k % 100 == 0:
+            now = time.time()
+            if k % 100 == 0 or now - tlast > 20.0:
+                tlast = now
                 print("  step %d: %.1f fixed-point passes per step so far, %d unconverged, %.1f s" % (
-                    k, passes / k, unconverged, time.time() - tstart), file=log, flush=True)
+                    k, passes / k, unconverged, now - tstart), file=log, flush=True)
         torch.cuda.synchronize()
         W = step.energy()
         sp = device_spectra(parts, bg)
@@ -195,7 +197,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=None, help="default: to t c / L_y = 7.77")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--standard", action="store_true", help="the standard step (gbar = gamma(u^n))")
-    ap.add_argument("--anderson", type=int, default=3, help="Anderson depth of the fixed point (0: plain passes)")
+    ap.add_argument("--anderson", type=int, default=0, help="Anderson depth of the fixed point (default 0: plain passes)")
     ap.add_argument("--out", default=None, help="write the record as JSON")
     ap.add_argument("--nx", type=int, default=None)
     ap.add_argument("--ny", type=int, default=None)
