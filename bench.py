@@ -120,6 +120,20 @@ def measured_traffic(tag, kernel):
     return None if k is None else k["hbm_bytes"]
 
 
+def measured_valu(tag, kernel):
+    """VALU issue of a kernel from the committed rocprofv3 counter summary
+    (busy fraction, lane use, clock, VALU instructions per 64 particles), or
+    None when the kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "valu_%s.json" % tag)
+    if not os.path.exists(path):
+        return None
+    js = json.load(open(path))
+    code = device_code_sha256()
+    if code is None or js.get("device_code_sha256") != code:
+        return None
+    return js["kernels"].get(KERNEL_SYMBOL.get(kernel, kernel))
+
+
 def run_energy_conserving(prec, wl, host, steps, warmup, rtol, group=0):
     """Whole energy-conserving steps (relsim.Step(energy_conserving=True):
     fixed-point passes of deposit, solve and relsim_gamma_mean, then the
@@ -493,6 +507,7 @@ def roofline_of(res, wl, copy_gbs):
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(ach / PEAK_HBM_GBS, 4),
             "traffic": measured_traffic("%s_%s" % (wl.name, prec), dom),
+            "valu": measured_valu("%s_%s" % (wl.name, prec), dom),
             "bytes_per_launch": byt, "ms_per_launch": round(cand[dom]["ms_per_launch"], 4)}
     per_kernel = {}
     for k, v in cand.items():

@@ -480,6 +480,35 @@ class _AndersonMix:
         Fg.copy_(torch.clamp(nxt, min=1.0).to(Fg.dtype))
 
 
+class _SecantMix:
+    """Per-particle secant steps for the fixed point g = F(g): with the
+    residual r = F(g) - g of this pass and the last, each particle's next
+    input is g - r (g - g_prev) / (r - r_prev), the root of the line through
+    its last two residuals, where that line falls with a slope in [-10,
+    -0.1] (an estimated contraction dF/dg in [-9, 0.9]); elsewhere (first
+    pass, a flat or rising residual, a step too small to measure) the plain
+    update F(g).  Each particle's gbar is nearly its own scalar fixed point
+    (the field couples them weakly), so a per-particle secant follows each
+    one's own contraction rate.  The fixed point, the stopping test and the
+    final push are those of the plain iteration."""
+
+    def __init__(self):
+        self.g_prev = self.r_prev = None
+
+    def __call__(self, g: torch.Tensor, Fg: torch.Tensor) -> None:
+        """g: the pass's input, Fg: its output; Fg is overwritten with the
+        next input."""
+        gd = g.to(torch.float64, copy=True)
+        r = Fg.double() - gd
+        if self.g_prev is not None:
+            dg = gd - self.g_prev
+            slope = (r - self.r_prev) / torch.where(dg == 0, torch.ones_like(dg), dg)
+            use = (dg.abs() > 1e-12 * gd) & (slope <= -0.1) & (slope >= -10.0)
+            nxt = torch.where(use, gd - r / torch.where(use, slope, -torch.ones_like(slope)), gd + r)
+            Fg.copy_(torch.clamp(nxt, min=1.0).to(Fg.dtype))
+        self.g_prev, self.r_prev = gd, r
+
+
 class PicardNotConverged(RuntimeError):
     """The energy-conserving step's fixed point did not reach its tolerance."""
 
@@ -525,13 +554,18 @@ class Step:
     final push (with the last pass's input) are those of the plain
     iteration, so the fixed point reached is the same.
 
+    secant=True (with anderson=0) replaces the plain update by per-particle
+    secant steps (each particle's next gbar from the line through its last
+    two residuals, see _SecantMix).
+
     warm_start=True (the default) starts each pass's GMRES after the first
     from the previous pass's E_theta (relsim_field_solve_guess); the solve's
     tolerance is unchanged."""
 
     def __init__(self, ctx: Context, parts: Particles, E: torch.Tensor, B: torch.Tensor,
                  energy_conserving: bool = False, picard_tol: Optional[float] = None, picard_maxit: int = 30,
-                 allow_unconverged: bool = False, anderson: int = 0, warm_start: bool = True):
+                 allow_unconverged: bool = False, anderson: int = 0, warm_start: bool = True,
+                 secant: bool = False):
         _grid_ok(ctx, E, B)
         self.ctx, self.parts = ctx, parts
         self.E, self.B = E.clone(), B.clone()
@@ -546,6 +580,7 @@ class Step:
         self.allow_unconverged = allow_unconverged
         self.anderson = int(anderson)
         self.warm_start = bool(warm_start)
+        self.secant = bool(secant)
         self.picard_iters, self.picard_change, self.picard_converged = 0, 0.0, True
         self._pushed = False
         if energy_conserving:
@@ -563,7 +598,11 @@ class Step:
             if self.energy_conserving:
                 gamma_mean(self.ctx, self.parts, self.E, self.B, None, self._gb[0])
                 gbar, nxt = self._gb[0], 1
-                mix = _AndersonMix(self.anderson) if self.anderson > 0 else None
+                mix = None
+                if self.anderson > 0:
+                    mix = _AndersonMix(self.anderson)
+                elif self.secant:
+                    mix = _SecantMix()
                 for it in range(1, self.picard_maxit + 1):
                     # after the first pass GMRES starts from the last pass's E_theta
                     self._solve(gbar, guess=self.warm_start and it > 1)

@@ -645,13 +645,13 @@ def test_energy_conserving_passes(gname, precision):
     check_disp(periodic_diff(g, s1["x"][:, new], xr), disp, TOL[precision])
 
 
-@pytest.mark.parametrize("anderson", [0, 3])
-def test_energy_conserving_steps_match_oracle_and_conserve_energy(anderson):
+@pytest.mark.parametrize("anderson,secant", [(0, False), (3, False), (0, True)])
+def test_energy_conserving_steps_match_oracle_and_conserve_energy(anderson, secant):
     """Three energy-conserving FP64 steps of the 64 x 32 pair sheet (sheet
     temperature kT = m c^2, relativistic; time centring theta = 1/2) against
     the oracle's fixed point; the energy stays constant to the iteration's
-    tolerance where the standard step drifts.  With Anderson mixing the same
-    fixed point is reached in fewer passes."""
+    tolerance where the standard step drifts.  With Anderson mixing or
+    per-particle secant steps the same fixed point is reached."""
     need_gpu()
     from paper_2509_11100_amd import relsim
 
@@ -661,7 +661,7 @@ def test_energy_conserving_steps_match_oracle_and_conserve_energy(anderson):
     ctx = make_ctx(g, "fp64", p["w"].shape[0], rtol=1e-13)
     parts = load(ctx, p["cell"], p["species"], p["off"], p["u"], p["w"], p["bin_start"])
     step = relsim.Step(ctx, parts, torch_grid(E), torch_grid(B), energy_conserving=True, picard_tol=1e-14,
-                       anderson=anderson)
+                       anderson=anderson, secant=secant)
     W = [step.energy()]
     passes = []
     for _ in range(steps):
@@ -669,7 +669,7 @@ def test_energy_conserving_steps_match_oracle_and_conserve_energy(anderson):
         assert step.picard_change <= 1e-14 and step.picard_iters < 30
         passes.append(step.picard_iters)
         W.append(step.energy())
-    print("anderson %d: passes per step %s" % (anderson, passes))
+    print("anderson %d, secant %s: passes per step %s" % (anderson, secant, passes))
     W = np.array(W)
     x = positions(g, p["cell"], p["off"])
     u, Er, Br = p["u"], E, B
