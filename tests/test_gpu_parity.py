@@ -28,7 +28,14 @@ def grids():
         "2d_3x3": oracle.Grid(dim=2, nx=3, ny=3, dx=1.0, dy=1.0, dt=0.4),
         "3d_5x4x3": oracle.Grid(dim=3, nx=5, ny=4, nz=3, dx=1.1, dy=0.9, dz=1.2, dt=0.4),
         "3d_3x3x3": oracle.Grid(dim=3, nx=3, ny=3, nz=3, dx=1.0, dy=1.0, dz=1.0, dt=0.4),
+        # larger 3D grids (many segments and tiles per row and layer)
+        "3d_32x4x3": oracle.Grid(dim=3, nx=32, ny=4, nz=3, dx=1.1, dy=0.9, dz=1.2, dt=0.4),
+        "3d_32x8x40": oracle.Grid(dim=3, nx=32, ny=8, nz=40, dx=1.0, dy=1.1, dz=0.9, dt=0.4),
     }
+
+
+def g_cells(gname):
+    return grids()[gname].N
 
 
 def torch_grid(a):
@@ -77,10 +84,10 @@ def test_general_sort_is_stable_sort_by_bin(gname, precision):
 # a2-a4: deposit
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("gname", ["2d_7x5", "2d_3x3", "3d_5x4x3", "3d_3x3x3"])
+@pytest.mark.parametrize("gname", ["2d_7x5", "2d_3x3", "3d_5x4x3", "3d_3x3x3", "3d_32x4x3", "3d_32x8x40"])
 def test_deposit_parity(gname, precision):
     need_gpu()
-    g, ctx, parts, B, E = setup_random(gname, precision, 2500, 21)
+    g, ctx, parts, B, E = setup_random(gname, precision, 2500 if g_cells(gname) < 1000 else 40000, 21)
     from paper_2509_11100_amd import relsim
 
     J, M = relsim.deposit_moments(ctx, parts, torch_grid(B))
