@@ -162,7 +162,7 @@ Layout make_layout(const relsim_params *p) {
     o = align_up(o + bytes);
     return at;
   };
-  L.S = take((size_t)n_cell_moments(p->dim) * nc * es);
+  L.S = take((size_t)n_cell_moments(p->dim) * ((nc + kMomBlock - 1) / kMomBlock * kMomBlock) * es);
   L.cnt = take(nd * nb * 2);
   L.pre = take(nd * nb * 2);
   L.total = take(nb * 4);

@@ -496,7 +496,6 @@ __global__ __launch_bounds__(64) void k_deposit_split3(KParams kp, const int32_t
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
   const PC<T> pc(kp);
-  const size_t NC = (size_t)kp.ncells;
   stage_B_block<T, G, 3>(kp, Bs, cs.gc, gl, bsh[grp]);
   fill_species_table<T>(pc, stab, lane);
   __syncthreads();
@@ -610,19 +609,20 @@ __global__ __launch_bounds__(64) void k_deposit_split3(KParams kp, const int32_t
     p = pn;
   }
   if (!cs.valid) return;
-  T *const base = S + cs.cell;
+  // moment (block row) layout: see mom3_index
+  T *const base = S + mom3_index(0, cs.cell);
   if (!isJ) {
-    T *const q = base + (size_t)(gl * 81) * NC;
+    T *const q = base + (size_t)(gl * 81) * kMomBlock;
 #pragma unroll
-    for (int e = 0; e < 81; ++e) q[(size_t)e * NC] = acc[e];
+    for (int e = 0; e < 81; ++e) q[(size_t)e * kMomBlock] = acc[e];
   } else {
     // accumulator (x + 3 y) * 9 + k holds the current of corner (x, y, k / 3)
     // along k % 3
-    T *const q = base + (size_t)243 * NC;
+    T *const q = base + (size_t)243 * kMomBlock;
 #pragma unroll
     for (int e = 0; e < 81; ++e) {
       const int m = e / 9, k = e % 9, x = m % 3, y = m / 3;
-      if (x < 2 && y < 2 && k < 6) q[(size_t)((k / 3) * 12 + (x + 2 * y) * 3 + k % 3) * NC] = acc[e];
+      if (x < 2 && y < 2 && k < 6) q[(size_t)((k / 3) * 12 + (x + 2 * y) * 3 + k % 3) * kMomBlock] = acc[e];
     }
   }
 }
@@ -664,7 +664,7 @@ __global__ __launch_bounds__(256) void k_assemble(KParams kp, const T *__restric
       const int mono = (ax + bx) + 3 * (ay + by);
       const int base = DIM == 3 ? (az + bz) * 81 + mono * 9 : mono * 9;
 #pragma unroll
-      for (int q = 0; q < 9; ++q) acc[q] += (double)S[(size_t)(base + q) * N + cidx[a]];
+      for (int q = 0; q < 9; ++q) acc[q] += (double)S[DIM == 3 ? mom3_index(base + q, cidx[a]) : (size_t)(base + q) * N + cidx[a]];
     }
 #pragma unroll
     for (int q = 0; q < 9; ++q) M[((size_t)off * 9 + q) * N + g] = acc[q];
@@ -675,7 +675,8 @@ __global__ __launch_bounds__(256) void k_assemble(KParams kp, const T *__restric
     const int cxy = (a & 1) + 2 * ((a >> 1) & 1);
     const int base = DIM == 3 ? 243 + ((a >> 2) & 1) * 12 + cxy * 3 : 81 + cxy * 3;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) jacc[q] += (double)S[(size_t)(base + q) * N + cidx[a]];
+    for (int q = 0; q < 3; ++q)
+      jacc[q] += (double)S[DIM == 3 ? mom3_index(base + q, cidx[a]) : (size_t)(base + q) * N + cidx[a]];
   }
 #pragma unroll
   for (int q = 0; q < 3; ++q) J[(size_t)q * N + g] = jacc[q];
