@@ -383,7 +383,6 @@ __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t 
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
   const PC<T> pc(kp);
-  const size_t NC = (size_t)kp.ncells;
 
   stage_B_block<T, G, 2>(kp, Bs, cs.gc, gl, bsh[grp]);
   fill_species_table<T>(pc, stab, lane);
@@ -457,7 +456,7 @@ __global__ __launch_bounds__(64) void k_deposit_cells(KParams kp, const int32_t 
       T s = T(0);
 #pragma unroll 8
       for (int j = 0; j < G; ++j) s += red[(grp * G + j) * (CH + 1) + k];
-      if (cs.valid) S[(size_t)(c0 + k) * NC + cs.cell] = s;
+      if (cs.valid) S[mom_index<2>(c0 + k, cs.cell)] = s;
     }
     __syncthreads();
   }
@@ -609,8 +608,8 @@ __global__ __launch_bounds__(64) void k_deposit_split3(KParams kp, const int32_t
     p = pn;
   }
   if (!cs.valid) return;
-  // moment (block row) layout: see mom3_index
-  T *const base = S + mom3_index(0, cs.cell);
+  // moment (block row) layout: see mom_index
+  T *const base = S + mom_index<3>(0, cs.cell);
   if (!isJ) {
     T *const q = base + (size_t)(gl * 81) * kMomBlock;
 #pragma unroll
@@ -664,7 +663,7 @@ __global__ __launch_bounds__(256) void k_assemble(KParams kp, const T *__restric
       const int mono = (ax + bx) + 3 * (ay + by);
       const int base = DIM == 3 ? (az + bz) * 81 + mono * 9 : mono * 9;
 #pragma unroll
-      for (int q = 0; q < 9; ++q) acc[q] += (double)S[DIM == 3 ? mom3_index(base + q, cidx[a]) : (size_t)(base + q) * N + cidx[a]];
+      for (int q = 0; q < 9; ++q) acc[q] += (double)S[mom_index<DIM>(base + q, cidx[a])];
     }
 #pragma unroll
     for (int q = 0; q < 9; ++q) M[((size_t)off * 9 + q) * N + g] = acc[q];
@@ -676,7 +675,7 @@ __global__ __launch_bounds__(256) void k_assemble(KParams kp, const T *__restric
     const int base = DIM == 3 ? 243 + ((a >> 2) & 1) * 12 + cxy * 3 : 81 + cxy * 3;
 #pragma unroll
     for (int q = 0; q < 3; ++q)
-      jacc[q] += (double)S[DIM == 3 ? mom3_index(base + q, cidx[a]) : (size_t)(base + q) * N + cidx[a]];
+      jacc[q] += (double)S[mom_index<DIM>(base + q, cidx[a])];
   }
 #pragma unroll
   for (int q = 0; q < 3; ++q) J[(size_t)q * N + g] = jacc[q];

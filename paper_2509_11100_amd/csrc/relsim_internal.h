@@ -43,18 +43,20 @@ constexpr int kSinkSlots = 512;     // per-lane store sinks of the particle kern
 // moments (one set per z-monomial type) plus 2 x 12 current moments.
 inline int n_cell_moments(int dim) { return dim == 3 ? 3 * 81 + 2 * 12 : 81 + 12; }
 
-// Per-cell moments in memory.  2D: moment m of cell c at m * ncells + c (one
-// plane per moment).  3D: blocks of 64 consecutive cells, each block holding
-// its 267 moments as 64-cell rows, moment m of cell c at ((c / 64) 267 + m)
-// 64 + c % 64.  The 3D deposit's wave (16 consecutive cells) then writes its
-// 267 moment pieces of 64 bytes inside one 68 KB block, a few DRAM pages,
-// instead of one page per moment plane; the assembly's wave (64 consecutive
-// nodes) still reads 256 contiguous bytes per moment.  Room: ncells rounded
-// up to a multiple of 64.
+// Per-cell moments in memory (93 per cell in 2D, 267 in 3D): blocks of 64
+// consecutive cells, each block holding its moments as 64-cell rows, moment
+// m of cell c at ((c / 64) nmom + m) 64 + c % 64.  A deposit wave (8 or 16
+// consecutive cells) then writes its moment pieces inside one block, a few
+// DRAM pages, instead of one page per moment plane; the assembly's wave (64
+// consecutive nodes) still reads 256 contiguous bytes per moment.  Room:
+// ncells rounded up to a multiple of 64.
 constexpr int kMomBlock = 64;
-__host__ __device__ inline size_t mom3_index(int m, int c) {
-  return ((size_t)(c >> 6) * 267 + (size_t)m) * kMomBlock + (size_t)(c & (kMomBlock - 1));
+template <int DIM>
+__host__ __device__ inline size_t mom_index(int m, int c) {
+  constexpr size_t NM = DIM == 3 ? 267 : 93;
+  return ((size_t)(c >> 6) * NM + (size_t)m) * kMomBlock + (size_t)(c & (kMomBlock - 1));
 }
+
 inline int n_dirs(int dim) { return dim == 3 ? 27 : 9; }
 
 // Packed records: a ghosted field point (three components and a pad) or a
