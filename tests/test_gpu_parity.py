@@ -26,6 +26,8 @@ def grids():
     return {
         "2d_7x5": oracle.Grid(dim=2, nx=7, ny=5, dx=1.1, dy=0.9, dt=0.45),
         "2d_3x3": oracle.Grid(dim=2, nx=3, ny=3, dx=1.0, dy=1.0, dt=0.4),
+        # 143 cells: two full 64-cell moment blocks and a partial one
+        "2d_13x11": oracle.Grid(dim=2, nx=13, ny=11, dx=1.0, dy=0.8, dt=0.4),
         "3d_5x4x3": oracle.Grid(dim=3, nx=5, ny=4, nz=3, dx=1.1, dy=0.9, dz=1.2, dt=0.4),
         "3d_3x3x3": oracle.Grid(dim=3, nx=3, ny=3, nz=3, dx=1.0, dy=1.0, dz=1.0, dt=0.4),
         # larger 3D grids (many segments and tiles per row and layer)
@@ -84,7 +86,7 @@ def test_general_sort_is_stable_sort_by_bin(gname, precision):
 # a2-a4: deposit
 # ----------------------------------------------------------------------------
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("gname", ["2d_7x5", "2d_3x3", "3d_5x4x3", "3d_3x3x3", "3d_32x4x3", "3d_32x8x40"])
+@pytest.mark.parametrize("gname", ["2d_7x5", "2d_3x3", "2d_13x11", "3d_5x4x3", "3d_3x3x3", "3d_32x4x3", "3d_32x8x40"])
 def test_deposit_parity(gname, precision):
     need_gpu()
     g, ctx, parts, B, E = setup_random(gname, precision, 2500 if g_cells(gname) < 1000 else 40000, 21)
