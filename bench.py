@@ -58,9 +58,10 @@ def kernel_bytes(name, wl, prec, n, nbins, ncells):
         nmom = 93 if d == 2 else 267
         return n * (d + 4) * T + ncells * grid + ncells * nmom * T
     if name == "assemble_nodes":
-        # in: per-cell moments; out: J-hat and M at nodes (FP64)
+        # in: per-cell moments; out: J-hat and the stored half of M at nodes
+        # (FP64; 5 of the 9 node-pair blocks in 2D, 14 of 27 in 3D)
         nmom = 93 if d == 2 else 267
-        return ncells * nmom * T + ncells * (grid + 8 * 9 * noff)
+        return ncells * nmom * T + ncells * (grid + 8 * 9 * (noff // 2 + 1))
     if name == "push_count":
         # first pass of push + re-sort: in: offsets + (momentum, weight)
         # records, E_theta, B^n; out: 1-byte move code (+ per-bin counts)
@@ -291,7 +292,9 @@ def path_bytes_per_particle(wl, prec, n, nbins, ncells):
     and one write of each particle's offsets, momentum and weight (the mixed
     state counted with a 4-byte cell index beside its FP32 values), plus the
     grid traffic of a step with push and the next deposit in one pass: M and
-    J-hat written once, E_theta, B^n and B^{n+1} read once per node."""
+    J-hat written once, E_theta, B^n and B^{n+1} read once per node.  M is
+    counted with all 9 (2D) or 27 (3D) blocks per node, as the roofline
+    target was set, although the library writes only the unique half."""
     T = 4 if prec == "mixed" else 8
     d = wl.dim
     noff = 27 if d == 3 else 9
@@ -350,7 +353,7 @@ def gpu_sampled_results(prec, wl, host, rtol):
     W = relsim.energy(ctx, parts, E, B)
     J, M = relsim.deposit_moments(ctx, parts, B)
     nt = torch.as_tensor(nodes, device=J.device)
-    out = {"W": W, "J": J[:, nt].cpu().numpy(), "M": M[:, :, nt].cpu().numpy()}
+    out = {"W": W, "J": J[:, nt].cpu().numpy(), "M": _all_blocks_at(wl, M, nodes)}
     Eth, _, _, _, _ = relsim.field_solve(ctx, M, J, E, B)
     del J, M
     perm = torch.empty(n, dtype=torch.int32, device=E.device)
@@ -365,6 +368,27 @@ def gpu_sampled_results(prec, wl, host, rtol):
     del parts, ctx, E, B, Eth
     torch.cuda.empty_cache()
     return out
+
+
+def _all_blocks_at(wl, M, nodes):
+    """The 9 (2D) or 27 (3D) node-pair blocks of some nodes, [noff][9][n],
+    from the library's stored half (offsets o >= c at the node itself; o < c
+    is slot c - o of the node at offset o)."""
+    import numpy as np
+    import torch
+
+    noff = 27 if wl.dim == 3 else 9
+    c = noff // 2
+    nodes = np.asarray(nodes)
+    nz = wl.nz if wl.dim == 3 else 1
+    i, j, k = nodes % wl.nx, (nodes // wl.nx) % wl.ny, nodes // (wl.nx * wl.ny)
+    out = []
+    for o in range(noff):
+        dx, dy, dz = o % 3 - 1, (o // 3) % 3 - 1, (o // 9 - 1 if wl.dim == 3 else 0)
+        nb = (i + dx) % wl.nx + wl.nx * (((j + dy) % wl.ny) + wl.ny * ((k + dz) % nz))
+        slot, ids = (o - c, nodes) if o >= c else (c - o, nb)
+        out.append(M[slot][:, torch.as_tensor(ids, device=M.device)].cpu().numpy())
+    return np.stack(out)
 
 
 def _oracle_grid(wl):

@@ -22,10 +22,15 @@
  *     (i+1/2, j+1/2, k+1/2)*dx.  Node and cell (i,j,k) share the linear index
  *     i + nx*(j + ny*k); N = nx*ny*nz (nz = 1 in 2D, where d/dz = 0).
  *   - Grid arrays are FP64, component-major: E, B, Jhat [3][N].
- *     M is [noff][9][N]: noff = 9 (2D) or 27 (3D); offset index
- *     sum_d (delta_d + 1) 3^d over delta in {-1,0,1}^dim (x fastest); the
- *     3x3 block row-major.  Entry [o][3r+c][g] couples E_c at node g+delta(o)
- *     into row r of node g.
+ *     M holds the node-pair blocks M_{g,g+delta} for the 9 (2D) or 27 (3D)
+ *     offsets delta in {-1,0,1}^dim, numbered o = sum_d (delta_d + 1) 3^d (x
+ *     fastest).  The block is symmetric in the pair, M_{g,g'} = M_{g',g}
+ *     (one 3x3 block; Sec. 2, the mass matrices are sums of W_g W_g' alpha_p
+ *     over the particles), so only the upper half o >= c is stored, c = 4
+ *     (2D) or 13 (3D): M is [m_slots][9][N], m_slots = 5 (2D) or 14 (3D).
+ *     Entry [h][3r+s][g] couples E_s at node g+delta(c+h) into row r of node
+ *     g; the block of offset o < c at node g is slot c - o of node
+ *     g+delta(o).  Each 3x3 block is row-major.
  *   - Every array argument is a DEVICE pointer owned by the caller.  The
  *     library allocates no device memory after relsim_init: it carves the
  *     caller's workspace.  Host scalars returned (iters, residuals, energies)
@@ -131,7 +136,8 @@ void relsim_finalize(relsim_ctx *ctx);
 int relsim_sort(relsim_ctx *ctx, relsim_particles *part);
 
 /* a2-a4 (S1-S3): gather B^n, form alpha per particle and deposit Jhat [3][N]
- * and M [noff][9][N] (both overwritten, FP64).  Particles must be bin-sorted. */
+ * and M [m_slots][9][N] (the stored half of the node-pair blocks, see
+ * Conventions; both overwritten, FP64).  Particles must be bin-sorted. */
 int relsim_deposit_moments(relsim_ctx *ctx, const relsim_particles *part, const double *B_n, double *Jhat,
                            double *M);
 
@@ -263,8 +269,8 @@ int relsim_curl_nc(relsim_ctx *ctx, const double *in, double *out);
 int relsim_curl_cn(relsim_ctx *ctx, const double *in, double *out);
 int relsim_apply_A(relsim_ctx *ctx, const double *M, const double *x, double *out);
 
-/* out = A^T x, the transposed S4 operator (block transpose of M, mirrored
- * offsets; the curl-curl term is symmetric). */
+/* out = A^T x, the transposed S4 operator (each block of M transposed; the
+ * curl-curl term is symmetric). */
 int relsim_apply_AT(relsim_ctx *ctx, const double *M, const double *x, double *out);
 
 /* a8: reverse-mode adjoint of one step, RELSIM_FP64 contexts only.  All

@@ -347,70 +347,6 @@ __global__ __launch_bounds__(256) void k_deposit_adjoint(KParams kp, AdjIn in, i
   for (int k = 0; k < 3; ++k) lu_out[(size_t)k * n + p] += lu[k];
 }
 
-// out = x + a^2 C_CN C_NC x + b M^T x with t = C_NC x precomputed;
-// (M^T x)_g = sum_off (M[opp(off)] at node g + delta(off))^T x_{g + delta(off)}
-template <int DIM>
-__global__ __launch_bounds__(256) void k_apply_AT_tail(KParams kp, const double *__restrict__ M,
-                                                       const double *__restrict__ x, const double *__restrict__ t,
-                                                       double *__restrict__ out) {
-  constexpr int NOFF = DIM == 3 ? 27 : 9;
-  const int g = blockIdx.x * 256 + threadIdx.x;
-  if (g >= kp.ncells) return;
-  const size_t N = (size_t)kp.ncells;
-  const int i = g % kp.nx, j = (g / kp.nx) % kp.ny, k = g / (kp.nx * kp.ny);
-  // C_CN t at node g: cube of centres starting at (i-1, j-1, k-1)
-  double cc[3];
-  {
-    double c[3][8];
-    const int x0 = wrapi(i - 1, kp.nx), x1 = i;
-    const int y0 = wrapi(j - 1, kp.ny), y1 = j;
-    const int z0 = DIM == 3 ? wrapi(k - 1, kp.nz) : 0, z1 = DIM == 3 ? k : 0;
-#pragma unroll
-    for (int a = 0; a < (DIM == 3 ? 8 : 4); ++a) {
-      const size_t id = (size_t)((a & 1) ? x1 : x0) +
-                        (size_t)kp.nx * ((size_t)((a & 2) ? y1 : y0) + (size_t)kp.ny * ((a & 4) ? z1 : z0));
-      c[0][a] = t[id];
-      c[1][a] = t[N + id];
-      c[2][a] = t[2 * N + id];
-    }
-    const double ax = kp.inv_dx / (DIM == 3 ? 4.0 : 2.0), ay = kp.inv_dy / (DIM == 3 ? 4.0 : 2.0);
-    const double az = kp.inv_dz / 4.0;
-    double d[3][3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      if (DIM == 2) {
-        d[q][0] = ax * ((c[q][1] - c[q][0]) + (c[q][3] - c[q][2]));
-        d[q][1] = ay * ((c[q][2] - c[q][0]) + (c[q][3] - c[q][1]));
-        d[q][2] = 0.0;
-      } else {
-        d[q][0] = ax * ((c[q][1] - c[q][0]) + (c[q][3] - c[q][2]) + (c[q][5] - c[q][4]) + (c[q][7] - c[q][6]));
-        d[q][1] = ay * ((c[q][2] - c[q][0]) + (c[q][3] - c[q][1]) + (c[q][6] - c[q][4]) + (c[q][7] - c[q][5]));
-        d[q][2] = az * ((c[q][4] - c[q][0]) + (c[q][5] - c[q][1]) + (c[q][6] - c[q][2]) + (c[q][7] - c[q][3]));
-      }
-    }
-    cc[0] = d[2][1] - d[1][2];
-    cc[1] = d[0][2] - d[2][0];
-    cc[2] = d[1][0] - d[0][1];
-  }
-  const double a = kp.c * kp.theta * kp.dt;
-  const double bm = 4.0 * M_PI * kp.theta * kp.dt;
-  double mx[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int off = 0; off < NOFF; ++off) {
-    const int dx = off % 3 - 1, dy = (off / 3) % 3 - 1, dz = off / 9 - 1;
-    const int opp = (1 - dx) + 3 * (1 - dy) + (DIM == 3 ? 9 * (1 - dz) : 0);
-    const size_t id = (size_t)wrapi(i + dx, kp.nx) +
-                      (size_t)kp.nx * ((size_t)wrapi(j + dy, kp.ny) + (size_t)kp.ny * (DIM == 3 ? wrapi(k + dz, kp.nz) : 0));
-    const double x0 = x[id], x1 = x[N + id], x2 = x[2 * N + id];
-    const double *Mo = M + (size_t)opp * 9 * N + id;  // block (g+delta, -delta), transposed
-    mx[0] += Mo[0] * x0 + Mo[3 * N] * x1 + Mo[6 * N] * x2;
-    mx[1] += Mo[N] * x0 + Mo[4 * N] * x1 + Mo[7 * N] * x2;
-    mx[2] += Mo[2 * N] * x0 + Mo[5 * N] * x1 + Mo[8 * N] * x2;
-  }
-#pragma unroll
-  for (int q = 0; q < 3; ++q) out[q * N + g] = x[q * N + g] + a * a * cc[q] + bm * mx[q];
-}
-
 // rhs of the transposed solve: l_th + l_E1/theta - c dt C_CN l_B1  (curl precomputed in t)
 __global__ __launch_bounds__(256) void k_adj_rhs(size_t n3, double theta, double cdt, const double *__restrict__ lth,
                                                  const double *__restrict__ lE1, const double *__restrict__ ccn_lB1,
@@ -456,15 +392,6 @@ void launch_deposit_adjoint(const KParams &kp, const AdjInPtrs &in, int n, const
     hipLaunchKernelGGL(k_deposit_adjoint<2>, dim3(nb), dim3(256), 0, st, kp, a, n, B, Eth, mu, lx_out, lu_out, lB);
   else
     hipLaunchKernelGGL(k_deposit_adjoint<3>, dim3(nb), dim3(256), 0, st, kp, a, n, B, Eth, mu, lx_out, lu_out, lB);
-}
-
-void launch_apply_AT_tail(const KParams &kp, const double *M, const double *x, const double *t, double *out,
-                          hipStream_t st) {
-  const int nb = (kp.ncells + 255) / 256;
-  if (kp.dim == 2)
-    hipLaunchKernelGGL(k_apply_AT_tail<2>, dim3(nb), dim3(256), 0, st, kp, M, x, t, out);
-  else
-    hipLaunchKernelGGL(k_apply_AT_tail<3>, dim3(nb), dim3(256), 0, st, kp, M, x, t, out);
 }
 
 void launch_adj_rhs(size_t n3, double theta, double cdt, const double *lth, const double *lE1, const double *ccn_lB1,

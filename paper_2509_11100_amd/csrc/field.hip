@@ -77,12 +77,53 @@ __global__ __launch_bounds__(256) void k_curl(KParams kp, const double *__restri
   out[2 * N + g] = r[2];
 }
 
-// out = x + a^2 C_CN t + b M x, with t = C_NC x precomputed
+// Linear index of node (i + dx, j + dy, k + dz), periodic.
 template <int DIM>
+__device__ __forceinline__ size_t node_at(const KParams &kp, int i, int j, int k, int dx, int dy, int dz) {
+  return (size_t)wrapi(i + dx, kp.nx) +
+         (size_t)kp.nx * ((size_t)wrapi(j + dy, kp.ny) + (size_t)kp.ny * (DIM == 3 ? wrapi(k + dz, kp.nz) : 0));
+}
+
+// (M x)_g, or (M^T x)_g with TR (each 3x3 block transposed), from the stored
+// half of the blocks: slot h of node g couples x at g + delta(h), and for
+// h > 0 the same slot of node g - delta(h) couples x at g - delta(h)
+// (M_{g,g-delta} = M_{g-delta,g}).
+template <int DIM, bool TR>
+__device__ __forceinline__ void apply_M(const KParams &kp, const double *__restrict__ M,
+                                        const double *__restrict__ x, int g, int i, int j, int k, double mx[3]) {
+  constexpr int NSLOT = m_slots<DIM>(), CEN = m_centre<DIM>();
+  const size_t N = (size_t)kp.ncells;
+#pragma unroll
+  for (int h = 0; h < NSLOT; ++h) {
+    const int off = CEN + h;
+    const int dx = off % 3 - 1, dy = (off / 3) % 3 - 1, dz = DIM == 3 ? off / 9 - 1 : 0;
+#pragma unroll
+    for (int side = 0; side < (h ? 2 : 1); ++side) {
+      // side 0: own block times x at g + delta; side 1: the neighbour's
+      // block times x at g - delta
+      const size_t id = side ? node_at<DIM>(kp, i, j, k, -dx, -dy, -dz) : node_at<DIM>(kp, i, j, k, dx, dy, dz);
+      const double x0 = x[id], x1 = x[N + id], x2 = x[2 * N + id];
+      const double *Mo = M + (size_t)h * 9 * N + (side ? id : (size_t)g);
+      if constexpr (!TR) {
+        mx[0] += Mo[0] * x0 + Mo[N] * x1 + Mo[2 * N] * x2;
+        mx[1] += Mo[3 * N] * x0 + Mo[4 * N] * x1 + Mo[5 * N] * x2;
+        mx[2] += Mo[6 * N] * x0 + Mo[7 * N] * x1 + Mo[8 * N] * x2;
+      } else {
+        mx[0] += Mo[0] * x0 + Mo[3 * N] * x1 + Mo[6 * N] * x2;
+        mx[1] += Mo[N] * x0 + Mo[4 * N] * x1 + Mo[7 * N] * x2;
+        mx[2] += Mo[2 * N] * x0 + Mo[5 * N] * x1 + Mo[8 * N] * x2;
+      }
+    }
+  }
+}
+
+// out = x + a^2 C_CN t + b M x, with t = C_NC x precomputed; with TR the
+// transposed operator, x + a^2 C_CN t + b M^T x (the curl-curl term is
+// symmetric, C_CN being the transpose of C_NC)
+template <int DIM, bool TR>
 __global__ __launch_bounds__(256) void k_apply_A_tail(KParams kp, const double *__restrict__ M,
                                                       const double *__restrict__ x, const double *__restrict__ t,
                                                       double *__restrict__ out) {
-  constexpr int NOFF = DIM == 3 ? 27 : 9;
   const int g = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
   if (g >= kp.ncells) return;
   const size_t N = (size_t)kp.ncells;
@@ -93,18 +134,7 @@ __global__ __launch_bounds__(256) void k_apply_A_tail(KParams kp, const double *
   const double a = kp.c * kp.theta * kp.dt;
   const double b = 4.0 * M_PI * kp.theta * kp.dt;
   double mx[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int off = 0; off < NOFF; ++off) {
-    const int ii = wrapi(i + off % 3 - 1, kp.nx);
-    const int jj = wrapi(j + (off / 3) % 3 - 1, kp.ny);
-    const int kk = DIM == 3 ? wrapi(k + off / 9 - 1, kp.nz) : 0;
-    const size_t id = (size_t)ii + (size_t)kp.nx * ((size_t)jj + (size_t)kp.ny * kk);
-    const double x0 = x[id], x1 = x[N + id], x2 = x[2 * N + id];
-    const double *Mo = M + (size_t)off * 9 * N + g;
-    mx[0] += Mo[0] * x0 + Mo[N] * x1 + Mo[2 * N] * x2;
-    mx[1] += Mo[3 * N] * x0 + Mo[4 * N] * x1 + Mo[5 * N] * x2;
-    mx[2] += Mo[6 * N] * x0 + Mo[7 * N] * x1 + Mo[8 * N] * x2;
-  }
+  apply_M<DIM, TR>(kp, M, x, g, i, j, k, mx);
 #pragma unroll
   for (int q = 0; q < 3; ++q) out[q * N + g] = x[q * N + g] + a * a * cc[q] + b * mx[q];
 }
@@ -336,9 +366,17 @@ void launch_curl(const KParams &kp, const double *in, double *out, int to_centre
 void launch_apply_A_tail(const KParams &kp, const double *M, const double *x, const double *t, double *out,
                          hipStream_t st) {
   if (kp.dim == 2)
-    hipLaunchKernelGGL(k_apply_A_tail<2>, dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, M, x, t, out);
+    hipLaunchKernelGGL((k_apply_A_tail<2, false>), dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, M, x, t, out);
   else
-    hipLaunchKernelGGL(k_apply_A_tail<3>, dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, M, x, t, out);
+    hipLaunchKernelGGL((k_apply_A_tail<3, false>), dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, M, x, t, out);
+}
+
+void launch_apply_AT_tail(const KParams &kp, const double *M, const double *x, const double *t, double *out,
+                          hipStream_t st) {
+  if (kp.dim == 2)
+    hipLaunchKernelGGL((k_apply_A_tail<2, true>), dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, M, x, t, out);
+  else
+    hipLaunchKernelGGL((k_apply_A_tail<3, true>), dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, M, x, t, out);
 }
 
 void launch_rhs(const KParams &kp, const double *En, const double *Bn, const double *J, double *out, hipStream_t st) {

@@ -632,7 +632,7 @@ __global__ __launch_bounds__(64) void k_deposit_split3(KParams kp, const int32_t
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_assemble(KParams kp, const T *__restrict__ S, double *__restrict__ J,
                                                   double *__restrict__ M) {
-  constexpr int NOFF = DIM == 3 ? 27 : 9;
+  constexpr int NSLOT = m_slots<DIM>(), CEN = m_centre<DIM>();
   constexpr int NCORN = DIM == 3 ? 8 : 4;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int g = blk * blockDim.x + threadIdx.x;
@@ -648,9 +648,12 @@ __global__ __launch_bounds__(256) void k_assemble(KParams kp, const T *__restric
     const int kk = DIM == 3 ? wrapi(k - ((a >> 2) & 1), kp.nz) : 0;
     cidx[a] = ii + kp.nx * (jj + kp.ny * kk);
   }
+  // the stored half of the offsets (the other half is the same blocks seen
+  // from the other node of each pair)
 #pragma unroll
-  for (int off = 0; off < NOFF; ++off) {
-    const int dx = off % 3 - 1, dy = (off / 3) % 3 - 1, dz = off / 9 - 1;
+  for (int h = 0; h < NSLOT; ++h) {
+    const int off = CEN + h;
+    const int dx = off % 3 - 1, dy = (off / 3) % 3 - 1, dz = DIM == 3 ? off / 9 - 1 : 0;
     double acc[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) acc[q] = 0.0;
@@ -666,7 +669,7 @@ __global__ __launch_bounds__(256) void k_assemble(KParams kp, const T *__restric
       for (int q = 0; q < 9; ++q) acc[q] += (double)S[mom_index<DIM>(base + q, cidx[a])];
     }
 #pragma unroll
-    for (int q = 0; q < 9; ++q) M[((size_t)off * 9 + q) * N + g] = acc[q];
+    for (int q = 0; q < 9; ++q) M[((size_t)h * 9 + q) * N + g] = acc[q];
   }
   double jacc[3] = {0.0, 0.0, 0.0};
 #pragma unroll

@@ -59,6 +59,17 @@ __host__ __device__ inline size_t mom_index(int m, int c) {
 
 inline int n_dirs(int dim) { return dim == 3 ? 27 : 9; }
 
+// Mass-matrix storage.  The node-pair block of the linearised current is
+// symmetric in the pair, M_{g,g'} = M_{g',g} as one 3x3 block (Sec. 2: both
+// are sums of W_g W_g' alpha_p over the same particles), so of the 3^dim
+// offsets only the upper half in the offset order (x fastest) is stored:
+// slot h in [0, m_slots) of node g holds M_{g, g+delta(m_centre + h)}; the
+// block of the mirrored offset -delta at node g is slot h of node g - delta.
+template <int DIM>
+__host__ __device__ constexpr int m_slots() { return DIM == 3 ? 14 : 5; }
+template <int DIM>
+__host__ __device__ constexpr int m_centre() { return DIM == 3 ? 13 : 4; }
+
 // Packed records: a ghosted field point (three components and a pad) or a
 // particle's (u_x, u_y, u_z, w); a particle's (off_x, off_y).
 template <typename T>
@@ -143,8 +154,6 @@ void launch_push_adjoint(const KParams &kp, const AdjInPtrs &in, int n, const do
                          double *lu_out, double *lEth, double *lB, hipStream_t st);
 void launch_deposit_adjoint(const KParams &kp, const AdjInPtrs &in, int n, const double *B, const double *Eth,
                             const double *mu, double *lx_out, double *lu_out, double *lB, hipStream_t st);
-void launch_apply_AT_tail(const KParams &kp, const double *M, const double *x, const double *t, double *out,
-                          hipStream_t st);
 void launch_adj_rhs(size_t n3, double theta, double cdt, const double *lth, const double *lE1, const double *ccn_lB1,
                     double *out, hipStream_t st);
 void launch_adj_finish(size_t n3, double theta, double ctdt, const double *lE1, const double *lB1, const double *mu,
@@ -154,6 +163,8 @@ void launch_adj_finish(size_t n3, double theta, double ctdt, const double *lE1, 
 void launch_curl(const KParams &kp, const double *in, double *out, int to_centres, hipStream_t st);
 void launch_apply_A_tail(const KParams &kp, const double *M, const double *x, const double *t, double *out,
                          hipStream_t st);
+void launch_apply_AT_tail(const KParams &kp, const double *M, const double *x, const double *t, double *out,
+                          hipStream_t st);
 void launch_rhs(const KParams &kp, const double *En, const double *Bn, const double *J, double *out, hipStream_t st);
 void launch_field_update(const KParams &kp, const double *En, const double *Bn, const double *Eth, double *En1,
                          double *Bn1, hipStream_t st);

@@ -83,6 +83,13 @@ class Context:
         return 27 if self.params.dim == 3 else 9
 
     @property
+    def m_slots(self) -> int:
+        """Stored node-pair blocks of M per node: the offsets from the centre
+        on in the offset order (M_{g,g'} = M_{g',g}, so the other half is the
+        same blocks seen from the other node)."""
+        return self.noff // 2 + 1
+
+    @property
     def dtype(self) -> torch.dtype:
         return torch.float64 if self.precision == "fp64" else torch.float32
 
@@ -96,7 +103,7 @@ class Context:
         return torch.zeros((3, self.ncells), dtype=torch.float64, device=self.device)
 
     def mass_matrix(self) -> torch.Tensor:
-        return torch.empty((self.noff, 9, self.ncells), dtype=torch.float64, device=self.device)
+        return torch.empty((self.m_slots, 9, self.ncells), dtype=torch.float64, device=self.device)
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -237,6 +244,13 @@ def _grid_ok(ctx: Context, *ts):
             raise ValueError("grid arrays must be contiguous float64 tensors on the context device")
 
 
+def _mass_ok(ctx: Context, M):
+    # the stored half of the node-pair blocks, [m_slots][9][N]
+    _grid_ok(ctx, M)
+    if M.numel() < ctx.m_slots * 9 * ctx.ncells:
+        raise ValueError("M must hold [%d][9][%d] values" % (ctx.m_slots, ctx.ncells))
+
+
 def sort(ctx: Context, parts: Particles) -> None:
     """relsim_sort"""
     parts.s.n = parts.n
@@ -253,11 +267,12 @@ def _gbar_ok(ctx: Context, parts: "Particles", *ts):
 
 def deposit_moments(ctx: Context, parts: Particles, B: torch.Tensor, J: Optional[torch.Tensor] = None,
                     M: Optional[torch.Tensor] = None, gbar: Optional[torch.Tensor] = None):
-    """relsim_deposit_moments -> (Jhat [3][N], M [noff][9][N]); with gbar
+    """relsim_deposit_moments -> (Jhat [3][N], M [m_slots][9][N]); with gbar
     (per particle, particle type), relsim_deposit_moments_ec"""
     J = ctx.grid() if J is None else J
     M = ctx.mass_matrix() if M is None else M
-    _grid_ok(ctx, B, J, M)
+    _grid_ok(ctx, B, J)
+    _mass_ok(ctx, M)
     parts.s.n = parts.n
     if gbar is None:
         ctx.check(ctx.lib.relsim_deposit_moments(ctx.handle, C.byref(parts.s), _ptr(B), _ptr(J), _ptr(M)))
@@ -300,7 +315,8 @@ def field_solve(ctx: Context, M, J, E, B, E_theta=None, E1=None, B1=None, allow_
     E_theta = ctx.grid() if E_theta is None else E_theta
     E1 = ctx.grid() if E1 is None else E1
     B1 = ctx.grid() if B1 is None else B1
-    _grid_ok(ctx, M, J, E, B, E_theta, E1, B1)
+    _grid_ok(ctx, J, E, B, E_theta, E1, B1)
+    _mass_ok(ctx, M)
     it = C.c_int32(0)
     rr = C.c_double(0.0)
     fn = ctx.lib.relsim_field_solve_guess if guess else ctx.lib.relsim_field_solve
@@ -334,7 +350,8 @@ def push(ctx: Context, parts: Particles, E_theta: torch.Tensor, B: torch.Tensor,
 def apply_AT(ctx: Context, M: torch.Tensor, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """relsim_apply_AT"""
     out = ctx.grid() if out is None else out
-    _grid_ok(ctx, M, x, out)
+    _grid_ok(ctx, x, out)
+    _mass_ok(ctx, M)
     ctx.check(ctx.lib.relsim_apply_AT(ctx.handle, _ptr(M), _ptr(x), _ptr(out)))
     return out
 
@@ -358,6 +375,7 @@ def push_adjoint(ctx: Context, state: Particles, E_theta, B, new_index, lam_x_in
 def field_solve_adjoint(ctx: Context, M, lam_E_theta, lam_E1, lam_B1, mu, lam_E, lam_B):
     """relsim_field_solve_adjoint -> (iterations, relative residual); lam_E, lam_B accumulated into"""
     _f64(ctx, M, lam_E_theta, lam_E1, lam_B1, mu, lam_E, lam_B)
+    _mass_ok(ctx, M)
     it = C.c_int32(0)
     rr = C.c_double(0.0)
     ctx.check(ctx.lib.relsim_field_solve_adjoint(ctx.handle, _ptr(M), _ptr(lam_E_theta), _ptr(lam_E1), _ptr(lam_B1),
@@ -653,7 +671,8 @@ def curl_cn(ctx: Context, x: torch.Tensor, out: Optional[torch.Tensor] = None) -
 def apply_A(ctx: Context, M: torch.Tensor, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """relsim_apply_A"""
     out = ctx.grid() if out is None else out
-    _grid_ok(ctx, M, x, out)
+    _grid_ok(ctx, x, out)
+    _mass_ok(ctx, M)
     ctx.check(ctx.lib.relsim_apply_A(ctx.handle, _ptr(M), _ptr(x), _ptr(out)))
     return out
 

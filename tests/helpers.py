@@ -99,3 +99,52 @@ def check_disp(dx, disp, tol: float, what: str = "positions"):
     assert nw < tol, "%s normwise %.3e >= %.1e" % (what, nw, tol)
     assert mx < tol, "%s max-abs/max-displacement %.3e >= %.1e" % (what, mx, tol)
     return nw, mx
+
+
+def m_centre(g: oracle.Grid) -> int:
+    """Index of the zero offset; the library stores the offsets from it on."""
+    return g.noff // 2
+
+
+def stored_half(M):
+    """The slots of a full [noff][9][N] mass matrix that the library stores:
+    offsets m_centre .. noff-1 (a view)."""
+    return M[M.shape[0] // 2:]
+
+
+def full_from_half(g: oracle.Grid, Mh) -> np.ndarray:
+    """Rebuild the full [noff][9][N] layout from the stored half: the block of
+    offset o < c at node n is slot c - o of node n + delta(o), by
+    M_{g,g'} = M_{g',g}.  Index bookkeeping only."""
+    Mh = np.asarray(Mh, dtype=np.float64)
+    c = m_centre(g)
+    nz = g.nz if g.dim == 3 else 1
+    idx = np.arange(g.N)
+    i, j, k = idx % g.nx, (idx // g.nx) % g.ny, idx // (g.nx * g.ny)
+    M = np.empty((g.noff, 9, g.N))
+    for o in range(g.noff):
+        if o >= c:
+            M[o] = Mh[o - c]
+            continue
+        dx, dy, dz = o % 3 - 1, (o // 3) % 3 - 1, (o // 9 - 1 if g.dim == 3 else 0)
+        nb = (i + dx) % g.nx + g.nx * (((j + dy) % g.ny) + g.ny * ((k + dz) % nz))
+        M[o] = Mh[c - o][:, nb]
+    return M
+
+
+def neighbour_nodes(g: oracle.Grid, nodes, o: int) -> np.ndarray:
+    """Linear indices of nodes + delta(o), periodic."""
+    nodes = np.asarray(nodes)
+    nz = g.nz if g.dim == 3 else 1
+    i, j, k = nodes % g.nx, (nodes // g.nx) % g.ny, nodes // (g.nx * g.ny)
+    dx, dy, dz = o % 3 - 1, (o // 3) % 3 - 1, (o // 9 - 1 if g.dim == 3 else 0)
+    return (i + dx) % g.nx + g.nx * (((j + dy) % g.ny) + g.ny * ((k + dz) % nz))
+
+
+def full_at_nodes(g: oracle.Grid, take, nodes) -> np.ndarray:
+    """The full [noff][9][len(nodes)] blocks of some nodes from the stored
+    half, with take(slot, node_ids) -> [9][len(node_ids)] reading the stored
+    array (device or host)."""
+    c = m_centre(g)
+    return np.stack([np.asarray(take(o - c, np.asarray(nodes))) if o >= c
+                     else np.asarray(take(c - o, neighbour_nodes(g, nodes, o))) for o in range(g.noff)])

@@ -31,7 +31,7 @@ import pytest
 import oracle
 from paper_2509_11100_amd import harris
 from tests.gpu_helpers import load, make_ctx, need_gpu, rounded
-from tests.helpers import check_disp, check_rel, grid_of, normwise, periodic_diff, positions
+from tests.helpers import check_disp, check_rel, full_at_nodes, grid_of, normwise, periodic_diff, positions
 
 pytestmark = pytest.mark.gpu
 
@@ -94,7 +94,9 @@ def check_deposit(wl, p, B, ctx, parts, precision):
                                   p["species"][sel].astype(np.int32), B, nodes)
     nt = torch.as_tensor(nodes, device=J.device)
     Jg = J[:, nt].cpu().numpy()
-    Mg = M[:, :, nt].cpu().numpy()
+    # every block of the sampled nodes: the stored half at the node, the
+    # mirrored half from the neighbours' slots
+    Mg = full_at_nodes(g, lambda h, ids: M[h][:, torch.as_tensor(ids, device=M.device)].cpu().numpy(), nodes)
     check_rel(Jg, Jr, TOL[precision])
     check_rel(Mg, Mr, TOL[precision])
     return J, M

@@ -21,7 +21,7 @@ import pytest
 import oracle
 from paper_2509_11100_amd import harris
 from tests.gpu_helpers import host_state, load, make_ctx, need_gpu, random_cells, rounded
-from tests.helpers import check_disp, check_rel, grid_of, normwise, periodic_diff, positions
+from tests.helpers import check_disp, check_rel, full_from_half, grid_of, normwise, periodic_diff, positions
 
 pytestmark = pytest.mark.gpu
 
@@ -87,7 +87,7 @@ def test_nonrelativistic_deposit_push_energy(dim, precision):
     J, M = relsim.deposit_moments(ctx, parts, torch_grid(B))
     Jr, Mr = oracle.deposit(g, st["x"], st["u"], st["w"], st["species"], B)
     check_rel(J.cpu().numpy(), Jr, TOL[precision], "J")
-    check_rel(M.cpu().numpy(), Mr, TOL[precision], "M")
+    check_rel(full_from_half(g, M.cpu().numpy()), Mr, TOL[precision], "M")
     W = relsim.energy(ctx, parts, torch_grid(E), torch_grid(B))
     Wr = oracle.energy(g, st["u"], st["w"], st["species"], E, B)
     np.testing.assert_allclose(W, Wr, rtol=1e-12)
@@ -157,7 +157,7 @@ def test_field_solve_and_update_at_theta(dim, theta):
     J, M = relsim.deposit_moments(ctx, parts, torch_grid(B))
     Eth, E1, B1, it, rr = relsim.field_solve(ctx, M, J, torch_grid(E), torch_grid(B))
     assert rr <= 1e-13 and it > 0
-    Jh, Mh = J.cpu().numpy(), M.cpu().numpy()
+    Jh, Mh = J.cpu().numpy(), full_from_half(g, M.cpu().numpy())
     check_rel(relsim.apply_A(ctx, M, torch_grid(E)).cpu().numpy(), oracle.apply_A(g, Mh, E), 1e-13, "A E")
     ref = oracle.solve(g, Mh, oracle.rhs(g, E, B, Jh))
     E1r, B1r = oracle.field_update(g, E, B, ref)
@@ -312,7 +312,7 @@ def test_edge_case_particles(dim, precision):
     J, M = relsim.deposit_moments(ctx, parts, torch_grid(B))
     Jr, Mr = oracle.deposit(g, st["x"], st["u"], st["w"], st["species"], B)
     check_rel(J.cpu().numpy(), Jr, TOL[precision], "J")
-    check_rel(M.cpu().numpy(), Mr, TOL[precision], "M")
+    check_rel(full_from_half(g, M.cpu().numpy()), Mr, TOL[precision], "M")
     W = relsim.energy(ctx, parts, torch_grid(E), torch_grid(B))
     np.testing.assert_allclose(W, oracle.energy(g, st["u"], st["w"], st["species"], E, B), rtol=1e-12)
     st0, s1, new = push_and_compare(g, ctx, parts, E, B, precision)

@@ -15,7 +15,8 @@ import pytest
 import oracle
 from paper_2509_11100_amd import harris
 from tests.gpu_helpers import host_state, load, make_ctx, need_gpu, random_cells, rounded
-from tests.helpers import cell_and_offset, check_disp, check_rel, grid_of, normwise, periodic_diff, positions
+from tests.helpers import (cell_and_offset, check_disp, check_rel, full_from_half, grid_of, normwise, periodic_diff,
+                           positions, stored_half)
 
 pytestmark = pytest.mark.gpu
 
@@ -97,16 +98,12 @@ def test_deposit_parity(gname, precision):
     Jr, Mr = oracle.deposit(g, st["x"], st["u"], st["w"], st["species"], B)
     J, M = J.cpu().numpy(), M.cpu().numpy()
     check_rel(J, Jr, TOL[precision])
-    check_rel(M, Mr, TOL[precision])
-    # node-pair symmetry is exact on the GPU (same cell moments, same order)
-    nz = g.nz if g.dim == 3 else 1
-    idx = np.arange(g.N)
-    i, j, k = idx % g.nx, (idx // g.nx) % g.ny, idx // (g.nx * g.ny)
-    for off in range(g.noff):
-        dx, dy, dz = off % 3 - 1, (off // 3) % 3 - 1, off // 9 - 1
-        opp = (1 - dx) + 3 * (1 - dy) + (9 * (1 - dz) if g.dim == 3 else 0)
-        gj = (i + dx) % g.nx + g.nx * (((j + dy) % g.ny) + g.ny * ((k + dz) % nz))
-        np.testing.assert_array_equal(M[off], M[opp][:, gj])
+    # the stored half against the oracle's blocks of the same offsets, and
+    # the mirrored half (read from the neighbours' slots) against the
+    # oracle's own, separately summed, blocks of the other offsets
+    assert M.shape == (g.noff // 2 + 1, 9, g.N)
+    check_rel(M, stored_half(Mr), TOL[precision], "stored M")
+    check_rel(full_from_half(g, M), Mr, TOL[precision], "full M")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -131,7 +128,7 @@ def test_deposit_every_lane_group_width(group, precision):
     st = host_state(g, parts)
     Jr, Mr = oracle.deposit(g, st["x"], st["u"], st["w"], st["species"], B)
     check_rel(J.cpu().numpy(), Jr, TOL[precision])
-    check_rel(M.cpu().numpy(), Mr, TOL[precision])
+    check_rel(full_from_half(g, M.cpu().numpy()), Mr, TOL[precision])
     W = relsim.energy(ctx, parts, torch_grid(E), torch_grid(B))
     np.testing.assert_allclose(W, oracle.energy(g, st["u"], st["w"], st["species"], E, B), rtol=1e-12)
 
@@ -160,7 +157,7 @@ def test_field_operators(gname):
     from paper_2509_11100_amd import relsim
 
     J, M = relsim.deposit_moments(ctx, parts, torch_grid(B))
-    Mh = M.cpu().numpy()
+    Mh = full_from_half(g, M.cpu().numpy())
     c1 = relsim.curl_nc(ctx, torch_grid(E)).cpu().numpy()
     c2 = relsim.curl_cn(ctx, torch_grid(B)).cpu().numpy()
     check_rel(c1, oracle.curl_nc(g, E), 1e-13)
@@ -178,7 +175,7 @@ def test_field_solve_parity(gname):
     J, M = relsim.deposit_moments(ctx, parts, torch_grid(B))
     Eth, E1, B1, it, rr = relsim.field_solve(ctx, M, J, torch_grid(E), torch_grid(B))
     assert rr <= 1e-13 and it > 0
-    Jh, Mh = J.cpu().numpy(), M.cpu().numpy()
+    Jh, Mh = J.cpu().numpy(), full_from_half(g, M.cpu().numpy())
     r = oracle.rhs(g, E, B, Jh)
     ref = oracle.solve(g, Mh, r)
     E1r, B1r = oracle.field_update(g, E, B, ref)
@@ -211,7 +208,7 @@ def test_field_solve_from_a_guess(restart):
     Eg = torch_grid(E + 0.01 * rng.standard_normal(E.shape))
     Eth3, E13, B13, it3, rr3 = relsim.field_solve(ctx, M, J, torch_grid(E), torch_grid(B), E_theta=Eg, guess=True)
     assert rr3 <= 1e-13
-    Jh, Mh = J.cpu().numpy(), M.cpu().numpy()
+    Jh, Mh = J.cpu().numpy(), full_from_half(g, M.cpu().numpy())
     ref = oracle.solve(g, Mh, oracle.rhs(g, E, B, Jh))
     E1r, B1r = oracle.field_update(g, E, B, ref)
     check_rel(Eth3.cpu().numpy(), ref, 1e-12)
@@ -231,7 +228,7 @@ def test_field_solve_with_a_long_restart_cycle():
     J, M = relsim.deposit_moments(ctx, parts, torch_grid(B))
     Eth, E1, B1, it, rr = relsim.field_solve(ctx, M, J, torch_grid(E), torch_grid(B), allow_unconverged=True)
     print("GMRES(64) to 1e-15: %d Arnoldi steps, relative residual %.3e" % (it, rr))
-    Jh, Mh = J.cpu().numpy(), M.cpu().numpy()
+    Jh, Mh = J.cpu().numpy(), full_from_half(g, M.cpu().numpy())
     ref = oracle.solve(g, Mh, oracle.rhs(g, E, B, Jh))
     check_rel(Eth.cpu().numpy(), ref, 1e-13)
 
@@ -358,7 +355,7 @@ def test_species_counts_other_than_two(gname, ns, precision):
     J, M = relsim.deposit_moments(ctx, parts, torch_grid(B))
     Jr, Mr = oracle.deposit(g, st["x"], st["u"], st["w"], st["species"], B)
     check_rel(J.cpu().numpy(), Jr, TOL[precision])
-    check_rel(M.cpu().numpy(), Mr, TOL[precision])
+    check_rel(full_from_half(g, M.cpu().numpy()), Mr, TOL[precision])
     W = relsim.energy(ctx, parts, torch_grid(E), torch_grid(B))
     Wr = oracle.energy(g, st["u"], st["w"], st["species"], E, B)
     np.testing.assert_allclose(W, Wr, rtol=1e-12)
@@ -627,7 +624,7 @@ def test_energy_conserving_passes(gname, precision):
     J, M = relsim.deposit_moments(ctx, parts, torch_grid(B), gbar=gbar)
     Jr, Mr = oracle.deposit(g, st["x"], st["u"], st["w"], st["species"], B, gb)
     check_rel(J.cpu().numpy(), Jr, TOL[precision])
-    check_rel(M.cpu().numpy(), Mr, TOL[precision])
+    check_rel(full_from_half(g, M.cpu().numpy()), Mr, TOL[precision])
     # the fixed-point pass, with the given gbar and from gamma(u^n)
     xr, ur = oracle.push(g, st["x"], st["u"], st["species"], E, B, gb)
     nxt = 0.5 * (g0 + np.sqrt(1 + (ur ** 2).sum(0)))
