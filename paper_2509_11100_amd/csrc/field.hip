@@ -65,9 +65,10 @@ __device__ __forceinline__ void cube_curl(const KParams &kp, const double c[3][8
 template <int DIM>
 __global__ __launch_bounds__(256) void k_curl(KParams kp, const double *__restrict__ in, double *__restrict__ out,
                                               int shift) {
-  const int g = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  if (g >= kp.ncells) return;
-  const int i = g % kp.nx, j = (g / kp.nx) % kp.ny, k = g / (kp.nx * kp.ny);
+  int i, j, k;
+  const int g = strip_node(kp.nx, kp.ny, kp.nz, xcd_remap(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6),
+                           (int)(threadIdx.x & 63), i, j, k);
+  if (g < 0) return;
   double c[3][8], r[3];
   load_cube<DIM>(kp, in, i - shift, j - shift, k - shift, c);
   cube_curl<DIM>(kp, c, r);
@@ -124,10 +125,11 @@ template <int DIM, bool TR>
 __global__ __launch_bounds__(256) void k_apply_A_tail(KParams kp, const double *__restrict__ M,
                                                       const double *__restrict__ x, const double *__restrict__ t,
                                                       double *__restrict__ out) {
-  const int g = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  if (g >= kp.ncells) return;
+  int i, j, k;
+  const int g = strip_node(kp.nx, kp.ny, kp.nz, xcd_remap(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6),
+                           (int)(threadIdx.x & 63), i, j, k);
+  if (g < 0) return;
   const size_t N = (size_t)kp.ncells;
-  const int i = g % kp.nx, j = (g / kp.nx) % kp.ny, k = g / (kp.nx * kp.ny);
   double c[3][8], cc[3];
   load_cube<DIM>(kp, t, i - 1, j - 1, k - 1, c);
   cube_curl<DIM>(kp, c, cc);
@@ -142,10 +144,11 @@ __global__ __launch_bounds__(256) void k_apply_A_tail(KParams kp, const double *
 template <int DIM>
 __global__ __launch_bounds__(256) void k_rhs(KParams kp, const double *__restrict__ En, const double *__restrict__ Bn,
                                              const double *__restrict__ J, double *__restrict__ out) {
-  const int g = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  if (g >= kp.ncells) return;
+  int i, j, k;
+  const int g = strip_node(kp.nx, kp.ny, kp.nz, xcd_remap(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6),
+                           (int)(threadIdx.x & 63), i, j, k);
+  if (g < 0) return;
   const size_t N = (size_t)kp.ncells;
-  const int i = g % kp.nx, j = (g / kp.nx) % kp.ny, k = g / (kp.nx * kp.ny);
   double c[3][8], cc[3];
   load_cube<DIM>(kp, Bn, i - 1, j - 1, k - 1, c);
   cube_curl<DIM>(kp, c, cc);
@@ -159,10 +162,11 @@ template <int DIM>
 __global__ __launch_bounds__(256) void k_field_update(KParams kp, const double *__restrict__ En,
                                                       const double *__restrict__ Bn, const double *__restrict__ Eth,
                                                       double *__restrict__ En1, double *__restrict__ Bn1) {
-  const int g = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-  if (g >= kp.ncells) return;
+  int i, j, k;
+  const int g = strip_node(kp.nx, kp.ny, kp.nz, xcd_remap(blockIdx.x, gridDim.x) * 4 + (int)(threadIdx.x >> 6),
+                           (int)(threadIdx.x & 63), i, j, k);
+  if (g < 0) return;
   const size_t N = (size_t)kp.ncells;
-  const int i = g % kp.nx, j = (g / kp.nx) % kp.ny, k = g / (kp.nx * kp.ny);
   double c[3][8], cc[3];
   load_cube<DIM>(kp, Eth, i, j, k, c);
   cube_curl<DIM>(kp, c, cc);
@@ -352,46 +356,48 @@ __global__ __launch_bounds__(256) void k_sumsq(const double *__restrict__ x, siz
 }
 
 inline int grid_of(size_t n) { return (int)((n + 255) / 256); }
+// blocks of the per-node kernels (strip node order)
+inline int node_blocks(const KParams &kp) { return grid_node_blocks(kp.nx, kp.ny, kp.nz); }
 
 }  // namespace
 
 void launch_curl(const KParams &kp, const double *in, double *out, int to_centres, hipStream_t st) {
   const int shift = to_centres ? 0 : 1;
   if (kp.dim == 2)
-    hipLaunchKernelGGL(k_curl<2>, dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, in, out, shift);
+    hipLaunchKernelGGL(k_curl<2>, dim3(node_blocks(kp)), dim3(256), 0, st, kp, in, out, shift);
   else
-    hipLaunchKernelGGL(k_curl<3>, dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, in, out, shift);
+    hipLaunchKernelGGL(k_curl<3>, dim3(node_blocks(kp)), dim3(256), 0, st, kp, in, out, shift);
 }
 
 void launch_apply_A_tail(const KParams &kp, const double *M, const double *x, const double *t, double *out,
                          hipStream_t st) {
   if (kp.dim == 2)
-    hipLaunchKernelGGL((k_apply_A_tail<2, false>), dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, M, x, t, out);
+    hipLaunchKernelGGL((k_apply_A_tail<2, false>), dim3(node_blocks(kp)), dim3(256), 0, st, kp, M, x, t, out);
   else
-    hipLaunchKernelGGL((k_apply_A_tail<3, false>), dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, M, x, t, out);
+    hipLaunchKernelGGL((k_apply_A_tail<3, false>), dim3(node_blocks(kp)), dim3(256), 0, st, kp, M, x, t, out);
 }
 
 void launch_apply_AT_tail(const KParams &kp, const double *M, const double *x, const double *t, double *out,
                           hipStream_t st) {
   if (kp.dim == 2)
-    hipLaunchKernelGGL((k_apply_A_tail<2, true>), dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, M, x, t, out);
+    hipLaunchKernelGGL((k_apply_A_tail<2, true>), dim3(node_blocks(kp)), dim3(256), 0, st, kp, M, x, t, out);
   else
-    hipLaunchKernelGGL((k_apply_A_tail<3, true>), dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, M, x, t, out);
+    hipLaunchKernelGGL((k_apply_A_tail<3, true>), dim3(node_blocks(kp)), dim3(256), 0, st, kp, M, x, t, out);
 }
 
 void launch_rhs(const KParams &kp, const double *En, const double *Bn, const double *J, double *out, hipStream_t st) {
   if (kp.dim == 2)
-    hipLaunchKernelGGL(k_rhs<2>, dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, En, Bn, J, out);
+    hipLaunchKernelGGL(k_rhs<2>, dim3(node_blocks(kp)), dim3(256), 0, st, kp, En, Bn, J, out);
   else
-    hipLaunchKernelGGL(k_rhs<3>, dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, En, Bn, J, out);
+    hipLaunchKernelGGL(k_rhs<3>, dim3(node_blocks(kp)), dim3(256), 0, st, kp, En, Bn, J, out);
 }
 
 void launch_field_update(const KParams &kp, const double *En, const double *Bn, const double *Eth, double *En1,
                          double *Bn1, hipStream_t st) {
   if (kp.dim == 2)
-    hipLaunchKernelGGL(k_field_update<2>, dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, En, Bn, Eth, En1, Bn1);
+    hipLaunchKernelGGL(k_field_update<2>, dim3(node_blocks(kp)), dim3(256), 0, st, kp, En, Bn, Eth, En1, Bn1);
   else
-    hipLaunchKernelGGL(k_field_update<3>, dim3(grid_of(kp.ncells)), dim3(256), 0, st, kp, En, Bn, Eth, En1, Bn1);
+    hipLaunchKernelGGL(k_field_update<3>, dim3(node_blocks(kp)), dim3(256), 0, st, kp, En, Bn, Eth, En1, Bn1);
 }
 
 void launch_mdot(const double *V, size_t ld, int nvec, const double *w, size_t n, double *partials, double *res,

@@ -70,6 +70,30 @@ __host__ __device__ constexpr int m_slots() { return DIM == 3 ? 14 : 5; }
 template <int DIM>
 __host__ __device__ constexpr int m_centre() { return DIM == 3 ? 13 : 4; }
 
+// Node order of the field solve's per-node kernels (S4 operator, curls,
+// right-hand side, update): 64-node chunks of x-rows, the rows taken in slabs
+// of kStrip consecutive z-planes swept along y, z fastest inside a slab.  A
+// node reads rows k-1 and j-1 (the mirrored mass-matrix slots, the curl
+// cubes); in this order they were read one and kStrip rows earlier and are
+// still in the L2, where the plain order read the row at k-1 a whole z-plane
+// earlier.  The chunks in flight stay within kStrip planes.  In 2D it is the
+// plain order.  Blocks of 256 threads take 4 chunks.
+constexpr int kStrip = 4;
+inline int grid_node_blocks(int nx, int ny, int nz) { return (((nx + 63) >> 6) * ny * nz + 3) >> 2; }
+// chunk L (of the grid's ((nx + 63) / 64) ny nz), lane in [0, 64) -> node
+// (i, j, k) and its linear index, or -1 past the grid
+__device__ __forceinline__ int strip_node(int nx, int ny, int nz, int L, int lane, int &i, int &j, int &k) {
+  const int nxc = (nx + 63) >> 6;
+  const int xc = L % nxc, q = L / nxc;
+  const int S = nz % kStrip == 0 ? kStrip : 1;
+  const int per = S * ny;
+  const int kb = q / per, r = q - kb * per;
+  j = r / S;
+  k = kb * S + (r - j * S);
+  i = xc * 64 + lane;
+  return (i < nx && k < nz) ? i + nx * (j + ny * k) : -1;
+}
+
 // Packed records: a ghosted field point (three components and a pad) or a
 // particle's (u_x, u_y, u_z, w); a particle's (off_x, off_y).
 template <typename T>
