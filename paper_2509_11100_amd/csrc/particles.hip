@@ -71,6 +71,30 @@ __device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
 __device__ __forceinline__ float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
 
+// S7's relativistic kinetic term w m |u|^2 / (gamma + 1) in FP64, gamma =
+// sqrt(1 + v), v = |u|^2 / c^2, given y ~ 1 / gamma from the push.  In FP64
+// the quotient is formed directly.  From an FP32 y (relative error about
+// 1e-7): two Newton steps for the square root, gamma <- gamma + (1 + v -
+// gamma^2) y / 2, and two for the reciprocal of d = gamma + 1 from its FP32
+// estimate, r <- r + r (1 - d r); each step squares the relative error, which
+// ends within a few units of FP64 rounding (checked against exact arithmetic
+// over |u| / c from 1e-4 to 3e3 with 3-ulp FP32 estimates: worst 3.2e-16).
+// All full-rate FMAs, where the correctly rounded FP64 square root and
+// division take twice as many instructions, two of them quarter rate.
+__device__ __forceinline__ double kinetic_rel(double wmuu, double v, double) { return wmuu / (sqrt(1.0 + v) + 1.0); }
+__device__ __forceinline__ double kinetic_rel(double wmuu, double v, float y32) {
+  const double t = 1.0 + v;
+  const double y = y32, hy = 0.5 * y;
+  double g = t * y;
+  g = fma(fma(-g, g, t), hy, g);
+  g = fma(fma(-g, g, t), hy, g);
+  const double d = g + 1.0;
+  double r = (double)__builtin_amdgcn_rcpf((float)d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return wmuu * r;
+}
+
 // alpha = (I - [b]x + b b^T) / (1 + |b|^2), row-major, as its numerator
 // (written to a) and the returned scale 1 / (1 + |b|^2); the kernels fold
 // the scale into their per-particle coefficients.
@@ -756,7 +780,7 @@ struct CellFields {
 // that they all round identically.
 template <typename T, int DIM, bool GB = false>
 __device__ __forceinline__ void push_one(const KParams &kp, const PC<T> &pc, const CellFields<T> &cf, T bs,
-                                         const PRec<T> &cur, T &fx, T &fy, T &fz, T &nx, T &ny, T &nz) {
+                                         const PRec<T> &cur, T &fx, T &fy, T &fz, T &nx, T &ny, T &nz, T &ign) {
   constexpr int NCORN = DIM == 3 ? 8 : 4;
   fx = cur.fx;
   fy = cur.fy;
@@ -786,7 +810,7 @@ __device__ __forceinline__ void push_one(const KParams &kp, const PC<T> &pc, con
   nx = inv2 * ubx - ux;
   ny = inv2 * uby - uy;
   nz = inv2 * ubz - uz;
-  const T ign = kp.nonrel ? T(1) : rsqrt_t(T(1) + (nx * nx + ny * ny + nz * nz) * pc.invc2);
+  ign = kp.nonrel ? T(1) : rsqrt_t(T(1) + (nx * nx + ny * ny + nz * nz) * pc.invc2);
   const T dtg = pc.dt * ign;
   fx += dtg * nx * pc.idx;
   fy += dtg * ny * pc.idy;
@@ -1027,7 +1051,8 @@ __global__ __launch_bounds__(64) void k_push(KParams kp, int C, const int32_t *_
     T qs, bs;
     species_consts<T>(S, s, sq0, sq1, sb0, sb1, sg.stab, qs, bs);
     T fx, fy, fz, nx, ny, nz;
-    push_one<T, DIM, LOADG>(kp, pc, segment_fields(sg, lc), bs, cur, fx, fy, fz, nx, ny, nz);
+    T ign;
+    push_one<T, DIM, LOADG>(kp, pc, segment_fields(sg, lc), bs, cur, fx, fy, fz, nx, ny, nz, ign);
     if constexpr (TRIAL) {
       const T g0 = kp.nonrel ? T(1) : sqrt(T(1) + (cur.ux * cur.ux + cur.uy * cur.uy + cur.uz * cur.uz) * pc.invc2);
       const T g1 = kp.nonrel ? T(1) : sqrt(T(1) + (nx * nx + ny * ny + nz * nz) * pc.invc2);
@@ -1147,8 +1172,8 @@ __device__ __forceinline__ void scatter_round(const KParams &kp, const PC<T> &pc
   const int lc = S == 2 ? b >> 1 : b / S, s = b - lc * S;
   T qs, bs;
   species_consts<T>(S, s, q0, q1, b0, b1, sg.stab, qs, bs);
-  T fx, fy, fz, nx, ny, nz;
-  push_one<T, DIM, GB>(kp, pc, segment_fields(sg, lc), bs, cur, fx, fy, fz, nx, ny, nz);
+  T fx, fy, fz, nx, ny, nz, ign;
+  push_one<T, DIM, GB>(kp, pc, segment_fields(sg, lc), bs, cur, fx, fy, fz, nx, ny, nz, ign);
   // S7's kinetic term of the pushed particle, in FP64 whatever T:
   // w m c^2 (gamma - 1) = w m |u|^2 / (gamma + 1), or w m |u|^2 / 2 without
   // relativity
@@ -1156,7 +1181,7 @@ __device__ __forceinline__ void scatter_round(const KParams &kp, const PC<T> &pc
     const double ux = nx, uy = ny, uz = nz;
     const double uu = ux * ux + uy * uy + uz * uz;
     const double wm = (double)cur.w * (S == 2 ? (s ? m1 : m0) : sg.mtab[s]);
-    const double term = kp.nonrel ? 0.5 * wm * uu : wm * uu / (sqrt(1.0 + uu * kp.inv_c2) + 1.0);
+    const double term = kp.nonrel ? 0.5 * wm * uu : kinetic_rel(wm * uu, uu * kp.inv_c2, ign);
     ke += pv ? term : 0.0;
   }
   // the new state goes where the counting pass counted it (move dcur),
