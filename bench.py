@@ -458,7 +458,7 @@ def oracle_errors(prec, wl, host, gpu):
 
 
 def host_cores():
-    """Host cores this process may use, capped at the 16 a one-GPU machine gives."""
+    """Host cores this process may use, capped at 16 (the host share of one GPU)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:

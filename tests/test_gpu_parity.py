@@ -34,6 +34,10 @@ def grids():
         # larger 3D grids (many segments and tiles per row and layer)
         "3d_32x4x3": oracle.Grid(dim=3, nx=32, ny=4, nz=3, dx=1.1, dy=0.9, dz=1.2, dt=0.4),
         "3d_32x8x40": oracle.Grid(dim=3, nx=32, ny=8, nz=40, dx=1.0, dy=1.1, dz=0.9, dt=0.4),
+        # the field kernels' node order: rows of two 64-node chunks, the
+        # second partial; in 3D z-slabs of 4 planes (nz a multiple of 4)
+        "2d_70x9": oracle.Grid(dim=2, nx=70, ny=9, dx=1.0, dy=0.9, dt=0.4),
+        "3d_70x6x8": oracle.Grid(dim=3, nx=70, ny=6, nz=8, dx=1.0, dy=0.9, dz=1.1, dt=0.4),
     }
 
 
@@ -150,7 +154,7 @@ def test_deposit_with_no_particles():
 # ----------------------------------------------------------------------------
 # a5: field operators and solve
 # ----------------------------------------------------------------------------
-@pytest.mark.parametrize("gname", ["2d_7x5", "3d_5x4x3", "3d_3x3x3"])
+@pytest.mark.parametrize("gname", ["2d_7x5", "3d_5x4x3", "3d_3x3x3", "2d_70x9", "3d_70x6x8"])
 def test_field_operators(gname):
     need_gpu()
     g, ctx, parts, B, E = setup_random(gname, "fp64", 800, 31)
@@ -164,9 +168,13 @@ def test_field_operators(gname):
     check_rel(c2, oracle.curl_cn(g, B), 1e-13)
     A = relsim.apply_A(ctx, M, torch_grid(E)).cpu().numpy()
     check_rel(A, oracle.apply_A(g, Mh, E), 1e-13)
+    # the transposed operator (the same kernel with every block transposed)
+    # against the transpose of the oracle's sparse matrix
+    AT = relsim.apply_AT(ctx, M, torch_grid(E)).cpu().numpy()
+    check_rel(AT, (oracle.A_matrix(g, Mh).T @ E.reshape(-1)).reshape(3, g.N), 1e-13)
 
 
-@pytest.mark.parametrize("gname", ["2d_7x5", "3d_5x4x3"])
+@pytest.mark.parametrize("gname", ["2d_7x5", "3d_5x4x3", "3d_70x6x8"])
 def test_field_solve_parity(gname):
     need_gpu()
     g, ctx, parts, B, E = setup_random(gname, "fp64", 1500, 41)
