@@ -524,7 +524,10 @@ __global__ __launch_bounds__(64) void k_deposit_split3(KParams kp, const int32_t
   __shared__ P3<T> bsh[64 / G][27];
   __shared__ T stab[2][8];
   const int lane = threadIdx.x, grp = lane / G, gl = lane % G;
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  // blocks in launch order, not banded per XCD: the moment stores then
+  // interleave over the XCDs (measured 5 % faster on the 256 x 128 x 128
+  // sheet than XCD bands, 1 % on 128 x 64 x 64)
+  const int blk = (int)blockIdx.x;
   const CellSpan cs = slot_span<G>(kp, bin_start, blk, grp);
   const PC<T> pc(kp);
 #pragma unroll
