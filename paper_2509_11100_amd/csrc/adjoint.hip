@@ -12,7 +12,9 @@
 // one outer product per particle, no 9 x 9 x offset scatter.
 // Gradients of the CIC weights are piecewise constant (one-sided at a node,
 // taken from the particle's own cell).  Grid adjoints are accumulated with
-// FP64 atomics (the adjoint is not on the throughput path).
+// FP64 atomics, after summing the lanes of one cell within the wave (the
+// particles are bin-sorted, so a wave holds few cells): one atomic per grid
+// entry and cell instead of one per particle.
 #include "relsim_internal.h"
 
 namespace relsim {
@@ -165,6 +167,81 @@ __device__ __forceinline__ void atomic_add3(double *g, size_t N, int idx, double
   atomicAdd(&g[2 * N + idx], wt * v[2]);
 }
 
+// Butterfly sum over the 64 lanes of a wave (every lane gets the sum).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Lanes of one cell are summed in the wave before the atomics when the cell
+// has at least this many of the wave's lanes; sparser cells add per lane.
+constexpr int kSegMin = 16;
+
+// Linear index of the point (ci + ox, cj + oy, ck + oz), periodic.
+template <int DIM>
+__device__ __forceinline__ int grid_index(const KParams &kp, int ci, int cj, int ck, int ox, int oy, int oz) {
+  return wrapi(ci + ox, kp.nx) + kp.nx * (wrapi(cj + oy, kp.ny) + kp.ny * (DIM == 3 ? wrapi(ck + oz, kp.nz) : 0));
+}
+
+// g[k N + .] += the lanes' node-stencil contributions wt[a] v[k] (node a of
+// the lane's cell) and, with the centre stencil, wt[a] v[k] at the centre
+// (cell + a - 1 + h) (h: the lane's upper-half flags).  Lanes of one cell are
+// summed over the wave first (per node or centre slot of that cell), then
+// one lane per slot adds with an atomic; `active` lanes only.
+template <int DIM>
+__device__ void add_stencil(const KParams &kp, double *__restrict__ g, bool active, int cell, int ci, int cj, int ck,
+                            const Stencil<DIM> &S, bool centres, const double (&hf)[3], const double v[3]) {
+  constexpr int NA = 1 << DIM, NS = DIM == 3 ? 27 : 9;
+  const size_t N = (size_t)kp.ncells;
+  const int lane = threadIdx.x & 63;
+  int h[3] = {0, 0, 0};
+  if (centres) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) h[d] = hf[d] >= 0.5 ? 1 : 0;
+  }
+  bool pending = active;
+  unsigned long long todo = __ballot(pending);
+  while (todo) {
+    const int leader = __builtin_amdgcn_readfirstlane(__ffsll((long long)todo) - 1);
+    const int c = __shfl(cell, leader);
+    const bool mine = pending && cell == c;
+    const unsigned long long seg = __ballot(mine);
+    if (__popcll(seg) >= kSegMin) {
+      const int li = __shfl(ci, leader), lj = __shfl(cj, leader), lk = __shfl(ck, leader);
+      // slots of the cell: its 2^DIM nodes, or the 3^DIM centres around it
+      for (int sl = 0; sl < (centres ? NS : NA); ++sl) {
+        int o[3], a = 0;
+        bool hit = mine;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const int sd = centres ? (sl / (d == 0 ? 1 : (d == 1 ? 3 : 9))) % 3 : (sl >> d) & 1;
+          // the lane's stencil corner that lands on this slot
+          const int ad = centres ? sd - h[d] : sd;
+          if (d < DIM) {
+            hit = hit && ad >= 0 && ad <= 1;
+            a += (ad & 1) << d;
+          }
+          o[d] = centres ? sd - 1 : sd;
+        }
+        const double w = hit ? S.wt[a] : 0.0;
+        const double t0 = wave_sum(w * v[0]), t1 = wave_sum(w * v[1]), t2 = wave_sum(w * v[2]);
+        if (lane == leader) {
+          const int id = grid_index<DIM>(kp, li, lj, lk, o[0], o[1], o[2]);
+          atomicAdd(&g[id], t0);
+          atomicAdd(&g[N + id], t1);
+          atomicAdd(&g[2 * N + id], t2);
+        }
+      }
+    } else if (mine) {
+#pragma unroll
+      for (int a = 0; a < NA; ++a) atomic_add3(g, N, S.idx[a], S.wt[a], v);
+    }
+    pending = pending && !mine;
+    todo = __ballot(pending);
+  }
+}
+
 struct AdjIn {
   const int32_t *bin_start, *cell;
   const double *xy, *uw, *z;  // packed (off_x, off_y), (u_x, u_y, u_z, w); off_z
@@ -176,10 +253,14 @@ __global__ __launch_bounds__(256) void k_push_adjoint(KParams kp, AdjIn in, int 
                                                       const double *__restrict__ lx_in, const double *__restrict__ lu_in,
                                                       double *__restrict__ lx_out, double *__restrict__ lu_out,
                                                       double *__restrict__ lEth, double *__restrict__ lB) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= n) return;
+  // every lane stays to the end (the grid sums are wave-wide); lanes past
+  // the particles compute on the last one and add nothing
+  const int p0 = blockIdx.x * 256 + threadIdx.x;
+  const bool act = p0 < n;
+  const int p = act ? p0 : n - 1;
   const size_t N = (size_t)kp.ncells;
   const PState st = load_particle<DIM>(kp, in.bin_start, in.cell, in.xy, in.uw, in.z, p);
+  const int cell = in.cell[p];
   const double c2 = kp.c * kp.c;
   Stencil<DIM> sc, sn;
   stencil<DIM>(kp, st, true, sc);
@@ -240,11 +321,11 @@ __global__ __launch_bounds__(256) void k_push_adjoint(KParams kp, AdjIn in, int 
 #pragma unroll
   for (int a2 = 0; a2 < (1 << DIM); ++a2) {
     const int id = sn.idx[a2];
-    atomic_add3(lEth, N, id, sn.wt[a2], lEp);
     const double e = Eth[id] * lEp[0] + Eth[N + id] * lEp[1] + Eth[2 * N + id] * lEp[2];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) lx[d] += sn.grad[a2][d] * e;
   }
+  add_stencil<DIM>(kp, lEth, act, cell, st.ci, st.cj, st.ck, sn, false, st.f, lEp);
   // alpha(b(B_p, gbar))
   double lb[3];
   alpha_vjp(b, a, la, lb);
@@ -257,15 +338,17 @@ __global__ __launch_bounds__(256) void k_push_adjoint(KParams kp, AdjIn in, int 
 #pragma unroll
   for (int a2 = 0; a2 < (1 << DIM); ++a2) {
     const int id = sc.idx[a2];
-    atomic_add3(lB, N, id, sc.wt[a2], lBp);
     const double e = B[id] * lBp[0] + B[N + id] * lBp[1] + B[2 * N + id] * lBp[2];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) lx[d] += sc.grad[a2][d] * e;
   }
+  add_stencil<DIM>(kp, lB, act, cell, st.ci, st.cj, st.ck, sc, true, st.f, lBp);
+  if (act) {
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) lx_out[(size_t)d * n + p] = lx[d];
+    for (int d = 0; d < DIM; ++d) lx_out[(size_t)d * n + p] = lx[d];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) lu_out[(size_t)k * n + p] = lu[k];
+    for (int k = 0; k < 3; ++k) lu_out[(size_t)k * n + p] = lu[k];
+  }
 }
 
 template <int DIM>
@@ -273,10 +356,12 @@ __global__ __launch_bounds__(256) void k_deposit_adjoint(KParams kp, AdjIn in, i
                                                          const double *__restrict__ Eth, const double *__restrict__ mu,
                                                          double *__restrict__ lx_out, double *__restrict__ lu_out,
                                                          double *__restrict__ lB) {
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p >= n) return;
+  const int p0 = blockIdx.x * 256 + threadIdx.x;
+  const bool act = p0 < n;
+  const int p = act ? p0 : n - 1;
   const size_t N = (size_t)kp.ncells;
   const PState st = load_particle<DIM>(kp, in.bin_start, in.cell, in.xy, in.uw, in.z, p);
+  const int cell = in.cell[p];
   const double c2 = kp.c * kp.c;
   Stencil<DIM> sc, sn;
   stencil<DIM>(kp, st, true, sc);
@@ -336,15 +421,17 @@ __global__ __launch_bounds__(256) void k_deposit_adjoint(KParams kp, AdjIn in, i
 #pragma unroll
   for (int a2 = 0; a2 < (1 << DIM); ++a2) {
     const int id = sc.idx[a2];
-    atomic_add3(lB, N, id, sc.wt[a2], lBp);
     const double e = B[id] * lBp[0] + B[N + id] * lBp[1] + B[2 * N + id] * lBp[2];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) lx[d] += sc.grad[a2][d] * e;
   }
+  add_stencil<DIM>(kp, lB, act, cell, st.ci, st.cj, st.ck, sc, true, st.f, lBp);
+  if (act) {
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) lx_out[(size_t)d * n + p] += lx[d];
+    for (int d = 0; d < DIM; ++d) lx_out[(size_t)d * n + p] += lx[d];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) lu_out[(size_t)k * n + p] += lu[k];
+    for (int k = 0; k < 3; ++k) lu_out[(size_t)k * n + p] += lu[k];
+  }
 }
 
 // rhs of the transposed solve: l_th + l_E1/theta - c dt C_CN l_B1  (curl precomputed in t)
