@@ -570,6 +570,58 @@ def workload_label(wl, n, rtol):
                               rtol)
 
 
+def run_adjoint(steps, rtol=1e-14):
+    """The adjoint of `steps` FP64 steps of the 256 x 128 double Harris sheet
+    (32 particles per cell per species, 2,097,152 particles): the gradient of
+    the field energy after the steps with respect to the initial E and B
+    (autograd.field_energy_after, per-step checkpoints), timed against the
+    same steps run forward without gradients.  Returns ms per step."""
+    import numpy as np
+    import torch
+
+    from paper_2509_11100_amd import autograd, harris, relsim
+
+    wl = harris.workload("harris2d_256x128")
+    p = harris.make_particles(wl)
+    E0, Bh = harris.make_fields(wl, eps=0.0)
+    n = p["w"].shape[0]
+    ctx = relsim.Context(dim=2, nx=wl.nx, ny=wl.ny, dx=wl.dx, dy=wl.dx, dt=wl.dt, precision="fp64", q=wl.q, m=wl.m,
+                         max_particles=n, gmres_rtol=rtol)
+    parts = relsim.Particles(ctx).load(p["cell"], p["species"], p["off"], p["u"], p["w"], p["bin_start"])
+    st = autograd.Stepper(ctx)
+    base = [t.clone() for t in (parts.cell, parts.bin_start, parts.w)]
+    off0 = torch.stack([t.clone() for t in parts.off])
+    u0 = torch.stack([t.clone() for t in parts.u])
+
+    def dev(a):
+        return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+    E = dev(E0)
+    B = dev(Bh) + wl.eps * dev(harris.seed_direction(wl))
+    out = None
+    for rep in range(2):  # the first pass warms up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.no_grad():
+            off, u, Ee, Bb, c, b, w = off0, u0, E, B, *base
+            for _ in range(steps):
+                off, u, Ee, Bb, c, b, w = autograd.StepFn.apply(st, off, u, Ee, Bb, c, b, w)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Eg = E.clone().requires_grad_(True)
+        Bg = B.clone().requires_grad_(True)
+        F = autograd.field_energy_after(st, off0, u0, Eg, Bg, *base, steps)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        F.backward()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        out = {"particles": n, "steps": steps, "forward_ms_per_step": 1e3 * (t1 - t0) / steps,
+               "checkpointed_forward_ms_per_step": 1e3 * (t2 - t1) / steps,
+               "backward_ms_per_step": 1e3 * (t3 - t2) / steps, "grad_B_norm": float(Bg.grad.norm())}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -589,10 +641,26 @@ def main():
                     help="also time the energy-conserving step (reported beside the headline, not in it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration)")
+    ap.add_argument("--adjoint", type=int, default=0, metavar="K",
+                    help="instead of the step, time the adjoint of K FP64 steps of the 256 x 128 sheet")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU; the multi-GPU path is not built. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.adjoint > 0:
+        import torch
+
+        from paper_2509_11100_amd import _lib
+
+        _lib.load()
+        torch.cuda.set_device(0)
+        res = run_adjoint(args.adjoint)
+        log("adjoint of %d steps: forward %.2f ms/step, backward %.2f ms/step" % (
+            args.adjoint, res["forward_ms_per_step"], res["backward_ms_per_step"]))
+        print(json.dumps({"metric": "adjoint ms per step (gradient of the field energy after K steps)",
+                          "config": {"workload": "harris2d_256x128, 2D double Harris sheet 256x128 cells, "
+                                                 "32 particles/cell/species, FP64"}, **res}), flush=True)
+        return
 
     import torch
 

@@ -464,6 +464,10 @@ int relsim_init(const relsim_params *p, void *hip_stream, void *workspace, size_
   if (!workspace || workspace_bytes < L.end) return RELSIM_EINVAL;
   relsim_ctx *c = new (std::nothrow) relsim_ctx();
   if (!c) return RELSIM_EINVAL;
+  // an error that earlier calls of other code left pending in this thread
+  // (HIP keeps the last one until it is read) is not this call's: clear it
+  // before the check at the end
+  (void)hipGetLastError();
   c->p = *p;
   if (c->p.dim == 2) c->p.nz = 1;
   c->kp = make_kparams(&c->p);
