@@ -135,7 +135,7 @@ def measured_valu(tag, kernel):
     return js["kernels"].get(KERNEL_SYMBOL.get(kernel, kernel))
 
 
-def run_energy_conserving(prec, wl, host, steps, warmup, rtol, group=0):
+def run_energy_conserving(prec, wl, host, steps, warmup, rtol, group=0, secant=False):
     """Whole energy-conserving steps (relsim.Step(energy_conserving=True):
     fixed-point passes of deposit, solve and relsim_gamma_mean, then the
     push) on the same workload: wall time per step, passes per step and the
@@ -152,7 +152,7 @@ def run_energy_conserving(prec, wl, host, steps, warmup, rtol, group=0):
     parts = relsim.Particles(ctx).load(host["cell"], host["species"], host["off"], host["u"], host["w"],
                                        host["bin_start"])
     step = relsim.Step(ctx, parts, torch.as_tensor(host["E"]).cuda(), torch.as_tensor(host["B"]).cuda(),
-                       energy_conserving=True)
+                       energy_conserving=True, secant=secant)
     step(warmup)
     W0 = step.energy()
     passes = []
@@ -167,7 +167,8 @@ def run_energy_conserving(prec, wl, host, steps, warmup, rtol, group=0):
     del step, parts, ctx
     torch.cuda.empty_cache()
     return {"precision": prec, "particle_steps_per_s": n * steps / wall, "ms_per_step": 1e3 * wall / steps,
-            "picard_tol": 1e-12 if prec == "fp64" else 1e-6, "passes_per_step": float(np.mean(passes)),
+            "picard_tol": 1e-12 if prec == "fp64" else 1e-6, "fixed_point": "secant" if secant else "plain",
+            "passes_per_step": float(np.mean(passes)),
             "rel_energy_change": float(abs(W1[3] - W0[3]) / W0[3])}
 
 
@@ -639,6 +640,8 @@ def main():
                     help="skip the oracle leg (its timings and the errors against it)")
     ap.add_argument("--energy-conserving", action="store_true",
                     help="also time the energy-conserving step (reported beside the headline, not in it)")
+    ap.add_argument("--secant", action="store_true",
+                    help="the energy-conserving step's fixed point with per-particle secant steps")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration)")
     ap.add_argument("--adjoint", type=int, default=0, metavar="K",
@@ -696,7 +699,8 @@ def main():
         ec = {}
         for p in precs:
             log("running the energy-conserving step, %s" % p)
-            ec[p] = run_energy_conserving(p, wl, host, args.steps, args.warmup, args.rtol, group=args.group)
+            ec[p] = run_energy_conserving(p, wl, host, args.steps, args.warmup, args.rtol, group=args.group,
+                                          secant=args.secant)
             log("%s energy-conserving: %.3f ms/step, %.1f passes/step, |dW|/W %.2e" % (
                 p, ec[p]["ms_per_step"], ec[p]["passes_per_step"], ec[p]["rel_energy_change"]))
 
