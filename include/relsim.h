@@ -196,6 +196,24 @@ int relsim_push(relsim_ctx *ctx, relsim_particles *part, const double *E_theta, 
  * means gamma(u^n), which makes the first two calls the standard ones.  In the
  * non-relativistic limit gbar is ignored (gamma = 1). */
 
+/* Optional acceleration of that fixed point (the plain update above is the
+ * default): after relsim_gamma_mean(gbar -> gbar_next), with each particle's
+ * residual r = gbar_next - gbar of this pass and of the last (kept in g_prev,
+ * r_prev), gbar_next[p] becomes gbar - r (gbar - g_prev) / (r - r_prev), the
+ * root of the line through the particle's last two residuals, where that
+ * line falls with a slope in [-10, -0.1] and the step is measurable (|gbar -
+ * g_prev| > 1e-12 gbar); elsewhere it stays the plain update.  The result is
+ * kept >= 1 (a NaN passes through).  Each particle's gbar is nearly its own
+ * scalar fixed point, which the field couples only weakly, so a secant per
+ * particle follows each one's contraction rate.  The fixed point, the
+ * stopping test and the final relsim_push_ec are unchanged.
+ * gbar, gbar_next: n elements of the particle type T (as relsim_gamma_mean);
+ * g_prev, r_prev: FP64 device arrays of n elements owned by the caller,
+ * written on every call; first != 0 (a step's first pass) only records them.
+ * n <= max_particles.  Asynchronous. */
+int relsim_gamma_secant(relsim_ctx *ctx, int64_t n, const void *gbar, void *gbar_next, double *g_prev, double *r_prev,
+                        int first);
+
 /* relsim_deposit_moments with gbar in place of gamma(u^n). */
 int relsim_deposit_moments_ec(relsim_ctx *ctx, const relsim_particles *part, const double *B_n, const void *gbar,
                               double *Jhat, double *M);

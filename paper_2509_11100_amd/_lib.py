@@ -79,6 +79,7 @@ def load() -> C.CDLL:
         "relsim_push": (C.c_int, [vp, pt, vp, vp, i32, vp]),
         "relsim_deposit_moments_ec": (C.c_int, [vp, pt, vp, vp, vp, vp]),
         "relsim_gamma_mean": (C.c_int, [vp, pt, vp, vp, vp, vp, dp]),
+        "relsim_gamma_secant": (C.c_int, [vp, C.c_int64, vp, vp, vp, vp, C.c_int]),
         "relsim_push_ec": (C.c_int, [vp, pt, vp, vp, vp, i32, vp]),
         "relsim_apply_AT": (C.c_int, [vp, vp, vp, vp]),
         "relsim_push_adjoint": (C.c_int, [vp, pt, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
@@ -113,6 +114,6 @@ def exported_symbols():
         "relsim_field_solve", "relsim_field_solve_guess", "relsim_push", "relsim_fill_cells", "relsim_energy", "relsim_curl_nc", "relsim_curl_cn",
         "relsim_apply_A", "relsim_apply_AT", "relsim_push_adjoint", "relsim_field_solve_adjoint",
         "relsim_deposit_adjoint", "relsim_timing_enable", "relsim_timing_reset", "relsim_timing_read",
-        "relsim_strerror", "relsim_last_error", "relsim_deposit_moments_ec", "relsim_gamma_mean", "relsim_push_ec",
+        "relsim_strerror", "relsim_last_error", "relsim_deposit_moments_ec", "relsim_gamma_mean", "relsim_gamma_secant", "relsim_push_ec",
         "relsim_placement_clamps", "relsim_energy_noalloc", "relsim_energy_pushed",
     ]

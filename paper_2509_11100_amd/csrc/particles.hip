@@ -1675,6 +1675,39 @@ void launch_gamma_mean(const KParams &kp, int prec, int cells, const PartPtrs &p
            : gamma_mean_impl<double, 2>(kp, cells, pp, Est, Bst, err, sink, gbar_next, chg, st);
 }
 
+namespace {
+// Per-particle secant step of the energy-conserving fixed point (FP64
+// residuals and slopes whatever T); see relsim_gamma_secant.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gamma_secant(int n, const T *__restrict__ g, T *__restrict__ Fg,
+                                                      double *__restrict__ gp, double *__restrict__ rp, int first) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double gd = (double)g[i];
+  const double r = (double)Fg[i] - gd;
+  if (!first) {
+    const double dg = gd - gp[i];
+    const double slope = (r - rp[i]) / (dg == 0.0 ? 1.0 : dg);
+    const bool use = fabs(dg) > 1e-12 * gd && slope <= -0.1 && slope >= -10.0;
+    const double nxt = use ? gd - r / slope : gd + r;
+    Fg[i] = (T)(nxt < 1.0 ? 1.0 : nxt);  // a NaN passes through (and fails the caller's test)
+  }
+  gp[i] = gd;
+  rp[i] = r;
+}
+}  // namespace
+
+void launch_gamma_secant(int prec, int n, const void *g, void *Fg, double *gp, double *rp, int first, hipStream_t st) {
+  if (n <= 0) return;
+  const int nb = (n + 255) / 256;
+  if (prec == RELSIM_MIXED)
+    hipLaunchKernelGGL(k_gamma_secant<float>, dim3(nb), dim3(256), 0, st, n, cp<float>(g), mp<float>(Fg), gp, rp,
+                       first);
+  else
+    hipLaunchKernelGGL(k_gamma_secant<double>, dim3(nb), dim3(256), 0, st, n, cp<double>(g), mp<double>(Fg), gp, rp,
+                       first);
+}
+
 void launch_sort_offsets(const KParams &kp, const uint16_t *cnt, uint16_t *pre, int32_t *total, int32_t *err,
                          hipStream_t st) {
   const int nblk = (kp.nbins + 255) / 256;

@@ -499,32 +499,45 @@ class _AndersonMix:
 
 
 class _SecantMix:
-    """Per-particle secant steps for the fixed point g = F(g): with the
-    residual r = F(g) - g of this pass and the last, each particle's next
-    input is g - r (g - g_prev) / (r - r_prev), the root of the line through
-    its last two residuals, where that line falls with a slope in [-10,
-    -0.1] (an estimated contraction dF/dg in [-9, 0.9]); elsewhere (first
-    pass, a flat or rising residual, a step too small to measure) the plain
-    update F(g).  Each particle's gbar is nearly its own scalar fixed point
-    (the field couples them weakly), so a per-particle secant follows each
-    one's own contraction rate.  The fixed point, the stopping test and the
-    final push are those of the plain iteration."""
+    """Per-particle secant steps for the fixed point g = F(g) through
+    relsim_gamma_secant: with the residual r = F(g) - g of this pass and the
+    last, each particle's next input is g - r (g - g_prev) / (r - r_prev),
+    the root of the line through its last two residuals, where that line
+    falls with a slope in [-10, -0.1] (an estimated contraction dF/dg in [-9,
+    0.9]); elsewhere (first pass, a flat or rising residual, a step too small
+    to measure) the plain update F(g).  Each particle's gbar is nearly its own
+    scalar fixed point (the field couples them weakly), so a per-particle
+    secant follows each one's own contraction rate.  The fixed point, the
+    stopping test and the final push are those of the plain iteration."""
 
-    def __init__(self):
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
         self.g_prev = self.r_prev = None
 
     def __call__(self, g: torch.Tensor, Fg: torch.Tensor) -> None:
         """g: the pass's input, Fg: its output; Fg is overwritten with the
         next input."""
-        gd = g.to(torch.float64, copy=True)
-        r = Fg.double() - gd
-        if self.g_prev is not None:
-            dg = gd - self.g_prev
-            slope = (r - self.r_prev) / torch.where(dg == 0, torch.ones_like(dg), dg)
-            use = (dg.abs() > 1e-12 * gd) & (slope <= -0.1) & (slope >= -10.0)
-            nxt = torch.where(use, gd - r / torch.where(use, slope, -torch.ones_like(slope)), gd + r)
-            Fg.copy_(torch.clamp(nxt, min=1.0).to(Fg.dtype))
-        self.g_prev, self.r_prev = gd, r
+        first = self.g_prev is None
+        if first:
+            self.g_prev = torch.empty(g.numel(), dtype=torch.float64, device=g.device)
+            self.r_prev = torch.empty_like(self.g_prev)
+        gamma_secant(self.ctx, g, Fg, self.g_prev, self.r_prev, first)
+
+
+def gamma_secant(ctx: Context, gbar: torch.Tensor, gbar_next: torch.Tensor, g_prev: torch.Tensor,
+                 r_prev: torch.Tensor, first: bool) -> None:
+    """relsim_gamma_secant: gbar_next (the plain update F(gbar)) is replaced
+    by the per-particle secant step; g_prev, r_prev (FP64, n elements) carry
+    the last pass's input and residual; first only records them."""
+    n = gbar.numel()
+    for t in (gbar, gbar_next):
+        if t.device != ctx.device or t.dtype != ctx.dtype or not t.is_contiguous() or t.numel() < n:
+            raise ValueError("gbar arrays must be contiguous tensors of the particle type")
+    for t in (g_prev, r_prev):
+        if t.device != ctx.device or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() < n:
+            raise ValueError("g_prev and r_prev must be contiguous float64 tensors of at least n elements")
+    ctx.check(ctx.lib.relsim_gamma_secant(ctx.handle, C.c_int64(n), _ptr(gbar), _ptr(gbar_next), _ptr(g_prev),
+                                          _ptr(r_prev), 1 if first else 0))
 
 
 class PicardNotConverged(RuntimeError):
@@ -620,7 +633,7 @@ class Step:
                 if self.anderson > 0:
                     mix = _AndersonMix(self.anderson)
                 elif self.secant:
-                    mix = _SecantMix()
+                    mix = _SecantMix(self.ctx)
                 for it in range(1, self.picard_maxit + 1):
                     # after the first pass GMRES starts from the last pass's E_theta
                     self._solve(gbar, guess=self.warm_start and it > 1)

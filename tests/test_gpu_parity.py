@@ -659,6 +659,69 @@ def test_energy_conserving_passes(gname, precision):
     check_disp(periodic_diff(g, s1["x"][:, new], xr), disp, TOL[precision])
 
 
+def secant_reference(g, Fg, gp, rp):
+    """The per-particle secant step written out in FP64 (numpy): the root of
+    the line through the last two residuals r = F(g) - g where its slope lies
+    in [-10, -0.1] and the step is measurable, else the plain update; the
+    result is clamped to gamma >= 1."""
+    gd = g.astype(np.float64)
+    r = Fg.astype(np.float64) - gd
+    dg = gd - gp
+    with np.errstate(divide="ignore", invalid="ignore"):
+        slope = (r - rp) / np.where(dg == 0.0, 1.0, dg)
+        use = (np.abs(dg) > 1e-12 * gd) & (slope <= -0.1) & (slope >= -10.0)
+        nxt = np.where(use, gd - r / np.where(use, slope, 1.0), gd + r)
+    return np.where(nxt < 1.0, 1.0, nxt), gd, r
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gamma_secant_matches_its_definition(precision):
+    """relsim_gamma_secant on 1,000,003 particles (a ragged tail) over two
+    passes: the first only records g and r; the second takes the secant step
+    where the slope is in range and the plain update elsewhere (equal inputs,
+    slopes outside [-10, -0.1] and on both ends of it, steps below 1 clamped).
+    The branch is decided in FP64 on both sides."""
+    need_gpu()
+    import torch
+
+    from paper_2509_11100_amd import relsim
+
+    n = 1_000_003
+    g = grids()["2d_7x5"]
+    ctx = make_ctx(g, precision, n)
+    dt = np.float64 if precision == "fp64" else np.float32
+    rng = np.random.default_rng(31)
+    g0 = (1 + 3 * rng.random(n)).astype(dt)
+    F0 = (g0 + 0.1 * (2 * rng.random(n) - 1)).astype(dt)
+    # second pass: a chosen slope (F1 - g1) - (F0 - g0) = s (g1 - g0)
+    g1 = F0.copy()
+    s = rng.choice([-0.05, -0.1, -0.5, -9.0, -10.0, -20.0, 0.3], n)
+    r0 = F0.astype(np.float64) - g0
+    F1 = (g1 + r0 + s * (g1.astype(np.float64) - g0)).astype(dt)
+    g1[:1000] = g0[:1000]                      # no step: plain update
+    F1[1000:2000] = 0.5                        # clamped to 1 where the plain update falls below
+    dev = lambda a: torch.as_tensor(a).cuda()
+    gp = torch.empty(n, dtype=torch.float64, device="cuda")
+    rp = torch.empty_like(gp)
+    Fd = dev(F0.copy())
+    relsim.gamma_secant(ctx, dev(g0), Fd, gp, rp, True)
+    np.testing.assert_array_equal(Fd.cpu().numpy(), F0)
+    np.testing.assert_array_equal(gp.cpu().numpy(), g0.astype(np.float64))
+    np.testing.assert_array_equal(rp.cpu().numpy(), r0)
+    Fd = dev(F1.copy())
+    relsim.gamma_secant(ctx, dev(g1), Fd, gp, rp, False)
+    ref, gref, rref = secant_reference(g1, F1, g0.astype(np.float64), r0)
+    got = Fd.cpu().numpy()
+    np.testing.assert_allclose(got, ref.astype(dt), rtol=1e-15 if precision == "fp64" else 1.2e-7, atol=0)
+    np.testing.assert_array_equal(gp.cpu().numpy(), gref)
+    np.testing.assert_array_equal(rp.cpu().numpy(), rref)
+    # every branch was taken
+    with np.errstate(divide="ignore", invalid="ignore"):
+        slope = (rref - r0) / (gref - g0)
+    took = (np.abs(gref - g0) > 1e-12 * gref) & (slope <= -0.1) & (slope >= -10.0)
+    assert took.sum() > n // 3 and (~took).sum() > n // 3 and (got == 1.0).sum() >= 500
+
+
 @pytest.mark.parametrize("anderson,secant", [(0, False), (3, False), (0, True)])
 def test_energy_conserving_steps_match_oracle_and_conserve_energy(anderson, secant):
     """Three energy-conserving FP64 steps of the 64 x 32 pair sheet (sheet
