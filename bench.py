@@ -58,10 +58,10 @@ def kernel_bytes(name, wl, prec, n, nbins, ncells):
         nmom = 93 if d == 2 else 267
         return n * (d + 4) * T + ncells * grid + ncells * nmom * T
     if name == "assemble_nodes":
-        # in: per-cell moments; out: J-hat and the stored half of M at nodes
-        # (FP64; 5 of the 9 node-pair blocks in 2D, 14 of 27 in 3D)
+        # in: per-cell moments; out: J-hat (FP64) and the stored half of M
+        # at nodes (type T; 5 of the 9 node-pair blocks in 2D, 14 of 27 in 3D)
         nmom = 93 if d == 2 else 267
-        return ncells * nmom * T + ncells * (grid + 8 * 9 * (noff // 2 + 1))
+        return ncells * nmom * T + ncells * (grid + T * 9 * (noff // 2 + 1))
     if name == "push_count":
         # first pass of push + re-sort: in: offsets + (momentum, weight)
         # records, E_theta, B^n; out: 1-byte move code (+ per-bin counts)

@@ -21,7 +21,10 @@
  *     E, Jhat and M live at nodes (i,j,k)*dx, B at cell centres
  *     (i+1/2, j+1/2, k+1/2)*dx.  Node and cell (i,j,k) share the linear index
  *     i + nx*(j + ny*k); N = nx*ny*nz (nz = 1 in 2D, where d/dz = 0).
- *   - Grid arrays are FP64, component-major: E, B, Jhat [3][N].
+ *   - Grid arrays are FP64, component-major: E, B, Jhat [3][N]; M is of
+ *     the particle type T (FP32 in mixed precision, FP64 otherwise: it is
+ *     summed in FP64 from per-cell moments of type T, whose rounding it
+ *     already carries; the S4 products and sums with it are FP64).
  *     M holds the node-pair blocks M_{g,g+delta} for the 9 (2D) or 27 (3D)
  *     offsets delta in {-1,0,1}^dim, numbered o = sum_d (delta_d + 1) 3^d (x
  *     fastest).  The block is symmetric in the pair, M_{g,g'} = M_{g',g}
@@ -137,9 +140,10 @@ int relsim_sort(relsim_ctx *ctx, relsim_particles *part);
 
 /* a2-a4 (S1-S3): gather B^n, form alpha per particle and deposit Jhat [3][N]
  * and M [m_slots][9][N] (the stored half of the node-pair blocks, see
- * Conventions; both overwritten, FP64).  Particles must be bin-sorted. */
+ * Conventions; both overwritten; Jhat FP64, M of type T and aligned to it).
+ * Particles must be bin-sorted. */
 int relsim_deposit_moments(relsim_ctx *ctx, const relsim_particles *part, const double *B_n, double *Jhat,
-                           double *M);
+                           void *M);
 
 /* a5 (S4-S5): restarted GMRES for E_th from the initial guess E^n, then the
  * field update.  E_theta, E_np1, B_np1 are written.  iters / rel_resid (host
@@ -147,7 +151,7 @@ int relsim_deposit_moments(relsim_ctx *ctx, const relsim_particles *part, const 
  * relative residual.  Synchronous (one small device-to-host copy per Arnoldi
  * step).  Returns RELSIM_ENOTCONVERGED with the last iterate written when
  * gmres_maxit is reached. */
-int relsim_field_solve(relsim_ctx *ctx, const double *M, const double *Jhat, const double *E_n, const double *B_n,
+int relsim_field_solve(relsim_ctx *ctx, const void *M, const double *Jhat, const double *E_n, const double *B_n,
                        double *E_theta, double *E_np1, double *B_np1, int32_t *iters, double *rel_resid);
 
 /* a5 (S4-S5) from a caller's initial guess: as relsim_field_solve, with
@@ -157,7 +161,7 @@ int relsim_field_solve(relsim_ctx *ctx, const double *M, const double *Jhat, con
  * variant below): started from the previous pass's E_th, GMRES needs fewer
  * Arnoldi steps to the same relative tolerance.  The stopping rule and
  * everything else are relsim_field_solve's. */
-int relsim_field_solve_guess(relsim_ctx *ctx, const double *M, const double *Jhat, const double *E_n,
+int relsim_field_solve_guess(relsim_ctx *ctx, const void *M, const double *Jhat, const double *E_n,
                              const double *B_n, double *E_theta, double *E_np1, double *B_np1, int32_t *iters,
                              double *rel_resid);
 
@@ -216,7 +220,7 @@ int relsim_gamma_secant(relsim_ctx *ctx, int64_t n, const void *gbar, void *gbar
 
 /* relsim_deposit_moments with gbar in place of gamma(u^n). */
 int relsim_deposit_moments_ec(relsim_ctx *ctx, const relsim_particles *part, const double *B_n, const void *gbar,
-                              double *Jhat, double *M);
+                              double *Jhat, void *M);
 
 /* One fixed-point pass: pushes every particle as relsim_push would with
  * gbar (state untouched), writes gbar_next[p] = (gamma(u^n_p) +
@@ -285,11 +289,11 @@ int relsim_energy_noalloc(const relsim_params *p, void *hip_stream, const relsim
  * operator A applied to x. */
 int relsim_curl_nc(relsim_ctx *ctx, const double *in, double *out);
 int relsim_curl_cn(relsim_ctx *ctx, const double *in, double *out);
-int relsim_apply_A(relsim_ctx *ctx, const double *M, const double *x, double *out);
+int relsim_apply_A(relsim_ctx *ctx, const void *M, const double *x, double *out);
 
 /* out = A^T x, the transposed S4 operator (each block of M transposed; the
  * curl-curl term is symmetric). */
-int relsim_apply_AT(relsim_ctx *ctx, const double *M, const double *x, double *out);
+int relsim_apply_AT(relsim_ctx *ctx, const void *M, const double *x, double *out);
 
 /* a8: reverse-mode adjoint of one step, RELSIM_FP64 contexts only.  All
  * cotangent arrays are FP64 device arrays: particle ones [dim][n] for
@@ -317,7 +321,7 @@ int relsim_push_adjoint(relsim_ctx *ctx, const relsim_particles *state_n, const 
  * -(1-theta)/theta lam_E_np1 + mu into lam_E_n and lam_B_np1 +
  * c theta dt C_CN^T mu into lam_B_n.  M is the step's mass matrix.
  * Synchronous; RELSIM_ENOTCONVERGED as for relsim_field_solve. */
-int relsim_field_solve_adjoint(relsim_ctx *ctx, const double *M, const double *lam_E_theta, const double *lam_E_np1,
+int relsim_field_solve_adjoint(relsim_ctx *ctx, const void *M, const double *lam_E_theta, const double *lam_E_np1,
                                const double *lam_B_np1, double *mu, double *lam_E_n, double *lam_B_n, int32_t *iters,
                                double *rel_resid);
 

@@ -418,17 +418,17 @@ int fetch(relsim_ctx *c, const double *dev, int k) {
 }
 
 // out = A x   (uses gm_t as the curl scratch)
-void apply_A(relsim_ctx *c, const double *M, const double *x, double *out) {
+void apply_A(relsim_ctx *c, const void *M, const double *x, double *out) {
   double *t = c->at<double>(c->L.gm_t);
   timed(c, "curl_nc", [&] { launch_curl(c->kp, x, t, 1, c->st); });
-  timed(c, "apply_A", [&] { launch_apply_A_tail(c->kp, M, x, t, out, c->st); });
+  timed(c, "apply_A", [&] { launch_apply_A_tail(c->kp, c->p.precision, M, x, t, out, c->st); });
 }
 
 // out = A^T x
-void apply_AT(relsim_ctx *c, const double *M, const double *x, double *out) {
+void apply_AT(relsim_ctx *c, const void *M, const double *x, double *out) {
   double *t = c->at<double>(c->L.gm_t);
   timed(c, "curl_nc", [&] { launch_curl(c->kp, x, t, 1, c->st); });
-  timed(c, "apply_AT", [&] { launch_apply_AT_tail(c->kp, M, x, t, out, c->st); });
+  timed(c, "apply_AT", [&] { launch_apply_AT_tail(c->kp, c->p.precision, M, x, t, out, c->st); });
 }
 
 int norm2(relsim_ctx *c, const double *x, size_t n, double *out) {
@@ -531,16 +531,18 @@ int relsim_sort(relsim_ctx *c, relsim_particles *pt) {
   return RELSIM_OK;
 }
 
-int relsim_deposit_moments(relsim_ctx *c, const relsim_particles *pt, const double *B_n, double *Jhat, double *M) {
+int relsim_deposit_moments(relsim_ctx *c, const relsim_particles *pt, const double *B_n, double *Jhat, void *M) {
   return relsim_deposit_moments_ec(c, pt, B_n, nullptr, Jhat, M);
 }
 
 int relsim_deposit_moments_ec(relsim_ctx *c, const relsim_particles *pt, const double *B_n, const void *gbar,
-                              double *Jhat, double *M) {
+                              double *Jhat, void *M) {
   if (!c) return RELSIM_EINVAL;
   int rc = check_particles(c, pt, false);
   if (rc) return rc;
   if (!B_n || !Jhat || !M) return fail(c, RELSIM_EINVAL, "null grid array");
+  if (!aligned(M, c->p.precision == RELSIM_MIXED ? 4 : 8))
+    return fail(c, RELSIM_EINVAL, "M not aligned to its element size");
   if (gbar && !aligned(gbar, c->p.precision == RELSIM_MIXED ? 4 : 8))
     return fail(c, RELSIM_EINVAL, "gbar not aligned to its element size");
   const int G = choose_group(c, pt->n, K_DEPOSIT);
@@ -740,7 +742,7 @@ int relsim_curl_cn(relsim_ctx *c, const double *in, double *out) {
   return launch_status(c, "relsim_curl_cn");
 }
 
-int relsim_apply_A(relsim_ctx *c, const double *M, const double *x, double *out) {
+int relsim_apply_A(relsim_ctx *c, const void *M, const double *x, double *out) {
   if (!c || !M || !x || !out) return RELSIM_EINVAL;
   if (x == out) return fail(c, RELSIM_EINVAL, "relsim_apply_A cannot work in place");
   apply_A(c, M, x, out);
@@ -752,7 +754,7 @@ int relsim_apply_A(relsim_ctx *c, const double *M, const double *x, double *out)
 // Restarted GMRES for A x = b (or A^T x = b) from the initial guess in x.
 // b must live in the workspace slot gm_b.  Returns RELSIM_OK, or
 // RELSIM_ENOTCONVERGED with the last iterate in x.
-static int gmres_solve(relsim_ctx *c, const double *M, bool transpose, double *x, int32_t *iters, double *rel_resid) {
+static int gmres_solve(relsim_ctx *c, const void *M, bool transpose, double *x, int32_t *iters, double *rel_resid) {
   const size_t n3 = 3 * (size_t)c->kp.ncells;
   const int m = c->p.gmres_restart;
   double *V = c->at<double>(c->L.gm_V);
@@ -871,7 +873,7 @@ extern "C" {
 }  // extern "C"
 
 // S4-S5 from E^n (guess == false) or from E_theta's contents (guess == true).
-static int field_solve(relsim_ctx *c, const double *M, const double *Jhat, const double *E_n, const double *B_n,
+static int field_solve(relsim_ctx *c, const void *M, const double *Jhat, const double *E_n, const double *B_n,
                        double *E_theta, double *E_np1, double *B_np1, int32_t *iters, double *rel_resid,
                        bool guess) {
   if (!c) return RELSIM_EINVAL;
@@ -893,18 +895,18 @@ static int field_solve(relsim_ctx *c, const double *M, const double *Jhat, const
 
 extern "C" {
 
-int relsim_field_solve(relsim_ctx *c, const double *M, const double *Jhat, const double *E_n, const double *B_n,
+int relsim_field_solve(relsim_ctx *c, const void *M, const double *Jhat, const double *E_n, const double *B_n,
                        double *E_theta, double *E_np1, double *B_np1, int32_t *iters, double *rel_resid) {
   return field_solve(c, M, Jhat, E_n, B_n, E_theta, E_np1, B_np1, iters, rel_resid, false);
 }
 
-int relsim_field_solve_guess(relsim_ctx *c, const double *M, const double *Jhat, const double *E_n,
+int relsim_field_solve_guess(relsim_ctx *c, const void *M, const double *Jhat, const double *E_n,
                              const double *B_n, double *E_theta, double *E_np1, double *B_np1, int32_t *iters,
                              double *rel_resid) {
   return field_solve(c, M, Jhat, E_n, B_n, E_theta, E_np1, B_np1, iters, rel_resid, true);
 }
 
-int relsim_apply_AT(relsim_ctx *c, const double *M, const double *x, double *out) {
+int relsim_apply_AT(relsim_ctx *c, const void *M, const double *x, double *out) {
   if (!c || !M || !x || !out) return RELSIM_EINVAL;
   if (x == out) return fail(c, RELSIM_EINVAL, "relsim_apply_AT cannot work in place");
   apply_AT(c, M, x, out);
@@ -938,7 +940,7 @@ int relsim_push_adjoint(relsim_ctx *c, const relsim_particles *state_n, const do
   return launch_status(c, "relsim_push_adjoint");
 }
 
-int relsim_field_solve_adjoint(relsim_ctx *c, const double *M, const double *lam_E_theta, const double *lam_E_np1,
+int relsim_field_solve_adjoint(relsim_ctx *c, const void *M, const double *lam_E_theta, const double *lam_E_np1,
                                const double *lam_B_np1, double *mu, double *lam_E_n, double *lam_B_n, int32_t *iters,
                                double *rel_resid) {
   if (!c) return RELSIM_EINVAL;

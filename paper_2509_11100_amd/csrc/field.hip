@@ -88,9 +88,10 @@ __device__ __forceinline__ size_t node_at(const KParams &kp, int i, int j, int k
 // (M x)_g, or (M^T x)_g with TR (each 3x3 block transposed), from the stored
 // half of the blocks: slot h of node g couples x at g + delta(h), and for
 // h > 0 the same slot of node g - delta(h) couples x at g - delta(h)
-// (M_{g,g-delta} = M_{g-delta,g}).
-template <int DIM, bool TR>
-__device__ __forceinline__ void apply_M(const KParams &kp, const double *__restrict__ M,
+// (M_{g,g-delta} = M_{g-delta,g}).  MT is M's storage type (float in mixed
+// precision, double in FP64); the products and sums are FP64.
+template <int DIM, bool TR, typename MT>
+__device__ __forceinline__ void apply_M(const KParams &kp, const MT *__restrict__ M,
                                         const double *__restrict__ x, int g, int i, int j, int k, double mx[3]) {
   constexpr int NSLOT = m_slots<DIM>(), CEN = m_centre<DIM>();
   const size_t N = (size_t)kp.ncells;
@@ -104,15 +105,18 @@ __device__ __forceinline__ void apply_M(const KParams &kp, const double *__restr
       // block times x at g - delta
       const size_t id = side ? node_at<DIM>(kp, i, j, k, -dx, -dy, -dz) : node_at<DIM>(kp, i, j, k, dx, dy, dz);
       const double x0 = x[id], x1 = x[N + id], x2 = x[2 * N + id];
-      const double *Mo = M + (size_t)h * 9 * N + (side ? id : (size_t)g);
+      const MT *Mo = M + (size_t)h * 9 * N + (side ? id : (size_t)g);
+      double m[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) m[q] = (double)Mo[q * N];
       if constexpr (!TR) {
-        mx[0] += Mo[0] * x0 + Mo[N] * x1 + Mo[2 * N] * x2;
-        mx[1] += Mo[3 * N] * x0 + Mo[4 * N] * x1 + Mo[5 * N] * x2;
-        mx[2] += Mo[6 * N] * x0 + Mo[7 * N] * x1 + Mo[8 * N] * x2;
+        mx[0] += m[0] * x0 + m[1] * x1 + m[2] * x2;
+        mx[1] += m[3] * x0 + m[4] * x1 + m[5] * x2;
+        mx[2] += m[6] * x0 + m[7] * x1 + m[8] * x2;
       } else {
-        mx[0] += Mo[0] * x0 + Mo[3 * N] * x1 + Mo[6 * N] * x2;
-        mx[1] += Mo[N] * x0 + Mo[4 * N] * x1 + Mo[7 * N] * x2;
-        mx[2] += Mo[2 * N] * x0 + Mo[5 * N] * x1 + Mo[8 * N] * x2;
+        mx[0] += m[0] * x0 + m[3] * x1 + m[6] * x2;
+        mx[1] += m[1] * x0 + m[4] * x1 + m[7] * x2;
+        mx[2] += m[2] * x0 + m[5] * x1 + m[8] * x2;
       }
     }
   }
@@ -121,8 +125,8 @@ __device__ __forceinline__ void apply_M(const KParams &kp, const double *__restr
 // out = x + a^2 C_CN t + b M x, with t = C_NC x precomputed; with TR the
 // transposed operator, x + a^2 C_CN t + b M^T x (the curl-curl term is
 // symmetric, C_CN being the transpose of C_NC)
-template <int DIM, bool TR>
-__global__ __launch_bounds__(256) void k_apply_A_tail(KParams kp, const double *__restrict__ M,
+template <int DIM, bool TR, typename MT>
+__global__ __launch_bounds__(256) void k_apply_A_tail(KParams kp, const MT *__restrict__ M,
                                                       const double *__restrict__ x, const double *__restrict__ t,
                                                       double *__restrict__ out) {
   int i, j, k;
@@ -136,7 +140,7 @@ __global__ __launch_bounds__(256) void k_apply_A_tail(KParams kp, const double *
   const double a = kp.c * kp.theta * kp.dt;
   const double b = 4.0 * M_PI * kp.theta * kp.dt;
   double mx[3] = {0.0, 0.0, 0.0};
-  apply_M<DIM, TR>(kp, M, x, g, i, j, k, mx);
+  apply_M<DIM, TR, MT>(kp, M, x, g, i, j, k, mx);
 #pragma unroll
   for (int q = 0; q < 3; ++q) out[q * N + g] = x[q * N + g] + a * a * cc[q] + b * mx[q];
 }
@@ -369,20 +373,29 @@ void launch_curl(const KParams &kp, const double *in, double *out, int to_centre
     hipLaunchKernelGGL(k_curl<3>, dim3(node_blocks(kp)), dim3(256), 0, st, kp, in, out, shift);
 }
 
-void launch_apply_A_tail(const KParams &kp, const double *M, const double *x, const double *t, double *out,
-                         hipStream_t st) {
+template <bool TR, typename MT>
+void launch_apply_tail(const KParams &kp, const MT *M, const double *x, const double *t, double *out,
+                       hipStream_t st) {
   if (kp.dim == 2)
-    hipLaunchKernelGGL((k_apply_A_tail<2, false>), dim3(node_blocks(kp)), dim3(256), 0, st, kp, M, x, t, out);
+    hipLaunchKernelGGL((k_apply_A_tail<2, TR, MT>), dim3(node_blocks(kp)), dim3(256), 0, st, kp, M, x, t, out);
   else
-    hipLaunchKernelGGL((k_apply_A_tail<3, false>), dim3(node_blocks(kp)), dim3(256), 0, st, kp, M, x, t, out);
+    hipLaunchKernelGGL((k_apply_A_tail<3, TR, MT>), dim3(node_blocks(kp)), dim3(256), 0, st, kp, M, x, t, out);
 }
 
-void launch_apply_AT_tail(const KParams &kp, const double *M, const double *x, const double *t, double *out,
-                          hipStream_t st) {
-  if (kp.dim == 2)
-    hipLaunchKernelGGL((k_apply_A_tail<2, true>), dim3(node_blocks(kp)), dim3(256), 0, st, kp, M, x, t, out);
+void launch_apply_A_tail(const KParams &kp, int prec, const void *M, const double *x, const double *t, double *out,
+                         hipStream_t st) {
+  if (prec == RELSIM_MIXED)
+    launch_apply_tail<false>(kp, static_cast<const float *>(M), x, t, out, st);
   else
-    hipLaunchKernelGGL((k_apply_A_tail<3, true>), dim3(node_blocks(kp)), dim3(256), 0, st, kp, M, x, t, out);
+    launch_apply_tail<false>(kp, static_cast<const double *>(M), x, t, out, st);
+}
+
+void launch_apply_AT_tail(const KParams &kp, int prec, const void *M, const double *x, const double *t, double *out,
+                          hipStream_t st) {
+  if (prec == RELSIM_MIXED)
+    launch_apply_tail<true>(kp, static_cast<const float *>(M), x, t, out, st);
+  else
+    launch_apply_tail<true>(kp, static_cast<const double *>(M), x, t, out, st);
 }
 
 void launch_rhs(const KParams &kp, const double *En, const double *Bn, const double *J, double *out, hipStream_t st) {

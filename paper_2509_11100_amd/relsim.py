@@ -103,7 +103,9 @@ class Context:
         return torch.zeros((3, self.ncells), dtype=torch.float64, device=self.device)
 
     def mass_matrix(self) -> torch.Tensor:
-        return torch.empty((self.m_slots, 9, self.ncells), dtype=torch.float64, device=self.device)
+        """The stored half of M, [m_slots][9][N], of the particle type (FP32
+        in mixed precision, FP64 otherwise)."""
+        return torch.empty((self.m_slots, 9, self.ncells), dtype=self.dtype, device=self.device)
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -245,8 +247,9 @@ def _grid_ok(ctx: Context, *ts):
 
 
 def _mass_ok(ctx: Context, M):
-    # the stored half of the node-pair blocks, [m_slots][9][N]
-    _grid_ok(ctx, M)
+    # the stored half of the node-pair blocks, [m_slots][9][N], particle type
+    if M.device != ctx.device or M.dtype != ctx.dtype or not M.is_contiguous():
+        raise ValueError("M must be a contiguous %s tensor on the context device" % ctx.dtype)
     if M.numel() < ctx.m_slots * 9 * ctx.ncells:
         raise ValueError("M must hold [%d][9][%d] values" % (ctx.m_slots, ctx.ncells))
 

@@ -154,14 +154,19 @@ def test_deposit_with_no_particles():
 # ----------------------------------------------------------------------------
 # a5: field operators and solve
 # ----------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("gname", ["2d_7x5", "3d_5x4x3", "3d_3x3x3", "2d_70x9", "3d_70x6x8"])
-def test_field_operators(gname):
+def test_field_operators(gname, precision):
+    """Curls, A and A^T against the oracle on the library's own M (FP32 in
+    mixed precision, promoted exactly for the oracle; the products are FP64
+    on both sides)."""
     need_gpu()
-    g, ctx, parts, B, E = setup_random(gname, "fp64", 800, 31)
+    g, ctx, parts, B, E = setup_random(gname, precision, 800, 31)
     from paper_2509_11100_amd import relsim
 
     J, M = relsim.deposit_moments(ctx, parts, torch_grid(B))
-    Mh = full_from_half(g, M.cpu().numpy())
+    assert M.dtype == ctx.dtype
+    Mh = full_from_half(g, M.cpu().numpy().astype(np.float64))
     c1 = relsim.curl_nc(ctx, torch_grid(E)).cpu().numpy()
     c2 = relsim.curl_cn(ctx, torch_grid(B)).cpu().numpy()
     check_rel(c1, oracle.curl_nc(g, E), 1e-13)
@@ -174,16 +179,19 @@ def test_field_operators(gname):
     check_rel(AT, (oracle.A_matrix(g, Mh).T @ E.reshape(-1)).reshape(3, g.N), 1e-13)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("gname", ["2d_7x5", "3d_5x4x3", "3d_70x6x8"])
-def test_field_solve_parity(gname):
+def test_field_solve_parity(gname, precision):
+    """S4-S5 against the oracle's direct solve of the same system (the
+    library's Jhat and M; in mixed precision M is FP32 and the solve FP64)."""
     need_gpu()
-    g, ctx, parts, B, E = setup_random(gname, "fp64", 1500, 41)
+    g, ctx, parts, B, E = setup_random(gname, precision, 1500, 41)
     from paper_2509_11100_amd import relsim
 
     J, M = relsim.deposit_moments(ctx, parts, torch_grid(B))
     Eth, E1, B1, it, rr = relsim.field_solve(ctx, M, J, torch_grid(E), torch_grid(B))
     assert rr <= 1e-13 and it > 0
-    Jh, Mh = J.cpu().numpy(), full_from_half(g, M.cpu().numpy())
+    Jh, Mh = J.cpu().numpy(), full_from_half(g, M.cpu().numpy().astype(np.float64))
     r = oracle.rhs(g, E, B, Jh)
     ref = oracle.solve(g, Mh, r)
     E1r, B1r = oracle.field_update(g, E, B, ref)
