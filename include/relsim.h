@@ -64,7 +64,8 @@ extern "C" {
 
 #define RELSIM_FP64 0  /* particle state and particle arithmetic in double    */
 #define RELSIM_MIXED 1 /* particle state/arithmetic in float, per-cell moments
-                          reduced in float, grid accumulation in double      */
+                          reduced in float, grid accumulation in double, M
+                          stored in float, solve and energy in double        */
 
 typedef struct relsim_ctx relsim_ctx;
 
