@@ -45,9 +45,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(name, wl, prec, n, nbins, ncells):
+def kernel_bytes(name, wl, prec, n, nbins, ncells, mb=8):
     """Algorithmic bytes of one launch of a kernel: what it must read and
-    write at least once (particle state, grid fields, per-cell moments)."""
+    write at least once (particle state, grid fields, per-cell moments); mb
+    is the bytes of one stored value of M (8, or 4 with mass_fp32)."""
     T = 4 if prec == "mixed" else 8
     d = wl.dim
     noff = 27 if d == 3 else 9
@@ -59,9 +60,9 @@ def kernel_bytes(name, wl, prec, n, nbins, ncells):
         return n * (d + 4) * T + ncells * grid + ncells * nmom * T
     if name == "assemble_nodes":
         # in: per-cell moments; out: J-hat (FP64) and the stored half of M
-        # at nodes (type T; 5 of the 9 node-pair blocks in 2D, 14 of 27 in 3D)
+        # at nodes (5 of the 9 node-pair blocks in 2D, 14 of 27 in 3D)
         nmom = 93 if d == 2 else 267
-        return ncells * nmom * T + ncells * (grid + T * 9 * (noff // 2 + 1))
+        return ncells * nmom * T + ncells * (grid + mb * 9 * (noff // 2 + 1))
     if name == "push_count":
         # first pass of push + re-sort: in: offsets + (momentum, weight)
         # records, E_theta, B^n; out: 1-byte move code (+ per-bin counts)
@@ -135,7 +136,7 @@ def measured_valu(tag, kernel):
     return js["kernels"].get(KERNEL_SYMBOL.get(kernel, kernel))
 
 
-def run_energy_conserving(prec, wl, host, steps, warmup, rtol, group=0, secant=False):
+def run_energy_conserving(prec, wl, host, steps, warmup, rtol, group=0, secant=False, mass_fp32=False):
     """Whole energy-conserving steps (relsim.Step(energy_conserving=True):
     fixed-point passes of deposit, solve and relsim_gamma_mean, then the
     push) on the same workload: wall time per step, passes per step and the
@@ -148,7 +149,7 @@ def run_energy_conserving(prec, wl, host, steps, warmup, rtol, group=0, secant=F
     n = host["w"].shape[0]
     ctx = relsim.Context(dim=wl.dim, nx=wl.nx, ny=wl.ny, nz=wl.nz if wl.dim == 3 else 1, dx=wl.dx, dt=wl.dt,
                          precision=prec, q=wl.q, m=wl.m, max_particles=n, gmres_rtol=rtol, gmres_restart=30,
-                         gmres_maxit=5000, group=group)
+                         gmres_maxit=5000, group=group, mass_fp32=mass_fp32)
     parts = relsim.Particles(ctx).load(host["cell"], host["species"], host["off"], host["u"], host["w"],
                                        host["bin_start"])
     step = relsim.Step(ctx, parts, torch.as_tensor(host["E"]).cuda(), torch.as_tensor(host["B"]).cuda(),
@@ -168,11 +169,12 @@ def run_energy_conserving(prec, wl, host, steps, warmup, rtol, group=0, secant=F
     torch.cuda.empty_cache()
     return {"precision": prec, "particle_steps_per_s": n * steps / wall, "ms_per_step": 1e3 * wall / steps,
             "picard_tol": 1e-12 if prec == "fp64" else 1e-6, "fixed_point": "secant" if secant else "plain",
+            "mass_matrix": "fp32" if mass_fp32 else "fp64",
             "passes_per_step": float(np.mean(passes)),
             "rel_energy_change": float(abs(W1[3] - W0[3]) / W0[3])}
 
 
-def run_precision(prec, wl, host, steps, warmup, rtol, want_kernels=True, group=0):
+def run_precision(prec, wl, host, steps, warmup, rtol, want_kernels=True, group=0, mass_fp32=False):
     import numpy as np
     import torch
 
@@ -181,7 +183,7 @@ def run_precision(prec, wl, host, steps, warmup, rtol, want_kernels=True, group=
     n = host["w"].shape[0]
     ctx = relsim.Context(dim=wl.dim, nx=wl.nx, ny=wl.ny, nz=wl.nz if wl.dim == 3 else 1, dx=wl.dx, dt=wl.dt,
                          precision=prec, q=wl.q, m=wl.m, max_particles=n, gmres_rtol=rtol, gmres_restart=30,
-                         gmres_maxit=5000, group=group)
+                         gmres_maxit=5000, group=group, mass_fp32=mass_fp32)
     parts = relsim.Particles(ctx).load(host["cell"], host["species"], host["off"], host["u"], host["w"],
                                        host["bin_start"])
     E = torch.as_tensor(host["E"]).cuda()
@@ -244,6 +246,7 @@ def run_precision(prec, wl, host, steps, warmup, rtol, want_kernels=True, group=
     hot = dep + pus
     res = {
         "precision": prec,
+        "mass_matrix": "fp32" if mass_fp32 else "fp64",
         "particles": n,
         "value": n * steps / (hot * 1e-3),
         "hot_ms_per_step": hot / steps,
@@ -287,7 +290,7 @@ def device_copy_bandwidth(nbytes=1 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def path_bytes_per_particle(wl, prec, n, nbins, ncells):
+def path_bytes_per_particle(wl, prec, n, nbins, ncells, mb=8):
     """Algorithmic bytes per particle-step of this design (deposit + push +
     re-sort, as separate kernels) and the fused minimum of a step: one read
     and one write of each particle's offsets, momentum and weight (the mixed
@@ -299,7 +302,7 @@ def path_bytes_per_particle(wl, prec, n, nbins, ncells):
     T = 4 if prec == "mixed" else 8
     d = wl.dim
     noff = 27 if d == 3 else 9
-    this = sum(kernel_bytes(k, wl, prec, n, nbins, ncells) for k in
+    this = sum(kernel_bytes(k, wl, prec, n, nbins, ncells, mb) for k in
                ("deposit_cells", "assemble_nodes", "push_count", "push_scatter")) / n
     state = (d + 4) * T
     grid = ncells * (8 * 9 * noff + 24 + 3 * 24) / n
@@ -523,25 +526,28 @@ def roofline_of(res, wl, copy_gbs):
     prec = res["precision"]
     n = res["particles"]
     nbins = wl.ncells * wl.nspecies
-    cand = {k: v for k, v in res["kernels"].items() if kernel_bytes(k, wl, prec, n, nbins, wl.ncells)}
+    mb = 4 if res.get("mass_matrix") == "fp32" else 8
+    cand = {k: v for k, v in res["kernels"].items() if kernel_bytes(k, wl, prec, n, nbins, wl.ncells, mb)}
     if not cand:
         return None
     dom = max(cand, key=lambda k: cand[k]["ms_per_launch"] * cand[k]["launches"])
-    byt = kernel_bytes(dom, wl, prec, n, nbins, wl.ncells)
+    byt = kernel_bytes(dom, wl, prec, n, nbins, wl.ncells, mb)
+    # the committed counter summaries were taken with M stored in FP64
+    tag = "%s_%s" % (wl.name, prec) if mb == 8 else None
     ach = byt / (cand[dom]["ms_per_launch"] * 1e-3) / 1e9
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(ach / PEAK_HBM_GBS, 4),
-            "traffic": measured_traffic("%s_%s" % (wl.name, prec), dom),
-            "valu": measured_valu("%s_%s" % (wl.name, prec), dom),
+            "traffic": measured_traffic(tag, dom) if tag else None,
+            "valu": measured_valu(tag, dom) if tag else None,
             "bytes_per_launch": byt, "ms_per_launch": round(cand[dom]["ms_per_launch"], 4)}
     per_kernel = {}
     for k, v in cand.items():
-        b = kernel_bytes(k, wl, prec, n, nbins, wl.ncells)
+        b = kernel_bytes(k, wl, prec, n, nbins, wl.ncells, mb)
         per_kernel[k] = round(b / (v["ms_per_launch"] * 1e-3) / 1e9, 1)
     roof["achieved_by_kernel_GBs"] = per_kernel
     roof["measured_copy_GBs"] = round(copy_gbs, 1)
     roof["frac_of_measured_copy"] = round(ach / copy_gbs, 4)
-    this, fused = path_bytes_per_particle(wl, prec, n, nbins, wl.ncells)
+    this, fused = path_bytes_per_particle(wl, prec, n, nbins, wl.ncells, mb)
     roof["path"] = {
         "bytes_per_particle_step": round(this, 2),
         "achieved_GBs": round(res["value"] * this / 1e9, 1),
@@ -642,6 +648,8 @@ def main():
                     help="also time the energy-conserving step (reported beside the headline, not in it)")
     ap.add_argument("--secant", action="store_true",
                     help="the energy-conserving step's fixed point with per-particle secant steps")
+    ap.add_argument("--mass-fp32", action="store_true",
+                    help="mixed precision with the mass matrix stored in FP32 (the default stores it in FP64)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (for counter calibration)")
     ap.add_argument("--adjoint", type=int, default=0, metavar="K",
@@ -685,7 +693,8 @@ def main():
     results = {}
     for p in precs:
         log("running %s: %d warmup + %d timed steps" % (p, args.warmup, args.steps))
-        results[p] = run_precision(p, wl, host, args.steps, args.warmup, args.rtol, group=args.group)
+        results[p] = run_precision(p, wl, host, args.steps, args.warmup, args.rtol, group=args.group,
+                                   mass_fp32=args.mass_fp32 and p == "mixed")
         log("%s: %.4g particle-steps/s, hot %.3f ms/step, solve %.3f ms/step" % (
             p, results[p]["value"], results[p]["hot_ms_per_step"], results[p]["solve_ms_per_step"]))
     head = results[precs[0]]
@@ -700,7 +709,7 @@ def main():
         for p in precs:
             log("running the energy-conserving step, %s" % p)
             ec[p] = run_energy_conserving(p, wl, host, args.steps, args.warmup, args.rtol, group=args.group,
-                                          secant=args.secant)
+                                          secant=args.secant, mass_fp32=args.mass_fp32 and p == "mixed")
             log("%s energy-conserving: %.3f ms/step, %.1f passes/step, |dW|/W %.2e" % (
                 p, ec[p]["ms_per_step"], ec[p]["passes_per_step"], ec[p]["rel_energy_change"]))
 
@@ -712,7 +721,8 @@ def main():
         for p in precs:
             log("running %s on %s: %d warmup + %d timed steps" % (p, wl2.name, min(args.warmup, 2),
                                                                   args.secondary_steps))
-            r2 = run_precision(p, wl2, host2, args.secondary_steps, min(args.warmup, 2), args.rtol, group=args.group)
+            r2 = run_precision(p, wl2, host2, args.secondary_steps, min(args.warmup, 2), args.rtol, group=args.group,
+                               mass_fp32=args.mass_fp32 and p == "mixed")
             r2["roofline"] = roofline_of(r2, wl2, copy_gbs)
             secondary["results"][p] = r2
             log("%s %s: %.4g particle-steps/s, hot %.3f ms/step" % (wl2.name, p, r2["value"], r2["hot_ms_per_step"]))

@@ -21,10 +21,13 @@
  *     E, Jhat and M live at nodes (i,j,k)*dx, B at cell centres
  *     (i+1/2, j+1/2, k+1/2)*dx.  Node and cell (i,j,k) share the linear index
  *     i + nx*(j + ny*k); N = nx*ny*nz (nz = 1 in 2D, where d/dz = 0).
- *   - Grid arrays are FP64, component-major: E, B, Jhat [3][N]; M is of
- *     the particle type T (FP32 in mixed precision, FP64 otherwise: it is
- *     summed in FP64 from per-cell moments of type T, whose rounding it
- *     already carries; the S4 products and sums with it are FP64).
+ *   - Grid arrays are FP64, component-major: E, B, Jhat [3][N].  M is
+ *     summed in FP64 and stored in FP64, or in FP32 when the context was
+ *     created with mass_fp32 = 1 (mixed precision only: the per-cell moments
+ *     it is summed from are FP32 there, so the FP32 store rounds values that
+ *     already carry FP32 rounding, and it halves M's memory and the S4
+ *     operator's largest read; the S4 products and sums are FP64 either
+ *     way).
  *     M holds the node-pair blocks M_{g,g+delta} for the 9 (2D) or 27 (3D)
  *     offsets delta in {-1,0,1}^dim, numbered o = sum_d (delta_d + 1) 3^d (x
  *     fastest).  The block is symmetric in the pair, M_{g,g'} = M_{g',g}
@@ -64,8 +67,8 @@ extern "C" {
 
 #define RELSIM_FP64 0  /* particle state and particle arithmetic in double    */
 #define RELSIM_MIXED 1 /* particle state/arithmetic in float, per-cell moments
-                          reduced in float, grid accumulation in double, M
-                          stored in float, solve and energy in double        */
+                          reduced in float, grid accumulation, solve and
+                          energy in double                                   */
 
 typedef struct relsim_ctx relsim_ctx;
 
@@ -88,6 +91,9 @@ typedef struct {
                                   3D deposit always splits a cell's moments
                                   over 4 lanes; the push passes size their
                                   row segments themselves)                      */
+  int32_t mass_fp32;           /* 0: M stored in double (the default); 1 (only
+                                  with RELSIM_MIXED): M stored in float, see
+                                  Conventions                                   */
 } relsim_params;
 
 /* Particle state, sorted by bin = cell * nspecies + s, so that the
@@ -141,7 +147,8 @@ int relsim_sort(relsim_ctx *ctx, relsim_particles *part);
 
 /* a2-a4 (S1-S3): gather B^n, form alpha per particle and deposit Jhat [3][N]
  * and M [m_slots][9][N] (the stored half of the node-pair blocks, see
- * Conventions; both overwritten; Jhat FP64, M of type T and aligned to it).
+ * Conventions; both overwritten; Jhat FP64, M in its storage type and aligned
+ * to it).
  * Particles must be bin-sorted. */
 int relsim_deposit_moments(relsim_ctx *ctx, const relsim_particles *part, const double *B_n, double *Jhat,
                            void *M);

@@ -31,7 +31,7 @@ class relsim_params(C.Structure):
         ("q", C.c_double * 8), ("m", C.c_double * 8),
         ("max_particles", C.c_int64),
         ("gmres_rtol", C.c_double), ("gmres_restart", C.c_int32), ("gmres_maxit", C.c_int32),
-        ("nonrelativistic", C.c_int32), ("group", C.c_int32),
+        ("nonrelativistic", C.c_int32), ("group", C.c_int32), ("mass_fp32", C.c_int32),
     ]
 
 

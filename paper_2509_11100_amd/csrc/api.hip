@@ -145,6 +145,8 @@ int validate(const relsim_params *p, std::string &msg) {
   if (!(p->gmres_rtol > 0)) return msg = "gmres_rtol must be > 0", RELSIM_EINVAL;
   if (p->group != 0 && p->group != 4 && p->group != 8 && p->group != 16 && p->group != 32 && p->group != 64)
     return msg = "group must be 0, 4, 8, 16, 32 or 64", RELSIM_EINVAL;
+  if (p->mass_fp32 != 0 && (p->mass_fp32 != 1 || p->precision != RELSIM_MIXED))
+    return msg = "mass_fp32 must be 0, or 1 with mixed precision", RELSIM_EINVAL;
   return RELSIM_OK;
 }
 
@@ -421,14 +423,14 @@ int fetch(relsim_ctx *c, const double *dev, int k) {
 void apply_A(relsim_ctx *c, const void *M, const double *x, double *out) {
   double *t = c->at<double>(c->L.gm_t);
   timed(c, "curl_nc", [&] { launch_curl(c->kp, x, t, 1, c->st); });
-  timed(c, "apply_A", [&] { launch_apply_A_tail(c->kp, c->p.precision, M, x, t, out, c->st); });
+  timed(c, "apply_A", [&] { launch_apply_A_tail(c->kp, c->p.mass_fp32, M, x, t, out, c->st); });
 }
 
 // out = A^T x
 void apply_AT(relsim_ctx *c, const void *M, const double *x, double *out) {
   double *t = c->at<double>(c->L.gm_t);
   timed(c, "curl_nc", [&] { launch_curl(c->kp, x, t, 1, c->st); });
-  timed(c, "apply_AT", [&] { launch_apply_AT_tail(c->kp, c->p.precision, M, x, t, out, c->st); });
+  timed(c, "apply_AT", [&] { launch_apply_AT_tail(c->kp, c->p.mass_fp32, M, x, t, out, c->st); });
 }
 
 int norm2(relsim_ctx *c, const double *x, size_t n, double *out) {
@@ -541,8 +543,7 @@ int relsim_deposit_moments_ec(relsim_ctx *c, const relsim_particles *pt, const d
   int rc = check_particles(c, pt, false);
   if (rc) return rc;
   if (!B_n || !Jhat || !M) return fail(c, RELSIM_EINVAL, "null grid array");
-  if (!aligned(M, c->p.precision == RELSIM_MIXED ? 4 : 8))
-    return fail(c, RELSIM_EINVAL, "M not aligned to its element size");
+  if (!aligned(M, c->p.mass_fp32 ? 4 : 8)) return fail(c, RELSIM_EINVAL, "M not aligned to its element size");
   if (gbar && !aligned(gbar, c->p.precision == RELSIM_MIXED ? 4 : 8))
     return fail(c, RELSIM_EINVAL, "gbar not aligned to its element size");
   const int G = choose_group(c, pt->n, K_DEPOSIT);
@@ -552,7 +553,7 @@ int relsim_deposit_moments_ec(relsim_ctx *c, const relsim_particles *pt, const d
   pp.gbar = gbar;
   timed(c, "stage_fields", [&] { launch_stage_field(c->kp, c->p.precision, B_n, stB, c->st); });
   timed(c, "deposit_cells", [&] { launch_deposit_cells(c->kp, c->p.precision, G, pp, stB, S, c->st); });
-  timed(c, "assemble_nodes", [&] { launch_assemble(c->kp, c->p.precision, S, Jhat, M, c->st); });
+  timed(c, "assemble_nodes", [&] { launch_assemble(c->kp, c->p.precision, c->p.mass_fp32, S, Jhat, M, c->st); });
   return launch_status(c, "relsim_deposit_moments");
 }
 

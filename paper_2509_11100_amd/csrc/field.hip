@@ -88,8 +88,8 @@ __device__ __forceinline__ size_t node_at(const KParams &kp, int i, int j, int k
 // (M x)_g, or (M^T x)_g with TR (each 3x3 block transposed), from the stored
 // half of the blocks: slot h of node g couples x at g + delta(h), and for
 // h > 0 the same slot of node g - delta(h) couples x at g - delta(h)
-// (M_{g,g-delta} = M_{g-delta,g}).  MT is M's storage type (float in mixed
-// precision, double in FP64); the products and sums are FP64.
+// (M_{g,g-delta} = M_{g-delta,g}).  MT is M's storage type (double, or
+// float on request in mixed precision); the products and sums are FP64.
 template <int DIM, bool TR, typename MT>
 __device__ __forceinline__ void apply_M(const KParams &kp, const MT *__restrict__ M,
                                         const double *__restrict__ x, int g, int i, int j, int k, double mx[3]) {
@@ -382,17 +382,17 @@ void launch_apply_tail(const KParams &kp, const MT *M, const double *x, const do
     hipLaunchKernelGGL((k_apply_A_tail<3, TR, MT>), dim3(node_blocks(kp)), dim3(256), 0, st, kp, M, x, t, out);
 }
 
-void launch_apply_A_tail(const KParams &kp, int prec, const void *M, const double *x, const double *t, double *out,
-                         hipStream_t st) {
-  if (prec == RELSIM_MIXED)
+void launch_apply_A_tail(const KParams &kp, int mass_fp32, const void *M, const double *x, const double *t,
+                         double *out, hipStream_t st) {
+  if (mass_fp32)
     launch_apply_tail<false>(kp, static_cast<const float *>(M), x, t, out, st);
   else
     launch_apply_tail<false>(kp, static_cast<const double *>(M), x, t, out, st);
 }
 
-void launch_apply_AT_tail(const KParams &kp, int prec, const void *M, const double *x, const double *t, double *out,
-                          hipStream_t st) {
-  if (prec == RELSIM_MIXED)
+void launch_apply_AT_tail(const KParams &kp, int mass_fp32, const void *M, const double *x, const double *t,
+                          double *out, hipStream_t st) {
+  if (mass_fp32)
     launch_apply_tail<true>(kp, static_cast<const float *>(M), x, t, out, st);
   else
     launch_apply_tail<true>(kp, static_cast<const double *>(M), x, t, out, st);

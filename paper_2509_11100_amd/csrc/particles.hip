@@ -667,13 +667,12 @@ __global__ __launch_bounds__(64) void k_deposit_split3(KParams kp, const int32_t
 
 // ---------------------------------------------------------------------------
 // J-hat and M at nodes from the per-cell moments (fixed-order gather).  Both
-// are summed in FP64; J-hat is stored in FP64 and M in the moments' type T,
-// whose rounding the moments already carry (in mixed precision an FP32 M
-// halves the assembly's largest write and the solve's largest read).
+// are summed in FP64; J-hat is stored in FP64 and M in MT (double, or float
+// on request in mixed precision, where the moments are already FP32).
 // ---------------------------------------------------------------------------
-template <typename T, int DIM>
+template <typename T, int DIM, typename MT>
 __global__ __launch_bounds__(256) void k_assemble(KParams kp, const T *__restrict__ S, double *__restrict__ J,
-                                                  T *__restrict__ M) {
+                                                  MT *__restrict__ M) {
   constexpr int NSLOT = m_slots<DIM>(), CEN = m_centre<DIM>();
   constexpr int NCORN = DIM == 3 ? 8 : 4;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -711,7 +710,7 @@ __global__ __launch_bounds__(256) void k_assemble(KParams kp, const T *__restric
       for (int q = 0; q < 9; ++q) acc[q] += (double)S[mom_index<DIM>(base + q, cidx[a])];
     }
 #pragma unroll
-    for (int q = 0; q < 9; ++q) M[((size_t)h * 9 + q) * N + g] = (T)acc[q];
+    for (int q = 0; q < 9; ++q) M[((size_t)h * 9 + q) * N + g] = (MT)acc[q];
   }
   double jacc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -1635,21 +1634,23 @@ void launch_deposit_cells(const KParams &kp, int prec, int group, const PartPtrs
   }
 }
 
-void launch_assemble(const KParams &kp, int prec, const void *S, double *J, void *M, hipStream_t st) {
+template <typename T, typename MT>
+void assemble_as(const KParams &kp, const void *S, double *J, void *M, hipStream_t st) {
   const int nblk = (kp.ncells + 255) / 256;
-  if (prec == RELSIM_MIXED) {
-    if (kp.dim == 2)
-      hipLaunchKernelGGL((k_assemble<float, 2>), dim3(nblk), dim3(256), 0, st, kp, cp<float>(S), J, mp<float>(M));
-    else
-      hipLaunchKernelGGL((k_assemble<float, 3>), dim3(nblk), dim3(256), 0, st, kp, cp<float>(S), J, mp<float>(M));
-  } else {
-    if (kp.dim == 2)
-      hipLaunchKernelGGL((k_assemble<double, 2>), dim3(nblk), dim3(256), 0, st, kp, cp<double>(S), J,
-                         mp<double>(M));
-    else
-      hipLaunchKernelGGL((k_assemble<double, 3>), dim3(nblk), dim3(256), 0, st, kp, cp<double>(S), J,
-                         mp<double>(M));
-  }
+  if (kp.dim == 2)
+    hipLaunchKernelGGL((k_assemble<T, 2, MT>), dim3(nblk), dim3(256), 0, st, kp, cp<T>(S), J, mp<MT>(M));
+  else
+    hipLaunchKernelGGL((k_assemble<T, 3, MT>), dim3(nblk), dim3(256), 0, st, kp, cp<T>(S), J, mp<MT>(M));
+}
+
+void launch_assemble(const KParams &kp, int prec, int mass_fp32, const void *S, double *J, void *M,
+                     hipStream_t st) {
+  if (prec != RELSIM_MIXED)
+    assemble_as<double, double>(kp, S, J, M, st);
+  else if (mass_fp32)
+    assemble_as<float, float>(kp, S, J, M, st);
+  else
+    assemble_as<float, double>(kp, S, J, M, st);
 }
 
 size_t push_lds_bytes(const KParams &kp, int prec, int cells) {

@@ -123,7 +123,8 @@ struct PartPtrs {
 void launch_stage_field(const KParams &kp, int prec, const double *F, void *out, hipStream_t st);
 void launch_deposit_cells(const KParams &kp, int prec, int group, const PartPtrs &pp, const void *Bst, void *S,
                           hipStream_t st);
-void launch_assemble(const KParams &kp, int prec, const void *S, double *J, void *M, hipStream_t st);
+void launch_assemble(const KParams &kp, int prec, int mass_fp32, const void *S, double *J, void *M,
+                     hipStream_t st);
 // `sink`: kSinkSlots * 64 * 32 bytes of workspace that lanes without a
 // particle store into (contents meaningless)
 // The push passes give each wave `cells` consecutive cells of one grid row
@@ -187,11 +188,11 @@ void launch_adj_finish(size_t n3, double theta, double ctdt, const double *lE1, 
 
 // ---- field kernels (field.hip) ----
 void launch_curl(const KParams &kp, const double *in, double *out, int to_centres, hipStream_t st);
-// M: the stored half of the mass matrix, float in mixed precision, double in FP64
-void launch_apply_A_tail(const KParams &kp, int prec, const void *M, const double *x, const double *t, double *out,
-                         hipStream_t st);
-void launch_apply_AT_tail(const KParams &kp, int prec, const void *M, const double *x, const double *t, double *out,
-                          hipStream_t st);
+// M: the stored half of the mass matrix, float if mass_fp32, else double
+void launch_apply_A_tail(const KParams &kp, int mass_fp32, const void *M, const double *x, const double *t,
+                         double *out, hipStream_t st);
+void launch_apply_AT_tail(const KParams &kp, int mass_fp32, const void *M, const double *x, const double *t,
+                          double *out, hipStream_t st);
 void launch_rhs(const KParams &kp, const double *En, const double *Bn, const double *J, double *out, hipStream_t st);
 void launch_field_update(const KParams &kp, const double *En, const double *Bn, const double *Eth, double *En1,
                          double *Bn1, hipStream_t st);

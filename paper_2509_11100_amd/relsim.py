@@ -28,7 +28,7 @@ class Context:
                  dz: Optional[float] = None, dt: float, c: float = 1.0, theta: float = 0.5,
                  precision: str = "fp64", q: Sequence[float] = (1.0, -1.0), m: Sequence[float] = (1.0, 1.0),
                  max_particles: int, gmres_rtol: float = 1e-10, gmres_restart: int = 30, gmres_maxit: int = 3000,
-                 nonrelativistic: bool = False, group: int = 0, device: str = "cuda"):
+                 nonrelativistic: bool = False, group: int = 0, mass_fp32: bool = False, device: str = "cuda"):
         self.lib = _lib.load()
         p = _lib.relsim_params()
         p.dim, p.nx, p.ny, p.nz = dim, nx, ny, (nz if dim == 3 else 1)
@@ -47,6 +47,10 @@ class Context:
         p.gmres_rtol, p.gmres_restart, p.gmres_maxit = gmres_rtol, gmres_restart, gmres_maxit
         p.nonrelativistic = 1 if nonrelativistic else 0
         p.group = group
+        if mass_fp32 and precision != "mixed":
+            raise ValueError("mass_fp32 needs mixed precision")
+        p.mass_fp32 = 1 if mass_fp32 else 0
+        self.mass_dtype = torch.float32 if mass_fp32 else torch.float64
         self.params = p
         self.precision = precision
         dev = torch.device(device)
@@ -103,9 +107,9 @@ class Context:
         return torch.zeros((3, self.ncells), dtype=torch.float64, device=self.device)
 
     def mass_matrix(self) -> torch.Tensor:
-        """The stored half of M, [m_slots][9][N], of the particle type (FP32
-        in mixed precision, FP64 otherwise)."""
-        return torch.empty((self.m_slots, 9, self.ncells), dtype=self.dtype, device=self.device)
+        """The stored half of M, [m_slots][9][N]: FP64, or FP32 for a
+        context made with mass_fp32."""
+        return torch.empty((self.m_slots, 9, self.ncells), dtype=self.mass_dtype, device=self.device)
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -247,9 +251,9 @@ def _grid_ok(ctx: Context, *ts):
 
 
 def _mass_ok(ctx: Context, M):
-    # the stored half of the node-pair blocks, [m_slots][9][N], particle type
-    if M.device != ctx.device or M.dtype != ctx.dtype or not M.is_contiguous():
-        raise ValueError("M must be a contiguous %s tensor on the context device" % ctx.dtype)
+    # the stored half of the node-pair blocks, [m_slots][9][N], in M's storage type
+    if M.device != ctx.device or M.dtype != ctx.mass_dtype or not M.is_contiguous():
+        raise ValueError("M must be a contiguous %s tensor on the context device" % ctx.mass_dtype)
     if M.numel() < ctx.m_slots * 9 * ctx.ncells:
         raise ValueError("M must hold [%d][9][%d] values" % (ctx.m_slots, ctx.ncells))
 

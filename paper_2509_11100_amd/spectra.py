@@ -118,7 +118,7 @@ def device_spectra(parts, species: Sequence[int], edges: np.ndarray = EDGES) -> 
 def run(steps: Optional[int] = None, snapshots: Sequence[float] = (0, 1, 2, 3, 4, 5, 6, 7, 7.77),
         precision: str = "mixed", energy_conserving: bool = True, rtol: float = 1e-10,
         workers: int = 16, log=sys.stdout, anderson: int = 0, secant: bool = True, out: Optional[str] = None,
-        **overrides) -> Dict:
+        mass_fp32: bool = False, **overrides) -> Dict:
     """The fiducial Table 2 run: spectra of the background electrons and
     ions at the given times (t c / L_y), the energy history, and the slope
     and cutoff of the last electron spectrum.  With `out`, the record is
@@ -137,7 +137,8 @@ def run(steps: Optional[int] = None, snapshots: Sequence[float] = (0, 1, 2, 3, 4
     n = p["w"].shape[0]
     print("generated %d particles in %.1f s" % (n, time.time() - t0), file=log, flush=True)
     ctx = relsim.Context(dim=2, nx=wl.nx, ny=wl.ny, dx=wl.dx, dt=wl.dt, precision=precision, q=wl.q, m=wl.m,
-                         max_particles=n, gmres_rtol=rtol, gmres_restart=30, gmres_maxit=5000)
+                         max_particles=n, gmres_rtol=rtol, gmres_restart=30, gmres_maxit=5000,
+                         mass_fp32=mass_fp32)
     parts = relsim.Particles(ctx).load(p["cell"], p["species"], p["off"], p["u"], p["w"], p["bin_start"])
     del p
     # the fixed point of this sheet converges slowly (about a factor 0.4 per
@@ -151,7 +152,8 @@ def run(steps: Optional[int] = None, snapshots: Sequence[float] = (0, 1, 2, 3, 4
     sce = sigma_ce(wl)
     sci = sce * min(wl.m) / max(wl.m)
     marks = sorted(set(int(round(t / tcl)) for t in snapshots if round(t / tcl) <= nsteps) | {nsteps})
-    rec = {"workload": wl.name, "particles": n, "precision": precision, "energy_conserving": energy_conserving,
+    rec = {"workload": wl.name, "particles": n, "precision": precision, "mass_fp32": bool(mass_fp32),
+           "energy_conserving": energy_conserving,
            "fixed_point": "anderson %d" % anderson if anderson else ("secant" if secant else "plain"),
            "dt": wl.dt, "dx": wl.dx, "sigma_ce": sce, "sigma_ci": sci, "edges": EDGES.tolist(), "snapshots": []}
     W0 = step.energy()
@@ -202,6 +204,7 @@ def main(argv=None):
     ap.add_argument("--anderson", type=int, default=0, help="Anderson depth of the fixed point (default 0: none)")
     ap.add_argument("--plain", action="store_true",
                     help="plain fixed-point passes (default: per-particle secant steps)")
+    ap.add_argument("--mass-fp32", action="store_true", help="mixed precision with M stored in FP32")
     ap.add_argument("--out", default=None, help="write the record as JSON")
     ap.add_argument("--nx", type=int, default=None)
     ap.add_argument("--ny", type=int, default=None)
@@ -211,7 +214,7 @@ def main(argv=None):
     over = {k: v for k, v in (("nx", args.nx), ("ny", args.ny), ("ppc", args.ppc), ("ppc_sheet", args.ppc_sheet))
             if v is not None}
     rec = run(args.steps, precision=args.precision, energy_conserving=not args.standard, anderson=args.anderson,
-              secant=not args.plain, out=args.out, **over)
+              secant=not args.plain, out=args.out, mass_fp32=args.mass_fp32, **over)
     last = rec["snapshots"][-1]
     print(json.dumps({"t_c_over_Ly": last["t_c_over_Ly"], "energy_error": last["energy_error"],
                       "electrons": last["electrons"], "ions": last["ions"], "ms_per_step": rec["ms_per_step"]}))

@@ -57,6 +57,17 @@ def test_invalid_parameters_are_rejected(field, value):
     assert lib.relsim_init(C.byref(p), None, None, 0, C.byref(h)) == _lib.RELSIM_EINVAL
 
 
+def test_fp32_mass_matrix_needs_mixed_precision():
+    lib = _lib.load()
+    p = base_params()
+    p.mass_fp32 = 1
+    assert lib.relsim_workspace_bytes(C.byref(p)) == 0
+    p.precision = _lib.RELSIM_MIXED
+    assert lib.relsim_workspace_bytes(C.byref(p)) > 0
+    p.mass_fp32 = 2
+    assert lib.relsim_workspace_bytes(C.byref(p)) == 0
+
+
 def test_3d_needs_nz_of_three():
     lib = _lib.load()
     p = base_params()

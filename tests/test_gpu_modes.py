@@ -203,9 +203,11 @@ def test_harris3d_end_to_end_fp64_five_steps():
     assert relsim.placement_clamps(ctx) == 0
 
 
-def test_harris3d_mixed_energy_drift_matches_oracle():
-    """Mixed precision on the same 3D sheet: the per-step energy change
-    relative to W0 within 1e-4 of the oracle's (teacher-forced start)."""
+@pytest.mark.parametrize("mass_fp32", [False, True])
+def test_harris3d_mixed_energy_drift_matches_oracle(mass_fp32):
+    """Mixed precision on the same 3D sheet (M stored in FP64, or in FP32):
+    the per-step energy change relative to W0 within 1e-4 of the oracle's
+    (teacher-forced start)."""
     need_gpu()
     from paper_2509_11100_amd import relsim
 
@@ -215,9 +217,10 @@ def test_harris3d_mixed_energy_drift_matches_oracle():
     g = grid_of(wl)
     for k in ("off", "u", "w"):
         p[k] = rounded("mixed", p[k])
-    ctx = make_ctx(g, "mixed", p["w"].shape[0], rtol=1e-13)
+    ctx = make_ctx(g, "mixed", p["w"].shape[0], rtol=1e-13, mass_fp32=mass_fp32)
     parts = load(ctx, p["cell"], p["species"], p["off"], p["u"], p["w"], p["bin_start"])
     step = relsim.Step(ctx, parts, torch_grid(E), torch_grid(B))
+    assert step.M.dtype == ctx.mass_dtype
     steps = 4
     Wg = [step.energy()]
     for _ in range(steps):
@@ -370,9 +373,10 @@ def test_harris3d_energy_conserving_fp64_steps():
     assert np.abs(Wg[:, 3] - Wg[0, 3]).max() < 1e-12 * Wg[0, 3]
 
 
+@pytest.mark.parametrize("mass_fp32", [False, True])
 @pytest.mark.parametrize("name,over", [("harris2d_64x32", {}),
                                        ("harris3d_128x64x64", dict(nx=16, ny=8, nz=8, ppc=4))])
-def test_energy_conserving_mixed_steps_remove_the_scheme_drift(name, over):
+def test_energy_conserving_mixed_steps_remove_the_scheme_drift(name, over, mass_fp32):
     """FP32-mixed, 64 x 32 pair sheet and 16 x 8 x 8 3D sheet: the standard
     step changes the energy by the relativistic term of the Sec. 2 methods
     paragraph; the energy-conserving step (fixed point to 1e-6 in FP32)
@@ -386,7 +390,7 @@ def test_energy_conserving_mixed_steps_remove_the_scheme_drift(name, over):
     g = grid_of(wl)
     drift = {}
     for ec in (False, True):
-        ctx = make_ctx(g, "mixed", p["w"].shape[0], rtol=1e-12)
+        ctx = make_ctx(g, "mixed", p["w"].shape[0], rtol=1e-12, mass_fp32=mass_fp32)
         parts = load(ctx, p["cell"], p["species"], p["off"], p["u"], p["w"], p["bin_start"])
         kw = dict(energy_conserving=True, picard_tol=1e-6) if ec else {}
         step = relsim.Step(ctx, parts, torch_grid(E), torch_grid(B), **kw)
