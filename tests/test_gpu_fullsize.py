@@ -171,10 +171,10 @@ def check_energy(wl, p, E, B, ctx, parts, precision):
     np.testing.assert_allclose(W[3], W[0] + W[1] + W[2], rtol=4 * eps)
 
 
-def setup(name, precision):
+def setup(name, precision, **kw):
     wl, p, E, B = inputs(name)
     g = grid_of(wl)
-    ctx = make_ctx(g, precision, p["w"].shape[0], rtol=1e-10)
+    ctx = make_ctx(g, precision, p["w"].shape[0], rtol=1e-10, **kw)
     parts = load(ctx, p["cell"], p["species"], p["off"], p["u"], p["w"], p["bin_start"])
     return wl, p, E, B, ctx, parts
 
@@ -195,6 +195,19 @@ def test_fullsize_push_resort_sampled_particles(name, precision):
     wl, p, E, B, ctx, parts = setup(name, precision)
     J, M = check_deposit(wl, p, B, ctx, parts, precision)
     check_push(wl, p, E, B, ctx, parts, J, M, precision)
+    del J, M, parts, ctx
+
+
+@pytest.mark.parametrize("name", ["harris2d_1024x512", "harris3d_256x128x128"])
+def test_fullsize_fp32_mass_matrix(name):
+    """Mixed precision with M stored in FP32 (mass_fp32): the sampled nodes'
+    blocks, then the solve on that M and the push + re-sort of the sampled
+    particles, against the oracle at the mixed tolerance."""
+    need_gpu()
+    wl, p, E, B, ctx, parts = setup(name, "mixed", mass_fp32=True)
+    J, M = check_deposit(wl, p, B, ctx, parts, "mixed")
+    assert M.dtype.itemsize == 4
+    check_push(wl, p, E, B, ctx, parts, J, M, "mixed")
     del J, M, parts, ctx
 
 
