@@ -220,10 +220,13 @@ int relsim_push(relsim_ctx *ctx, relsim_particles *part, const double *E_theta, 
  * particle follows each one's contraction rate.  The fixed point, the
  * stopping test and the final relsim_push_ec are unchanged.
  * gbar, gbar_next: n elements of the particle type T (as relsim_gamma_mean);
- * g_prev, r_prev: FP64 device arrays of n elements owned by the caller,
+ * g_prev, r_prev: device arrays of n elements of T owned by the caller,
  * written on every call; first != 0 (a step's first pass) only records them.
+ * The step is formed in FP64; g_prev holds gbar itself (exact in T), r_prev
+ * the residual rounded to T (exact in FP32 too while gbar_next lies within a
+ * factor 2 of gbar, by Sterbenz's lemma).
  * n <= max_particles.  Asynchronous. */
-int relsim_gamma_secant(relsim_ctx *ctx, int64_t n, const void *gbar, void *gbar_next, double *g_prev, double *r_prev,
+int relsim_gamma_secant(relsim_ctx *ctx, int64_t n, const void *gbar, void *gbar_next, void *g_prev, void *r_prev,
                         int first);
 
 /* relsim_deposit_moments with gbar in place of gamma(u^n). */

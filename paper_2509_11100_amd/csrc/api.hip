@@ -562,14 +562,14 @@ int relsim_push(relsim_ctx *c, relsim_particles *pt, const double *E_theta, cons
   return relsim_push_ec(c, pt, E_theta, B_n, nullptr, resort, new_index);
 }
 
-int relsim_gamma_secant(relsim_ctx *c, int64_t n, const void *gbar, void *gbar_next, double *g_prev, double *r_prev,
+int relsim_gamma_secant(relsim_ctx *c, int64_t n, const void *gbar, void *gbar_next, void *g_prev, void *r_prev,
                         int first) {
   if (!c) return RELSIM_EINVAL;
   if (n < 0 || n > c->p.max_particles) return fail(c, RELSIM_EINVAL, "particle count out of range");
   if (n == 0) return RELSIM_OK;
   if (!gbar || !gbar_next || !g_prev || !r_prev) return fail(c, RELSIM_EINVAL, "null array");
   const size_t es = c->p.precision == RELSIM_MIXED ? 4 : 8;
-  if (!aligned(gbar, es) || !aligned(gbar_next, es) || !aligned(g_prev, 8) || !aligned(r_prev, 8))
+  if (!aligned(gbar, es) || !aligned(gbar_next, es) || !aligned(g_prev, es) || !aligned(r_prev, es))
     return fail(c, RELSIM_EINVAL, "array not aligned to its element size");
   if (gbar == gbar_next) return fail(c, RELSIM_EINVAL, "gbar and gbar_next must not alias");
   timed(c, "gamma_secant", [&] {

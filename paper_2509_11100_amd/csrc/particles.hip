@@ -1686,14 +1686,14 @@ namespace {
 // residuals and slopes whatever T); see relsim_gamma_secant.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gamma_secant(int n, const T *__restrict__ g, T *__restrict__ Fg,
-                                                      double *__restrict__ gp, double *__restrict__ rp, int first) {
+                                                      T *__restrict__ gp, T *__restrict__ rp, int first) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   const double gd = (double)g[i];
   const double r = (double)Fg[i] - gd;
   if (!first) {
-    const double dg = gd - gp[i];
-    const double slope = (r - rp[i]) / (dg == 0.0 ? 1.0 : dg);
+    const double dg = gd - (double)gp[i];
+    const double slope = (r - (double)rp[i]) / (dg == 0.0 ? 1.0 : dg);
     const bool use = fabs(dg) > 1e-12 * gd && slope <= -0.1 && slope >= -10.0;
     const double nxt = use ? gd - r / slope : gd + r;
     Fg[i] = (T)(nxt < 1.0 ? 1.0 : nxt);  // a NaN passes through (and fails the caller's test)
@@ -1703,15 +1703,15 @@ __global__ __launch_bounds__(256) void k_gamma_secant(int n, const T *__restrict
 }
 }  // namespace
 
-void launch_gamma_secant(int prec, int n, const void *g, void *Fg, double *gp, double *rp, int first, hipStream_t st) {
+void launch_gamma_secant(int prec, int n, const void *g, void *Fg, void *gp, void *rp, int first, hipStream_t st) {
   if (n <= 0) return;
   const int nb = (n + 255) / 256;
   if (prec == RELSIM_MIXED)
-    hipLaunchKernelGGL(k_gamma_secant<float>, dim3(nb), dim3(256), 0, st, n, cp<float>(g), mp<float>(Fg), gp, rp,
-                       first);
+    hipLaunchKernelGGL(k_gamma_secant<float>, dim3(nb), dim3(256), 0, st, n, cp<float>(g), mp<float>(Fg),
+                       mp<float>(gp), mp<float>(rp), first);
   else
-    hipLaunchKernelGGL(k_gamma_secant<double>, dim3(nb), dim3(256), 0, st, n, cp<double>(g), mp<double>(Fg), gp, rp,
-                       first);
+    hipLaunchKernelGGL(k_gamma_secant<double>, dim3(nb), dim3(256), 0, st, n, cp<double>(g), mp<double>(Fg),
+                       mp<double>(gp), mp<double>(rp), first);
 }
 
 void launch_sort_offsets(const KParams &kp, const uint16_t *cnt, uint16_t *pre, int32_t *total, int32_t *err,

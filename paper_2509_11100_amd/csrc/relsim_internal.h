@@ -142,7 +142,7 @@ void launch_gamma_mean(const KParams &kp, int prec, int cells, const PartPtrs &p
                        const void *Bst, int32_t *err, void *sink, void *gbar_next, unsigned long long *chg,
                        hipStream_t st);
 // one secant step per particle of the energy-conserving fixed point
-void launch_gamma_secant(int prec, int n, const void *g, void *Fg, double *gp, double *rp, int first, hipStream_t st);
+void launch_gamma_secant(int prec, int n, const void *g, void *Fg, void *gp, void *rp, int first, hipStream_t st);
 void launch_sort_offsets(const KParams &kp, const uint16_t *cnt, uint16_t *pre, int32_t *total, int32_t *err,
                          hipStream_t st);
 void launch_scan(const int32_t *in, int32_t *out, int n, int32_t *tmp, hipStream_t st);

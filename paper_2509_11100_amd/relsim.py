@@ -526,7 +526,7 @@ class _SecantMix:
         next input."""
         first = self.g_prev is None
         if first:
-            self.g_prev = torch.empty(g.numel(), dtype=torch.float64, device=g.device)
+            self.g_prev = torch.empty(g.numel(), dtype=g.dtype, device=g.device)
             self.r_prev = torch.empty_like(self.g_prev)
         gamma_secant(self.ctx, g, Fg, self.g_prev, self.r_prev, first)
 
@@ -534,15 +534,16 @@ class _SecantMix:
 def gamma_secant(ctx: Context, gbar: torch.Tensor, gbar_next: torch.Tensor, g_prev: torch.Tensor,
                  r_prev: torch.Tensor, first: bool) -> None:
     """relsim_gamma_secant: gbar_next (the plain update F(gbar)) is replaced
-    by the per-particle secant step; g_prev, r_prev (FP64, n elements) carry
-    the last pass's input and residual; first only records them."""
+    by the per-particle secant step; g_prev, r_prev (n elements of the
+    particle type) carry the last pass's input and residual; first only
+    records them."""
     n = gbar.numel()
     for t in (gbar, gbar_next):
         if t.device != ctx.device or t.dtype != ctx.dtype or not t.is_contiguous() or t.numel() < n:
             raise ValueError("gbar arrays must be contiguous tensors of the particle type")
     for t in (g_prev, r_prev):
-        if t.device != ctx.device or t.dtype != torch.float64 or not t.is_contiguous() or t.numel() < n:
-            raise ValueError("g_prev and r_prev must be contiguous float64 tensors of at least n elements")
+        if t.device != ctx.device or t.dtype != ctx.dtype or not t.is_contiguous() or t.numel() < n:
+            raise ValueError("g_prev and r_prev must be contiguous tensors of the particle type, n elements")
     ctx.check(ctx.lib.relsim_gamma_secant(ctx.handle, C.c_int64(n), _ptr(gbar), _ptr(gbar_next), _ptr(g_prev),
                                           _ptr(r_prev), 1 if first else 0))
 
