@@ -1683,7 +1683,8 @@ void launch_gamma_mean(const KParams &kp, int prec, int cells, const PartPtrs &p
 
 namespace {
 // Per-particle secant step of the energy-conserving fixed point (FP64
-// residuals and slopes whatever T); see relsim_gamma_secant.
+// residuals and slopes whatever T, the history kept in T); see
+// relsim_gamma_secant.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gamma_secant(int n, const T *__restrict__ g, T *__restrict__ Fg,
                                                       T *__restrict__ gp, T *__restrict__ rp, int first) {
@@ -1698,8 +1699,8 @@ __global__ __launch_bounds__(256) void k_gamma_secant(int n, const T *__restrict
     const double nxt = use ? gd - r / slope : gd + r;
     Fg[i] = (T)(nxt < 1.0 ? 1.0 : nxt);  // a NaN passes through (and fails the caller's test)
   }
-  gp[i] = gd;
-  rp[i] = r;
+  gp[i] = (T)gd;  // exact: gd is g[i]
+  rp[i] = (T)r;
 }
 }  // namespace
 
