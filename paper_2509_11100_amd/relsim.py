@@ -440,71 +440,6 @@ def energy_noalloc(params, parts: Particles, E: torch.Tensor, B: torch.Tensor,
     return out
 
 
-class _AndersonMix:
-    """Anderson mixing of the fixed point g = F(g) (type II, depth m).  The
-    last m differences of inputs and residuals are kept on the device in
-    FP64 (preallocated rings); each pass forms the weighted m x m normal
-    equations with two small products on the device, solves them on the host
-    (one small copy), and writes the mixed input with device arithmetic."""
-
-    def __init__(self, m: int):
-        self.m = m
-        self.k = 0            # history entries in use
-        self.head = 0         # ring position of the next entry
-        self.dG = self.dF = None
-        self.g_prev = self.f_prev = None
-
-    def __call__(self, g: torch.Tensor, Fg: torch.Tensor) -> None:
-        """g: the pass's input, Fg: its output; Fg is overwritten with the
-        next input."""
-        # a copy: g's buffer receives the output of the pass after next
-        gd = g.to(torch.float64, copy=True)
-        f = Fg.double() - gd
-        if self.dG is None:
-            n = g.numel()
-            self.dG = torch.empty((self.m, n), dtype=torch.float64, device=g.device)
-            self.dF = torch.empty((self.m, n), dtype=torch.float64, device=g.device)
-        if self.g_prev is not None:
-            torch.sub(gd, self.g_prev, out=self.dG[self.head])
-            torch.sub(f, self.f_prev, out=self.dF[self.head])
-            self.head = (self.head + 1) % self.m
-            self.k = min(self.k + 1, self.m)
-        self.g_prev, self.f_prev = gd, f
-        if self.k == 0:
-            return  # first pass: the plain fixed-point update (Fg as it is)
-        dF, dG = self.dF[: self.k], self.dG[: self.k]
-        w2 = 1.0 / (gd * gd)  # least squares on the residual relative to g
-        wF = dF * w2
-        k = self.k
-        # the k(k+1)/2 + k inner products as separate dot products: a
-        # (k x n)(n x k) matrix product with n in the millions runs as one
-        # long serial reduction per output in the BLAS
-        dots = [torch.dot(wF[i], dF[j]) for i in range(k) for j in range(i, k)]
-        dots += [torch.dot(wF[i], f) for i in range(k)]
-        small = torch.stack(dots).cpu().numpy()
-        A = np.empty((k, k))
-        t = 0
-        for i in range(k):
-            for j in range(i, k):
-                A[i, j] = A[j, i] = small[t]
-                t += 1
-        b = small[t:]
-        if not np.all(np.isfinite(A)) or not np.all(np.isfinite(b)):
-            return
-        # a small ridge keeps the normal equations solvable when two
-        # differences are nearly parallel
-        A = A + 1e-12 * max(np.trace(A), 1e-300) * np.eye(k)
-        try:
-            theta = np.linalg.solve(A, b)
-        except np.linalg.LinAlgError:
-            return
-        if not np.all(np.isfinite(theta)):
-            return
-        th = torch.as_tensor(theta, dtype=torch.float64, device=g.device)
-        nxt = gd + f - th @ (dG + dF)
-        Fg.copy_(torch.clamp(nxt, min=1.0).to(Fg.dtype))
-
-
 class _SecantMix:
     """Per-particle secant steps for the fixed point g = F(g) through
     relsim_gamma_secant: with the residual r = F(g) - g of this pass and the
@@ -582,18 +517,7 @@ class Step:
     conserved to the stated tolerance; with allow_unconverged=True a finite
     change only clears picard_converged and the step goes on.
 
-    anderson=m > 0 accelerates the fixed point gbar = F(gbar) by Anderson
-    mixing of the last m passes (Walker and Ni 2011, type II): with the
-    residuals f_k = F(g_k) - g_k, the next input is g_k + f_k - (dG + dF)
-    theta, theta minimising |(f_k - dF theta) / g_k| over the differences dF,
-    dG of the last m residuals and inputs (least squares on their FP64 dot
-    products, weighted by 1 / g_k so that every particle counts relatively);
-    gbar is kept >= 1, and a non-finite mix falls back to the plain pass.
-    The stopping test (the largest relative change of one pass) and the
-    final push (with the last pass's input) are those of the plain
-    iteration, so the fixed point reached is the same.
-
-    secant=True (with anderson=0) replaces the plain update by per-particle
+    secant=True replaces the plain update by per-particle
     secant steps (each particle's next gbar from the line through its last
     two residuals, see _SecantMix).
 
@@ -603,8 +527,7 @@ class Step:
 
     def __init__(self, ctx: Context, parts: Particles, E: torch.Tensor, B: torch.Tensor,
                  energy_conserving: bool = False, picard_tol: Optional[float] = None, picard_maxit: int = 30,
-                 allow_unconverged: bool = False, anderson: int = 0, warm_start: bool = True,
-                 secant: bool = False):
+                 allow_unconverged: bool = False, warm_start: bool = True, secant: bool = False):
         _grid_ok(ctx, E, B)
         self.ctx, self.parts = ctx, parts
         self.E, self.B = E.clone(), B.clone()
@@ -617,7 +540,6 @@ class Step:
             picard_tol = 1e-12 if ctx.precision == "fp64" else 1e-6
         self.picard_tol, self.picard_maxit = picard_tol, picard_maxit
         self.allow_unconverged = allow_unconverged
-        self.anderson = int(anderson)
         self.warm_start = bool(warm_start)
         self.secant = bool(secant)
         self.picard_iters, self.picard_change, self.picard_converged = 0, 0.0, True
@@ -637,11 +559,7 @@ class Step:
             if self.energy_conserving:
                 gamma_mean(self.ctx, self.parts, self.E, self.B, None, self._gb[0])
                 gbar, nxt = self._gb[0], 1
-                mix = None
-                if self.anderson > 0:
-                    mix = _AndersonMix(self.anderson)
-                elif self.secant:
-                    mix = _SecantMix(self.ctx)
+                mix = _SecantMix(self.ctx) if self.secant else None
                 for it in range(1, self.picard_maxit + 1):
                     # after the first pass GMRES starts from the last pass's E_theta
                     self._solve(gbar, guess=self.warm_start and it > 1)

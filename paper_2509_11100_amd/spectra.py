@@ -117,7 +117,7 @@ def device_spectra(parts, species: Sequence[int], edges: np.ndarray = EDGES) -> 
 
 def run(steps: Optional[int] = None, snapshots: Sequence[float] = (0, 1, 2, 3, 4, 5, 6, 7, 7.77),
         precision: str = "mixed", energy_conserving: bool = True, rtol: float = 1e-10,
-        workers: int = 16, log=sys.stdout, anderson: int = 0, secant: bool = True, out: Optional[str] = None,
+        workers: int = 16, log=sys.stdout, secant: bool = True, out: Optional[str] = None,
         mass_fp32: bool = False, **overrides) -> Dict:
     """The fiducial Table 2 run: spectra of the background electrons and
     ions at the given times (t c / L_y), the energy history, and the slope
@@ -146,7 +146,7 @@ def run(steps: Optional[int] = None, snapshots: Sequence[float] = (0, 1, 2, 3, 4
     # still miss the tolerance instead of stopping the run
     step = relsim.Step(ctx, parts, torch.as_tensor(E).cuda(), torch.as_tensor(B).cuda(),
                        energy_conserving=energy_conserving, picard_maxit=60, allow_unconverged=True,
-                       anderson=anderson, secant=secant)
+                       secant=secant)
     S = wl.nspecies
     bg = (S - 2, S - 1)  # background ion and electron species
     sce = sigma_ce(wl)
@@ -154,7 +154,7 @@ def run(steps: Optional[int] = None, snapshots: Sequence[float] = (0, 1, 2, 3, 4
     marks = sorted(set(int(round(t / tcl)) for t in snapshots if round(t / tcl) <= nsteps) | {nsteps})
     rec = {"workload": wl.name, "particles": n, "precision": precision, "mass_fp32": bool(mass_fp32),
            "energy_conserving": energy_conserving,
-           "fixed_point": "anderson %d" % anderson if anderson else ("secant" if secant else "plain"),
+           "fixed_point": "secant" if secant else "plain",
            "dt": wl.dt, "dx": wl.dx, "sigma_ce": sce, "sigma_ci": sci, "edges": EDGES.tolist(), "snapshots": []}
     W0 = step.energy()
     k = 0
@@ -201,7 +201,6 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=None, help="default: to t c / L_y = 7.77")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--standard", action="store_true", help="the standard step (gbar = gamma(u^n))")
-    ap.add_argument("--anderson", type=int, default=0, help="Anderson depth of the fixed point (default 0: none)")
     ap.add_argument("--plain", action="store_true",
                     help="plain fixed-point passes (default: per-particle secant steps)")
     ap.add_argument("--mass-fp32", action="store_true", help="mixed precision with M stored in FP32")
@@ -213,8 +212,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
     over = {k: v for k, v in (("nx", args.nx), ("ny", args.ny), ("ppc", args.ppc), ("ppc_sheet", args.ppc_sheet))
             if v is not None}
-    rec = run(args.steps, precision=args.precision, energy_conserving=not args.standard, anderson=args.anderson,
-              secant=not args.plain, out=args.out, mass_fp32=args.mass_fp32, **over)
+    rec = run(args.steps, precision=args.precision, energy_conserving=not args.standard, secant=not args.plain,
+              out=args.out, mass_fp32=args.mass_fp32, **over)
     last = rec["snapshots"][-1]
     print(json.dumps({"t_c_over_Ly": last["t_c_over_Ly"], "energy_error": last["energy_error"],
                       "electrons": last["electrons"], "ions": last["ions"], "ms_per_step": rec["ms_per_step"]}))
