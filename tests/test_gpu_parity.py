@@ -804,7 +804,8 @@ def test_energy_conserving_steps_match_oracle_and_conserve_energy(secant):
 
 def test_energy_conserving_argument_checks():
     """relsim_gamma_mean refuses an output that aliases its input and a
-    misaligned gbar; the binding refuses gbar of the wrong type or length.
+    misaligned gbar; relsim_gamma_secant refuses aliased, misaligned, null or
+    oversized arrays; the binding refuses arrays of the wrong type or length.
     All are caught on the host before any kernel runs."""
     need_gpu()
     import ctypes as C
@@ -833,3 +834,15 @@ def test_energy_conserving_argument_checks():
         relsim.deposit_moments(ctx, parts, B, gbar=torch.ones(n, dtype=torch.float32, device="cuda"))
     with pytest.raises(ValueError):
         relsim.push(ctx, parts, E, B, gbar=torch.ones(n - 1, dtype=torch.float64, device="cuda"))
+    # relsim_gamma_secant: aliased pair, misaligned history, too many
+    # particles, null arrays; and the binding's type check
+    h = torch.ones(n + 1, dtype=torch.float64, device="cuda")
+    lib, hd = ctx.lib, ctx.handle
+    assert lib.relsim_gamma_secant(hd, n, gb.data_ptr(), gb.data_ptr(), h.data_ptr(), h.data_ptr(), 1) == RELSIM_EINVAL
+    assert lib.relsim_gamma_secant(hd, n, gb.data_ptr(), h.data_ptr(), h.data_ptr() + 4, h.data_ptr(), 1) \
+        == RELSIM_EINVAL
+    assert lib.relsim_gamma_secant(hd, n + 10**6, gb.data_ptr(), h.data_ptr(), h.data_ptr(), h.data_ptr(), 1) \
+        == RELSIM_EINVAL
+    assert lib.relsim_gamma_secant(hd, n, gb.data_ptr(), None, h.data_ptr(), h.data_ptr(), 1) == RELSIM_EINVAL
+    with pytest.raises(ValueError):
+        relsim.gamma_secant(ctx, gb[:n], h[:n], torch.ones(n, dtype=torch.float32, device="cuda"), h[:n], True)
