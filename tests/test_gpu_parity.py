@@ -120,8 +120,10 @@ def test_deposit_parity(gname, precision):
 def test_fp32_mass_matrix_is_the_fp64_one_rounded(gname):
     """mass_fp32 stores the same FP64 sums rounded to FP32: on the same
     particles the two contexts' M agree bit for bit after rounding the FP64
-    one, and Jhat is identical."""
+    one, and Jhat is identical.  Each context refuses the other's M."""
     need_gpu()
+    import ctypes as C
+
     import torch
 
     from paper_2509_11100_amd import relsim
@@ -134,6 +136,17 @@ def test_fp32_mass_matrix_is_the_fp64_one_rounded(gname):
     assert M.dtype == torch.float64 and M32.dtype == torch.float32
     assert torch.equal(J, J32)
     assert torch.equal(M.to(torch.float32), M32)
+    # each context takes only its own storage type, and M aligned to it
+    from paper_2509_11100_amd._lib import RELSIM_EINVAL
+
+    with pytest.raises(ValueError):
+        relsim.apply_A(ctx, M32, torch_grid(E))
+    with pytest.raises(ValueError):
+        relsim.deposit_moments(ctx32, parts32, torch_grid(B), J32, M)
+    parts.s.n = parts.n
+    Bt = torch_grid(B)
+    rc = ctx.lib.relsim_deposit_moments(ctx.handle, C.byref(parts.s), Bt.data_ptr(), J.data_ptr(), M.data_ptr() + 4)
+    assert rc == RELSIM_EINVAL
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
